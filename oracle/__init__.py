@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for the local-GP SDF back-end (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP path.  The arithmetic lives
+in ``ksdf_oracle.cpp`` (plain C++17, double precision, OpenMP over independent
+cells and queries); this module compiles it with g++ and marshals arrays.
+``tiny_dense`` holds an independent NumPy/SciPy dense-GP check for tiny inputs.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ksdf_oracle.cpp")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_lp = ctypes.POINTER(ctypes.c_long)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_i8p = ctypes.POINTER(ctypes.c_int8)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with g++ (no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        L.oracle_cells_build.restype = ctypes.c_void_p
+        L.oracle_cells_build.argtypes = [_dp, ctypes.c_long, _dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_int, _u8p, _ip, _ip]
+        L.oracle_cells_count.restype = ctypes.c_int
+        L.oracle_cells_count.argtypes = [ctypes.c_void_p, _lp]
+        L.oracle_cells_copy.argtypes = [ctypes.c_void_p, _ip, _ip, _ip, _dp]
+        L.oracle_cells_free.argtypes = [ctypes.c_void_p]
+        L.oracle_fit.restype = ctypes.c_int
+        L.oracle_fit.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, ctypes.c_double, ctypes.c_double,
+                                 _dp, _dp, _ip]
+        L.oracle_query.argtypes = ([_dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp] +
+                                   [ctypes.c_double] * 3 + [ctypes.c_int] * 3 +
+                                   [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
+                                    _ip, _dp, _dp, _dp, _dp, _dp, _ip, _dp])
+        L.oracle_vjp.restype = ctypes.c_double
+        L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
+                                  ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp,
+                                  _dp, _dp])
+        _lib = L
+    return _lib
+
+
+def _p(a, t):
+    if a is None:
+        return None
+    return a.ctypes.data_as(t)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+@dataclasses.dataclass
+class Cells:
+    offsets: np.ndarray    # int32 [n+1]
+    samples: np.ndarray    # int32 [nnz]
+    keys: np.ndarray       # int32 [n,3]
+    centres: np.ndarray    # float64 [n,3]
+
+    @property
+    def n(self):
+        return len(self.offsets) - 1
+
+    @property
+    def m(self):
+        return np.diff(self.offsets)
+
+
+def build_cells(points, origin, h, margin, m_max, m_min, cap_grid=None, key_lo=(0, 0, 0)) -> Cells:
+    L = lib()
+    pts = _f64(points)
+    org = _f64(origin)
+    cg = None if cap_grid is None else np.ascontiguousarray(cap_grid, dtype=np.uint8)
+    klo = np.ascontiguousarray(key_lo, dtype=np.int32)
+    kd = np.ascontiguousarray(cg.shape if cg is not None else (0, 0, 0), dtype=np.int32)
+    hdl = L.oracle_cells_build(_p(pts, _dp), len(pts), _p(org, _dp), h, margin, m_max, m_min,
+                               _p(cg, _u8p), _p(klo, _ip), _p(kd, _ip))
+    nnz = ctypes.c_long()
+    n = L.oracle_cells_count(hdl, ctypes.byref(nnz))
+    off = np.zeros(n + 1, np.int32)
+    smp = np.zeros(nnz.value, np.int32)
+    keys = np.zeros((n, 3), np.int32)
+    ctr = np.zeros((n, 3), np.float64)
+    L.oracle_cells_copy(hdl, _p(off, _ip), _p(smp, _ip), _p(keys, _ip), _p(ctr, _dp))
+    L.oracle_cells_free(hdl)
+    return Cells(off, smp, keys, ctr)
+
+
+def cells_for(wl) -> Cells:
+    return build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                       wl.m_cap_grid, wl.key_lo)
+
+
+@dataclasses.dataclass
+class Fit:
+    a: np.ndarray        # [nnz]
+    L: np.ndarray        # concatenated row-major m x m factors
+    lofs: np.ndarray     # [n+1] offsets into L
+    ok: np.ndarray       # [n] 1 if the cell factored
+    n_failed: int
+
+    def factor(self, c, cells: Cells):
+        m = cells.offsets[c + 1] - cells.offsets[c]
+        return self.L[self.lofs[c]:self.lofs[c + 1]].reshape(m, m)
+
+
+def fit(points, cells: Cells, ell, noise, svar=None) -> Fit:
+    L = lib()
+    pts = _f64(points)
+    sv = None if svar is None else _f64(svar)
+    m = cells.m.astype(np.int64)
+    lofs = np.concatenate([[0], np.cumsum(m * m)])
+    a = np.zeros(cells.offsets[-1], np.float64)
+    Lf = np.zeros(int(lofs[-1]), np.float64)
+    ok = np.zeros(cells.n, np.int32)
+    nf = L.oracle_fit(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
+                      _p(cells.samples, _ip), ell, noise, _p(a, _dp), _p(Lf, _dp), _p(ok, _ip))
+    return Fit(a, Lf, lofs, ok, nf)
+
+
+def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=8,
+          cand_prec=64, d_mode=0, sign=None, svar=None) -> dict:
+    """All outputs of the back-end at each query (see ``oracle_query``)."""
+    L = lib()
+    pts = _f64(points)
+    q = _f64(queries).reshape(-1, 3)
+    nq = len(q)
+    alpha = 1.0 / (2 * ell * ell) if alpha is None else alpha
+    sv = None if svar is None else _f64(svar)
+    sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.int8)
+    out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "var2",
+                                     "var_f2", "ratio", "ratio2")}
+    out["grad"] = np.zeros((nq, 3))
+    out["grad2"] = np.zeros((nq, 3))
+    out["argmin"] = np.zeros(nq, np.int32)
+    out["argmin2"] = np.zeros(nq, np.int32)
+    out["status"] = np.zeros(nq, np.int32)
+    out["cand"] = np.zeros((nq, k_fuse), np.int32)
+    out["ucand"] = np.zeros((nq, k_fuse))
+    ctr = _f64(cells.centres)
+    L.oracle_query(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
+                   _p(cells.samples, _ip), _p(ctr, _dp), _p(f.a, _dp), _p(f.L, _dp), ell, noise,
+                   alpha, k_fuse, cand_prec, d_mode, _p(q, _dp), nq, _p(sg, _i8p),
+                   _p(out["mean"], _dp), _p(out["grad"], _dp), _p(out["var"], _dp),
+                   _p(out["var_f"], _dp), _p(out["argmin"], _ip), _p(out["status"], _ip),
+                   _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["argmin2"], _ip),
+                   _p(out["grad2"], _dp), _p(out["var2"], _dp), _p(out["var_f2"], _dp),
+                   _p(out["ratio"], _dp), _p(out["ratio2"], _dp), _p(out["cand"], _ip),
+                   _p(out["ucand"], _dp))
+    return out
+
+
+def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_prec=64, sign=None,
+        mode=0, margin=0.3, weight=1.0, d_mean=None, d_grad=None, d_var=None, d_var_f=None):
+    """Dual-number VJP.  mode 0: given cotangents; mode 1: softplus collision cost.
+    Returns (loss, d_points [Q,3], d_hyper [2] = d/d(l, sigma^2))."""
+    L = lib()
+    pts = _f64(points)
+    q = _f64(queries).reshape(-1, 3)
+    sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.int8)
+    dp = np.zeros((len(q), 3))
+    dh = np.zeros(2)
+    cot = [None if c is None else _f64(c) for c in (d_mean, d_grad, d_var, d_var_f)]
+    ctr = _f64(cells.centres)
+    loss = L.oracle_vjp(_p(pts, _dp), cells.n, _p(cells.offsets, _ip), _p(cells.samples, _ip),
+                        _p(ctr, _dp), ell, noise, -1.0 if alpha is None else alpha, k_fuse,
+                        cand_prec, _p(q, _dp), len(q), _p(sg, _i8p), mode, margin, weight,
+                        *[_p(c, _dp) for c in cot], _p(dp, _dp), _p(dh, _dp))
+    return loss, dp, dh
+
+
+def run(points, cells: Cells, queries, ell, noise, **kw):
+    """Fit then query, returning (fit, outputs)."""
+    f = fit(points, cells, ell, noise, svar=kw.get("svar"))
+    return f, query(points, cells, f, queries, ell, noise, **kw)

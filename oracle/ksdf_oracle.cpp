@@ -1,0 +1,587 @@
+// FP64 CPU oracle for the local-GP SDF back-end of Kernel-SDF (arXiv 2603.29227).
+//
+// TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+// benchmark's CPU-baseline leg may load this library.  It shares no code with
+// the HIP path and must never serve as a fallback for it.
+//
+// Plain, slow, obviously correct: every step follows the paper's definitions in
+// their own order, in double precision, with straightforward loops and no
+// blocking or fusion.  Sections cited below are the paper's:
+//   Sec. IV-B.1  log-GP posterior mean, gradient and variance (eq. log_gp_posterior_mean),
+//                kernel vector / matrix / noise, UDF gradient, local GPs per octant with
+//                overlapping collection boxes, min-fusion of the K nearest GPs
+//   Table I      RBF kernel and its inverse transform r(f)
+//   App. D       adaptive scaling (gamma = exp(d^2 / 2 l^2), r(f') = sqrt(-2 l^2 log f' + d^2))
+//   Sec. IV-B.3  softmin SDF variance V[u] = sum_i |grad_{x_i} h|^2 sigma_i^2
+//   Sec. IV-B.1  sign decomposition d = s * u
+//
+// Readings where the paper is silent (all shared with the GPU path as inputs):
+//   cells: collection box = cell box grown by `margin` per side; up to m_c samples
+//   nearest the cell centre (ties by lower sample index); candidate GPs = the
+//   K nearest occupied cell centres (ties by id); d in App. D = nearest sample;
+//   f' <= 0 excludes the cell (u = +inf); u^2 < 0 clamps u to 0; softmin
+//   temperature alpha = 1/(2 l^2) unless given.
+//
+// Scalar type T is double for the forward pass and Dual<N> (forward-mode
+// automatic differentiation) for the vector-Jacobian products.
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers
+// ---------------------------------------------------------------------------
+template <int N>
+struct Dual {
+  double v;
+  double d[N];
+  Dual() : v(0) { for (int k = 0; k < N; ++k) d[k] = 0; }
+  Dual(double x) : v(x) { for (int k = 0; k < N; ++k) d[k] = 0; }  // NOLINT
+};
+template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v + b.v); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v - b.v); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+template <int N> Dual<N> operator-(const Dual<N>& a) {
+  Dual<N> r(-a.v); for (int k = 0; k < N; ++k) r.d[k] = -a.d[k]; return r; }
+template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v * b.v); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
+  Dual<N> r(a.v / b.v);
+  for (int k = 0; k < N; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r; }
+template <int N> Dual<N> exp(const Dual<N>& a) {
+  Dual<N> r(std::exp(a.v)); for (int k = 0; k < N; ++k) r.d[k] = r.v * a.d[k]; return r; }
+template <int N> Dual<N> log(const Dual<N>& a) {
+  Dual<N> r(std::log(a.v)); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / a.v; return r; }
+template <int N> Dual<N> sqrt(const Dual<N>& a) {
+  Dual<N> r(std::sqrt(a.v));
+  for (int k = 0; k < N; ++k) r.d[k] = (r.v > 0) ? a.d[k] / (2 * r.v) : 0.0;
+  return r; }
+template <int N> Dual<N> log1p(const Dual<N>& a) {
+  Dual<N> r(std::log1p(a.v)); for (int k = 0; k < N; ++k) r.d[k] = a.d[k] / (1 + a.v); return r; }
+template <int N> Dual<N> fabs(const Dual<N>& a) { return a.v < 0 ? -a : a; }
+
+inline double val(double x) { return x; }
+template <int N> double val(const Dual<N>& x) { return x.v; }
+
+using std::exp; using std::log; using std::sqrt; using std::log1p; using std::fabs;
+
+// ---------------------------------------------------------------------------
+// cells (the per-octant GP training buffers with overlapping collection boxes)
+// ---------------------------------------------------------------------------
+struct Key { long i, j, k; };
+bool operator<(const Key& a, const Key& b) {
+  return std::tie(a.i, a.j, a.k) < std::tie(b.i, b.j, b.k);
+}
+
+struct CellSet {
+  std::vector<int> offsets, samples, keys;
+  std::vector<double> centres;
+};
+
+}  // namespace
+
+extern "C" {
+
+// Build the cells.  Keys are floor((x - origin) / h) per axis; a key is occupied
+// when its own box holds a sample; its training set is the up-to-m_c samples of
+// the collection box (cell box grown by `margin`, bounds inclusive) nearest the
+// cell centre origin + (key + 1/2) h, ties by lower sample index; cells with fewer
+// than m_min samples are dropped; ids follow lexicographic key order.
+void* oracle_cells_build(const double* pts, long n, const double* origin, double h,
+                         double margin, int m_max, int m_min, const uint8_t* cap_grid,
+                         const int* key_lo, const int* key_dims) {
+  std::map<Key, std::vector<long>> bins;
+  for (long s = 0; s < n; ++s) {
+    Key k{(long)std::floor((pts[3 * s + 0] - origin[0]) / h),
+          (long)std::floor((pts[3 * s + 1] - origin[1]) / h),
+          (long)std::floor((pts[3 * s + 2] - origin[2]) / h)};
+    bins[k].push_back(s);
+  }
+  const long reach = (long)std::ceil(margin / h) + 1;
+  auto* out = new CellSet;
+  out->offsets.push_back(0);
+  for (const auto& kv : bins) {
+    const Key& c = kv.first;
+    double lo[3], hi[3], ctr[3];
+    const long kc[3] = {c.i, c.j, c.k};
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = origin[d] + (double)kc[d] * h - margin;
+      hi[d] = origin[d] + (double)(kc[d] + 1) * h + margin;
+      ctr[d] = origin[d] + ((double)kc[d] + 0.5) * h;
+    }
+    std::vector<std::pair<double, long>> cand;
+    for (long di = -reach; di <= reach; ++di)
+      for (long dj = -reach; dj <= reach; ++dj)
+        for (long dk = -reach; dk <= reach; ++dk) {
+          auto it = bins.find(Key{c.i + di, c.j + dj, c.k + dk});
+          if (it == bins.end()) continue;
+          for (long s : it->second) {
+            const double* x = pts + 3 * s;
+            bool in = true;
+            for (int d = 0; d < 3; ++d) in = in && (x[d] >= lo[d]) && (x[d] <= hi[d]);
+            if (!in) continue;
+            double dx = x[0] - ctr[0], dy = x[1] - ctr[1], dz = x[2] - ctr[2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            cand.push_back({r2, s});
+          }
+        }
+    std::sort(cand.begin(), cand.end());
+    long m_c = m_max;
+    if (cap_grid) {
+      long g[3] = {kc[0] - key_lo[0], kc[1] - key_lo[1], kc[2] - key_lo[2]};
+      if (g[0] >= 0 && g[0] < key_dims[0] && g[1] >= 0 && g[1] < key_dims[1] && g[2] >= 0 &&
+          g[2] < key_dims[2])
+        m_c = std::min<long>(m_max, cap_grid[(g[0] * key_dims[1] + g[1]) * key_dims[2] + g[2]]);
+    }
+    long take = std::min<long>(m_c, (long)cand.size());
+    if (take < m_min) continue;
+    for (long t = 0; t < take; ++t) out->samples.push_back((int)cand[t].second);
+    out->offsets.push_back((int)out->samples.size());
+    out->keys.push_back((int)c.i); out->keys.push_back((int)c.j); out->keys.push_back((int)c.k);
+    for (int d = 0; d < 3; ++d) out->centres.push_back(ctr[d]);
+  }
+  return out;
+}
+
+int oracle_cells_count(void* hdl, long* nnz) {
+  auto* c = static_cast<CellSet*>(hdl);
+  *nnz = (long)c->samples.size();
+  return (int)c->offsets.size() - 1;
+}
+
+void oracle_cells_copy(void* hdl, int* offsets, int* samples, int* keys, double* centres) {
+  auto* c = static_cast<CellSet*>(hdl);
+  std::copy(c->offsets.begin(), c->offsets.end(), offsets);
+  std::copy(c->samples.begin(), c->samples.end(), samples);
+  std::copy(c->keys.begin(), c->keys.end(), keys);
+  std::copy(c->centres.begin(), c->centres.end(), centres);
+}
+
+void oracle_cells_free(void* hdl) { delete static_cast<CellSet*>(hdl); }
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// fit: A = K + Sigma (eq. log_gp_posterior_mean with K_ij = k(x_i, x_j), Sigma_ii =
+// sigma_i^2), RBF k(r) = exp(-r^2 / 2 l^2) (Table I); A = L L^T (textbook
+// Cholesky); a = A^{-1} 1 (all labels equal exp(-lambda * 0) = 1).
+// ---------------------------------------------------------------------------
+struct Inputs {
+  const double* pts;        // [N,3] surface samples
+  const double* svar;       // [N] per-sample sigma_i^2 or null (uniform)
+  int n_cells;
+  const int* offsets;       // [n_cells+1]
+  const int* samples;       // [nnz]
+  const double* centres;    // [n_cells,3]
+  const long* lofs;         // [n_cells] offset of each cell's m x m factor
+};
+
+template <class T>
+T sample_var(const Inputs& in, int s, const T& noise) {
+  return in.svar ? T(in.svar[s]) : noise;
+}
+
+// Returns false when a pivot is not positive (cell not SPD).
+template <class T>
+bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L) {
+  const int b = in.offsets[c], m = in.offsets[c + 1] - b;
+  std::vector<T> A((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      const double* xi = in.pts + 3 * (long)in.samples[b + i];
+      const double* xj = in.pts + 3 * (long)in.samples[b + j];
+      double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
+      double r2 = dx * dx + dy * dy + dz * dz;
+      A[(size_t)i * m + j] = exp(T(-r2) / (T(2.0) * ell * ell));
+      if (i == j) A[(size_t)i * m + j] = A[(size_t)i * m + j] + sample_var(in, in.samples[b + i], noise);
+    }
+  for (int i = 0; i < m * m; ++i) L[i] = T(0.0);
+  for (int j = 0; j < m; ++j) {
+    T s = A[(size_t)j * m + j];
+    for (int k = 0; k < j; ++k) s = s - L[(size_t)j * m + k] * L[(size_t)j * m + k];
+    if (!(val(s) > 0)) return false;
+    L[(size_t)j * m + j] = sqrt(s);
+    for (int i = j + 1; i < m; ++i) {
+      T t = A[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) t = t - L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      L[(size_t)i * m + j] = t / L[(size_t)j * m + j];
+    }
+  }
+  std::vector<T> y(m);
+  for (int i = 0; i < m; ++i) {            // L y = 1
+    T t = T(1.0);
+    for (int k = 0; k < i; ++k) t = t - L[(size_t)i * m + k] * y[k];
+    y[i] = t / L[(size_t)i * m + i];
+  }
+  for (int i = m - 1; i >= 0; --i) {       // L^T a = y
+    T t = y[i];
+    for (int k = i + 1; k < m; ++k) t = t - L[(size_t)k * m + i] * a[k];
+    a[i] = t / L[(size_t)i * m + i];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// query
+// ---------------------------------------------------------------------------
+struct QueryOpts {
+  double ell_v, alpha_v;
+  int k_fuse;
+  int cand_prec;        // 64: candidate distances in double; 32: in float (fmaf order)
+  int d_mode;           // 0: d = nearest sample (default); 1: d = first sample; 2: d = 0
+  bool alpha_tied;      // alpha = 1/(2 l^2) follows l
+};
+
+// K nearest occupied cell centres, ties by lower id (Sec. IV-B.1, "K nearest GPs").
+std::vector<int> candidates(const Inputs& in, const double* q, const QueryOpts& o) {
+  std::vector<std::pair<double, int>> d(in.n_cells);
+  for (int c = 0; c < in.n_cells; ++c) {
+    const double* ce = in.centres + 3 * (long)c;
+    double r2;
+    if (o.cand_prec == 32) {
+      float dx = (float)q[0] - (float)ce[0];
+      float dy = (float)q[1] - (float)ce[1];
+      float dz = (float)q[2] - (float)ce[2];
+      float t = dx * dx;
+      t = std::fmaf(dy, dy, t);
+      t = std::fmaf(dz, dz, t);
+      r2 = (double)t;
+    } else {
+      double dx = q[0] - ce[0], dy = q[1] - ce[1], dz = q[2] - ce[2];
+      r2 = dx * dx + dy * dy + dz * dz;
+    }
+    d[c] = {r2, c};
+  }
+  int k = std::min(o.k_fuse, in.n_cells);
+  std::partial_sort(d.begin(), d.begin() + k, d.end());
+  std::vector<int> out(k);
+  for (int i = 0; i < k; ++i) out[i] = d[i].second;
+  return out;
+}
+
+// Per-candidate UDF (eq. log_gp_posterior_mean mean with App. D scaling, Table I transform).
+template <class T>
+T cell_udf(const Inputs& in, int c, const T* q, const T* a, const T& ell, const QueryOpts& o,
+           bool* clamped) {
+  const int b = in.offsets[c], m = in.offsets[c + 1] - b;
+  std::vector<T> z2(m);
+  for (int i = 0; i < m; ++i) {
+    const double* x = in.pts + 3 * (long)in.samples[b + i];
+    T dx = q[0] - T(x[0]), dy = q[1] - T(x[1]), dz = q[2] - T(x[2]);
+    z2[i] = dx * dx + dy * dy + dz * dz;
+  }
+  T d2 = T(0.0);
+  if (o.d_mode == 0) {
+    d2 = z2[0];
+    for (int i = 1; i < m; ++i) if (val(z2[i]) < val(d2)) d2 = z2[i];
+  } else if (o.d_mode == 1) {
+    d2 = z2[0];
+  }
+  T f = T(0.0);
+  for (int i = 0; i < m; ++i) f = f + a[b + i] * exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
+  if (!(val(f) > 0)) return T(std::numeric_limits<double>::infinity());
+  T u2 = d2 - T(2.0) * ell * ell * log(f);
+  if (val(u2) < 0) { if (clamped) *clamped = true; return T(0.0); }
+  if (clamped) *clamped = false;
+  return sqrt(u2);
+}
+
+template <class T>
+struct CellOut {
+  T grad[3];
+  T var, var_f;
+  double ratio;          // cancellation ratio sum|a_i| e_i |x*-x_i| / |w|
+  bool grad_zero;
+};
+
+// Gradient, GP variance and softmin SDF variance of one cell at q.
+template <class T>
+CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T* L,
+                        const T& ell, const T& noise, const T& alpha, const QueryOpts& o) {
+  const int b = in.offsets[c], m = in.offsets[c + 1] - b;
+  std::vector<T> z2(m), diff(3 * (size_t)m);
+  for (int i = 0; i < m; ++i) {
+    const double* x = in.pts + 3 * (long)in.samples[b + i];
+    for (int d = 0; d < 3; ++d) diff[3 * i + d] = q[d] - T(x[d]);
+    z2[i] = diff[3 * i] * diff[3 * i] + diff[3 * i + 1] * diff[3 * i + 1] + diff[3 * i + 2] * diff[3 * i + 2];
+  }
+  T d2 = z2[0];
+  for (int i = 1; i < m; ++i) if (val(z2[i]) < val(d2)) d2 = z2[i];
+  if (o.d_mode == 1) d2 = z2[0];
+  if (o.d_mode == 2) d2 = T(0.0);
+  CellOut<T> r;
+  // gradient: grad f = -(1/l^2) sum a_i k_i (x* - x_i); the UDF gradient is
+  // -grad f / |grad f| = w / |w| with w = sum a_i k_i (x* - x_i) (scaled by gamma).
+  T w[3] = {T(0.0), T(0.0), T(0.0)};
+  double absum = 0;
+  for (int i = 0; i < m; ++i) {
+    T e = exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
+    for (int d = 0; d < 3; ++d) w[d] = w[d] + a[b + i] * e * diff[3 * i + d];
+    absum += std::fabs(val(a[b + i]) * val(e)) * std::sqrt(val(z2[i]));
+  }
+  T wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  r.grad_zero = !(val(wn) > 0);
+  for (int d = 0; d < 3; ++d) r.grad[d] = r.grad_zero ? T(0.0) : w[d] / wn;
+  r.ratio = r.grad_zero ? std::numeric_limits<double>::infinity() : absum / val(wn);
+  // GP variance: k(x*, x*) - k*^T (K + Sigma)^{-1} k* = 1 - |L^{-1} k*|^2 (unscaled k*).
+  std::vector<T> v(m);
+  T vv = T(0.0);
+  for (int i = 0; i < m; ++i) {
+    T t = exp(-z2[i] / (T(2.0) * ell * ell));
+    for (int k = 0; k < i; ++k) t = t - L[in.lofs[c] + (long)i * m + k] * v[k];
+    v[i] = t / L[in.lofs[c] + (long)i * m + i];
+    vv = vv + v[i] * v[i];
+  }
+  r.var_f = T(1.0) - vv;
+  if (val(r.var_f) < 0) r.var_f = T(0.0);
+  // softmin SDF variance: s = softmax(-alpha z), h = s^T z,
+  // grad_{x_i} h = -s_i (alpha h - alpha z_i + 1)(x* - x_i)/z_i, |.|^2 = c_i^2.
+  std::vector<T> z(m), s(m);
+  T zmin = T(0.0);
+  for (int i = 0; i < m; ++i) {
+    z[i] = sqrt(z2[i]);
+    if (i == 0 || val(z[i]) < val(zmin)) zmin = z[i];
+  }
+  T ssum = T(0.0);
+  for (int i = 0; i < m; ++i) { s[i] = exp(-alpha * (z[i] - zmin)); ssum = ssum + s[i]; }
+  T hval = T(0.0);
+  for (int i = 0; i < m; ++i) { s[i] = s[i] / ssum; hval = hval + s[i] * z[i]; }
+  T var = T(0.0);
+  for (int i = 0; i < m; ++i) {
+    T ci = s[i] * (alpha * hval - alpha * z[i] + T(1.0));
+    var = var + ci * ci * sample_var(in, in.samples[b + i], noise);
+  }
+  r.var = var;
+  return r;
+}
+
+template <class T>
+struct PointOut {
+  T mean, grad[3], var, var_f;
+  int argmin, argmin2;
+  double u_best, u_second, ratio, ratio2;
+  T grad2[3], var2, var_f2;
+  int status;
+  std::vector<int> cand;
+  std::vector<double> ucand;
+};
+
+enum { ST_NO_VALID = 1, ST_CLAMPED = 2, ST_GRAD_ZERO = 4 };
+
+template <class T>
+PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, const T* L,
+                        const T& ell, const T& noise, const T& alpha, const QueryOpts& o) {
+  double qv[3] = {val(q[0]), val(q[1]), val(q[2])};
+  PointOut<T> r;
+  r.status = 0;
+  r.cand = candidates(in, qv, o);
+  std::vector<std::tuple<double, int, T, bool>> us;
+  for (int c : r.cand) {
+    bool cl = false;
+    T u = cell_udf(in, c, q, a, ell, o, &cl);
+    us.push_back(std::make_tuple(val(u), c, u, cl));
+    r.ucand.push_back(val(u));
+  }
+  std::sort(us.begin(), us.end(), [](const auto& x, const auto& y) {
+    return std::make_pair(std::get<0>(x), std::get<1>(x)) < std::make_pair(std::get<0>(y), std::get<1>(y));
+  });
+  const double inf = std::numeric_limits<double>::infinity();
+  r.argmin = -1; r.argmin2 = -1; r.u_best = inf; r.u_second = inf; r.ratio = inf; r.ratio2 = inf;
+  if (us.empty() || !(std::get<0>(us[0]) < inf)) {
+    r.status = ST_NO_VALID;
+    r.mean = T(inf);
+    for (int d = 0; d < 3; ++d) { r.grad[d] = T(0.0); r.grad2[d] = T(0.0); }
+    r.var = T(inf); r.var_f = T(1.0); r.var2 = T(inf); r.var_f2 = T(1.0);
+    return r;
+  }
+  r.argmin = std::get<1>(us[0]);
+  r.u_best = std::get<0>(us[0]);
+  if (std::get<3>(us[0])) r.status |= ST_CLAMPED;
+  // d = s * u; grad d = s * grad u; V[d] = V[u] (deterministic sign).
+  r.mean = T((double)sign) * std::get<2>(us[0]);
+  CellOut<T> co = cell_outputs(in, r.argmin, q, a, L, ell, noise, alpha, o);
+  for (int d = 0; d < 3; ++d) r.grad[d] = T((double)sign) * co.grad[d];
+  r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio;
+  if (co.grad_zero) r.status |= ST_GRAD_ZERO;
+  if (us.size() > 1 && std::get<0>(us[1]) < inf) {
+    r.argmin2 = std::get<1>(us[1]);
+    r.u_second = std::get<0>(us[1]);
+    CellOut<T> c2 = cell_outputs(in, r.argmin2, q, a, L, ell, noise, alpha, o);
+    for (int d = 0; d < 3; ++d) r.grad2[d] = T((double)sign) * c2.grad[d];
+    r.var2 = c2.var; r.var_f2 = c2.var_f; r.ratio2 = c2.ratio;
+  } else {
+    for (int d = 0; d < 3; ++d) r.grad2[d] = r.grad[d];
+    r.var2 = r.var; r.var_f2 = r.var_f;
+  }
+  return r;
+}
+
+Inputs make_inputs(const double* pts, const double* svar, int n_cells, const int* offsets,
+                   const int* samples, const double* centres, std::vector<long>& lofs) {
+  lofs.assign(n_cells + 1, 0);
+  for (int c = 0; c < n_cells; ++c) {
+    long m = offsets[c + 1] - offsets[c];
+    lofs[c + 1] = lofs[c] + m * m;
+  }
+  return Inputs{pts, svar, n_cells, offsets, samples, centres, lofs.data()};
+}
+
+template <class T>
+int fit_all(const Inputs& in, const T& ell, const T& noise, std::vector<T>& a, std::vector<T>& L,
+            int* ok) {
+  a.assign(in.offsets[in.n_cells], T(0.0));
+  L.assign(in.lofs[in.n_cells], T(0.0));
+  int nfail = 0;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : nfail)
+  for (int c = 0; c < in.n_cells; ++c) {
+    bool good = fit_cell(in, c, ell, noise, a.data() + in.offsets[c], L.data() + in.lofs[c]);
+    if (ok) ok[c] = good ? 1 : 0;
+    if (!good) {
+      // a failed cell is excluded: all-zero weights give f' = 0 -> u = +inf.
+      for (int i = in.offsets[c]; i < in.offsets[c + 1]; ++i) a[i] = T(0.0);
+      for (long i = in.lofs[c]; i < in.lofs[c + 1]; ++i) L[i] = T(1.0);
+      ++nfail;
+    }
+  }
+  return nfail;
+}
+
+double softplus(double t) { return std::max(t, 0.0) + std::log1p(std::exp(-std::fabs(t))); }
+template <int N> Dual<N> softplus(const Dual<N>& t) {
+  Dual<N> m = t.v > 0 ? t : Dual<N>(0.0);
+  return m + log1p(exp(-fabs(t)));
+}
+
+}  // namespace
+
+extern "C" {
+
+// Fit every cell in FP64.  a: [nnz]; L: concatenated row-major m_c x m_c factors.
+int oracle_fit(const double* pts, const double* svar, int n_cells, const int* offsets,
+               const int* samples, double ell, double noise, double* a_out, double* L_out,
+               int* ok) {
+  std::vector<long> lofs;
+  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, nullptr, lofs);
+  std::vector<double> a, L;
+  int nfail = fit_all<double>(in, ell, noise, a, L, ok);
+  std::copy(a.begin(), a.end(), a_out);
+  if (L_out) std::copy(L.begin(), L.end(), L_out);
+  return nfail;
+}
+
+// Query every point.  Outputs per query: mean, grad[3], var, var_f, argmin, status,
+// the runner-up cell's id, u and outputs (for near-tie acceptance), the
+// cancellation ratio of each, the K candidate ids and their u values.
+void oracle_query(const double* pts, const double* svar, int n_cells, const int* offsets,
+                  const int* samples, const double* centres, const double* a_in,
+                  const double* L_in, double ell, double noise, double alpha, int k_fuse,
+                  int cand_prec, int d_mode, const double* q, long nq, const int8_t* sign,
+                  double* mean, double* grad, double* var, double* var_f, int* argmin,
+                  int* status, double* u_best, double* u_second, int* argmin2, double* grad2,
+                  double* var2, double* var_f2, double* ratio, double* ratio2, int* cand,
+                  double* ucand) {
+  std::vector<long> lofs;
+  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs);
+  QueryOpts o{ell, alpha, k_fuse, cand_prec, d_mode, false};
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long p = 0; p < nq; ++p) {
+    PointOut<double> r = query_point<double>(in, q + 3 * p, sign ? sign[p] : 1, a_in, L_in,
+                                             ell, noise, alpha, o);
+    mean[p] = r.mean; var[p] = r.var; var_f[p] = r.var_f;
+    for (int d = 0; d < 3; ++d) grad[3 * p + d] = r.grad[d];
+    argmin[p] = r.argmin; status[p] = r.status;
+    if (u_best) u_best[p] = r.u_best;
+    if (u_second) u_second[p] = r.u_second;
+    if (argmin2) argmin2[p] = r.argmin2;
+    if (grad2) for (int d = 0; d < 3; ++d) grad2[3 * p + d] = r.grad2[d];
+    if (var2) var2[p] = r.var2;
+    if (var_f2) var_f2[p] = r.var_f2;
+    if (ratio) ratio[p] = r.ratio;
+    if (ratio2) ratio2[p] = r.ratio2;
+    if (cand)
+      for (int i = 0; i < k_fuse; ++i)
+        cand[(long)k_fuse * p + i] = i < (int)r.cand.size() ? r.cand[i] : -1;
+    if (ucand)
+      for (int i = 0; i < k_fuse; ++i)
+        ucand[(long)k_fuse * p + i] = i < (int)r.ucand.size() ? r.ucand[i]
+                                                              : std::numeric_limits<double>::infinity();
+  }
+}
+
+// Vector-Jacobian product by forward-mode dual numbers.
+//   mode 0: L = sum_q d_mean*mean + d_grad.grad + d_var*var + d_var_f*var_f
+//   mode 1: L = sum_q softplus(margin - mean + weight*sqrt(var))   (cotangent args unused)
+// d_points [nq,3] = dL/dq; d_hyper[2] = dL/d(l, sigma^2) through the fit as well
+// (the whole fit is redone in dual arithmetic); alpha = 1/(2 l^2) follows l
+// unless alpha_fixed > 0.  Returns L.
+double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int* samples,
+                  const double* centres, double ell, double noise, double alpha_fixed,
+                  int k_fuse, int cand_prec, const double* q, long nq, const int8_t* sign,
+                  int mode, double margin, double weight, const double* d_mean,
+                  const double* d_grad, const double* d_var, const double* d_var_f,
+                  double* d_points, double* d_hyper) {
+  std::vector<long> lofs;
+  Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs);
+  QueryOpts o{ell, 0, k_fuse, cand_prec, 0, alpha_fixed <= 0};
+  auto loss_of = [&](long p, auto mean, auto* g, auto var, auto var_f) {
+    using T = decltype(mean);
+    if (mode == 1) return softplus(T(margin) - mean + T(weight) * sqrt(var));
+    T l = T(d_mean ? d_mean[p] : 0.0) * mean + T(d_var ? d_var[p] : 0.0) * var +
+          T(d_var_f ? d_var_f[p] : 0.0) * var_f;
+    if (d_grad) for (int d = 0; d < 3; ++d) l = l + T(d_grad[3 * p + d]) * g[d];
+    return l;
+  };
+  // (1) hyperparameters: fit and queries in Dual<2>.
+  using D2 = Dual<2>;
+  D2 ell2(ell); ell2.d[0] = 1.0;
+  D2 noise2(noise); noise2.d[1] = 1.0;
+  D2 alpha2 = alpha_fixed > 0 ? D2(alpha_fixed) : D2(1.0) / (D2(2.0) * ell2 * ell2);
+  std::vector<D2> a2, L2;
+  fit_all<D2>(in, ell2, noise2, a2, L2, nullptr);
+  double total = 0, dh0 = 0, dh1 = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total, dh0, dh1)
+  for (long p = 0; p < nq; ++p) {
+    D2 qd[3] = {D2(q[3 * p]), D2(q[3 * p + 1]), D2(q[3 * p + 2])};
+    PointOut<D2> r = query_point<D2>(in, qd, sign ? sign[p] : 1, a2.data(), L2.data(), ell2,
+                                     noise2, alpha2, o);
+    if (r.status & ST_NO_VALID) continue;
+    D2 l = loss_of(p, r.mean, r.grad, r.var, r.var_f);
+    total += l.v; dh0 += l.d[0]; dh1 += l.d[1];
+  }
+  d_hyper[0] = dh0; d_hyper[1] = dh1;
+  // (2) query points: fit fixed in double, queries in Dual<3>.
+  std::vector<double> a, L;
+  fit_all<double>(in, ell, noise, a, L, nullptr);
+  using D3 = Dual<3>;
+  std::vector<D3> a3(a.begin(), a.end()), L3(L.begin(), L.end());
+  D3 ell3(ell), noise3(noise);
+  D3 alpha3 = alpha_fixed > 0 ? D3(alpha_fixed) : D3(1.0) / (D3(2.0) * ell3 * ell3);
+#pragma omp parallel for schedule(dynamic, 64)
+  for (long p = 0; p < nq; ++p) {
+    D3 qd[3];
+    for (int d = 0; d < 3; ++d) { qd[d] = D3(q[3 * p + d]); qd[d].d[d] = 1.0; }
+    PointOut<D3> r = query_point<D3>(in, qd, sign ? sign[p] : 1, a3.data(), L3.data(), ell3,
+                                     noise3, alpha3, o);
+    if (r.status & ST_NO_VALID) {
+      for (int d = 0; d < 3; ++d) d_points[3 * p + d] = 0;
+      continue;
+    }
+    D3 l = loss_of(p, r.mean, r.grad, r.var, r.var_f);
+    for (int d = 0; d < 3; ++d) d_points[3 * p + d] = l.d[d];
+  }
+  return total;
+}
+
+}  // extern "C"
