@@ -1,0 +1,185 @@
+/*
+ * ksdf — batched local Gaussian-process SDF regression on MI355X (gfx950).
+ *
+ * The back-end of Kernel-SDF (arXiv 2603.29227): per spatial cell a log-GP is fitted
+ * on nearby surface samples; a query evaluates its K nearest cells, maps each
+ * cell's posterior mean to a distance and keeps the smallest (min-fusion), then
+ * returns the analytic gradient, the GP variance and the softmin SDF variance.
+ *
+ *   Sec. IV-B.1  eq. log_gp_posterior_mean: f = k*^T (K + Sigma)^{-1} 1 (all labels 1),
+ *                grad f = (grad k*)^T (K + Sigma)^{-1} 1,  V[f] = k(x*,x*) - k*^T (K+Sigma)^{-1} k*;
+ *                UDF gradient -grad f / |grad f|; local GPs per octant trained on
+ *                overlapping collection boxes; u = min over the K nearest GPs;
+ *                SDF d = s * u with a sign s supplied by the caller.
+ *   Table I      RBF kernel k(r) = exp(-r^2 / 2 l^2), inverse transform r(f) = sqrt(-2 l^2 log f).
+ *   App. D       scaled kernel k' = gamma k, r(f') = sqrt(-2 l^2 log f' + d^2).
+ *   Sec. IV-B.3  V[u] = sum_i |grad_{x_i} h|^2 sigma_i^2 with the softmin h = s^T z,
+ *                grad_{x_i} h = -s_i (alpha s^T z - alpha z_i + 1)(x* - x_i)/z_i.
+ *
+ * Conventions for every entry point:
+ *   - "device" pointers are HIP device (or managed) memory on the current device;
+ *     "host" pointers are ordinary host memory.  The caller owns every buffer it
+ *     passes; the library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Device
+ *     work is enqueued asynchronously on it; unless stated, no host synchronisation.
+ *   - Return value: KSDF_OK (0) or a negative ksdf_status.  No C++ exception and no
+ *     abort crosses this boundary.  Argument errors are detected on the host before
+ *     any work is enqueued.  Numerical outcomes (an ill-conditioned cell refitted in
+ *     FP64, a failed cell, a clamped UDF, a query with no valid cell) are reported
+ *     per cell / per query in the optional status arrays, not as errors.
+ *   - Floating arrays of points and outputs are float (KSDF_FP32 models) or double
+ *     (KSDF_FP64 models), row-major; [n,3] means 3 consecutive values per point.
+ */
+#ifndef KSDF_H
+#define KSDF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ksdf_status {
+  KSDF_OK = 0,
+  KSDF_ERR_INVALID_ARGUMENT = -1, /* null pointer, bad size, bad enum, bad hyperparameter */
+  KSDF_ERR_INVALID_INPUT = -2,    /* NaN / Inf in host-visible inputs or hyperparameters */
+  KSDF_ERR_WORKSPACE = -3,        /* workspace smaller than the *_workspace_bytes query */
+  KSDF_ERR_HIP = -4,              /* a HIP runtime call failed (message in ksdf_last_error) */
+  KSDF_ERR_DEVICE = -5,           /* no usable gfx950 device, or the model lives on another device */
+  KSDF_ERR_UNSUPPORTED = -6,      /* a feature this build does not provide (e.g. m > 128) */
+  KSDF_ERR_OUT_OF_MEMORY = -7
+} ksdf_status;
+
+enum { KSDF_FP64 = 0, KSDF_FP32 = 1 };           /* model precision */
+enum { KSDF_DTYPE_F32 = 0, KSDF_DTYPE_F64 = 1 };  /* element type of surface points */
+
+/* per-query status bits (uint8) */
+enum { KSDF_Q_NO_VALID_CELL = 1, KSDF_Q_CLAMPED = 2, KSDF_Q_GRAD_ZERO = 4, KSDF_Q_OUTSIDE_INDEX = 8 };
+/* per-cell status bits (uint8) */
+enum { KSDF_C_FP64 = 1, KSDF_C_FAILED = 2 };
+
+#define KSDF_MAX_M 128     /* samples per cell */
+#define KSDF_MAX_K 16      /* fused cells per query */
+
+/* Hyperparameters (host struct).  ell: RBF length-scale l (m), > 0.  noise_var:
+ * uniform surface-sample variance sigma^2 >= 0 (used where no per-sample variance is
+ * given).  alpha: softmin temperature; <= 0 ties it to the length-scale as
+ * alpha = 1/(2 l^2), which the backward then differentiates through.  k_fuse:
+ * number of nearest cells fused by the min, 1..KSDF_MAX_K.  precision: KSDF_FP64
+ * (every step in double, one block per cell and one thread per query) or KSDF_FP32
+ * (FP32 bulk; cells whose condition estimate exceeds cond_fp64_threshold, or whose
+ * FP32 pivot fails, are factored in FP64). */
+typedef struct ksdf_hyper {
+  double ell;
+  double noise_var;
+  double alpha;
+  int k_fuse;
+  int precision;
+  double cond_fp64_threshold;
+} ksdf_hyper;
+
+/* ---------------------------------------------------------------------------
+ * Cell builder (host, OpenMP).  The per-octant GP training buffers of Sec. IV-B.1:
+ * key = floor((x - origin)/h) per axis; a key is occupied when its own box holds a
+ * sample; its training set is the up-to-m_c samples of its collection box (the cell
+ * box grown by `margin` on every side, inclusive bounds) nearest the cell centre
+ * origin + (key + 1/2) h, nearest first, ties by lower sample index; cells with fewer
+ * than m_min samples are dropped; ids follow lexicographic key order.
+ * m_c = min(m_max, cap_grid[key - key_lo]) where cap_grid (uint8, C order, dims
+ * key_dims) covers the key, else m_max.  cap_grid may be NULL.
+ * pts: host [n,3] float or double (dtype).  Distances are taken in double.
+ * On success *out holds a host handle; read it with ksdf_cellset_info/copy and free
+ * it with ksdf_cellset_destroy.
+ * ------------------------------------------------------------------------- */
+typedef struct ksdf_cellset ksdf_cellset;
+int ksdf_build_cells(const void* pts, int dtype, long n, const double origin[3], double h,
+                     double margin, int m_max, int m_min, const uint8_t* cap_grid,
+                     const int key_lo[3], const int key_dims[3], ksdf_cellset** out);
+int ksdf_cellset_info(const ksdf_cellset* cs, int* n_cells, long* nnz);
+/* offsets [n_cells+1], samples [nnz], keys [n_cells,3]: host int32 arrays. */
+int ksdf_cellset_copy(const ksdf_cellset* cs, int* offsets, int* samples, int* keys);
+void ksdf_cellset_destroy(ksdf_cellset* cs);
+
+/* ---------------------------------------------------------------------------
+ * Model: the per-cell store (gathered samples, weights a = (K+Sigma)^{-1} 1, packed
+ * Cholesky factors, flags) and the candidate index for the K-nearest-cell search.
+ *
+ * ksdf_model_create allocates the model's device memory on the current device,
+ * uploads the cell structure and builds the candidate index (it synchronises the
+ * device once).  offsets/samples/keys: host int32 CSR as produced by the builder;
+ * origin/h: the builder's lattice; n_points: number of surface samples the fits will
+ * receive.  query_lo/query_hi (host, may be NULL): a box the queries are expected in;
+ * the index covers it (queries outside still get exact answers through a slower
+ * brute-force candidate scan and carry KSDF_Q_OUTSIDE_INDEX).  The model keeps the
+ * hyperparameters' k_fuse and precision; ell, noise_var and alpha may change per fit.
+ * ------------------------------------------------------------------------- */
+typedef struct ksdf_model ksdf_model;
+int ksdf_model_create(int n_cells, const int* offsets, const int* samples, const int* keys,
+                      const double origin[3], double h, long n_points, const ksdf_hyper* hyper,
+                      const double query_lo[3], const double query_hi[3], ksdf_model** out);
+void ksdf_model_destroy(ksdf_model* model);
+/* Host-side facts about a model: n_cells, nnz, largest m, index entries, device bytes. */
+int ksdf_model_info(const ksdf_model* model, int* n_cells, long* nnz, int* max_m,
+                    long* index_entries, size_t* device_bytes);
+
+/* ---------------------------------------------------------------------------
+ * ksdf_fit_cells — Sec. IV-B.1 training of every cell's log-GP.
+ * Gathers each cell's samples (cell-local coordinates), assembles A = K + Sigma with
+ * the RBF kernel of Table I, factors A = L L^T and solves a = A^{-1} 1.  FP32 models
+ * estimate cond_2(A) (power and inverse iteration on the FP32 factor) and refit
+ * cells above the threshold (or
+ * with a non-positive pivot) in FP64; a cell that also fails in FP64 is flagged
+ * KSDF_C_FAILED and excluded from every query (u = +inf).
+ * surface_pts: device [n_points,3] float or double (dtype); sample_var: device
+ * [n_points] of the same type, or NULL for the uniform hyper->noise_var.
+ * cell_status: device uint8 [n_cells] or NULL.  Asynchronous on `stream`; allocates
+ * nothing.  The model must not be used by another stream concurrently.
+ * ------------------------------------------------------------------------- */
+int ksdf_fit_cells(ksdf_model* model, const void* surface_pts, int dtype, long n_points,
+                   const void* sample_var, const ksdf_hyper* hyper, uint8_t* cell_status,
+                   void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ksdf_query — SDF mean, gradient and variances at Q points.
+ * points: device [Q,3].  sign: device int8 [Q] (+1/-1) or NULL (all +1).
+ * Outputs (device, overwritten): mean [Q] = s*u; grad [Q,3] = s*w/|w| (unit); var [Q]
+ * = softmin V[u] (m^2) of the argmin cell; var_f [Q] = GP variance 1 - |L^{-1} k*|^2 of
+ * the argmin cell, or NULL; argmin [Q] int32 cell id or NULL; q_status [Q] uint8 or
+ * NULL.  A query with no valid cell gets mean = +inf, grad = 0, var = +inf, var_f = 1.
+ * workspace: device scratch of at least ksdf_query_workspace_bytes(model, Q) bytes
+ * (may be NULL when that is 0).  Asynchronous; allocates nothing.
+ * ------------------------------------------------------------------------- */
+size_t ksdf_query_workspace_bytes(const ksdf_model* model, long Q);
+int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
+               void* mean, void* grad, void* var, void* var_f, int* argmin, uint8_t* q_status,
+               void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ksdf_query_backward — vector-Jacobian product of ksdf_query.
+ * Given cotangents d_mean [Q], d_grad [Q,3] (or NULL), d_var [Q] (or NULL) and d_var_f
+ * [Q] (or NULL) of L = sum_q d_mean*mean + d_grad.grad + d_var*var + d_var_f*var_f,
+ * writes d_points [Q,3] = dL/dpoints (overwritten) and d_hyper (device double [2],
+ * overwritten) = (dL/d ell, dL/d noise_var), the latter including the dependence
+ * through the fit (a and L are functions of ell and noise_var) and, when alpha is
+ * tied, through alpha = 1/(2 l^2).  The argmin cell of each query is held fixed (the
+ * min is piecewise); clamped queries contribute zero.  d_hyper for noise_var is
+ * defined for the uniform variance (no per-sample variances).  k* is recomputed, not
+ * stored.  The theta reduction is deterministic (fixed order, FP64).
+ * workspace: at least ksdf_backward_workspace_bytes(model, Q) bytes.
+ * ------------------------------------------------------------------------- */
+size_t ksdf_backward_workspace_bytes(const ksdf_model* model, long Q);
+int ksdf_query_backward(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
+                        const void* d_mean, const void* d_grad, const void* d_var,
+                        const void* d_var_f, void* d_points, double* d_hyper, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+/* Static description of a status code; ksdf_last_error() gives the calling
+ * thread's last detailed message (never NULL). */
+const char* ksdf_status_string(int status);
+const char* ksdf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KSDF_H */

@@ -56,7 +56,7 @@ def lib():
         L.oracle_query.argtypes = ([_dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp] +
                                    [ctypes.c_double] * 3 + [ctypes.c_int] * 3 +
                                    [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
-                                    _ip, _dp, _dp, _dp, _dp, _dp, _ip, _dp])
+                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp])
         L.oracle_vjp.restype = ctypes.c_double
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
@@ -145,8 +145,10 @@ def fit(points, cells: Cells, ell, noise, svar=None) -> Fit:
 
 
 def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=8,
-          cand_prec=64, d_mode=0, sign=None, svar=None) -> dict:
-    """All outputs of the back-end at each query (see ``oracle_query``)."""
+          cand_prec=64, d_mode=0, sign=None, svar=None, all_candidates=False) -> dict:
+    """All outputs of the back-end at each query (see ``oracle_query``).  With
+    all_candidates, also every candidate cell's gradient, variances and ratio
+    (keys cgrad [Q,K,3], cvar, cvar_f, cratio [Q,K])."""
     L = lib()
     pts = _f64(points)
     q = _f64(queries).reshape(-1, 3)
@@ -154,25 +156,26 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
     alpha = 1.0 / (2 * ell * ell) if alpha is None else alpha
     sv = None if svar is None else _f64(svar)
     sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.int8)
-    out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "var2",
-                                     "var_f2", "ratio", "ratio2")}
+    out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "ratio")}
     out["grad"] = np.zeros((nq, 3))
-    out["grad2"] = np.zeros((nq, 3))
     out["argmin"] = np.zeros(nq, np.int32)
-    out["argmin2"] = np.zeros(nq, np.int32)
     out["status"] = np.zeros(nq, np.int32)
     out["cand"] = np.zeros((nq, k_fuse), np.int32)
     out["ucand"] = np.zeros((nq, k_fuse))
+    if all_candidates:
+        out["cgrad"] = np.zeros((nq, k_fuse, 3))
+        for k in ("cvar", "cvar_f", "cratio"):
+            out[k] = np.zeros((nq, k_fuse))
+    g = out.get
     ctr = _f64(cells.centres)
     L.oracle_query(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
                    _p(cells.samples, _ip), _p(ctr, _dp), _p(f.a, _dp), _p(f.L, _dp), ell, noise,
                    alpha, k_fuse, cand_prec, d_mode, _p(q, _dp), nq, _p(sg, _i8p),
                    _p(out["mean"], _dp), _p(out["grad"], _dp), _p(out["var"], _dp),
                    _p(out["var_f"], _dp), _p(out["argmin"], _ip), _p(out["status"], _ip),
-                   _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["argmin2"], _ip),
-                   _p(out["grad2"], _dp), _p(out["var2"], _dp), _p(out["var_f2"], _dp),
-                   _p(out["ratio"], _dp), _p(out["ratio2"], _dp), _p(out["cand"], _ip),
-                   _p(out["ucand"], _dp))
+                   _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["ratio"], _dp),
+                   _p(out["cand"], _ip), _p(out["ucand"], _dp), _p(g("cgrad"), _dp),
+                   _p(g("cvar"), _dp), _p(g("cvar_f"), _dp), _p(g("cratio"), _dp))
     return out
 
 

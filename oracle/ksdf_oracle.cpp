@@ -370,19 +370,20 @@ CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T
 template <class T>
 struct PointOut {
   T mean, grad[3], var, var_f;
-  int argmin, argmin2;
-  double u_best, u_second, ratio, ratio2;
-  T grad2[3], var2, var_f2;
+  int argmin;
+  double u_best, u_second, ratio;
   int status;
   std::vector<int> cand;
   std::vector<double> ucand;
+  std::vector<CellOut<T>> cout;   // per-candidate outputs (when requested)
 };
 
 enum { ST_NO_VALID = 1, ST_CLAMPED = 2, ST_GRAD_ZERO = 4 };
 
 template <class T>
 PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, const T* L,
-                        const T& ell, const T& noise, const T& alpha, const QueryOpts& o) {
+                        const T& ell, const T& noise, const T& alpha, const QueryOpts& o,
+                        bool all_candidates = false) {
   double qv[3] = {val(q[0]), val(q[1]), val(q[2])};
   PointOut<T> r;
   r.status = 0;
@@ -394,16 +395,23 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
     us.push_back(std::make_tuple(val(u), c, u, cl));
     r.ucand.push_back(val(u));
   }
+  if (all_candidates)
+    for (int c : r.cand) {
+      CellOut<T> co = cell_outputs(in, c, q, a, L, ell, noise, alpha, o);
+      for (int d = 0; d < 3; ++d) co.grad[d] = T((double)sign) * co.grad[d];
+      r.cout.push_back(co);
+    }
   std::sort(us.begin(), us.end(), [](const auto& x, const auto& y) {
     return std::make_pair(std::get<0>(x), std::get<1>(x)) < std::make_pair(std::get<0>(y), std::get<1>(y));
   });
   const double inf = std::numeric_limits<double>::infinity();
-  r.argmin = -1; r.argmin2 = -1; r.u_best = inf; r.u_second = inf; r.ratio = inf; r.ratio2 = inf;
+  r.argmin = -1; r.u_best = inf; r.u_second = inf; r.ratio = inf;
+  if (us.size() > 1) r.u_second = std::get<0>(us[1]);
   if (us.empty() || !(std::get<0>(us[0]) < inf)) {
     r.status = ST_NO_VALID;
     r.mean = T(inf);
-    for (int d = 0; d < 3; ++d) { r.grad[d] = T(0.0); r.grad2[d] = T(0.0); }
-    r.var = T(inf); r.var_f = T(1.0); r.var2 = T(inf); r.var_f2 = T(1.0);
+    for (int d = 0; d < 3; ++d) r.grad[d] = T(0.0);
+    r.var = T(inf); r.var_f = T(1.0);
     return r;
   }
   r.argmin = std::get<1>(us[0]);
@@ -415,16 +423,6 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
   for (int d = 0; d < 3; ++d) r.grad[d] = T((double)sign) * co.grad[d];
   r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio;
   if (co.grad_zero) r.status |= ST_GRAD_ZERO;
-  if (us.size() > 1 && std::get<0>(us[1]) < inf) {
-    r.argmin2 = std::get<1>(us[1]);
-    r.u_second = std::get<0>(us[1]);
-    CellOut<T> c2 = cell_outputs(in, r.argmin2, q, a, L, ell, noise, alpha, o);
-    for (int d = 0; d < 3; ++d) r.grad2[d] = T((double)sign) * c2.grad[d];
-    r.var2 = c2.var; r.var_f2 = c2.var_f; r.ratio2 = c2.ratio;
-  } else {
-    for (int d = 0; d < 3; ++d) r.grad2[d] = r.grad[d];
-    r.var2 = r.var; r.var_f2 = r.var_f;
-  }
   return r;
 }
 
@@ -482,41 +480,42 @@ int oracle_fit(const double* pts, const double* svar, int n_cells, const int* of
 }
 
 // Query every point.  Outputs per query: mean, grad[3], var, var_f, argmin, status,
-// the runner-up cell's id, u and outputs (for near-tie acceptance), the
-// cancellation ratio of each, the K candidate ids and their u values.
+// the best and second-best u, the cancellation ratio of the argmin cell, the K
+// candidate ids and their u values, and (when cgrad is given) every candidate
+// cell's gradient, variances and ratio, for near-tie acceptance.
 void oracle_query(const double* pts, const double* svar, int n_cells, const int* offsets,
                   const int* samples, const double* centres, const double* a_in,
                   const double* L_in, double ell, double noise, double alpha, int k_fuse,
                   int cand_prec, int d_mode, const double* q, long nq, const int8_t* sign,
                   double* mean, double* grad, double* var, double* var_f, int* argmin,
-                  int* status, double* u_best, double* u_second, int* argmin2, double* grad2,
-                  double* var2, double* var_f2, double* ratio, double* ratio2, int* cand,
-                  double* ucand) {
+                  int* status, double* u_best, double* u_second, double* ratio, int* cand,
+                  double* ucand, double* cgrad, double* cvar, double* cvar_f, double* cratio) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs);
   QueryOpts o{ell, alpha, k_fuse, cand_prec, d_mode, false};
+  const double inf = std::numeric_limits<double>::infinity();
 #pragma omp parallel for schedule(dynamic, 64)
   for (long p = 0; p < nq; ++p) {
     PointOut<double> r = query_point<double>(in, q + 3 * p, sign ? sign[p] : 1, a_in, L_in,
-                                             ell, noise, alpha, o);
+                                             ell, noise, alpha, o, cgrad != nullptr);
     mean[p] = r.mean; var[p] = r.var; var_f[p] = r.var_f;
     for (int d = 0; d < 3; ++d) grad[3 * p + d] = r.grad[d];
     argmin[p] = r.argmin; status[p] = r.status;
     if (u_best) u_best[p] = r.u_best;
     if (u_second) u_second[p] = r.u_second;
-    if (argmin2) argmin2[p] = r.argmin2;
-    if (grad2) for (int d = 0; d < 3; ++d) grad2[3 * p + d] = r.grad2[d];
-    if (var2) var2[p] = r.var2;
-    if (var_f2) var_f2[p] = r.var_f2;
     if (ratio) ratio[p] = r.ratio;
-    if (ratio2) ratio2[p] = r.ratio2;
-    if (cand)
-      for (int i = 0; i < k_fuse; ++i)
-        cand[(long)k_fuse * p + i] = i < (int)r.cand.size() ? r.cand[i] : -1;
-    if (ucand)
-      for (int i = 0; i < k_fuse; ++i)
-        ucand[(long)k_fuse * p + i] = i < (int)r.ucand.size() ? r.ucand[i]
-                                                              : std::numeric_limits<double>::infinity();
+    for (int i = 0; i < k_fuse; ++i) {
+      bool have = i < (int)r.cand.size();
+      long j = (long)k_fuse * p + i;
+      if (cand) cand[j] = have ? r.cand[i] : -1;
+      if (ucand) ucand[j] = have ? r.ucand[i] : inf;
+      if (cgrad) {
+        for (int d = 0; d < 3; ++d) cgrad[3 * j + d] = have ? r.cout[i].grad[d] : 0.0;
+        cvar[j] = have ? r.cout[i].var : inf;
+        cvar_f[j] = have ? r.cout[i].var_f : 1.0;
+        cratio[j] = have ? r.cout[i].ratio : inf;
+      }
+    }
   }
 }
 

@@ -1,0 +1,326 @@
+// C ABI of libksdf: argument checking, model memory, launches.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "ksdf_internal.h"
+
+namespace ksdf {
+
+namespace {
+thread_local std::string g_last_error;
+
+bool finite3(const double* v) {
+  return v && std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+int check_hyper(const ksdf_hyper* hp) {
+  if (!hp) {
+    set_error("hyperparameters are null");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!std::isfinite(hp->ell) || !std::isfinite(hp->noise_var) || !std::isfinite(hp->alpha) ||
+      !std::isfinite(hp->cond_fp64_threshold)) {
+    set_error("non-finite hyperparameter");
+    return KSDF_ERR_INVALID_INPUT;
+  }
+  if (!(hp->ell > 0) || hp->noise_var < 0 || hp->k_fuse < 1 || hp->k_fuse > KSDF_MAX_K ||
+      (hp->precision != KSDF_FP64 && hp->precision != KSDF_FP32) ||
+      !(hp->cond_fp64_threshold > 0)) {
+    set_error("hyperparameter out of range (ell > 0, noise_var >= 0, 1 <= k_fuse <= 16, "
+              "precision KSDF_FP64|KSDF_FP32, cond threshold > 0)");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  return KSDF_OK;
+}
+
+int check_device(const ksdf_model* m) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != m->device) {
+    set_error("the current device is not the model's device");
+    return KSDF_ERR_DEVICE;
+  }
+  return KSDF_OK;
+}
+
+template <class T>
+int dalloc(ksdf_model* m, T** p, size_t n) {
+  n = std::max<size_t>(n, 1);
+  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed");
+    return KSDF_ERR_OUT_OF_MEMORY;
+  }
+  m->device_bytes += n * sizeof(T);
+  return KSDF_OK;
+}
+
+void free_model(ksdf_model* m) {
+  if (!m) return;
+  void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
+                  m->L32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
+                  m->L64, m->cstatus, m->bucket_cells, m->index.box_off, m->index.box_list};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace ksdf
+
+using namespace ksdf;
+
+#define TRY(x)                 \
+  do {                         \
+    int _r = (x);              \
+    if (_r != KSDF_OK) {       \
+      free_model(m);           \
+      return _r;               \
+    }                          \
+  } while (0)
+
+extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* samples,
+                                 const int* keys, const double origin[3], double h,
+                                 long n_points, const ksdf_hyper* hyper, const double query_lo[3],
+                                 const double query_hi[3], ksdf_model** out) {
+  if (!out) {
+    set_error("out is null");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  int r = check_hyper(hyper);
+  if (r) return r;
+  if (n_cells < 0 || !offsets || (n_cells > 0 && (!samples || !keys)) || !finite3(origin) ||
+      !(h > 0) || n_points < 0 || ((query_lo == nullptr) != (query_hi == nullptr))) {
+    set_error("ksdf_model_create: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (query_lo && (!finite3(query_lo) || !finite3(query_hi))) {
+    set_error("ksdf_model_create: non-finite query box");
+    return KSDF_ERR_INVALID_INPUT;
+  }
+  if (offsets[0] != 0) {
+    set_error("offsets[0] must be 0");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int max_m = 0;
+  for (int c = 0; c < n_cells; ++c) {
+    const int mc = offsets[c + 1] - offsets[c];
+    if (mc < 1) {
+      set_error("every cell needs at least one sample");
+      return KSDF_ERR_INVALID_ARGUMENT;
+    }
+    if (mc > KSDF_MAX_M) {
+      set_error("a cell has more than 128 samples");
+      return KSDF_ERR_UNSUPPORTED;
+    }
+    max_m = std::max(max_m, mc);
+  }
+  const long nnz = offsets[n_cells];
+  for (long i = 0; i < nnz; ++i)
+    if (samples[i] < 0 || samples[i] >= n_points) {
+      set_error("a cell references a sample index outside [0, n_points)");
+      return KSDF_ERR_INVALID_ARGUMENT;
+    }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    set_error("no HIP device");
+    return KSDF_ERR_DEVICE;
+  }
+  auto* m = new ksdf_model;
+  (void)hipGetDevice(&m->device);
+  m->precision = hyper->precision;
+  m->k_fuse = hyper->k_fuse;
+  m->cond_thr = hyper->cond_fp64_threshold;
+  m->n_cells = n_cells;
+  m->nnz = nnz;
+  m->max_m = max_m;
+  m->n_points = n_points;
+  for (int d = 0; d < 3; ++d) m->origin[d] = origin[d];
+  m->h = h;
+  m->h_offsets.assign(offsets, offsets + n_cells + 1);
+  m->h_loff.assign(n_cells + 1, 0);
+  for (int c = 0; c < n_cells; ++c) {
+    const long mc = offsets[c + 1] - offsets[c];
+    m->h_loff[c + 1] = m->h_loff[c] + mc * (mc + 1) / 2;
+  }
+  m->h_centre.resize(3L * n_cells);
+  std::vector<float> c32(4L * n_cells, 0.f);
+  for (int c = 0; c < n_cells; ++c)
+    for (int d = 0; d < 3; ++d) {
+      const double v = origin[d] + ((double)keys[3 * c + d] + 0.5) * h;
+      m->h_centre[3 * c + d] = v;
+      c32[4 * c + d] = (float)v;
+    }
+  const long lsize = m->h_loff[n_cells];
+  TRY(dalloc(m, &m->offsets, n_cells + 1));
+  TRY(dalloc(m, &m->samples, nnz));
+  TRY(dalloc(m, &m->loff, n_cells + 1));
+  TRY(dalloc(m, &m->centre32, 4L * n_cells));
+  TRY(dalloc(m, &m->centre64, 3L * n_cells));
+  TRY(dalloc(m, &m->box32, 8L * n_cells));
+  TRY(dalloc(m, &m->cstatus, n_cells));
+  TRY(dalloc(m, &m->ps64, 4L * nnz));
+  TRY(dalloc(m, &m->sv64, nnz));
+  TRY(dalloc(m, &m->L64, lsize));
+  if (m->precision == KSDF_FP32) {
+    // padded so the wave-uniform chunked loads of the last cell stay in bounds
+    TRY(dalloc(m, &m->ps32, 4L * (nnz + KSDF_PAD_SAMPLES)));
+    TRY(dalloc(m, &m->plo32, 4L * (nnz + KSDF_PAD_SAMPLES)));
+    TRY(dalloc(m, &m->sv32, nnz + KSDF_PAD_SAMPLES));
+    TRY(dalloc(m, &m->L32, lsize + KSDF_PAD_FACTOR));
+    KSDF_HIP_TRY(hipMemset(m->ps32, 0, 4L * (nnz + KSDF_PAD_SAMPLES) * sizeof(float)));
+    KSDF_HIP_TRY(hipMemset(m->sv32, 0, (nnz + KSDF_PAD_SAMPLES) * sizeof(float)));
+    KSDF_HIP_TRY(hipMemset(m->L32, 0, (lsize + KSDF_PAD_FACTOR) * sizeof(float)));
+    TRY(dalloc(m, &m->cond32, n_cells));
+    TRY(dalloc(m, &m->fb_list, n_cells));
+    TRY(dalloc(m, &m->fb_count, 1));
+  }
+  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return KSDF_OK;
+    KSDF_HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    return KSDF_OK;
+  };
+  TRY(up(m->offsets, offsets, (n_cells + 1) * sizeof(int)));
+  TRY(up(m->samples, samples, nnz * sizeof(int)));
+  TRY(up(m->loff, m->h_loff.data(), (n_cells + 1) * sizeof(long)));
+  TRY(up(m->centre32, c32.data(), c32.size() * sizeof(float)));
+  TRY(up(m->centre64, m->h_centre.data(), m->h_centre.size() * sizeof(double)));
+  {
+    // cells grouped by m bucket for the FP32 fit kernels
+    const int edges[4] = {16, 32, 64, 128};
+    std::vector<int> order;
+    order.reserve(n_cells);
+    m->bucket_start[0] = 0;
+    for (int bk = 0; bk < 4; ++bk) {
+      for (int c = 0; c < n_cells; ++c) {
+        const int mc = offsets[c + 1] - offsets[c];
+        const int lo = bk == 0 ? 0 : edges[bk - 1];
+        if (mc > lo && mc <= edges[bk]) order.push_back(c);
+      }
+      m->bucket_start[bk + 1] = (int)order.size();
+    }
+    TRY(dalloc(m, &m->bucket_cells, n_cells));
+    TRY(up(m->bucket_cells, order.data(), order.size() * sizeof(int)));
+  }
+  TRY(build_candidate_index(m, query_lo, query_hi));
+  *out = m;
+  return KSDF_OK;
+}
+
+extern "C" void ksdf_model_destroy(ksdf_model* model) {
+  if (model) (void)hipDeviceSynchronize();
+  free_model(model);
+}
+
+extern "C" int ksdf_model_info(const ksdf_model* m, int* n_cells, long* nnz, int* max_m,
+                               long* index_entries, size_t* device_bytes) {
+  if (!m) return KSDF_ERR_INVALID_ARGUMENT;
+  if (n_cells) *n_cells = m->n_cells;
+  if (nnz) *nnz = m->nnz;
+  if (max_m) *max_m = m->max_m;
+  if (index_entries) *index_entries = m->index.entries;
+  if (device_bytes) *device_bytes = m->device_bytes;
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
+                              const void* sample_var, const ksdf_hyper* hyper,
+                              uint8_t* cell_status, void* stream) {
+  if (!m) {
+    set_error("model is null");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int r = check_hyper(hyper);
+  if (r) return r;
+  if ((m->n_cells > 0 && !surface_pts) || (dtype != KSDF_DTYPE_F32 && dtype != KSDF_DTYPE_F64) ||
+      n_points != m->n_points || hyper->k_fuse != m->k_fuse || hyper->precision != m->precision) {
+    set_error("ksdf_fit_cells: arguments do not match the model (n_points, dtype, k_fuse, precision)");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if ((r = check_device(m))) return r;
+  m->ell = hyper->ell;
+  m->noise_var = hyper->noise_var;
+  m->alpha_tied = !(hyper->alpha > 0);
+  m->alpha = m->alpha_tied ? 1.0 / (2.0 * hyper->ell * hyper->ell) : hyper->alpha;
+  m->cond_thr = hyper->cond_fp64_threshold;
+  m->has_svar = sample_var != nullptr;
+  r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, (hipStream_t)stream);
+  if (r == KSDF_OK) m->fitted = true;
+  return r;
+}
+
+extern "C" size_t ksdf_query_workspace_bytes(const ksdf_model* m, long Q) {
+  return m ? query_workspace_bytes(m, Q) : 0;
+}
+
+extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
+                          void* mean, void* grad, void* var, void* var_f, int* argmin,
+                          uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
+  if (!m || Q < 0 || (Q > 0 && (!points || !mean || !grad || !var))) {
+    set_error("ksdf_query: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!m->fitted) {
+    set_error("ksdf_query: the model has not been fitted");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = query_workspace_bytes(m, Q);
+  if (ws_bytes < need || (need > 0 && !workspace)) {
+    set_error("ksdf_query: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+                      ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" size_t ksdf_backward_workspace_bytes(const ksdf_model* m, long Q) {
+  return m ? backward_workspace_bytes(m, Q) : 0;
+}
+
+extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long Q,
+                                   const int8_t* sign, const void* d_mean, const void* d_grad,
+                                   const void* d_var, const void* d_var_f, void* d_points,
+                                   double* d_hyper, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+  if (!m || Q < 0 || (Q > 0 && (!points || !d_mean || !d_points)) || !d_hyper) {
+    set_error("ksdf_query_backward: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!m->fitted) {
+    set_error("ksdf_query_backward: the model has not been fitted");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = backward_workspace_bytes(m, Q);
+  if (ws_bytes < need || (need > 0 && !workspace)) {
+    set_error("ksdf_query_backward: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  return launch_backward(m, points, Q, sign, d_mean, d_grad, d_var, d_var_f, d_points, d_hyper,
+                         workspace, ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" const char* ksdf_status_string(int status) {
+  switch (status) {
+    case KSDF_OK: return "ok";
+    case KSDF_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case KSDF_ERR_INVALID_INPUT: return "invalid (non-finite) input";
+    case KSDF_ERR_WORKSPACE: return "workspace too small";
+    case KSDF_ERR_HIP: return "HIP runtime error";
+    case KSDF_ERR_DEVICE: return "no usable device / wrong device";
+    case KSDF_ERR_UNSUPPORTED: return "unsupported";
+    case KSDF_ERR_OUT_OF_MEMORY: return "out of device memory";
+    default: return "unknown status";
+  }
+}
+
+extern "C" const char* ksdf_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,98 @@
+// Float-float ("double-single") arithmetic on FP32 instructions.
+//
+// A value is the unevaluated sum hi + lo of two floats with |lo| <= ulp(hi)/2,
+// about 44 significant bits.  The error-free transformations are the classical
+// ones: Knuth's TwoSum, Dekker's Fast2Sum, and the FMA-based TwoProduct
+// (Dekker 1971; Knuth, TAOCP vol. 2, sec. 4.2.2).  Contraction is disabled in this
+// header so the compiler cannot fuse the steps that carry the rounding errors.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ksdf {
+
+struct ff {
+  float hi, lo;
+};
+
+__host__ __device__ __forceinline__ ff ff_two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b;
+  const float bb = s - a;
+  const float e = (a - (s - bb)) + (b - bb);
+  return {s, e};
+}
+
+__host__ __device__ __forceinline__ ff ff_fast_two_sum(float a, float b) {  // |a| >= |b|
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return {s, b - (s - a)};
+}
+
+__host__ __device__ __forceinline__ ff ff_two_prod(float a, float b) {
+#pragma clang fp contract(off)
+  const float p = a * b;
+  return {p, __builtin_fmaf(a, b, -p)};
+}
+
+__host__ __device__ __forceinline__ ff ff_add(ff a, ff b) {
+#pragma clang fp contract(off)
+  ff s = ff_two_sum(a.hi, b.hi);
+  const ff t = ff_two_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = ff_fast_two_sum(s.hi, s.lo);
+  s.lo += t.lo;
+  return ff_fast_two_sum(s.hi, s.lo);
+}
+
+__host__ __device__ __forceinline__ ff ff_neg(ff a) { return {-a.hi, -a.lo}; }
+
+__host__ __device__ __forceinline__ ff ff_mul(ff a, ff b) {
+#pragma clang fp contract(off)
+  ff p = ff_two_prod(a.hi, b.hi);
+  p.lo = __builtin_fmaf(a.hi, b.lo, p.lo);
+  p.lo = __builtin_fmaf(a.lo, b.hi, p.lo);
+  return ff_fast_two_sum(p.hi, p.lo);
+}
+
+__host__ __device__ __forceinline__ ff ff_mul_f(ff a, float b) {
+#pragma clang fp contract(off)
+  ff p = ff_two_prod(a.hi, b);
+  p.lo = __builtin_fmaf(a.lo, b, p.lo);
+  return ff_fast_two_sum(p.hi, p.lo);
+}
+
+// exp(-t) for t >= 0 in float-float.  Range reduction t = n ln2 + r with ln2 split
+// into three floats (Cody-Waite; the first part has 16 significant bits so n*c1 is
+// exact for n < 2^8), then the Taylor series of exp(-r), |r| <= ln2/2, to degree 13
+// (truncation < 2e-17), then an exact scaling by 2^-n.
+__host__ __device__ __forceinline__ ff ff_exp_neg(ff t) {
+#pragma clang fp contract(off)
+  constexpr double LN2 = 0.69314718055994530941723212145818;
+  constexpr float C1 = 0.693145751953125f;
+  constexpr float C2 = (float)(LN2 - (double)C1);
+  constexpr float C3 = (float)(LN2 - (double)C1 - (double)C2);
+  if (!(t.hi < 103.0f)) return {0.f, 0.f};
+  const float n = rintf(t.hi * 1.44269504088896341f);
+  ff r = ff_two_sum(t.hi - n * C1, t.lo);          // t.hi - n*C1 is exact (Sterbenz)
+  r = ff_add(r, ff_neg(ff_two_prod(n, C2)));
+  r = ff_add(r, ff{-n * C3, 0.f});
+  const ff x = ff_neg(r);
+  // Horner on 1/k!, k = 13..0, coefficients split to float-float at compile time
+#define KSDF_INV_FACT(k, v) {(float)(v), (float)((v) - (double)(float)(v))}
+  constexpr ff coef[14] = {
+      KSDF_INV_FACT(0, 1.0), KSDF_INV_FACT(1, 1.0), KSDF_INV_FACT(2, 1.0 / 2),
+      KSDF_INV_FACT(3, 1.0 / 6), KSDF_INV_FACT(4, 1.0 / 24), KSDF_INV_FACT(5, 1.0 / 120),
+      KSDF_INV_FACT(6, 1.0 / 720), KSDF_INV_FACT(7, 1.0 / 5040), KSDF_INV_FACT(8, 1.0 / 40320),
+      KSDF_INV_FACT(9, 1.0 / 362880), KSDF_INV_FACT(10, 1.0 / 3628800),
+      KSDF_INV_FACT(11, 1.0 / 39916800), KSDF_INV_FACT(12, 1.0 / 479001600),
+      KSDF_INV_FACT(13, 1.0 / 6227020800)};
+#undef KSDF_INV_FACT
+  ff p = coef[13];
+#pragma unroll
+  for (int k = 12; k >= 0; --k) p = ff_add(ff_mul(p, x), coef[k]);
+  const int e = -(int)n;
+  return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
+}
+
+}  // namespace ksdf

@@ -1,0 +1,117 @@
+// Internal declarations shared by the ksdf HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ksdf.h"
+
+namespace ksdf {
+
+// Padding (entries) after the FP32 per-sample arrays and after the packed factors,
+// so chunked loads past the last cell stay inside the allocation.
+#define KSDF_PAD_SAMPLES 16
+#define KSDF_PAD_FACTOR 64
+
+// Per-thread error message behind ksdf_last_error().
+void set_error(const std::string& msg);
+
+#define KSDF_HIP_TRY(expr)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess) {                                                             \
+      ::ksdf::set_error(std::string(#expr) + ": " + hipGetErrorString(_e));            \
+      return KSDF_ERR_HIP;                                                              \
+    }                                                                                   \
+  } while (0)
+
+// Candidate index over a lattice of cell-sized boxes: for lattice box B, every
+// occupied cell that can be among the K nearest cell centres of some point of B.
+struct CandidateIndex {
+  int lo[3] = {0, 0, 0};       // lattice key of box (0,0,0)
+  int dims[3] = {0, 0, 0};
+  long n_boxes = 0;
+  long entries = 0;
+  int* box_off = nullptr;      // [n_boxes+1]
+  int* box_list = nullptr;     // [entries] cell ids, ascending within a box
+  int max_list = 0;
+};
+
+}  // namespace ksdf
+
+// The model: per-cell store and candidate index (device memory owned by the model).
+struct ksdf_model {
+  int device = 0;
+  int precision = KSDF_FP32;
+  int k_fuse = 8;
+  int n_cells = 0;
+  long nnz = 0;
+  int max_m = 0;
+  long n_points = 0;
+  double origin[3] = {0, 0, 0};
+  double h = 0;
+  double ell = 0, noise_var = 0, alpha = 0;   // of the last fit
+  double cond_thr = 1e6;
+  bool alpha_tied = true;
+  bool fitted = false;
+  bool has_svar = false;
+
+  std::vector<int> h_offsets;   // host copy of the CSR offsets
+  std::vector<long> h_loff;     // host copy of packed-factor offsets
+  std::vector<double> h_centre; // host copy of the cell centres [n,3]
+
+  // structure (device)
+  int* offsets = nullptr;       // [n+1]
+  int* samples = nullptr;       // [nnz] global sample ids
+  long* loff = nullptr;         // [n+1] packed lower-triangle offsets, m(m+1)/2 each
+  float* centre32 = nullptr;    // [n,4] centre xyz (exact), pad
+  double* centre64 = nullptr;   // [n,3]
+
+  // FP32 store (KSDF_FP32 models)
+  float* ps32 = nullptr;        // [nnz,4] cell-local (px,py,pz) and weight a
+  float* plo32 = nullptr;       // [nnz,4] float-float low parts of ps32
+  float* sv32 = nullptr;        // [nnz] sample variance sigma_i^2
+  float* L32 = nullptr;         // packed rows of L; diagonal holds 1/L_jj
+  float* box32 = nullptr;       // [n,8] sample AABB lo xyz, A+ (sum of positive a), hi xyz, pad
+  float* cond32 = nullptr;      // [n] condition estimate (FP32 factor)
+  int* fb_list = nullptr;       // [n] cells to refit in FP64
+  int* fb_count = nullptr;      // [1]
+
+  // FP64 store (KSDF_FP64 models, and FP64 refits of FP32 models)
+  double* ps64 = nullptr;       // [nnz,4]
+  double* sv64 = nullptr;       // [nnz]
+  double* L64 = nullptr;        // packed rows of L; diagonal holds 1/L_jj
+
+  uint8_t* cstatus = nullptr;   // [n] KSDF_C_* bits of the last fit
+  int* bucket_cells = nullptr;  // [n] cell ids grouped by m bucket (<=16, <=32, <=64, <=128)
+  int bucket_start[5] = {0, 0, 0, 0, 0};
+
+  ksdf::CandidateIndex index;
+  size_t device_bytes = 0;
+};
+
+namespace ksdf {
+
+// launchers (each returns KSDF_OK or an error after setting the message)
+int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint8_t* user_status,
+               hipStream_t s);
+int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
+int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
+                 void* grad, void* var, void* var_f, int* argmin, uint8_t* q_status, void* ws,
+                 size_t ws_bytes, hipStream_t s);
+size_t query_workspace_bytes(const ksdf_model* m, long Q);
+int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
+                      void* mean, void* grad, void* var, void* var_f, int* argmin,
+                      uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
+size_t query_fast_workspace_bytes(const ksdf_model* m, long Q);
+int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
+                    const void* d_mean, const void* d_grad, const void* d_var,
+                    const void* d_var_f, void* d_points, double* d_hyper, void* ws,
+                    size_t ws_bytes, hipStream_t s);
+size_t backward_workspace_bytes(const ksdf_model* m, long Q);
+
+}  // namespace ksdf

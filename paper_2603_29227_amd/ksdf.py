@@ -1,0 +1,311 @@
+"""Python binding of libksdf (argument marshalling only).
+
+Every step of the fit, the query and the backward runs in the library's HIP
+kernels; PyTorch provides device memory and the stream.  There is no fallback:
+if ``libksdf.so`` is missing or no GPU is present, the calls raise.
+
+    cells = build_cells(points_np, origin, h, margin, m_max, m_min)
+    model = Model(cells, n_points, origin, h, ell=0.2, noise_var=1e-4)
+    model.fit(points_cuda)
+    out = model.query(queries_cuda, sign_cuda)      # mean, grad, var, var_f, argmin, status
+    mean, grad, var, var_f = sdf(model, queries_cuda, sign=sign_cuda, theta=theta)  # autograd
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libksdf.so")
+
+FP64, FP32 = 0, 1
+DTYPE_F32, DTYPE_F64 = 0, 1
+Q_NO_VALID_CELL, Q_CLAMPED, Q_GRAD_ZERO, Q_OUTSIDE_INDEX = 1, 2, 4, 8
+C_FP64, C_FAILED = 1, 2
+
+EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_cellset_destroy",
+           "ksdf_model_create", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
+           "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
+           "ksdf_query_backward", "ksdf_status_string", "ksdf_last_error"]
+
+
+class KsdfError(RuntimeError):
+    pass
+
+
+class Hyper(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_double), ("noise_var", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("k_fuse", ctypes.c_int),
+                ("precision", ctypes.c_int), ("cond_fp64_threshold", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libksdf.so; raise if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise KsdfError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        i, l, d, sz = ctypes.c_int, ctypes.c_long, ctypes.c_double, ctypes.c_size_t
+        pi = ctypes.POINTER(ctypes.c_int)
+        pl = ctypes.POINTER(ctypes.c_long)
+        pd = ctypes.POINTER(ctypes.c_double)
+        psz = ctypes.POINTER(ctypes.c_size_t)
+        H = ctypes.POINTER(Hyper)
+        L.ksdf_build_cells.argtypes = [_vp, i, l, pd, d, d, i, i, _vp, pi, pi, ctypes.POINTER(_vp)]
+        L.ksdf_cellset_info.argtypes = [_vp, pi, pl]
+        L.ksdf_cellset_copy.argtypes = [_vp, _vp, _vp, _vp]
+        L.ksdf_cellset_destroy.argtypes = [_vp]
+        L.ksdf_cellset_destroy.restype = None
+        L.ksdf_model_create.argtypes = [i, _vp, _vp, _vp, pd, d, l, H, pd, pd, ctypes.POINTER(_vp)]
+        L.ksdf_model_destroy.argtypes = [_vp]
+        L.ksdf_model_destroy.restype = None
+        L.ksdf_model_info.argtypes = [_vp, pi, pl, pi, pl, psz]
+        L.ksdf_fit_cells.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp]
+        L.ksdf_query_workspace_bytes.argtypes = [_vp, l]
+        L.ksdf_query_workspace_bytes.restype = sz
+        L.ksdf_query.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz, _vp]
+        L.ksdf_backward_workspace_bytes.argtypes = [_vp, l]
+        L.ksdf_backward_workspace_bytes.restype = sz
+        L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          sz, _vp]
+        L.ksdf_status_string.argtypes = [i]
+        L.ksdf_status_string.restype = ctypes.c_char_p
+        L.ksdf_last_error.argtypes = []
+        L.ksdf_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        L = lib()
+        raise KsdfError(f"{what}: {L.ksdf_status_string(rc).decode()} ({rc}): "
+                        f"{L.ksdf_last_error().decode()}")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _d3(v):
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
+
+
+@dataclasses.dataclass
+class CellSet:
+    offsets: np.ndarray   # int32 [n+1]
+    samples: np.ndarray   # int32 [nnz]
+    keys: np.ndarray      # int32 [n,3]
+
+    @property
+    def n(self):
+        return len(self.offsets) - 1
+
+    @property
+    def m(self):
+        return np.diff(self.offsets)
+
+
+def build_cells(points, origin, h, margin, m_max, m_min, cap_grid=None, key_lo=(0, 0, 0)) -> CellSet:
+    """Host cell builder (the per-octant training buffers with overlapping boxes)."""
+    L = lib()
+    pts = np.ascontiguousarray(points)
+    if pts.dtype not in (np.float32, np.float64) or pts.ndim != 2 or pts.shape[1] != 3:
+        raise ValueError("points must be [N,3] float32 or float64")
+    dt = DTYPE_F64 if pts.dtype == np.float64 else DTYPE_F32
+    cg = None if cap_grid is None else np.ascontiguousarray(cap_grid, dtype=np.uint8)
+    klo = (ctypes.c_int * 3)(*[int(v) for v in key_lo])
+    kd = (ctypes.c_int * 3)(*(cg.shape if cg is not None else (0, 0, 0)))
+    hdl = ctypes.c_void_p()
+    _check(L.ksdf_build_cells(pts.ctypes.data, dt, len(pts), _d3(origin), float(h), float(margin),
+                              int(m_max), int(m_min), None if cg is None else cg.ctypes.data,
+                              klo, kd, ctypes.byref(hdl)), "ksdf_build_cells")
+    try:
+        n, nnz = ctypes.c_int(), ctypes.c_long()
+        _check(L.ksdf_cellset_info(hdl, ctypes.byref(n), ctypes.byref(nnz)), "ksdf_cellset_info")
+        off = np.zeros(n.value + 1, np.int32)
+        smp = np.zeros(max(nnz.value, 1), np.int32)
+        keys = np.zeros((max(n.value, 1), 3), np.int32)
+        _check(L.ksdf_cellset_copy(hdl, off.ctypes.data, smp.ctypes.data, keys.ctypes.data),
+               "ksdf_cellset_copy")
+    finally:
+        L.ksdf_cellset_destroy(hdl)
+    return CellSet(off, smp[:nnz.value], keys[:n.value])
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Model:
+    """A fitted set of local GPs (device memory owned by the library)."""
+
+    def __init__(self, cells: CellSet, n_points: int, origin, h: float, ell: float = 0.2,
+                 noise_var: float = 1e-4, k_fuse: int = 8, precision: str = "fp32",
+                 alpha: Optional[float] = None, cond_threshold: float = 1e6, query_box=None):
+        if not torch.cuda.is_available():
+            raise KsdfError("no GPU: libksdf needs a gfx950 device")
+        self._lib = lib()
+        self.cells = cells
+        self.n_points = int(n_points)
+        self.origin = tuple(float(v) for v in origin)
+        self.h = float(h)
+        self.precision = FP64 if precision == "fp64" else FP32
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self.hyper = Hyper(float(ell), float(noise_var), -1.0 if alpha is None else float(alpha),
+                           int(k_fuse), self.precision, float(cond_threshold))
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._h = ctypes.c_void_p()
+        qlo = qhi = None
+        if query_box is not None:
+            qlo, qhi = _d3(query_box[0]), _d3(query_box[1])
+        off = np.ascontiguousarray(cells.offsets, np.int32)
+        smp = np.ascontiguousarray(cells.samples, np.int32)
+        keys = np.ascontiguousarray(cells.keys, np.int32)
+        _check(self._lib.ksdf_model_create(cells.n, off.ctypes.data, smp.ctypes.data,
+                                           keys.ctypes.data, _d3(origin), self.h, self.n_points,
+                                           ctypes.byref(self.hyper), qlo, qhi,
+                                           ctypes.byref(self._h)), "ksdf_model_create")
+        self._ws = None
+        self.points = None
+        self.sample_var = None
+
+    @property
+    def n_cells(self):
+        return self.cells.n
+
+    def info(self) -> dict:
+        n, nnz, mm, ie, db = (ctypes.c_int(), ctypes.c_long(), ctypes.c_int(), ctypes.c_long(),
+                              ctypes.c_size_t())
+        _check(self._lib.ksdf_model_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
+                                         ctypes.byref(mm), ctypes.byref(ie), ctypes.byref(db)),
+               "ksdf_model_info")
+        return dict(n_cells=n.value, nnz=nnz.value, max_m=mm.value, index_entries=ie.value,
+                    device_bytes=db.value)
+
+    def set_hyper(self, ell=None, noise_var=None, alpha=None):
+        if ell is not None:
+            self.hyper.ell = float(ell)
+        if noise_var is not None:
+            self.hyper.noise_var = float(noise_var)
+        if alpha is not None:
+            self.hyper.alpha = float(alpha)
+
+    def fit(self, points: torch.Tensor, sample_var: Optional[torch.Tensor] = None,
+            cell_status: Optional[torch.Tensor] = None, stream=None) -> None:
+        if not points.is_cuda or points.dim() != 2 or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [N,3] CUDA tensor")
+        if points.dtype not in (torch.float32, torch.float64):
+            raise ValueError("points must be float32 or float64")
+        dt = DTYPE_F64 if points.dtype == torch.float64 else DTYPE_F32
+        if sample_var is not None and (sample_var.dtype != points.dtype or sample_var.numel() != len(points)):
+            raise ValueError("sample_var must match the points' dtype and count")
+        if cell_status is not None and (cell_status.dtype != torch.uint8 or cell_status.numel() < self.n_cells):
+            raise ValueError("cell_status must be uint8 [n_cells]")
+        _check(self._lib.ksdf_fit_cells(self._h, _ptr(points), dt, len(points), _ptr(sample_var),
+                                        ctypes.byref(self.hyper), _ptr(cell_status),
+                                        _stream(stream)), "ksdf_fit_cells")
+        self.points = points
+        self.sample_var = sample_var
+
+    def _workspace(self, nbytes: int):
+        if nbytes == 0:
+            return None
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def query(self, points: torch.Tensor, sign: Optional[torch.Tensor] = None, var_f=True,
+              argmin=True, status=True, out: Optional[dict] = None, stream=None) -> dict:
+        if points.dtype != self.dtype or not points.is_cuda or not points.is_contiguous() \
+                or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError(f"points must be a contiguous [Q,3] CUDA {self.dtype} tensor")
+        if sign is not None and (sign.dtype != torch.int8 or sign.numel() != len(points)):
+            raise ValueError("sign must be int8 [Q]")
+        Q = len(points)
+        if out is None:
+            dev, dt = points.device, self.dtype
+            out = dict(mean=torch.empty(Q, dtype=dt, device=dev),
+                       grad=torch.empty(Q, 3, dtype=dt, device=dev),
+                       var=torch.empty(Q, dtype=dt, device=dev))
+            if var_f:
+                out["var_f"] = torch.empty(Q, dtype=dt, device=dev)
+            if argmin:
+                out["argmin"] = torch.empty(Q, dtype=torch.int32, device=dev)
+            if status:
+                out["status"] = torch.empty(Q, dtype=torch.uint8, device=dev)
+        nb = self._lib.ksdf_query_workspace_bytes(self._h, Q)
+        ws = self._workspace(nb)
+        _check(self._lib.ksdf_query(self._h, _ptr(points), Q, _ptr(sign), _ptr(out["mean"]),
+                                    _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
+                                    _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
+                                    _stream(stream)), "ksdf_query")
+        return out
+
+    def backward(self, points, sign, d_mean, d_grad=None, d_var=None, d_var_f=None, stream=None):
+        Q = len(points)
+        d_points = torch.empty(Q, 3, dtype=self.dtype, device=points.device)
+        d_hyper = torch.empty(2, dtype=torch.float64, device=points.device)
+        nb = self._lib.ksdf_backward_workspace_bytes(self._h, Q)
+        ws = self._workspace(nb)
+        c = [None if t is None else t.contiguous() for t in (d_mean, d_grad, d_var, d_var_f)]
+        for t in c:
+            if t is not None and t.dtype != self.dtype:
+                raise ValueError("cotangents must match the model dtype")
+        _check(self._lib.ksdf_query_backward(self._h, _ptr(points), Q, _ptr(sign), *[_ptr(t) for t in c],
+                                             _ptr(d_points), _ptr(d_hyper), _ptr(ws), nb,
+                                             _stream(stream)), "ksdf_query_backward")
+        return d_points, d_hyper
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.ksdf_model_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class _SDF(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, points, theta, model: Model, sign):
+        if theta is not None:
+            model.set_hyper(ell=float(theta[0]), noise_var=float(theta[1]))
+            model.fit(model.points, model.sample_var)
+        out = model.query(points.detach().contiguous(), sign, argmin=False, status=False)
+        ctx.model = model
+        ctx.sign = sign
+        ctx.has_theta = theta is not None
+        ctx.save_for_backward(points)
+        return out["mean"], out["grad"], out["var"], out["var_f"]
+
+    @staticmethod
+    def backward(ctx, g_mean, g_grad, g_var, g_var_f):
+        (points,) = ctx.saved_tensors
+        m = ctx.model
+        z = lambda g: None if g is None else g.contiguous()  # noqa: E731
+        gm = g_mean if g_mean is not None else torch.zeros(len(points), dtype=m.dtype, device=points.device)
+        d_points, d_hyper = m.backward(points.detach().contiguous(), ctx.sign, z(gm), z(g_grad),
+                                       z(g_var), z(g_var_f))
+        return d_points, (d_hyper if ctx.has_theta else None), None, None
+
+
+def sdf(model: Model, points: torch.Tensor, sign: Optional[torch.Tensor] = None,
+        theta: Optional[torch.Tensor] = None):
+    """Differentiable (mean, grad, var, var_f).  With theta = tensor([ell, noise_var])
+    (float64, requires_grad), the model is refitted at theta and dL/dtheta flows back."""
+    return _SDF.apply(points, theta, model, sign)

@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol ksdf.h declares, and its host cell builder agrees with the oracle's."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ksdf.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ksdf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = ksdf.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(ksdf.EXPORTS) <= set(names)
+
+
+@pytest.mark.parametrize("make", [scenes.sphere_workload,
+                                  lambda: scenes.small_room_workload(n_queries=8),
+                                  lambda: scenes.small_room_workload(n_queries=8, uneven=True)])
+def test_host_cell_builder_matches_oracle_bit_exactly(make):
+    wl = make()
+    c = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                         wl.m_cap_grid, wl.key_lo)
+    o = oracle.cells_for(wl)
+    np.testing.assert_array_equal(c.offsets, o.offsets)
+    np.testing.assert_array_equal(c.samples, o.samples)
+    np.testing.assert_array_equal(c.keys, o.keys)
+
+
+def test_builder_rejects_bad_arguments():
+    pts = np.zeros((4, 3), np.float32)
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.build_cells(pts, (0, 0, 0), -1.0, 0.5, 8, 1)
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.build_cells(pts, (0, 0, 0), 1.0, 0.5, 500, 1)
+    bad = pts.copy()
+    bad[2, 1] = np.nan
+    with pytest.raises(ksdf.KsdfError, match="non-finite"):
+        ksdf.build_cells(bad, (0, 0, 0), 1.0, 0.5, 8, 1)
+
+
+def test_empty_point_set_gives_no_cells():
+    c = ksdf.build_cells(np.zeros((0, 3), np.float64), (0, 0, 0), 1.0, 0.5, 8, 1)
+    assert c.n == 0 and c.offsets.tolist() == [0]
+
+
+def test_status_strings():
+    L = ksdf.lib()
+    assert L.ksdf_status_string(0) == b"ok"
+    assert b"workspace" in L.ksdf_status_string(-3)

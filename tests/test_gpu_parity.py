@@ -1,0 +1,154 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by
+element, on seeded synthetic workloads (see tests/parity.py for the tolerances)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def gpu_run(wl, queries=None, sign=None, precision="fp32", k_fuse=8, query_box=None, svar=None,
+            cells=None):
+    cells = cells or ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                                      wl.m_cap_grid, wl.key_lo)
+    q = wl.queries if queries is None else queries
+    s = wl.sign if (queries is None and sign is None) else sign
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       k_fuse=k_fuse, precision=precision, query_box=query_box)
+    pts = torch.from_numpy(np.ascontiguousarray(wl.points)).to("cuda", dt)
+    st = torch.zeros(max(cells.n, 1), dtype=torch.uint8, device="cuda")
+    sv = None if svar is None else torch.from_numpy(svar).to("cuda", dt)
+    model.fit(pts, sample_var=sv, cell_status=st)
+    qt = torch.from_numpy(np.ascontiguousarray(q)).to("cuda", dt)
+    sg = None if s is None else torch.from_numpy(np.ascontiguousarray(s)).to("cuda")
+    out = model.query(qt, sg)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in out.items()}
+    res["cell_status"] = st.cpu().numpy()[:cells.n]
+    return model, cells, res
+
+
+def oracle_run(wl, cells, queries, sign, precision, k_fuse=8, svar=None):
+    oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                      np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, svar=svar)
+    return oracle.query(wl.points, oc, f, queries, wl.ell, wl.noise_var, k_fuse=k_fuse,
+                        cand_prec=64 if precision == "fp64" else 32, sign=sign, svar=svar,
+                        all_candidates=True)
+
+
+def test_sphere_fp64_plain_path_matches_oracle():
+    _say("sphere fp64 full 10k queries")
+    wl = scenes.sphere_workload()
+    _, cells, g = gpu_run(wl, precision="fp64")
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp64")
+    rep = assert_parity(g, o, wl.ell, "fp64", label="sphere fp64")
+    assert rep["mean_err_max"] < 1e-10
+
+
+def test_sphere_fp32_matches_oracle():
+    _say("sphere fp32")
+    wl = scenes.sphere_workload()
+    wl32 = scenes.Workload(**{**wl.__dict__, "points": wl.points.astype(np.float32),
+                              "queries": wl.queries.astype(np.float32)})
+    _, cells, g = gpu_run(wl32, precision="fp32")
+    o = oracle_run(wl32, cells, wl32.queries, wl32.sign, "fp32")
+    assert_parity(g, o, wl.ell, "fp32", label="sphere fp32")
+
+
+@pytest.mark.parametrize("uneven", [False, True])
+def test_small_room_fp32_matches_oracle(uneven):
+    _say(f"small room fp32 uneven={uneven}")
+    wl = scenes.small_room_workload(n_queries=4096, uneven=uneven)
+    _, cells, g = gpu_run(wl)
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp32")
+    rep = assert_parity(g, o, wl.ell, "fp32", label=f"small room uneven={uneven}")
+    print(rep, flush=True)
+
+
+def test_per_sample_variance_fp32():
+    _say("per-sample variance")
+    wl = scenes.small_room_workload(n_queries=1024, cfg_id=21)
+    rng = np.random.default_rng(0)
+    sv = rng.uniform(2e-5, 3e-4, len(wl.points)).astype(np.float32)
+    _, cells, g = gpu_run(wl, svar=sv)
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp32", svar=sv.astype(np.float64))
+    assert_parity(g, o, wl.ell, "fp32", label="per-sample variance")
+
+
+def test_queries_outside_index_use_exact_scan():
+    _say("queries outside the index lattice")
+    wl = scenes.sphere_workload(n_queries=64)
+    q = np.array([[30.0, 0.0, 0.0], [-5.0, 7.0, 2.0], [0.0, 0.0, -12.0], [0.3, 0.2, 0.1]])
+    _, cells, g = gpu_run(wl, queries=q, sign=np.ones(4, np.int8), precision="fp64")
+    assert np.all((g["status"][:3] & ksdf.Q_OUTSIDE_INDEX) != 0)
+    assert (g["status"][3] & ksdf.Q_OUTSIDE_INDEX) == 0
+    o = oracle_run(wl, cells, q, np.ones(4, np.int8), "fp64")
+    assert_parity(g, o, wl.ell, "fp64", label="outside index")
+
+
+def test_k_fuse_larger_than_cell_count_and_single_cell():
+    _say("single cell, k_fuse 8")
+    rng = np.random.default_rng(3)
+    pts = (rng.normal(size=(20, 3)) * 0.05).astype(np.float64)
+    wl = scenes.Workload(99, "tiny", pts, (0.0, 0.0, 0.0), 1.0, 0.5, 32, 1,
+                         rng.normal(size=(50, 3)) * 0.5, np.ones(50, np.int8))
+    _, cells, g = gpu_run(wl, precision="fp64")
+    assert cells.n >= 1
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp64")
+    assert_parity(g, o, wl.ell, "fp64", label="tiny")
+
+
+def test_failed_cells_are_excluded_and_reported():
+    _say("non-SPD cells")
+    # duplicated samples with zero noise cannot be factored in any precision
+    base = np.array([[0.1, 0.1, 0.1], [2.1, 0.1, 0.1]])
+    pts = np.repeat(base, 3, 0).astype(np.float32)
+    wl = scenes.Workload(98, "dup", pts, (0.0, 0.0, 0.0), 1.0, 0.5, 8, 1,
+                         np.array([[0.5, 0.5, 0.5], [1.9, 0.2, 0.2]], np.float32),
+                         np.ones(2, np.int8), noise_var=0.0)
+    _, cells, g = gpu_run(wl)
+    assert np.all(g["cell_status"] & ksdf.C_FAILED)
+    assert np.all(g["status"] & ksdf.Q_NO_VALID_CELL)
+    assert np.all(np.isinf(g["mean"])) and np.all(g["var_f"] == 1.0) and np.all(g["grad"] == 0)
+
+
+def test_ill_conditioned_cells_fall_back_to_fp64():
+    _say("forced FP64 fallback")
+    wl = scenes.small_room_workload(n_queries=512, cfg_id=22)
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       cond_threshold=10.0)
+    pts = torch.from_numpy(wl.points).cuda()
+    st = torch.zeros(cells.n, dtype=torch.uint8, device="cuda")
+    model.fit(pts, cell_status=st)
+    out = model.query(torch.from_numpy(wl.queries).cuda(), torch.from_numpy(wl.sign).cuda())
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    assert np.all(st.cpu().numpy() & ksdf.C_FP64)
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp32")
+    assert_parity(g, o, wl.ell, "fp32", label="all FP64 refit")
+
+
+def test_empty_query_and_argument_errors():
+    _say("empty query, argument errors")
+    wl = scenes.sphere_workload(n_queries=8)
+    model, cells, _ = gpu_run(wl, precision="fp64")
+    out = model.query(torch.zeros(0, 3, dtype=torch.float64, device="cuda"))
+    assert out["mean"].numel() == 0
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=float("nan"), precision="fp64")
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=0.2, k_fuse=40, precision="fp64")
+    bad = ksdf.CellSet(cells.offsets.copy(), cells.samples.copy(), cells.keys.copy())
+    bad.samples[0] = len(wl.points) + 5
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.Model(bad, len(wl.points), wl.origin, wl.h, precision="fp64")
