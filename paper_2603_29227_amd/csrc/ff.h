@@ -95,4 +95,61 @@ __host__ __device__ __forceinline__ ff ff_exp_neg(ff t) {
   return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
 }
 
+// Table-driven exp(-t), t >= 0, in float-float: t = k ln2/64 + r with |r| <= ln2/128,
+// exp(-t) = 2^-(k/64) * exp(-r); 2^-(j/64) for j < 64 comes from a compile-time table
+// (double-precision Taylor sums split into float pairs) and exp(-r) from its Taylor
+// series to degree 6 (truncation below 1e-19).  ln2/64 is split into three floats,
+// the first with 10 significant bits so k*C1 is exact for k < 2^14.
+namespace exp_tab_detail {
+constexpr double taylor_exp(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 40; ++k) {
+    term *= x / k;
+    sum += term;
+  }
+  return sum;
+}
+struct Tab {
+  float hi[64], lo[64];
+};
+constexpr Tab make_tab() {
+  Tab t{};
+  for (int j = 0; j < 64; ++j) {
+    const double v = taylor_exp(-0.69314718055994530942 * j / 64.0);
+    t.hi[j] = (float)v;
+    t.lo[j] = (float)(v - (double)(float)v);
+  }
+  return t;
+}
+}  // namespace exp_tab_detail
+
+__host__ __device__ __forceinline__ ff ff_exp_neg_tab(ff t) {
+#pragma clang fp contract(off)
+  constexpr exp_tab_detail::Tab TAB = exp_tab_detail::make_tab();
+  constexpr float C1 = 0.0108184814453125f;
+  constexpr float C2 = 1.1943250683543738e-05f;
+  constexpr float C3 = 2.531013593154441e-13f;
+  constexpr float INV = 92.33248261689366f;    // 64 / ln 2
+  if (!(t.hi < 103.0f)) return {0.f, 0.f};
+  const float k = rintf(t.hi * INV);
+  ff r = ff_two_sum(t.hi - k * C1, t.lo);
+  r = ff_add(r, ff_neg(ff_two_prod(k, C2)));
+  r = ff_add(r, ff{-k * C3, 0.f});
+  const ff x = ff_neg(r);
+#define KSDF_C(v) ff{(float)(v), (float)((v) - (double)(float)(v))}
+  ff p = KSDF_C(1.0 / 720);
+  p = ff_add(ff_mul(p, x), KSDF_C(1.0 / 120));
+  p = ff_add(ff_mul(p, x), KSDF_C(1.0 / 24));
+  p = ff_add(ff_mul(p, x), KSDF_C(1.0 / 6));
+  p = ff_add(ff_mul(p, x), KSDF_C(0.5));
+  p = ff_add(ff_mul(p, x), ff{1.f, 0.f});
+  p = ff_add(ff_mul(p, x), ff{1.f, 0.f});
+#undef KSDF_C
+  const int ki = (int)k;
+  const int j = ki & 63;
+  p = ff_mul(p, ff{TAB.hi[j], TAB.lo[j]});
+  const int e = -(ki >> 6);
+  return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
+}
+
 }  // namespace ksdf

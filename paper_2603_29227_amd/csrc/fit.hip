@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
       const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
       r2 = ff_add(r2, ff_mul(dd, dd));
     }
-    ff v = ff_exp_neg(ff_mul(r2, inv2l2));
+    ff v = ff_exp_neg_tab(ff_mul(r2, inv2l2));
     if (i == k) v = ff_add(v, ff{sv[i], svl[i]});
     Ahi[e] = v.hi;
     Alo[e] = v.lo;
