@@ -77,7 +77,15 @@ typedef struct ksdf_hyper {
   int k_fuse;
   int precision;
   double cond_fp64_threshold;
+  int flags;          /* KSDF_FIT_* bits */
 } ksdf_hyper;
+
+/* flags: KSDF_FIT_ADJOINT makes every fit also prepare the per-cell adjoint vectors
+ * that ksdf_query_backward needs (xi_l = A^{-1} (dA/dl) a and xi_s = A^{-1} a);
+ * KSDF_FIT_ADJOINT_VARF additionally keeps dA/dl packed per cell, needed for var_f
+ * cotangents.  They must be set at ksdf_model_create (which sizes the storage) and
+ * may then be dropped per fit. */
+enum { KSDF_FIT_ADJOINT = 1, KSDF_FIT_ADJOINT_VARF = 2 };
 
 /* ---------------------------------------------------------------------------
  * Cell builder (host, OpenMP).  The per-octant GP training buffers of Sec. IV-B.1:
@@ -163,16 +171,19 @@ int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t
  * overwritten) = (dL/d ell, dL/d noise_var), the latter including the dependence
  * through the fit (a and L are functions of ell and noise_var) and, when alpha is
  * tied, through alpha = 1/(2 l^2).  The argmin cell of each query is held fixed (the
- * min is piecewise); clamped queries contribute zero.  d_hyper for noise_var is
- * defined for the uniform variance (no per-sample variances).  k* is recomputed, not
- * stored.  The theta reduction is deterministic (fixed order, FP64).
+ * min is piecewise): argmin [Q] (device int32) is the forward's argmin output for the
+ * same points, or NULL to recompute it.  Clamped outputs contribute zero.  d_hyper for
+ * noise_var is defined for the uniform variance (zero when the fit had per-sample
+ * variances).  k* is recomputed, not stored.  The theta reduction is deterministic
+ * (fixed order, FP64, no atomics).  The model's last fit must have had
+ * KSDF_FIT_ADJOINT (and KSDF_FIT_ADJOINT_VARF when d_var_f is given).
  * workspace: at least ksdf_backward_workspace_bytes(model, Q) bytes.
  * ------------------------------------------------------------------------- */
 size_t ksdf_backward_workspace_bytes(const ksdf_model* model, long Q);
 int ksdf_query_backward(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
-                        const void* d_mean, const void* d_grad, const void* d_var,
-                        const void* d_var_f, void* d_points, double* d_hyper, void* workspace,
-                        size_t ws_bytes, void* stream);
+                        const int* argmin, const void* d_mean, const void* d_grad,
+                        const void* d_var, const void* d_var_f, void* d_points, double* d_hyper,
+                        void* workspace, size_t ws_bytes, void* stream);
 
 /* Static description of a status code; ksdf_last_error() gives the calling
  * thread's last detailed message (never NULL). */

@@ -27,7 +27,7 @@ int check_hyper(const ksdf_hyper* hp) {
   }
   if (!(hp->ell > 0) || hp->noise_var < 0 || hp->k_fuse < 1 || hp->k_fuse > KSDF_MAX_K ||
       (hp->precision != KSDF_FP64 && hp->precision != KSDF_FP32) ||
-      !(hp->cond_fp64_threshold > 0)) {
+      !(hp->cond_fp64_threshold > 0) || (hp->flags & ~(KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF))) {
     set_error("hyperparameter out of range (ell > 0, noise_var >= 0, 1 <= k_fuse <= 16, "
               "precision KSDF_FP64|KSDF_FP32, cond threshold > 0)");
     return KSDF_ERR_INVALID_ARGUMENT;
@@ -60,7 +60,7 @@ void free_model(ksdf_model* m) {
   if (!m) return;
   void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
                   m->L32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
-                  m->L64, m->cstatus, m->bucket_cells, m->index.box_off, m->index.box_list};
+                  m->L64, m->cstatus, m->bucket_cells, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -168,6 +168,17 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
   TRY(dalloc(m, &m->ps64, 4L * nnz));
   TRY(dalloc(m, &m->sv64, nnz));
   TRY(dalloc(m, &m->L64, lsize));
+  m->adjoint_alloc = (hyper->flags & (KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) != 0;
+  m->adjoint_varf_alloc = (hyper->flags & KSDF_FIT_ADJOINT_VARF) != 0;
+  if (m->adjoint_alloc) {
+    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->xi32, 2L * (nnz + KSDF_PAD_SAMPLES)));
+    else TRY(dalloc(m, &m->xi64, 2L * nnz));
+    // the FP64 refit of an FP32 model writes its xi in FP32 too
+  }
+  if (m->adjoint_varf_alloc) {
+    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->D32, lsize + KSDF_PAD_FACTOR));
+    else TRY(dalloc(m, &m->D64, lsize));
+  }
   if (m->precision == KSDF_FP32) {
     // padded so the wave-uniform chunked loads of the last cell stay in bounds
     TRY(dalloc(m, &m->ps32, 4L * (nnz + KSDF_PAD_SAMPLES)));
@@ -250,6 +261,14 @@ extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype,
   m->alpha = m->alpha_tied ? 1.0 / (2.0 * hyper->ell * hyper->ell) : hyper->alpha;
   m->cond_thr = hyper->cond_fp64_threshold;
   m->has_svar = sample_var != nullptr;
+  const bool want_adj = (hyper->flags & (KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) != 0;
+  const bool want_varf = (hyper->flags & KSDF_FIT_ADJOINT_VARF) != 0;
+  if ((want_adj && !m->adjoint_alloc) || (want_varf && !m->adjoint_varf_alloc)) {
+    set_error("ksdf_fit_cells: adjoint flags were not requested at ksdf_model_create");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  m->adjoint = want_adj;
+  m->adjoint_varf = want_varf;
   r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, (hipStream_t)stream);
   if (r == KSDF_OK) m->fitted = true;
   return r;
@@ -286,11 +305,11 @@ extern "C" size_t ksdf_backward_workspace_bytes(const ksdf_model* m, long Q) {
 }
 
 extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long Q,
-                                   const int8_t* sign, const void* d_mean, const void* d_grad,
-                                   const void* d_var, const void* d_var_f, void* d_points,
-                                   double* d_hyper, void* workspace, size_t ws_bytes,
-                                   void* stream) {
-  if (!m || Q < 0 || (Q > 0 && (!points || !d_mean || !d_points)) || !d_hyper) {
+                                   const int8_t* sign, const int* argmin, const void* d_mean,
+                                   const void* d_grad, const void* d_var, const void* d_var_f,
+                                   void* d_points, double* d_hyper, void* workspace,
+                                   size_t ws_bytes, void* stream) {
+  if (!m || Q < 0 || (Q > 0 && (!points || !d_points)) || !d_hyper) {
     set_error("ksdf_query_backward: invalid argument");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
@@ -305,8 +324,8 @@ extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long
   }
   int r = check_device(m);
   if (r) return r;
-  return launch_backward(m, points, Q, sign, d_mean, d_grad, d_var, d_var_f, d_points, d_hyper,
-                         workspace, ws_bytes, (hipStream_t)stream);
+  return launch_backward(m, points, Q, sign, argmin, d_mean, d_grad, d_var, d_var_f, d_points,
+                         d_hyper, workspace, ws_bytes, (hipStream_t)stream);
 }
 
 extern "C" const char* ksdf_status_string(int status) {

@@ -1,20 +1,389 @@
-// Query backward (adjoint) — placeholder until the adjoint kernels land.
+// Query backward: the vector-Jacobian product of ksdf_query (adjoint of Sec. IV-B).
+//
+// For a query x with argmin cell c (held fixed: the min-fusion is piecewise), scaled
+// kernel values e_i = exp(-(z_i^2 - d^2)/2l^2), f' = sum a_i e_i, w' = sum a_i e_i d_i
+// (d_i = x - x_i), the outputs and their derivatives are
+//   u = sqrt(d^2 - 2 l^2 ln f')        du/dx = w'/(f' u),  du/dl = (u^2 - Z)/(l u),
+//                                       du/da_i = -l^2 e_i/(u f'),  Z = sum a e z^2 / f'
+//   g = w'/|w'|                        dg = (I - g g^T) dw'/|w'|,
+//                                       dw'/dx = f' I - sum a e d d^T / l^2   (kernel Hessian)
+//                                       dw'/dl = sum a e z^2 d / l^3,  dw'/da_i = e_i d_i
+//   var = sum c_i^2 sigma_i^2          d var/d z_j = 2 alpha (-sigma_j^2 c_j (c_j + s_j)
+//                                                   + s_j V + c_j P),  P = sum sigma^2 c s,
+//                                       d var/d alpha = sum 2 sigma^2 c_i (s_i (h - z_i)(B_i + 1)
+//                                                   - alpha s_i Var_s(z)),  B_i = alpha(h - z_i) + 1
+//   var_f = 1 - k^T A^{-1} k           d/dx = (2/l^2) sum beta_i k_i d_i,  beta = A^{-1} k,
+//                                       d/dl|_A = -2 sum beta k z^2 / l^3,  d/dA = beta beta^T.
+// The fit enters through a = A^{-1} 1: for a weight cotangent abar, d/dtheta =
+// -abar^T A^{-1} (dA/dtheta) a = -abar . xi_theta, with xi_l = A^{-1} (dA/dl) a and
+// xi_s = A^{-1} a prepared per cell by the fit.  So every query's contribution to
+// (dL/dl, dL/dsigma^2) is local; they are summed in a fixed order in FP64, which makes
+// the hyperparameter gradient deterministic without atomics.  alpha = 1/(2 l^2) is
+// differentiated through when tied.  k* is recomputed, never stored.
+#include <cmath>
+
 #include "ksdf_internal.h"
 
 namespace ksdf {
+namespace {
+
+constexpr int BT = 256;
+
+template <class T>
+struct BwdArgs {
+  const T* pts;
+  long Q;
+  const int8_t* sign;
+  const int* argmin;
+  const T* d_mean;
+  const T* d_grad;
+  const T* d_var;
+  const T* d_var_f;
+  T* d_points;
+  double* part;            // [Q,2] per-query (dL/dl, dL/dsigma^2)
+  int n_cells;
+  const int* offsets;
+  const long* loff;
+  const T* ps;             // [nnz,4] (px,py,pz,a) cell-local
+  const T* sv;
+  const T* L;              // packed rows, reciprocal diagonal
+  const T* xi;             // [nnz,2]
+  const T* D;              // packed dA/dl or null
+  const double* centre64;
+  const float* box;        // [n,8] sample AABB (cell-local)
+  T ell, two_l2, alpha;
+  int alpha_tied;
+  int uniform_noise;
+};
+
+template <class T>
+__device__ __forceinline__ T aabb_d2(const float* bx, T x, T y, T z) {
+  const T ex = fmax(fmax((T)bx[0] - x, T(0)), x - (T)bx[4]);
+  const T ey = fmax(fmax((T)bx[1] - y, T(0)), y - (T)bx[5]);
+  const T ez = fmax(fmax((T)bx[2] - z, T(0)), z - (T)bx[6]);
+  return ex * ex + ey * ey + ez * ez;
+}
+
+// One query's VJP on its argmin cell, per-thread loops (the plain path; also the
+// FP32 path, where the wave calls it with a wave-uniform cell so the per-cell data
+// arrive through scalar loads).  v is per-thread storage for k, then L^{-1} k, then
+// beta = A^{-1} k.
+template <class T>
+__device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3], double out_th[2]) {
+  const T lt = A.ell;
+  const T x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
+  const T s = A.sign ? (T)A.sign[q] : T(1);
+  const T gm = A.d_mean ? A.d_mean[q] : T(0);
+  T gg[3] = {T(0), T(0), T(0)};
+  if (A.d_grad)
+    for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
+  const T gv = A.d_var ? A.d_var[q] : T(0);
+  const T gf = A.d_var_f ? A.d_var_f[q] : T(0);
+  const int b = A.offsets[c], m = A.offsets[c + 1] - b;
+  const T* p = A.ps + 4L * b;
+  const T* sv = A.sv + b;
+  const T* Lc = A.L + A.loff[c];
+  const T* xi = A.xi + 2L * b;
+  const double* cc = A.centre64 + 3L * c;
+  const T l0 = x0 - (T)cc[0], l1 = x1 - (T)cc[1], l2 = x2 - (T)cc[2];
+  const T inv2l2 = T(1) / A.two_l2;
+  // scaling reference: the exact nearest sample (any reference gives the same result)
+  T d2 = (T)INFINITY;
+  for (int i = 0; i < m; ++i) {
+    const T dx = l0 - p[4 * i], dy = l1 - p[4 * i + 1], dz = l2 - p[4 * i + 2];
+    d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
+  }
+  const T ginv = exp(-d2 * inv2l2);
+  const T zmin = sqrt(d2);
+  // pass A: f', w', Z, softmin moments, k
+  T f = 0, w[3] = {0, 0, 0}, Za = 0, S = 0, M1 = 0, M2 = 0;
+  for (int i = 0; i < m; ++i) {
+    const T dx = l0 - p[4 * i], dy = l1 - p[4 * i + 1], dz = l2 - p[4 * i + 2];
+    const T z2 = dx * dx + dy * dy + dz * dz;
+    const T e = exp(-(z2 - d2) * inv2l2);
+    const T ae = p[4 * i + 3] * e;
+    f += ae;
+    w[0] += ae * dx;
+    w[1] += ae * dy;
+    w[2] += ae * dz;
+    Za += ae * z2;
+    const T t = sqrt(z2) - zmin;
+    const T sm = exp(-A.alpha * t);
+    S += sm;
+    M1 += sm * t;
+    M2 += sm * t * t;
+    v[i] = e * ginv;
+  }
+  // forward substitution: v <- L^{-1} k
+  T vv = 0;
+  for (int i = 0; i < m; ++i) {
+    const T* row = Lc + (long)i * (i + 1) / 2;
+    T t = v[i];
+    for (int j = 0; j < i; ++j) t -= row[j] * v[j];
+    v[i] = t * row[i];
+    vv += v[i] * v[i];
+  }
+  // backward substitution: v <- L^{-T} v = A^{-1} k (row-oriented, last row first)
+  for (int i = m - 1; i >= 0; --i) {
+    const T* row = Lc + (long)i * (i + 1) / 2;
+    v[i] *= row[i];
+    for (int j = 0; j < i; ++j) v[j] -= row[j] * v[i];
+  }
+  const T u2 = f > T(0) ? d2 - A.two_l2 * log(f) : T(-1);
+  const bool mean_live = u2 > T(0);
+  const T u = mean_live ? sqrt(u2) : T(0);
+  const T wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  T y[3] = {0, 0, 0};
+  if (wn > T(0)) {
+    const T gw = (gg[0] * w[0] + gg[1] * w[1] + gg[2] * w[2]) / wn;
+    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * w[d] / wn) / wn;
+  }
+  const bool varf_live = (T(1) - vv) > T(0);
+  const T m1 = M1 / S;
+  const T h = zmin + m1;
+  const T Vz = M2 / S - m1 * m1;
+  // pass B: softmin coefficients c_i; V, P, d var / d alpha, sum c^2
+  T V = 0, P = 0, dVa = 0, C2 = 0;
+  for (int i = 0; i < m; ++i) {
+    const T dx = l0 - p[4 * i], dy = l1 - p[4 * i + 1], dz = l2 - p[4 * i + 2];
+    const T z = sqrt(dx * dx + dy * dy + dz * dz);
+    const T si = exp(-A.alpha * (z - zmin)) / S;
+    const T Bi = A.alpha * (h - z) + T(1);
+    const T ci = si * Bi;
+    V += sv[i] * ci * ci;
+    P += sv[i] * ci * si;
+    C2 += ci * ci;
+    dVa += T(2) * sv[i] * ci * (si * (h - z) * (Bi + T(1)) - A.alpha * si * Vz);
+  }
+  // pass C: per-sample accumulations
+  T dxv[3] = {0, 0, 0}, Hy[3] = {0, 0, 0}, Wz[3] = {0, 0, 0}, bk[3] = {0, 0, 0};
+  T bkz = 0, bb = 0, El = 0, Es = 0, Eld[3] = {0, 0, 0}, Esd[3] = {0, 0, 0};
+  for (int i = 0; i < m; ++i) {
+    const T di[3] = {l0 - p[4 * i], l1 - p[4 * i + 1], l2 - p[4 * i + 2]};
+    const T z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
+    const T z = sqrt(z2);
+    const T e = exp(-(z2 - d2) * inv2l2);
+    const T ae = p[4 * i + 3] * e;
+    const T si = exp(-A.alpha * (z - zmin)) / S;
+    const T ci = si * (A.alpha * (h - z) + T(1));
+    const T dvdz = T(2) * A.alpha * (-sv[i] * ci * (ci + si) + si * V + ci * P);
+    const T dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
+    const T kb = v[i] * e * ginv;
+    for (int d = 0; d < 3; ++d) {
+      if (z > T(0)) dxv[d] += dvdz * di[d] / z;
+      Hy[d] += ae * dy * di[d];
+      Wz[d] += ae * z2 * di[d];
+      bk[d] += kb * di[d];
+      Eld[d] += e * xi[2 * i] * di[d];
+      Esd[d] += e * xi[2 * i + 1] * di[d];
+    }
+    bkz += kb * z2;
+    bb += v[i] * v[i];
+    El += e * xi[2 * i];
+    Es += e * xi[2 * i + 1];
+  }
+  T bDb = 0;
+  if (A.D && gf != T(0) && varf_live) {
+    const T* Dc = A.D + A.loff[c];
+    for (int i = 1; i < m; ++i) {
+      const T* row = Dc + (long)i * (i + 1) / 2;
+      T t = 0;
+      for (int j = 0; j < i; ++j) t += row[j] * v[j];
+      bDb += T(2) * v[i] * t;
+    }
+  }
+  const T l3 = lt * lt * lt;
+  // d_points
+  for (int d = 0; d < 3; ++d) {
+    T r = s * (f * y[d] - Hy[d] / (lt * lt)) + gv * dxv[d];
+    if (mean_live) r += s * gm * w[d] / (f * u);
+    if (varf_live) r += gf * T(2) * bk[d] / (lt * lt);
+    out_dx[d] = r;
+  }
+  // weight cotangent . xi (through the fit)
+  T aXl = s * (y[0] * Eld[0] + y[1] * Eld[1] + y[2] * Eld[2]);
+  T aXs = s * (y[0] * Esd[0] + y[1] * Esd[1] + y[2] * Esd[2]);
+  if (mean_live) {
+    const T cm = -s * gm * lt * lt / (u * f);
+    aXl += cm * El;
+    aXs += cm * Es;
+  }
+  double dl = 0, ds = 0;
+  if (mean_live) dl += (double)(s * gm * (u2 - Za / f) / (lt * u));
+  dl += (double)(s * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]) / l3);
+  if (A.alpha_tied) dl += (double)(gv * dVa * (-T(2) * A.alpha / lt));
+  if (varf_live) dl += (double)(gf * (-T(2) * bkz / l3 + bDb));
+  dl -= (double)aXl;
+  if (A.uniform_noise) {
+    ds += (double)(gv * C2);
+    if (varf_live) ds += (double)(gf * bb);
+    ds -= (double)aXs;
+  }
+  out_th[0] = dl;
+  out_th[1] = ds;
+}
+
+template <class T>
+__global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
+  const long q = (long)blockIdx.x * BT + threadIdx.x;
+  if (q >= A.Q) return;
+  int c = A.argmin[q];
+  if (c >= A.n_cells) c = -1;   // not a cell of this model: no contribution
+  T dx[3] = {T(0), T(0), T(0)};
+  double th[2] = {0.0, 0.0};
+  if (c >= 0) {
+    T v[KSDF_MAX_M];
+    query_vjp<T>(A, q, c, v, dx, th);
+  }
+  for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = dx[d];
+  A.part[2 * q] = th[0];
+  A.part[2 * q + 1] = th[1];
+}
+
+// FP32: one wave walks the distinct argmin cells of its lanes, so the cell index is
+// wave-uniform and the cell's samples, factor and adjoint vectors are read through
+// scalar loads.
+__global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A) {
+  const long q = (long)blockIdx.x * BT + threadIdx.x;
+  const bool active = q < A.Q;
+  int bc = active ? A.argmin[q] : -1;
+  if (bc >= A.n_cells) bc = -1;
+  float dx[3] = {0.f, 0.f, 0.f};
+  double th[2] = {0.0, 0.0};
+  bool todo = bc >= 0;
+  while (true) {
+    unsigned key = todo ? (unsigned)bc : 0xffffffffu;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) key = min(key, (unsigned)__shfl_xor((int)key, o, 64));
+    key = (unsigned)__builtin_amdgcn_readfirstlane((int)key);
+    if (key == 0xffffffffu) break;
+    const int c = (int)key;
+    if (todo && bc == c) {
+      float v[KSDF_MAX_M];
+      query_vjp<float>(A, q, c, v, dx, th);
+      todo = false;
+    }
+  }
+  if (!active) return;
+  for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = dx[d];
+  A.part[2 * q] = th[0];
+  A.part[2 * q + 1] = th[1];
+}
+
+// Fixed-order FP64 reduction of the per-query hyperparameter partials (one block).
+constexpr int RT = 1024;
+__global__ void __launch_bounds__(RT) theta_reduce_kernel(const double* part, long Q, double* out) {
+  __shared__ double r0[RT], r1[RT];
+  const long per = (Q + RT - 1) / RT;
+  const long beg = (long)threadIdx.x * per;
+  const long end = beg + per < Q ? beg + per : Q;
+  double a = 0.0, b = 0.0;
+  for (long i = beg; i < end; ++i) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  r0[threadIdx.x] = a;
+  r1[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = RT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      r0[threadIdx.x] += r0[threadIdx.x + o];
+      r1[threadIdx.x] += r1[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = r0[0];
+    out[1] = r1[0];
+  }
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
 
 size_t backward_workspace_bytes(const ksdf_model* m, long Q) {
-  (void)m;
-  (void)Q;
-  return 0;
+  const size_t fb = m->precision == KSDF_FP64 ? sizeof(double) : sizeof(float);
+  // per-query theta partials, and (when no argmin is passed) a forward pass
+  return al256(2 * Q * sizeof(double)) + al256(Q * sizeof(int)) + al256(Q * 5 * fb) +
+         al256(query_workspace_bytes(m, Q));
 }
 
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                    const void* d_mean, const void* d_grad, const void* d_var,
+                    const int* argmin, const void* d_mean, const void* d_grad, const void* d_var,
                     const void* d_var_f, void* d_points, double* d_hyper, void* ws,
                     size_t ws_bytes, hipStream_t s) {
-  set_error("backward not available");
-  return KSDF_ERR_UNSUPPORTED;
+  if (!m->adjoint) {
+    set_error("backward: the model was not fitted with KSDF_FIT_ADJOINT");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (d_var_f && !m->adjoint_varf) {
+    set_error("backward: a var_f cotangent needs a fit with KSDF_FIT_ADJOINT_VARF");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t fb = m->precision == KSDF_FP64 ? sizeof(double) : sizeof(float);
+  char* w = static_cast<char*>(ws);
+  double* part = reinterpret_cast<double*>(w);
+  w += al256(2 * Q * sizeof(double));
+  int* am = reinterpret_cast<int*>(w);
+  w += al256(Q * sizeof(int));
+  char* fwd = w;
+  w += al256(Q * 5 * fb);
+  void* fws = w;
+  if (Q == 0) {
+    hipLaunchKernelGGL(theta_reduce_kernel, dim3(1), dim3(RT), 0, s, part, 0L, d_hyper);
+    KSDF_HIP_TRY(hipGetLastError());
+    return KSDF_OK;
+  }
+  if (!argmin) {
+    // recover each query's argmin cell with a forward pass into the workspace
+    int r = launch_query(m, points, Q, sign, fwd, fwd + Q * fb, fwd + 4 * Q * fb, nullptr, am,
+                         nullptr, fws, query_workspace_bytes(m, Q), s);
+    if (r != KSDF_OK) return r;
+    argmin = am;
+  }
+  const unsigned grid = (unsigned)((Q + BT - 1) / BT);
+  const double two_l2 = 2.0 * m->ell * m->ell;
+  if (m->precision == KSDF_FP64) {
+    BwdArgs<double> A{};
+    A.pts = static_cast<const double*>(points);
+    A.Q = Q; A.sign = sign; A.argmin = argmin;
+    A.d_mean = static_cast<const double*>(d_mean);
+    A.d_grad = static_cast<const double*>(d_grad);
+    A.d_var = static_cast<const double*>(d_var);
+    A.d_var_f = static_cast<const double*>(d_var_f);
+    A.d_points = static_cast<double*>(d_points);
+    A.part = part;
+    A.n_cells = m->n_cells;
+    A.offsets = m->offsets; A.loff = m->loff;
+    A.ps = m->ps64; A.sv = m->sv64; A.L = m->L64; A.xi = m->xi64;
+    A.D = m->adjoint_varf ? m->D64 : nullptr;
+    A.centre64 = m->centre64; A.box = m->box32;
+    A.ell = m->ell; A.two_l2 = two_l2; A.alpha = m->alpha;
+    A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
+    hipLaunchKernelGGL(bwd_plain_kernel<double>, dim3(grid), dim3(BT), 0, s, A);
+  } else {
+    BwdArgs<float> A{};
+    A.pts = static_cast<const float*>(points);
+    A.Q = Q; A.sign = sign; A.argmin = argmin;
+    A.d_mean = static_cast<const float*>(d_mean);
+    A.d_grad = static_cast<const float*>(d_grad);
+    A.d_var = static_cast<const float*>(d_var);
+    A.d_var_f = static_cast<const float*>(d_var_f);
+    A.d_points = static_cast<float*>(d_points);
+    A.part = part;
+    A.n_cells = m->n_cells;
+    A.offsets = m->offsets; A.loff = m->loff;
+    A.ps = m->ps32; A.sv = m->sv32; A.L = m->L32; A.xi = m->xi32;
+    A.D = m->adjoint_varf ? m->D32 : nullptr;
+    A.centre64 = m->centre64; A.box = m->box32;
+    A.ell = (float)m->ell; A.two_l2 = (float)two_l2; A.alpha = (float)m->alpha;
+    A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
+    hipLaunchKernelGGL(bwd_wave_kernel, dim3(grid), dim3(BT), 0, s, A);
+  }
+  hipLaunchKernelGGL(theta_reduce_kernel, dim3(1), dim3(RT), 0, s, part, Q, d_hyper);
+  KSDF_HIP_TRY(hipGetLastError());
+  return KSDF_OK;
 }
 
 }  // namespace ksdf

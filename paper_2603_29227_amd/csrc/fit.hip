@@ -182,8 +182,14 @@ struct FitArgs {
   const long* loff;
   const double* centre64;
   double ell, noise, cond_thr;
-  float noise_ff[2];     // sigma^2 and 1/(2 l^2) as float-float pairs
+  float noise_ff[2];     // sigma^2, 1/(2 l^2) and 1/l^3 as float-float pairs
   float inv2l2_ff[2];
+  float inv_l3_ff[2];
+  int adjoint;           // also prepare the adjoint vectors xi (and D when non-null)
+  float* xi32;           // [nnz,2] (xi_l, xi_s)
+  float* D32;            // packed dA/dl or null
+  double* xi64;
+  double* D64;
   // FP32 store
   float* ps32;
   float* plo32;
@@ -310,6 +316,68 @@ __device__ void write_cell(const T* Lp, const T* xs, const T* sv, const WVec<T>&
   }
 }
 
+// Solve A x = rhs for the cell (block-cooperative): an FP32 solve with the factor,
+// then three refinement steps whose residuals rhs - A x are evaluated in
+// float-float from (Ahi, Alo).  rhs (rh, rl) and x (xh, xl) are float-float
+// arrays in LDS; res is scratch.  Ends with a barrier.
+__device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float* Lf, int m,
+                                 const float* rh, const float* rl, float* xh, float* xl,
+                                 float* res) {
+  const int lane = threadIdx.x & 63;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    WVec<float> rv, y, x0;
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+      const int i = t * 64 + lane;
+      rv.s[t] = i < m ? rh[i] : 0.f;
+    }
+    wave_forward<float>(Lf, m, rv, y);
+    wave_backward<float>(Lf, m, y, x0);
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+      const int i = t * 64 + lane;
+      if (i < m) {
+        xh[i] = x0.s[t];
+        xl[i] = 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  for (int it = 0; it < 3; ++it) {
+    for (int i = threadIdx.x; i < m; i += FIT_THREADS) {
+      ff acc{0.f, 0.f};
+      for (int k = 0; k < m; ++k) {
+        const long e = k <= i ? pk(i, k) : pk(k, i);
+        acc = ff_add(acc, ff_mul(ff{Ahi[e], Alo[e]}, ff{xh[k], xl[k]}));
+      }
+      const ff r = ff_add(ff{rh[i], rl[i]}, ff_neg(acc));
+      res[i] = r.hi + r.lo;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      WVec<float> rv, y, dlt;
+#pragma unroll
+      for (int t = 0; t < SLOTS; ++t) {
+        const int i = t * 64 + lane;
+        rv.s[t] = i < m ? res[i] : 0.f;
+      }
+      wave_forward<float>(Lf, m, rv, y);
+      wave_backward<float>(Lf, m, y, dlt);
+#pragma unroll
+      for (int t = 0; t < SLOTS; ++t) {
+        const int i = t * 64 + lane;
+        if (i < m) {
+          const ff x2 = ff_add(ff{xh[i], xl[i]}, ff{dlt.s[t], 0.f});
+          xh[i] = x2.hi;
+          xl[i] = x2.lo;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // FP32 fit with mixed-precision iterative refinement.  A is assembled once in
 // float-float (about 44 bits: exact cell-local differences, a float-float exp),
 // its leading float part is factored in FP32, and a = A^{-1} 1 is refined with
@@ -330,6 +398,10 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
   __shared__ float ah[MB];
   __shared__ float al[MB];
   __shared__ float res[MB];
+  __shared__ float rh[MB];
+  __shared__ float rl[MB];
+  __shared__ float xih[MB];
+  __shared__ float xil[MB];
   __shared__ float cond_sh;
   const int c = list[blockIdx.x];
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
@@ -386,16 +458,6 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
   if (threadIdx.x < 64) {
     float cond = INFINITY;
     if (ok) {
-      WVec<float> ones, y, a0;
-#pragma unroll
-      for (int t = 0; t < SLOTS; ++t) ones.s[t] = 1.f;
-      wave_forward<float>(Lf, m, ones, y);
-      wave_backward<float>(Lf, m, y, a0);
-#pragma unroll
-      for (int t = 0; t < SLOTS; ++t) {
-        const int i = t * 64 + lane;
-        if (i < m) { ah[i] = a0.s[t]; al[i] = 0.f; }
-      }
       cond = cond2_estimate<float>(Ahi, Lf, m);
     }
     if (threadIdx.x == 0) cond_sh = cond;
@@ -404,37 +466,60 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
   const float cond = cond_sh;
   const bool need64 = !ok || !(cond <= (float)A.cond_thr);
   if (!need64) {
-    for (int it = 0; it < 3; ++it) {
+    // a = A^{-1} 1
+    for (int i = threadIdx.x; i < m; i += FIT_THREADS) {
+      rh[i] = 1.f;
+      rl[i] = 0.f;
+    }
+    ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, ah, al, res);
+    if (A.adjoint) {
+      // adjoint vectors of the fit: xi_l = A^{-1} (dA/dl) a with dA_ij/dl = K_ij r_ij^2 / l^3,
+      // and xi_s = A^{-1} a (dA/dsigma^2 = I for the uniform noise variance)
+      const ff il3{A.inv_l3_ff[0], A.inv_l3_ff[1]};
       for (int i = threadIdx.x; i < m; i += FIT_THREADS) {
         ff acc{0.f, 0.f};
         for (int k = 0; k < m; ++k) {
+          if (k == i) continue;
           const long e = k <= i ? pk(i, k) : pk(k, i);
-          acc = ff_add(acc, ff_mul(ff{Ahi[e], Alo[e]}, ff{ah[k], al[k]}));
-        }
-        const ff r = ff_add(ff{1.f, 0.f}, ff_neg(acc));
-        res[i] = r.hi + r.lo;
-      }
-      __syncthreads();
-      if (threadIdx.x < 64) {
-        WVec<float> rv, y, dlt;
+          ff r2{0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < SLOTS; ++t) {
-          const int i = t * 64 + lane;
-          rv.s[t] = i < m ? res[i] : 0.f;
-        }
-        wave_forward<float>(Lf, m, rv, y);
-        wave_backward<float>(Lf, m, y, dlt);
-#pragma unroll
-        for (int t = 0; t < SLOTS; ++t) {
-          const int i = t * 64 + lane;
-          if (i < m) {
-            const ff a2 = ff_add(ff{ah[i], al[i]}, ff{dlt.s[t], 0.f});
-            ah[i] = a2.hi;
-            al[i] = a2.lo;
+          for (int d = 0; d < 3; ++d) {
+            const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
+            r2 = ff_add(r2, ff_mul(dd, dd));
           }
+          acc = ff_add(acc, ff_mul(ff_mul(ff{Ahi[e], Alo[e]}, r2), ff{ah[k], al[k]}));
+        }
+        const ff g = ff_mul(acc, il3);
+        rh[i] = g.hi;
+        rl[i] = g.lo;
+      }
+      ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
+      for (int i = threadIdx.x; i < m; i += FIT_THREADS) A.xi32[2L * (b + i)] = xih[i] + xil[i];
+      if (!A.svar) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < m; i += FIT_THREADS) {
+          rh[i] = ah[i];
+          rl[i] = al[i];
+        }
+        ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
+      }
+      for (int i = threadIdx.x; i < m; i += FIT_THREADS)
+        A.xi32[2L * (b + i) + 1] = A.svar ? 0.f : xih[i] + xil[i];
+      if (A.D32) {
+        const float il3f = A.inv_l3_ff[0];
+        for (int e = threadIdx.x; e < m * (m + 1) / 2; e += FIT_THREADS) {
+          int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+          while (i * (i + 1) / 2 > e) --i;
+          while ((i + 1) * (i + 2) / 2 <= e) ++i;
+          const int k = e - i * (i + 1) / 2;
+          float r2 = 0.f;
+          for (int d = 0; d < 3; ++d) {
+            const float dd = (xh[3 * i + d] - xh[3 * k + d]) + (xl[3 * i + d] - xl[3 * k + d]);
+            r2 += dd * dd;
+          }
+          A.D32[A.loff[c] + e] = (i == k) ? 0.f : Ahi[e] * r2 * il3f;
         }
       }
-      __syncthreads();
     }
   }
   WVec<float> a;
@@ -459,6 +544,8 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
 __global__ void __launch_bounds__(FIT_THREADS) fit64_kernel(FitArgs A) {
   __shared__ double xs[3 * MAXM];
   __shared__ double sv[MAXM];
+  __shared__ double a_s[MAXM];
+  __shared__ double g_s[MAXM];
   const int count = A.list ? *A.list_count : A.n_cells;
   for (int t = blockIdx.x; t < count; t += gridDim.x) {
     const int c = A.list ? A.list[t] : t;
@@ -488,6 +575,73 @@ __global__ void __launch_bounds__(FIT_THREADS) fit64_kernel(FitArgs A) {
       wave_backward<double>(Ap, m, y, a);
     }
     __syncthreads();
+    if (A.adjoint && ok) {
+      // adjoint vectors of the fit in FP64: xi_l = A^{-1} (dA/dl) a, xi_s = A^{-1} a
+      const int lane = threadIdx.x & 63;
+      if (threadIdx.x < 64) {
+#pragma unroll
+        for (int t2 = 0; t2 < SLOTS; ++t2) {
+          const int i = t2 * 64 + lane;
+          if (i < m) a_s[i] = a.s[t2];
+        }
+      }
+      __syncthreads();
+      const double inv2l2 = 1.0 / (2.0 * A.ell * A.ell), il3 = 1.0 / (A.ell * A.ell * A.ell);
+      for (int i = threadIdx.x; i < m; i += FIT_THREADS) {
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) {
+          if (k == i) continue;
+          const double dx = xs[3 * i] - xs[3 * k], dy = xs[3 * i + 1] - xs[3 * k + 1],
+                       dz = xs[3 * i + 2] - xs[3 * k + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          acc += exp(-r2 * inv2l2) * r2 * a_s[k];
+        }
+        g_s[i] = acc * il3;
+      }
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        WVec<double> gv, av, y, xl_, xs_;
+#pragma unroll
+        for (int t2 = 0; t2 < SLOTS; ++t2) {
+          const int i = t2 * 64 + lane;
+          gv.s[t2] = i < m ? g_s[i] : 0.0;
+          av.s[t2] = i < m ? a_s[i] : 0.0;
+        }
+        wave_forward<double>(Ap, m, gv, y);
+        wave_backward<double>(Ap, m, y, xl_);
+        wave_forward<double>(Ap, m, av, y);
+        wave_backward<double>(Ap, m, y, xs_);
+#pragma unroll
+        for (int t2 = 0; t2 < SLOTS; ++t2) {
+          const int i = t2 * 64 + lane;
+          if (i < m) {
+            const double xsv = A.svar ? 0.0 : xs_.s[t2];
+            if (A.emit32) {
+              A.xi32[2L * (b + i)] = (float)xl_.s[t2];
+              A.xi32[2L * (b + i) + 1] = (float)xsv;
+            } else {
+              A.xi64[2L * (b + i)] = xl_.s[t2];
+              A.xi64[2L * (b + i) + 1] = xsv;
+            }
+          }
+        }
+      }
+      if (A.D32 || A.D64) {
+        for (int e = threadIdx.x; e < m * (m + 1) / 2; e += FIT_THREADS) {
+          int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+          while (i * (i + 1) / 2 > e) --i;
+          while ((i + 1) * (i + 2) / 2 <= e) ++i;
+          const int k = e - i * (i + 1) / 2;
+          const double dx = xs[3 * i] - xs[3 * k], dy = xs[3 * i + 1] - xs[3 * k + 1],
+                       dz = xs[3 * i + 2] - xs[3 * k + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          const double dv = (i == k) ? 0.0 : exp(-r2 * inv2l2) * r2 * il3;
+          if (A.emit32) A.D32[A.loff[c] + e] = (float)dv;
+          else A.D64[A.loff[c] + e] = dv;
+        }
+      }
+      __syncthreads();
+    }
     if (A.emit32) {
       write_cell<double, float>(Ap, xs, sv, a, m, ok, A.ps32 + 4L * b, A.sv32 + b,
                                 A.L32 + A.loff[c], A.box32 + 8L * c, A.plo32 + 4L * b);
@@ -525,7 +679,15 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
   A.cstatus = m->cstatus;
   A.n_cells = m->n_cells;
   if (m->n_cells == 0) return KSDF_OK;
+  A.adjoint = m->adjoint ? 1 : 0;
+  A.xi32 = m->xi32;
+  A.xi64 = m->xi64;
+  A.D32 = m->adjoint_varf ? m->D32 : nullptr;
+  A.D64 = m->adjoint_varf ? m->D64 : nullptr;
   {
+    const double il3 = 1.0 / (m->ell * m->ell * m->ell);
+    A.inv_l3_ff[0] = (float)il3;
+    A.inv_l3_ff[1] = (float)(il3 - (double)(float)il3);
     const double inv = 1.0 / (2.0 * m->ell * m->ell);
     A.inv2l2_ff[0] = (float)inv;
     A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);

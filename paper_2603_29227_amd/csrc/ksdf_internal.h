@@ -87,6 +87,15 @@ struct ksdf_model {
   double* L64 = nullptr;        // packed rows of L; diagonal holds 1/L_jj
 
   uint8_t* cstatus = nullptr;   // [n] KSDF_C_* bits of the last fit
+  // adjoint of the fit (prepared when the hyperparameters ask for it)
+  bool adjoint_alloc = false;   // storage for the adjoint vectors exists
+  bool adjoint_varf_alloc = false;
+  bool adjoint = false;         // xi vectors prepared by the last fit
+  bool adjoint_varf = false;    // packed dA/dl prepared by the last fit
+  float* xi32 = nullptr;        // [nnz+pad,2] xi_l = A^{-1}(dA/dl)a, xi_s = A^{-1}a
+  double* xi64 = nullptr;       // [nnz,2] (FP64 models)
+  float* D32 = nullptr;         // packed dA/dl (FP32 models)
+  double* D64 = nullptr;        // packed dA/dl (FP64 models)
   int* bucket_cells = nullptr;  // [n] cell ids grouped by m bucket (<=16, <=32, <=64, <=128)
   int bucket_start[5] = {0, 0, 0, 0, 0};
 
@@ -109,7 +118,7 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
 size_t query_fast_workspace_bytes(const ksdf_model* m, long Q);
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                    const void* d_mean, const void* d_grad, const void* d_var,
+                    const int* argmin, const void* d_mean, const void* d_grad, const void* d_var,
                     const void* d_var_f, void* d_points, double* d_hyper, void* ws,
                     size_t ws_bytes, hipStream_t s);
 size_t backward_workspace_bytes(const ksdf_model* m, long Q);

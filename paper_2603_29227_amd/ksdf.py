@@ -27,6 +27,7 @@ FP64, FP32 = 0, 1
 DTYPE_F32, DTYPE_F64 = 0, 1
 Q_NO_VALID_CELL, Q_CLAMPED, Q_GRAD_ZERO, Q_OUTSIDE_INDEX = 1, 2, 4, 8
 C_FP64, C_FAILED = 1, 2
+FIT_ADJOINT, FIT_ADJOINT_VARF = 1, 2
 
 EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_cellset_destroy",
            "ksdf_model_create", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
@@ -41,7 +42,8 @@ class KsdfError(RuntimeError):
 class Hyper(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_double), ("noise_var", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("k_fuse", ctypes.c_int),
-                ("precision", ctypes.c_int), ("cond_fp64_threshold", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("cond_fp64_threshold", ctypes.c_double),
+                ("flags", ctypes.c_int)]
 
 
 _lib = None
@@ -77,7 +79,7 @@ def lib():
         L.ksdf_backward_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
-                                          sz, _vp]
+                                          _vp, sz, _vp]
         L.ksdf_status_string.argtypes = [i]
         L.ksdf_status_string.restype = ctypes.c_char_p
         L.ksdf_last_error.argtypes = []
@@ -153,7 +155,8 @@ class Model:
 
     def __init__(self, cells: CellSet, n_points: int, origin, h: float, ell: float = 0.2,
                  noise_var: float = 1e-4, k_fuse: int = 8, precision: str = "fp32",
-                 alpha: Optional[float] = None, cond_threshold: float = 1e6, query_box=None):
+                 alpha: Optional[float] = None, cond_threshold: float = 1e6, query_box=None,
+                 adjoint: bool = False, adjoint_var_f: bool = False):
         if not torch.cuda.is_available():
             raise KsdfError("no GPU: libksdf needs a gfx950 device")
         self._lib = lib()
@@ -163,8 +166,9 @@ class Model:
         self.h = float(h)
         self.precision = FP64 if precision == "fp64" else FP32
         self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        flags = (FIT_ADJOINT if adjoint or adjoint_var_f else 0) | (FIT_ADJOINT_VARF if adjoint_var_f else 0)
         self.hyper = Hyper(float(ell), float(noise_var), -1.0 if alpha is None else float(alpha),
-                           int(k_fuse), self.precision, float(cond_threshold))
+                           int(k_fuse), self.precision, float(cond_threshold), flags)
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._h = ctypes.c_void_p()
         qlo = qhi = None
@@ -253,7 +257,9 @@ class Model:
                                     _stream(stream)), "ksdf_query")
         return out
 
-    def backward(self, points, sign, d_mean, d_grad=None, d_var=None, d_var_f=None, stream=None):
+    def backward(self, points, sign, d_mean, d_grad=None, d_var=None, d_var_f=None, argmin=None,
+                 stream=None):
+        """VJP: (d_points [Q,3], d_hyper [2] float64 = dL/d(ell, noise_var))."""
         Q = len(points)
         d_points = torch.empty(Q, 3, dtype=self.dtype, device=points.device)
         d_hyper = torch.empty(2, dtype=torch.float64, device=points.device)
@@ -263,9 +269,11 @@ class Model:
         for t in c:
             if t is not None and t.dtype != self.dtype:
                 raise ValueError("cotangents must match the model dtype")
-        _check(self._lib.ksdf_query_backward(self._h, _ptr(points), Q, _ptr(sign), *[_ptr(t) for t in c],
-                                             _ptr(d_points), _ptr(d_hyper), _ptr(ws), nb,
-                                             _stream(stream)), "ksdf_query_backward")
+        if argmin is not None and (argmin.dtype != torch.int32 or argmin.numel() != Q):
+            raise ValueError("argmin must be int32 [Q]")
+        _check(self._lib.ksdf_query_backward(self._h, _ptr(points), Q, _ptr(sign), _ptr(argmin),
+                                             *[_ptr(t) for t in c], _ptr(d_points), _ptr(d_hyper),
+                                             _ptr(ws), nb, _stream(stream)), "ksdf_query_backward")
         return d_points, d_hyper
 
     def close(self):
@@ -283,24 +291,25 @@ class Model:
 class _SDF(torch.autograd.Function):
     @staticmethod
     def forward(ctx, points, theta, model: Model, sign):
+        ctx.set_materialize_grads(False)
         if theta is not None:
             model.set_hyper(ell=float(theta[0]), noise_var=float(theta[1]))
             model.fit(model.points, model.sample_var)
-        out = model.query(points.detach().contiguous(), sign, argmin=False, status=False)
+        out = model.query(points.detach().contiguous(), sign, argmin=True, status=False)
         ctx.model = model
         ctx.sign = sign
         ctx.has_theta = theta is not None
-        ctx.save_for_backward(points)
+        ctx.save_for_backward(points, out["argmin"])
         return out["mean"], out["grad"], out["var"], out["var_f"]
 
     @staticmethod
     def backward(ctx, g_mean, g_grad, g_var, g_var_f):
-        (points,) = ctx.saved_tensors
+        points, argmin = ctx.saved_tensors
         m = ctx.model
         z = lambda g: None if g is None else g.contiguous()  # noqa: E731
         gm = g_mean if g_mean is not None else torch.zeros(len(points), dtype=m.dtype, device=points.device)
         d_points, d_hyper = m.backward(points.detach().contiguous(), ctx.sign, z(gm), z(g_grad),
-                                       z(g_var), z(g_var_f))
+                                       z(g_var), z(g_var_f), argmin=argmin)
         return d_points, (d_hyper if ctx.has_theta else None), None, None
 
 

@@ -5,7 +5,8 @@ Tolerances (the parity contract):
          |ref| < 1 cm the square-root zone also passes with |d(u^2)| <= 2 l^2 tau'
          (tau' = 1e-5 / 1e-11), because sqrt amplifies the error of u^2 near 0.
   grad   |d| <= tau where the oracle's cancellation ratio sum|a_i| e_i |x*-x_i| / |w|
-         is <= 1e2 (elsewhere the direction is ill-posed: counted, not compared).
+         is <= 1e3 (elsewhere the direction is ill-conditioned for FP32 weights: the
+         measured FP32 error grows as about 3e-8 x ratio; counted, not compared).
   var    |d| <= 1e-3 |ref| (FP32) / 1e-10 |ref| (FP64).
   var_f  |d| <= 1e-3 (FP32) / 1e-10 (FP64), relative to the prior variance k(x,x) = 1.
 Near-ties of the min-fusion: the GPU's argmin cell is accepted when it is one of
@@ -18,8 +19,8 @@ from __future__ import annotations
 import numpy as np
 
 TOL = {
-    "fp32": dict(tau=1e-4, tau_sq=1e-5, var=1e-3, var_f=1e-3, ratio=1e2),
-    "fp64": dict(tau=1e-10, tau_sq=1e-11, var=1e-10, var_f=1e-10, ratio=1e2),
+    "fp32": dict(tau=1e-4, tau_sq=1e-5, var=1e-3, var_f=1e-3, ratio=1e3),
+    "fp64": dict(tau=1e-10, tau_sq=1e-11, var=1e-10, var_f=1e-10, ratio=1e6),
 }
 
 
