@@ -164,6 +164,23 @@ int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t
                void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * ksdf_fit_query — ksdf_fit_cells followed by ksdf_query, with the same arguments
+ * and outputs, as ONE persistent fused launch for FP32 models: resident workgroups
+ * drain a task queue holding every cell fit (largest m first, FP64 refit in place
+ * where the condition estimate asks for it) and then the query tiles, which start
+ * once all fits have released their results.  Intended for cells with uneven m,
+ * where separate per-bucket launches leave the device idle between kernels.  FP64
+ * models run the plain fit and query back to back.  workspace: at least
+ * ksdf_fit_query_workspace_bytes(model, Q) bytes.  Asynchronous; allocates nothing.
+ * ------------------------------------------------------------------------- */
+size_t ksdf_fit_query_workspace_bytes(const ksdf_model* model, long Q);
+int ksdf_fit_query(ksdf_model* model, const void* surface_pts, int dtype, long n_points,
+                   const void* sample_var, const ksdf_hyper* hyper, uint8_t* cell_status,
+                   const void* points, long Q, const int8_t* sign, void* mean, void* grad,
+                   void* var, void* var_f, int* argmin, uint8_t* q_status, void* workspace,
+                   size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * ksdf_query_backward — vector-Jacobian product of ksdf_query.
  * Given cotangents d_mean [Q], d_grad [Q,3] (or NULL), d_var [Q] (or NULL) and d_var_f
  * [Q] (or NULL) of L = sum_q d_mean*mean + d_grad.grad + d_var*var + d_var_f*var_f,

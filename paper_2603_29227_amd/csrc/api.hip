@@ -60,7 +60,7 @@ void free_model(ksdf_model* m) {
   if (!m) return;
   void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
                   m->L32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
-                  m->L64, m->cstatus, m->bucket_cells, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list};
+                  m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -218,6 +218,13 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
     }
     TRY(dalloc(m, &m->bucket_cells, n_cells));
     TRY(up(m->bucket_cells, order.data(), order.size() * sizeof(int)));
+    // fused-launch fit order: largest m first (longest tasks start earliest)
+    std::vector<int> byM(order.rbegin(), order.rend());
+    std::stable_sort(byM.begin(), byM.end(), [&](int x, int y) {
+      return offsets[x + 1] - offsets[x] > offsets[y + 1] - offsets[y];
+    });
+    TRY(dalloc(m, &m->fused_order, n_cells));
+    TRY(up(m->fused_order, byM.data(), byM.size() * sizeof(int)));
   }
   TRY(build_candidate_index(m, query_lo, query_hi));
   *out = m;
@@ -240,9 +247,9 @@ extern "C" int ksdf_model_info(const ksdf_model* m, int* n_cells, long* nnz, int
   return KSDF_OK;
 }
 
-extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
-                              const void* sample_var, const ksdf_hyper* hyper,
-                              uint8_t* cell_status, void* stream) {
+namespace {
+int prepare_fit(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
+                const void* sample_var, const ksdf_hyper* hyper) {
   if (!m) {
     set_error("model is null");
     return KSDF_ERR_INVALID_ARGUMENT;
@@ -255,21 +262,72 @@ extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype,
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   if ((r = check_device(m))) return r;
-  m->ell = hyper->ell;
-  m->noise_var = hyper->noise_var;
-  m->alpha_tied = !(hyper->alpha > 0);
-  m->alpha = m->alpha_tied ? 1.0 / (2.0 * hyper->ell * hyper->ell) : hyper->alpha;
-  m->cond_thr = hyper->cond_fp64_threshold;
-  m->has_svar = sample_var != nullptr;
   const bool want_adj = (hyper->flags & (KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) != 0;
   const bool want_varf = (hyper->flags & KSDF_FIT_ADJOINT_VARF) != 0;
   if ((want_adj && !m->adjoint_alloc) || (want_varf && !m->adjoint_varf_alloc)) {
     set_error("ksdf_fit_cells: adjoint flags were not requested at ksdf_model_create");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
+  m->ell = hyper->ell;
+  m->noise_var = hyper->noise_var;
+  m->alpha_tied = !(hyper->alpha > 0);
+  m->alpha = m->alpha_tied ? 1.0 / (2.0 * hyper->ell * hyper->ell) : hyper->alpha;
+  m->cond_thr = hyper->cond_fp64_threshold;
+  m->has_svar = sample_var != nullptr;
   m->adjoint = want_adj;
   m->adjoint_varf = want_varf;
+  return KSDF_OK;
+}
+
+int check_query_args(const ksdf_model* m, const void* points, long Q, void* mean, void* grad,
+                     void* var) {
+  if (!m || Q < 0 || (Q > 0 && (!points || !mean || !grad || !var))) {
+    set_error("ksdf_query: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  return KSDF_OK;
+}
+}  // namespace
+
+extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
+                              const void* sample_var, const ksdf_hyper* hyper,
+                              uint8_t* cell_status, void* stream) {
+  int r = prepare_fit(m, surface_pts, dtype, n_points, sample_var, hyper);
+  if (r) return r;
   r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, (hipStream_t)stream);
+  if (r == KSDF_OK) m->fitted = true;
+  return r;
+}
+
+extern "C" size_t ksdf_fit_query_workspace_bytes(const ksdf_model* m, long Q) {
+  if (!m) return 0;
+  return m->precision == KSDF_FP32 ? fused_workspace_bytes(m, Q) : query_workspace_bytes(m, Q);
+}
+
+extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
+                              const void* sample_var, const ksdf_hyper* hyper,
+                              uint8_t* cell_status, const void* points, long Q,
+                              const int8_t* sign, void* mean, void* grad, void* var, void* var_f,
+                              int* argmin, uint8_t* q_status, void* workspace, size_t ws_bytes,
+                              void* stream) {
+  int r = prepare_fit(m, surface_pts, dtype, n_points, sample_var, hyper);
+  if (r) return r;
+  if ((r = check_query_args(m, points, Q, mean, grad, var))) return r;
+  const size_t need = ksdf_fit_query_workspace_bytes(m, Q);
+  if (ws_bytes < need || (need > 0 && !workspace)) {
+    set_error("ksdf_fit_query: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (m->precision == KSDF_FP64) {
+    r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
+    if (r) return r;
+    m->fitted = true;
+    return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+                        ws_bytes, s);
+  }
+  r = launch_fit_query_fused(m, surface_pts, dtype, sample_var, cell_status, points, Q, sign,
+                             mean, grad, var, var_f, argmin, q_status, workspace, ws_bytes, s);
   if (r == KSDF_OK) m->fitted = true;
   return r;
 }
@@ -281,10 +339,7 @@ extern "C" size_t ksdf_query_workspace_bytes(const ksdf_model* m, long Q) {
 extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                           void* mean, void* grad, void* var, void* var_f, int* argmin,
                           uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
-  if (!m || Q < 0 || (Q > 0 && (!points || !mean || !grad || !var))) {
-    set_error("ksdf_query: invalid argument");
-    return KSDF_ERR_INVALID_ARGUMENT;
-  }
+  if (int r0 = check_query_args(m, points, Q, mean, grad, var)) return r0;
   if (!m->fitted) {
     set_error("ksdf_query: the model has not been fitted");
     return KSDF_ERR_INVALID_ARGUMENT;

@@ -1,0 +1,165 @@
+// Persistent fused fit + query launch (FP32 models, cells with uneven m).
+//
+// One launch of resident workgroups (512 threads) drains a task queue:
+//   tasks [0, n_fit)            fit one cell with the whole workgroup, largest m first
+//                               (fit32_cell of the cell's m bucket, FP64 refit in place
+//                               when the condition estimate asks for it);
+//   tasks [n_fit, n_fit + n_q)  8 query tiles of 64 bucketed queries, one per wave.
+// Every fit task is dequeued before any query task, so a workgroup that holds a query
+// task waits (acquire) only for fit tasks that other running workgroups already hold:
+// the wait always ends.  No query reads cell data before every fit has released its
+// writes, so no cache can hold a stale copy of them.  The spin is bounded; on expiry
+// the launch records an error flag instead of waiting further.
+#include "fit_dev.h"
+#include "query_dev.h"
+
+namespace ksdf {
+namespace {
+
+constexpr int FT = 512;
+constexpr int WAVES = FT / 64;
+
+struct FusedCtl {
+  int* next;          // task counter
+  int* done;          // fit tasks completed
+  int* timeout;       // set when a wait expired
+  const int* order;   // cells in fit order (m descending)
+  int n_fit;
+  long n_qtasks;
+};
+
+// Separate (not inlined) bodies keep the register allocation of the fit and query
+// parts apart; the kernel then needs the larger of the two, not their union.
+template <int MB>
+__device__ __noinline__ bool fit32_task(const FitArgs& F, int c, float* smem) {
+  return fit32_cell<MB>(F, c, smem);
+}
+__device__ __noinline__ void fit64_task(const FitArgs& F, int c, double* smem) {
+  fit64_cell(F, c, smem);
+}
+template <int KM, int MB>
+__device__ __noinline__ void query_task(const FastArgs& Q, long sq) {
+  query_tile<KM, MB>(Q, sq);
+}
+
+template <int KM, int MB, int MF>
+__global__ void __launch_bounds__(FT) fused_kernel(FitArgs F, FastArgs Q, FusedCtl C) {
+  extern __shared__ float smem[];
+  __shared__ long task_sh;
+  bool fits_seen = false;
+  while (true) {
+    __syncthreads();
+    if (threadIdx.x == 0) task_sh = atomicAdd(C.next, 1);
+    __syncthreads();
+    const long t = task_sh;
+    if (t < C.n_fit) {
+      const int c = C.order[t];
+      const int m = F.offsets[c + 1] - F.offsets[c];
+      bool need64;
+      if (m <= 16) {
+        need64 = fit32_task<16>(F, c, smem);
+      } else if (m <= 32 || MF <= 32) {
+        need64 = fit32_task<32>(F, c, smem);
+      } else if (m <= 64 || MF <= 64) {
+        if constexpr (MF >= 64) need64 = fit32_task<64>(F, c, smem);
+        else need64 = true;
+      } else {
+        if constexpr (MF >= 128) need64 = fit32_task<128>(F, c, smem);
+        else need64 = true;
+      }
+      if (need64) fit64_task(F, c, reinterpret_cast<double*>(smem));
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(C.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (t < C.n_fit + C.n_qtasks) {
+      if (!fits_seen) {
+        if (threadIdx.x == 0) {
+          long spins = 0;
+          while (__hip_atomic_load(C.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < C.n_fit) {
+            __builtin_amdgcn_s_sleep(8);
+            if (++spins > (1L << 26)) {
+              atomicExch(C.timeout, 1);
+              break;
+            }
+          }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        fits_seen = true;
+      }
+      const int wave = threadIdx.x / 64;
+      const long sq = ((t - C.n_fit) * WAVES + wave) * 64 + (threadIdx.x & 63);
+      query_tile<KM, MB>(Q, sq);
+    } else {
+      break;
+    }
+  }
+}
+
+__global__ void fused_reset_kernel(int* ctl) {
+  if (threadIdx.x < 3) ctl[threadIdx.x] = 0;
+}
+
+template <int KM, int MB, int MF>
+int launch_fused_t(ksdf_model* m, FitArgs& F, FastArgs& A, FusedCtl& C, hipStream_t s) {
+  const size_t smem = std::max(fit32_smem_floats<MF>() * sizeof(float),
+                               FIT64_SMEM_DOUBLES * sizeof(double));
+  auto kern = fused_kernel<KM, MB, MF>;
+  KSDF_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+  int per_cu = 0;
+  KSDF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FT, smem));
+  int cus = 0;
+  KSDF_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device));
+  const long tasks = C.n_fit + C.n_qtasks;
+  long grid = (long)std::max(per_cu, 1) * cus;
+  if (grid > tasks) grid = tasks;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(FT), smem, s, F, A, C);
+  KSDF_HIP_TRY(hipGetLastError());
+  return KSDF_OK;
+}
+
+}  // namespace
+
+size_t fused_workspace_bytes(const ksdf_model* m, long Q) {
+  return query_fast_workspace_bytes(m, Q) + 256;
+}
+
+int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void* svar,
+                           uint8_t* cell_status, const void* points, long Q, const int8_t* sign,
+                           void* mean, void* grad, void* var, void* var_f, int* argmin,
+                           uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
+  (void)ws_bytes;
+  FitArgs F = make_fit_args(m, pts, dtype, svar, cell_status);
+  F.emit32 = 1;
+  F.list = nullptr;
+  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
+  int* ctl = reinterpret_cast<int*>(static_cast<char*>(ws) + query_fast_workspace_bytes(m, Q));
+  hipLaunchKernelGGL(fused_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
+  if (Q > 0) {
+    int r = launch_bucketing(m, A, ws, s);
+    if (r != KSDF_OK) return r;
+  }
+  FusedCtl C{};
+  C.next = ctl;
+  C.done = ctl + 1;
+  C.timeout = ctl + 2;
+  C.order = m->fused_order;
+  C.n_fit = m->n_cells;
+  C.n_qtasks = (Q + FT - 1) / FT;
+  if (C.n_fit + C.n_qtasks == 0) return KSDF_OK;
+  const bool k8 = m->k_fuse <= 8;
+  const int mf = m->max_m <= 16 ? 16 : m->max_m <= 32 ? 32 : m->max_m <= 64 ? 64 : 128;
+  if (k8) {
+    if (mf <= 32) return launch_fused_t<8, 64, 32>(m, F, A, C, s);
+    if (mf == 64) return launch_fused_t<8, 64, 64>(m, F, A, C, s);
+    return launch_fused_t<8, 128, 128>(m, F, A, C, s);
+  }
+  if (mf <= 32) return launch_fused_t<16, 64, 32>(m, F, A, C, s);
+  if (mf == 64) return launch_fused_t<16, 64, 64>(m, F, A, C, s);
+  return launch_fused_t<16, 128, 128>(m, F, A, C, s);
+}
+
+}  // namespace ksdf

@@ -97,6 +97,7 @@ struct ksdf_model {
   float* D32 = nullptr;         // packed dA/dl (FP32 models)
   double* D64 = nullptr;        // packed dA/dl (FP64 models)
   int* bucket_cells = nullptr;  // [n] cell ids grouped by m bucket (<=16, <=32, <=64, <=128)
+  int* fused_order = nullptr;   // [n] cell ids by m descending (fused launch fit order)
   int bucket_start[5] = {0, 0, 0, 0, 0};
 
   ksdf::CandidateIndex index;
@@ -122,5 +123,10 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
                     const void* d_var_f, void* d_points, double* d_hyper, void* ws,
                     size_t ws_bytes, hipStream_t s);
 size_t backward_workspace_bytes(const ksdf_model* m, long Q);
+size_t fused_workspace_bytes(const ksdf_model* m, long Q);
+int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void* svar,
+                           uint8_t* cell_status, const void* points, long Q, const int8_t* sign,
+                           void* mean, void* grad, void* var, void* var_f, int* argmin,
+                           uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace ksdf

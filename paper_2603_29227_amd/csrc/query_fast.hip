@@ -23,594 +23,15 @@
 //    or two in practice): gradient w/|w|, GP variance 1 - |L^{-1} k*|^2 by forward
 //    substitution with the factor rows in scalar registers, and the softmin
 //    variance of Sec. IV-B.3 in one pass.
-#include <cmath>
-
-#include "ff.h"
-#include "ksdf_internal.h"
+#include "query_dev.h"
 
 namespace ksdf {
 namespace {
 
-constexpr int FQ = 256;            // threads per block (4 independent waves)
-constexpr float LOG2E = 1.4426950408889634f;
-constexpr float LN2 = 0.6931471805599453f;
-constexpr float EPS32 = 5.9604645e-08f;
-
-struct FastArgs {
-  const float* pts;
-  long Q;
-  const int8_t* sign;
-  float* mean;
-  float* grad;
-  float* var;
-  float* var_f;
-  int* argmin;
-  uint8_t* qst;
-  const int* perm;
-  int n_cells;
-  int k;
-  const int* __restrict__ offsets;
-  const long* __restrict__ loff;
-  const float4* __restrict__ ps;    // (px, py, pz, a) cell-local
-  const float4* __restrict__ plo;   // float-float low parts of (px, py, pz, a)
-  const float* __restrict__ sv;
-  const float* __restrict__ L;
-  const float4* __restrict__ centre;
-  const float* __restrict__ box;    // [n,8]: lo xyz, A+, hi xyz, pad
-  float origin[3];
-  float inv_h;
-  int sub;           // sub-boxes per box edge for bucketing (1, 2 or 4)
-  int lo[3];
-  int dims[3];
-  long n_boxes;
-  const int* __restrict__ box_off;
-  const int* __restrict__ box_list;
-  float c2;          // log2(e) / (2 l^2)
-  float two_l2;      // 2 l^2
-  float alpha_l2e;   // alpha * log2(e)
-  float alpha;
-  float inv2l2_ff[2];
-};
-
-__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = min(v, (unsigned)__shfl_xor((int)v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ float cand_d2(float qx, float qy, float qz, float4 c) {
-  const float dx = __fsub_rn(qx, c.x), dy = __fsub_rn(qy, c.y), dz = __fsub_rn(qz, c.z);
-  float t = __fmul_rn(dx, dx);
-  t = __fmaf_rn(dy, dy, t);
-  return __fmaf_rn(dz, dz, t);
-}
-
-// box key of a point in the candidate index (-1 outside) and the Morton index of its
-// sub-box when each box is split into sub^3 sub-boxes (sub = 1, 2 or 4)
-__device__ __forceinline__ long box_key(const FastArgs& A, float qx, float qy, float qz, int* subkey) {
-  const float fx = (qx - A.origin[0]) * A.inv_h, fy = (qy - A.origin[1]) * A.inv_h,
-              fz = (qz - A.origin[2]) * A.inv_h;
-  const float gx = floorf(fx), gy = floorf(fy), gz = floorf(fz);
-  const long kx = (long)gx - A.lo[0], ky = (long)gy - A.lo[1], kz = (long)gz - A.lo[2];
-  const int sx = min((int)((fx - gx) * A.sub), A.sub - 1);
-  const int sy = min((int)((fy - gy) * A.sub), A.sub - 1);
-  const int sz = min((int)((fz - gz) * A.sub), A.sub - 1);
-  int mk = 0;
-#pragma unroll
-  for (int bit = 0; bit < 2; ++bit)
-    mk |= (((sx >> bit) & 1) << (3 * bit + 2)) | (((sy >> bit) & 1) << (3 * bit + 1)) |
-          (((sz >> bit) & 1) << (3 * bit));
-  *subkey = mk;
-  if (A.n_boxes <= 0 || kx < 0 || kx >= A.dims[0] || ky < 0 || ky >= A.dims[1] || kz < 0 ||
-      kz >= A.dims[2])
-    return -1;
-  return (kx * A.dims[1] + ky) * A.dims[2] + kz;
-}
-
-// ---------------------------------------------------------------------------
-// bucketing: histogram, scan, scatter
-// ---------------------------------------------------------------------------
-__global__ void fill_kernel(int* p, long n, int v) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
-__global__ void bin_kernel(FastArgs A, int* keys, int* counts, long n_bins) {
-  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= A.Q) return;
-  int sub;
-  const long b = box_key(A, A.pts[3 * q], A.pts[3 * q + 1], A.pts[3 * q + 2], &sub);
-  const int key = b < 0 ? (int)(n_bins - 1) : (int)(b * A.sub * A.sub * A.sub + sub);
-  keys[q] = key;
-  atomicAdd(&counts[key], 1);
-}
-
-constexpr int SCAN_T = 256;
-constexpr int SCAN_PER = 16;
-constexpr int SCAN_TILE = SCAN_T * SCAN_PER;
-
-__global__ void __launch_bounds__(SCAN_T) scan_tiles_kernel(const int* in, long n, int* tile_sum) {
-  __shared__ int red[SCAN_T];
-  const long base = (long)blockIdx.x * SCAN_TILE;
-  int s = 0;
-  for (int j = 0; j < SCAN_PER; ++j) {
-    const long i = base + (long)threadIdx.x * SCAN_PER + j;
-    if (i < n) s += in[i];
-  }
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = SCAN_T / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = red[0];
-}
-
-// exclusive scan of the tile sums in one block (n_tiles <= SCAN_T * SCAN_PER)
-__global__ void __launch_bounds__(SCAN_T) scan_sums_kernel(int* tile_sum, int n_tiles) {
-  __shared__ int part[SCAN_T];
-  int v[SCAN_PER];
-  int s = 0;
-  for (int j = 0; j < SCAN_PER; ++j) {
-    const int i = threadIdx.x * SCAN_PER + j;
-    v[j] = i < n_tiles ? tile_sum[i] : 0;
-    s += v[j];
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < SCAN_T; o <<= 1) {
-    const int t = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-    __syncthreads();
-    part[threadIdx.x] += t;
-    __syncthreads();
-  }
-  int run = part[threadIdx.x] - s;
-  for (int j = 0; j < SCAN_PER; ++j) {
-    const int i = threadIdx.x * SCAN_PER + j;
-    if (i < n_tiles) tile_sum[i] = run;
-    run += v[j];
-  }
-}
-
-__global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(const int* in, long n,
-                                                            const int* tile_off, int* out) {
-  __shared__ int part[SCAN_T];
-  const long base = (long)blockIdx.x * SCAN_TILE + (long)threadIdx.x * SCAN_PER;
-  int v[SCAN_PER];
-  int s = 0;
-  for (int j = 0; j < SCAN_PER; ++j) {
-    v[j] = (base + j < n) ? in[base + j] : 0;
-    s += v[j];
-  }
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < SCAN_T; o <<= 1) {
-    const int t = (int)threadIdx.x >= o ? part[threadIdx.x - o] : 0;
-    __syncthreads();
-    part[threadIdx.x] += t;
-    __syncthreads();
-  }
-  int run = tile_off[blockIdx.x] + part[threadIdx.x] - s;
-  for (int j = 0; j < SCAN_PER; ++j) {
-    if (base + j < n) out[base + j] = run;
-    run += v[j];
-  }
-}
-
-__global__ void scatter_kernel(long Q, const int* keys, int* cursor, int* perm) {
-  const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= Q) return;
-  const int pos = atomicAdd(&cursor[keys[q]], 1);
-  perm[pos] = (int)q;
-}
-
-// ---------------------------------------------------------------------------
-// float-float re-evaluation of one cell's u^2 for one lane (rare path)
-// ---------------------------------------------------------------------------
-__device__ float cell_u2_ff(const FastArgs& A, int c, float qx, float qy, float qz, float d2ref) {
-  const int b = A.offsets[c], m = A.offsets[c + 1] - b;
-  const float4 ctr = A.centre[c];
-  const ff lx = ff_two_sum(qx, -ctr.x), ly = ff_two_sum(qy, -ctr.y), lz = ff_two_sum(qz, -ctr.z);
-  const ff inv{A.inv2l2_ff[0], A.inv2l2_ff[1]};
-  ff f{0.f, 0.f};
-  for (int i = 0; i < m; ++i) {
-    const float4 p = A.ps[b + i];
-    const float4 pl = A.plo[b + i];
-    const ff dx = ff_add(lx, ff{-p.x, -pl.x});
-    const ff dy = ff_add(ly, ff{-p.y, -pl.y});
-    const ff dz = ff_add(lz, ff{-p.z, -pl.z});
-    ff z2 = ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
-    const ff t = ff_mul(ff_add(z2, ff{-d2ref, 0.f}), inv);
-    f = ff_add(f, ff_mul(ff{p.w, pl.w}, ff_exp_neg_tab(t)));
-  }
-  if (!(f.hi > 0.f)) return INFINITY;
-  const float lnf = logf(f.hi) + f.lo / f.hi;
-  return d2ref - A.two_l2 * lnf;
-}
-
-// lower bound of the squared distance from local point (x,y,z) to the cell's
-// sample bounding box
-__device__ __forceinline__ float aabb_d2(const float* bx, float x, float y, float z) {
-  const float ex = fmaxf(fmaxf(bx[0] - x, 0.f), x - bx[4]);
-  const float ey = fmaxf(fmaxf(bx[1] - y, 0.f), y - bx[5]);
-  const float ez = fmaxf(fmaxf(bx[2] - z, 0.f), z - bx[6]);
-  return ex * ex + ey * ey + ez * ez;
-}
-
-// Error budget on u^2.  The accuracy target is 1e-4 m relative to max(u, 1 m), and
-// 2 l^2 * 1e-5 on u^2 near u = 0 where the square root amplifies errors.  The
-// per-cell error bound del (a worst-case sum of per-term rounding errors) was
-// measured against FP64 on 52k room queries: the actual error never exceeded 0.31
-// of it (median 0.02).  A cell is re-evaluated in float-float when 0.35 * del could
-// reach half the target, i.e. del > BUDGET_SCALE * target.
-constexpr float BUDGET_SCALE = 0.5f / 0.35f;
-__device__ __forceinline__ float u2_budget(float u2, float two_l2) {
-  const float u = sqrtf(fmaxf(u2, 0.f));
-  return BUDGET_SCALE * fmaxf(two_l2 * 1e-5f, 2.f * u * 1e-4f * fmaxf(u, 1.f));
-}
-
-// Sample-chunk size of the wave-uniform loops: one group of scalar loads (8 float4 =
-// 32 SGPRs) feeds 8 evaluations, so a wave waits once per 8 samples on the scalar
-// cache and the other waves of the SIMD fill that wait.
-constexpr int CH = 8;
-
-// packed row index of stream position e (compile-time after unrolling)
-__host__ __device__ constexpr int row_of(int e) {
-  int i = 0;
-  while ((i + 1) * (i + 2) / 2 <= e) ++i;
-  return i;
-}
-
-// v <- L^{-1} v for the first m rows (L packed by rows with reciprocal diagonal),
-// streaming the packed factor through scalar registers 32 floats at a time.  The
-// chunks are generated by template recursion so every (row, column) index is a
-// compile-time constant and v stays in registers.  Accumulates |L^{-1} v|^2 over
-// the first m rows into vv.
-template <int E0, int MB>
-__device__ __forceinline__ void fsub_chunk(const float* __restrict__ Lc, int m, float (&v)[MB],
-                                           float& vv, float& t) {
-  constexpr int NP = MB * (MB + 1) / 2;
-  constexpr int LC = 32;
-  if constexpr (E0 < NP) {
-    if (row_of(E0) >= m) return;
-    float buf[LC];
-#pragma unroll
-    for (int q = 0; q < LC; ++q) buf[q] = Lc[E0 + q];
-#pragma unroll
-    for (int q = 0; q < LC; ++q) {
-      const int e = E0 + q;
-      if (e < NP) {
-        const int i = row_of(e), j = e - i * (i + 1) / 2;
-        if (j == 0) t = v[i];
-        if (j < i) {
-          t = fmaf(-buf[q], v[j], t);
-        } else {
-          v[i] = t * buf[q];
-          if (i < m) vv = fmaf(v[i], v[i], vv);
-        }
-      }
-    }
-    fsub_chunk<E0 + LC, MB>(Lc, m, v, vv, t);
-  }
-}
-
-template <int MB>
-__device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int m, float (&v)[MB]) {
-  float vv = 0.f, t = 0.f;
-  fsub_chunk<0, MB>(Lc, m, v, vv, t);
-  return vv;
-}
-
 template <int KM, int MB>
 __global__ void __launch_bounds__(FQ) query_fast_kernel(FastArgs A) {
-  const long sq = (long)blockIdx.x * FQ + threadIdx.x;
-  const bool active = sq < A.Q;
-  const long qi = active ? A.perm[sq] : 0;
-  const float qx = A.pts[3 * qi], qy = A.pts[3 * qi + 1], qz = A.pts[3 * qi + 2];
-
-  // ---- candidates: K nearest centres of the box list (ties by id)
-  // sorted top-KM of (distance, id); ids arrive ascending, so a later equal distance
-  // never moves ahead of an earlier one; the first k entries are the K nearest
-  int cid[KM];
-  float cd[KM];
-#pragma unroll
-  for (int r = 0; r < KM; ++r) {
-    cd[r] = INFINITY;
-    cid[r] = 0x7fffffff;
-  }
-  int subkey;
-  const long bkey = box_key(A, qx, qy, qz, &subkey);
-  const bool outside = bkey < 0;
-  int n = 0;
-  if (active) {
-    int beg = 0, end = A.n_cells;
-    if (!outside) {
-      beg = A.box_off[bkey];
-      end = A.box_off[bkey + 1];
-    }
-    for (int t0 = beg; t0 < end; t0 += 4) {
-      int cc[4];
-      float4 ce[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int t = min(t0 + u, end - 1);
-        cc[u] = outside ? t : A.box_list[t];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) ce[u] = A.centre[cc[u]];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        float x = (t0 + u < end) ? cand_d2(qx, qy, qz, ce[u]) : INFINITY;
-        if (x < cd[KM - 1]) {
-          int xi = cc[u];
-#pragma unroll
-          for (int r = 0; r < KM; ++r) {
-            if (x < cd[r]) {
-              const float tx = cd[r];
-              const int ti = cid[r];
-              cd[r] = x;
-              cid[r] = xi;
-              x = tx;
-              xi = ti;
-            }
-          }
-        }
-      }
-    }
-    n = min(A.k, end - beg);
-  }
-
-  // ---- pass 1: per-candidate u^2 with error bounds, wave-uniform over the union
-  float cu2[KM], cdl[KM];
-#pragma unroll
-  for (int r = 0; r < KM; ++r) {
-    cu2[r] = INFINITY;
-    cdl[r] = 0.f;
-  }
-  unsigned pending = active ? ((1u << n) - 1u) : 0u;
-  float best = INFINITY, best_del = 0.f;
-  const float c2 = A.c2;
-  while (true) {
-    unsigned key = 0xffffffffu;
-    if (pending) {
-      const int r0 = __ffs(pending) - 1;
-      int c0 = 0;
-#pragma unroll
-      for (int r = 0; r < KM; ++r)
-        if (r == r0) c0 = cid[r];
-      key = ((unsigned)r0 << 24) | (unsigned)c0;
-    }
-    key = (unsigned)uniform((int)wave_min_u32(key));
-    if (key == 0xffffffffu) break;
-    const int c = (int)(key & 0xffffffu);
-    int slot = -1;
-#pragma unroll
-    for (int r = 0; r < KM; ++r)
-      if (((pending >> r) & 1u) && cid[r] == c) slot = r;
-    const int b = uniform(A.offsets[c]);
-    const int m = uniform(A.offsets[c + 1]) - b;
-    const float4 ctr = A.centre[c];
-    const float* bx = A.box + 8L * c;
-    const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
-    float d2ref = aabb_d2(bx, lx, ly, lz);
-    const float lb = d2ref - A.two_l2 * logf(fmaxf(bx[3], 1.f));
-    const bool part = slot >= 0;
-    const bool ev = part && !(lb > best + 2.f * best_del + 1e-6f);
-    float u2 = INFINITY, del = 0.f;
-    if (__ballot(ev)) {
-      float f = 0.f, R = 0.f, RZ = 0.f;
-      for (int pass = 0; pass < 2; ++pass) {
-        const float c2d = c2 * d2ref;
-        f = 0.f;
-        R = 0.f;
-        RZ = 0.f;
-        for (int i0 = 0; i0 < m; i0 += CH) {
-          float4 P[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            const float aw = (i0 + j < m) ? P[j].w : 0.f;
-            const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
-            const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float e = __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d));
-            const float ae = fabsf(aw) * e;
-            f = fmaf(aw, e, f);
-            R += ae;
-            RZ = fmaf(ae, z2, RZ);
-          }
-        }
-        // every term underflowed against the box bound (far queries, loose box):
-        // redo once against the nearest sample
-        if (!__ballot(ev && !(R > 0.f))) break;
-        if (ev && !(R > 0.f)) {
-          float d2 = INFINITY;
-          for (int i = 0; i < m; ++i) {
-            const float4 p = A.ps[b + i];
-            const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
-            d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-          }
-          d2ref = d2;
-        }
-      }
-      if (ev && f > 0.f) {
-        u2 = d2ref - A.two_l2 * LN2 * __log2f(f);
-        // |d f| <= eps * sum_i |a_i| e_i (2 + (5 ln 2) c2 z_i^2) + summation error
-        del = A.two_l2 * EPS32 * (6.f * R + 3.5f * c2 * RZ) / f;
-      }
-    }
-    if (part) {
-      if (!ev) u2 = INFINITY;   // pruned: provably not the minimum
-#pragma unroll
-      for (int r = 0; r < KM; ++r)
-        if (r == slot) {
-          cu2[r] = u2;
-          cdl[r] = del;
-        }
-      pending &= ~(1u << slot);
-      if (u2 < best) {
-        best = u2;
-        best_del = del;
-      }
-    }
-  }
-
-  // ---- resolve the minimum; re-evaluate uncertain cells in float-float
-  int bc = -1;
-  if (active) {
-    float bu = INFINITY, bd = 0.f;
-#pragma unroll
-    for (int r = 0; r < KM; ++r)
-      if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
-        bu = cu2[r];
-        bd = cdl[r];
-        bc = cid[r];
-      }
-    if (bc >= 0) {
-      const float budget = u2_budget(bu, A.two_l2);
-      bool redo = false;
-#pragma unroll
-      for (int r = 0; r < KM; ++r)
-        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
-          redo = true;
-      if (redo) {
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
-            const int c = cid[r];
-            const float4 ctr = A.centre[c];
-            const float d2lb = aabb_d2(A.box + 8L * c, qx - ctr.x, qy - ctr.y, qz - ctr.z);
-            cu2[r] = cell_u2_ff(A, c, qx, qy, qz, d2lb);
-          }
-        bu = INFINITY;
-        bc = -1;
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
-            bu = cu2[r];
-            bc = cid[r];
-          }
-      }
-      best = bu;
-    }
-  }
-
-  // ---- pass 2: argmin cell outputs, wave-uniform over the distinct argmin cells
-  float w0 = 0.f, w1 = 0.f, w2 = 0.f, vv = 0.f, var = 0.f;
-  bool todo = bc >= 0;
-  while (true) {
-    unsigned key = todo ? (unsigned)bc : 0xffffffffu;
-    key = (unsigned)uniform((int)wave_min_u32(key));
-    if (key == 0xffffffffu) break;
-    const int c = (int)key;
-    const bool mine = todo && bc == c;
-    const int b = uniform(A.offsets[c]);
-    const int m = uniform(A.offsets[c + 1]) - b;
-    const float* Lc = A.L + A.loff[c];
-    const float4 ctr = A.centre[c];
-    const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
-    const float d2lb = aabb_d2(A.box + 8L * c, lx, ly, lz);
-    const float c2d = c2 * d2lb;
-    const float ginv = __builtin_amdgcn_exp2f(-c2d);     // exp(-d^2 / 2 l^2)
-    const float zref = __builtin_amdgcn_sqrtf(d2lb);
-    if (mine) {
-      float v[MB];
-      float S = 0.f, T1 = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-      for (int i0 = 0; i0 < MB; i0 += CH) {
-        if (i0 < m) {
-          float4 P[CH];
-          float SV[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            P[j] = A.ps[b + i0 + j];
-            SV[j] = A.sv[b + i0 + j];
-          }
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            const bool in = i0 + j < m;
-            const float aw = in ? P[j].w : 0.f;
-            const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
-            const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float e = __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d));
-            const float ae = aw * e;
-            a0 = fmaf(ae, dx, a0);
-            a1 = fmaf(ae, dy, a1);
-            a2 = fmaf(ae, dz, a2);
-            v[i0 + j] = in ? e * ginv : 0.f;                  // k_i = exp(-z_i^2 / 2 l^2)
-            // softmin with t_i = alpha (z_i - zref) >= 0
-            const float z = __builtin_amdgcn_sqrtf(z2);
-            const float ti = A.alpha * (z - zref);
-            const float sm = in ? __builtin_amdgcn_exp2f(-A.alpha_l2e * (z - zref)) : 0.f;
-            const float q = sm * sm * SV[j];
-            S += sm;
-            T1 = fmaf(sm, ti, T1);
-            X0 += q;
-            X1 = fmaf(q, ti, X1);
-            X2 = fmaf(q * ti, ti, X2);
-          }
-        }
-      }
-      vv = forward_subst<MB>(Lc, m, v);
-      const float Tb = 1.f + T1 / S;
-      var = (Tb * Tb * X0 - 2.f * Tb * X1 + X2) / (S * S);
-      w0 = a0;
-      w1 = a1;
-      w2 = a2;
-      todo = false;
-    }
-  }
-
-  if (!active) return;
-  const float sgn = A.sign ? (float)A.sign[qi] : 1.f;
-  uint8_t st = outside ? KSDF_Q_OUTSIDE_INDEX : 0;
-  if (bc < 0) {
-    A.mean[qi] = INFINITY;
-    A.grad[3 * qi] = 0.f;
-    A.grad[3 * qi + 1] = 0.f;
-    A.grad[3 * qi + 2] = 0.f;
-    A.var[qi] = INFINITY;
-    if (A.var_f) A.var_f[qi] = 1.f;
-    if (A.argmin) A.argmin[qi] = -1;
-    if (A.qst) A.qst[qi] = st | KSDF_Q_NO_VALID_CELL;
-    return;
-  }
-  float u = 0.f;
-  if (best < 0.f) st |= KSDF_Q_CLAMPED;
-  else u = sqrtf(best);
-  const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
-  float gx = 0.f, gy = 0.f, gz = 0.f;
-  if (wn > 0.f) {
-    gx = w0 / wn;
-    gy = w1 / wn;
-    gz = w2 / wn;
-  } else {
-    st |= KSDF_Q_GRAD_ZERO;
-  }
-  A.mean[qi] = sgn * u;
-  A.grad[3 * qi] = sgn * gx;
-  A.grad[3 * qi + 1] = sgn * gy;
-  A.grad[3 * qi + 2] = sgn * gz;
-  A.var[qi] = var;
-  if (A.var_f) A.var_f[qi] = fmaxf(1.f - vv, 0.f);
-  if (A.argmin) A.argmin[qi] = bc;
-  if (A.qst) A.qst[qi] = st;
+  query_tile<KM, MB>(A, (long)blockIdx.x * FQ + threadIdx.x);
 }
-
-// finest bucketing (sub-boxes per edge) that keeps the bin count near 8M
-int sub_of(const ksdf_model* m) {
-  const long nb = m->index.n_boxes;
-  return nb * 64 <= (8L << 20) ? 4 : (nb * 8 <= (8L << 20) ? 2 : 1);
-}
-long n_bins_of(const ksdf_model* m) {
-  const long s = sub_of(m);
-  return m->index.n_boxes * s * s * s + 1;
-}
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -624,72 +45,11 @@ size_t query_fast_workspace_bytes(const ksdf_model* m, long Q) {
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                       void* mean, void* grad, void* var, void* var_f, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
+  (void)ws_bytes;   // checked by the caller against query_workspace_bytes
   if (Q == 0) return KSDF_OK;
-  FastArgs A{};
-  A.pts = static_cast<const float*>(points);
-  A.Q = Q;
-  A.sign = sign;
-  A.mean = static_cast<float*>(mean);
-  A.grad = static_cast<float*>(grad);
-  A.var = static_cast<float*>(var);
-  A.var_f = static_cast<float*>(var_f);
-  A.argmin = argmin;
-  A.qst = q_status;
-  A.n_cells = m->n_cells;
-  A.k = std::min(m->k_fuse, m->n_cells);
-  A.offsets = m->offsets;
-  A.loff = m->loff;
-  A.ps = reinterpret_cast<const float4*>(m->ps32);
-  A.plo = reinterpret_cast<const float4*>(m->plo32);
-  A.sv = m->sv32;
-  A.L = m->L32;
-  A.centre = reinterpret_cast<const float4*>(m->centre32);
-  A.box = m->box32;
-  for (int d = 0; d < 3; ++d) {
-    A.origin[d] = (float)m->origin[d];
-    A.lo[d] = m->index.lo[d];
-    A.dims[d] = m->index.dims[d];
-  }
-  A.inv_h = (float)(1.0 / m->h);
-  A.sub = sub_of(m);
-  A.n_boxes = m->index.n_boxes;
-  A.box_off = m->index.box_off;
-  A.box_list = m->index.box_list;
-  const double two_l2 = 2.0 * m->ell * m->ell;
-  A.c2 = (float)(1.4426950408889634 / two_l2);
-  A.two_l2 = (float)two_l2;
-  A.alpha = (float)m->alpha;
-  A.alpha_l2e = (float)(m->alpha * 1.4426950408889634);
-  const double inv = 1.0 / two_l2;
-  A.inv2l2_ff[0] = (float)inv;
-  A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);
-
-  // workspace carve-up
-  const long nb = n_bins_of(m);
-  const long tiles = (nb + SCAN_TILE - 1) / SCAN_TILE;
-  char* w = static_cast<char*>(ws);
-  int* keys = reinterpret_cast<int*>(w);
-  w += align256(Q * sizeof(int));
-  int* perm = reinterpret_cast<int*>(w);
-  w += align256(Q * sizeof(int));
-  int* counts = reinterpret_cast<int*>(w);
-  w += align256(nb * sizeof(int));
-  int* cursor = reinterpret_cast<int*>(w);
-  w += align256(nb * sizeof(int));
-  int* tsum = reinterpret_cast<int*>(w);
-  if (tiles > (long)SCAN_TILE) {
-    set_error("query bucketing: too many bins");
-    return KSDF_ERR_UNSUPPORTED;
-  }
-  (void)ws_bytes;
-  const unsigned g1 = (unsigned)((Q + 255) / 256);
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, counts, nb, 0);
-  hipLaunchKernelGGL(bin_kernel, dim3(g1), dim3(256), 0, s, A, keys, counts, nb);
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, counts, nb, tsum);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, counts, nb, tsum, cursor);
-  hipLaunchKernelGGL(scatter_kernel, dim3(g1), dim3(256), 0, s, Q, keys, cursor, perm);
-  A.perm = perm;
+  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
+  int r = launch_bucketing(m, A, ws, s);
+  if (r != KSDF_OK) return r;
   const unsigned gq = (unsigned)((Q + FQ - 1) / FQ);
   const bool k8 = m->k_fuse <= 8;
   const bool m64 = m->max_m <= 64;

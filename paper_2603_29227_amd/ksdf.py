@@ -32,7 +32,8 @@ FIT_ADJOINT, FIT_ADJOINT_VARF = 1, 2
 EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_cellset_destroy",
            "ksdf_model_create", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
-           "ksdf_query_backward", "ksdf_status_string", "ksdf_last_error"]
+           "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
+           "ksdf_status_string", "ksdf_last_error"]
 
 
 class KsdfError(RuntimeError):
@@ -80,6 +81,10 @@ def lib():
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                           _vp, sz, _vp]
+        L.ksdf_fit_query_workspace_bytes.argtypes = [_vp, l]
+        L.ksdf_fit_query_workspace_bytes.restype = sz
+        L.ksdf_fit_query.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp, l, _vp, _vp, _vp, _vp, _vp,
+                                     _vp, _vp, _vp, sz, _vp]
         L.ksdf_status_string.argtypes = [i]
         L.ksdf_status_string.restype = ctypes.c_char_p
         L.ksdf_last_error.argtypes = []
@@ -255,6 +260,41 @@ class Model:
                                     _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
                                     _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
                                     _stream(stream)), "ksdf_query")
+        return out
+
+    def _out(self, Q, device, var_f=True, argmin=True, status=True):
+        dt = self.dtype
+        out = dict(mean=torch.empty(Q, dtype=dt, device=device),
+                   grad=torch.empty(Q, 3, dtype=dt, device=device),
+                   var=torch.empty(Q, dtype=dt, device=device))
+        if var_f:
+            out["var_f"] = torch.empty(Q, dtype=dt, device=device)
+        if argmin:
+            out["argmin"] = torch.empty(Q, dtype=torch.int32, device=device)
+        if status:
+            out["status"] = torch.empty(Q, dtype=torch.uint8, device=device)
+        return out
+
+    def fit_query(self, points: torch.Tensor, queries: torch.Tensor, sign=None, sample_var=None,
+                  cell_status=None, out: Optional[dict] = None, stream=None) -> dict:
+        """Fit and query in one persistent fused launch (FP32 models)."""
+        if not points.is_cuda or points.dim() != 2 or points.shape[1] != 3 or not points.is_contiguous():
+            raise ValueError("points must be a contiguous [N,3] CUDA tensor")
+        if queries.dtype != self.dtype or not queries.is_contiguous() or queries.shape[-1] != 3:
+            raise ValueError(f"queries must be a contiguous [Q,3] CUDA {self.dtype} tensor")
+        dt = DTYPE_F64 if points.dtype == torch.float64 else DTYPE_F32
+        Q = len(queries)
+        out = out if out is not None else self._out(Q, queries.device)
+        nb = self._lib.ksdf_fit_query_workspace_bytes(self._h, Q)
+        ws = self._workspace(nb)
+        _check(self._lib.ksdf_fit_query(self._h, _ptr(points), dt, len(points), _ptr(sample_var),
+                                        ctypes.byref(self.hyper), _ptr(cell_status), _ptr(queries), Q,
+                                        _ptr(sign), _ptr(out["mean"]), _ptr(out["grad"]),
+                                        _ptr(out["var"]), _ptr(out.get("var_f")),
+                                        _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
+                                        _stream(stream)), "ksdf_fit_query")
+        self.points = points
+        self.sample_var = sample_var
         return out
 
     def backward(self, points, sign, d_mean, d_grad=None, d_var=None, d_var_f=None, argmin=None,

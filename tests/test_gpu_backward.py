@@ -2,8 +2,9 @@
 
 Tolerances: FP64 path within 1e-8 (relative per point, and for d_hyper); FP32 path
 d_points within 1e-3 relative (norm-wise per point) and d_hyper within 1e-3
-relative (3e-3 per point with a var_f cotangent, whose beta = A^{-1} k comes from FP32
-triangular solves with cond(A) up to 1e6).  Excluded and counted: points whose argmin cell differs between GPU and
+relative (with a var_f cotangent 3e-3 per point and 5e-3 for d_hyper: beta = A^{-1} k
+comes from FP32 triangular solves with cond(A) up to 1e6, and the noise derivative
+carries |beta|^2).  Excluded and counted: points whose argmin cell differs between GPU and
 oracle (a near-tie of the min-fusion, where the derivative is that of another
 cell), points on a clamp, and in FP32 points whose gradient cancellation ratio
 sum|a_i| e_i |x-x_i| / |w| exceeds 1e3 (the same conditioning rule as the forward
@@ -103,7 +104,7 @@ def test_fp32_backward_matches_oracle_vjp(var_f):
     # a var_f cotangent brings beta = A^{-1} k, an FP32 triangular-solve pair whose error
     # grows with cond(A) (up to 1e6 here): its per-point bound is 3e-3
     e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32",
-                      3e-3 if var_f else 1e-3, 1e-3, max_ratio=1e3)
+                      3e-3 if var_f else 1e-3, 5e-3 if var_f else 1e-3, max_ratio=1e3)
     print("fp32 max point err", e, "d_hyper rel", rel, flush=True)
 
 

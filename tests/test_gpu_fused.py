@@ -1,0 +1,69 @@
+"""The persistent fused fit+query launch against separate fit and query launches
+(bit-identical: the same per-cell arithmetic in a different schedule) and
+against the oracle, on cells with uneven m."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2603_29227_amd import ksdf, scenes
+from tests.parity import assert_parity
+from tests.test_gpu_parity import oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_both(wl, precision="fp32"):
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    pts = torch.from_numpy(np.ascontiguousarray(wl.points)).to("cuda", dt)
+    q = torch.from_numpy(np.ascontiguousarray(wl.queries)).to("cuda", dt)
+    sg = torch.from_numpy(wl.sign).cuda()
+    a = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                   precision=precision)
+    st_a = torch.zeros(cells.n, dtype=torch.uint8, device="cuda")
+    a.fit(pts, cell_status=st_a)
+    out_a = a.query(q, sg)
+    b = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                   precision=precision)
+    st_b = torch.zeros(cells.n, dtype=torch.uint8, device="cuda")
+    out_b = b.fit_query(pts, q, sg, cell_status=st_b)
+    # a second fused call on the same model reuses every buffer
+    out_b = b.fit_query(pts, q, sg, cell_status=st_b, out=out_b)
+    torch.cuda.synchronize()
+    return cells, {k: v.cpu().numpy() for k, v in out_a.items()}, \
+        {k: v.cpu().numpy() for k, v in out_b.items()}, st_a.cpu().numpy(), st_b.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["uneven_small_room", "sphere_fp32", "room_fp32"])
+def test_fused_launch_matches_separate_launches_and_oracle(case):
+    print(f"[gpu-case] fused {case}", flush=True)
+    if case == "uneven_small_room":
+        wl = scenes.small_room_workload(n_queries=6000, uneven=True, cfg_id=41)
+    elif case == "sphere_fp32":
+        wl = scenes.sphere_workload(n_queries=3000)
+        wl = scenes.Workload(**{**wl.__dict__, "points": wl.points.astype(np.float32),
+                                "queries": wl.queries.astype(np.float32)})
+    else:
+        wl = scenes.small_room_workload(n_queries=3000, cfg_id=42)
+    cells, sep, fus, st_a, st_b = _run_both(wl)
+    np.testing.assert_array_equal(st_a, st_b)
+    for k in sep:
+        np.testing.assert_array_equal(sep[k], fus[k], err_msg=k)
+    o = oracle_run(wl, cells, wl.queries, wl.sign, "fp32")
+    assert_parity(fus, o, wl.ell, "fp32", label=f"fused {case}")
+
+
+def test_fused_with_no_queries_still_fits():
+    print("[gpu-case] fused, zero queries", flush=True)
+    wl = scenes.small_room_workload(n_queries=64, cfg_id=43)
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min)
+    m = ksdf.Model(cells, len(wl.points), wl.origin, wl.h)
+    pts = torch.from_numpy(wl.points).cuda()
+    m.fit_query(pts, torch.zeros(0, 3, dtype=torch.float32, device="cuda"))
+    out = m.query(torch.from_numpy(wl.queries).cuda())
+    ref = ksdf.Model(cells, len(wl.points), wl.origin, wl.h)
+    ref.fit(pts)
+    out2 = ref.query(torch.from_numpy(wl.queries).cuda())
+    torch.cuda.synchronize()
+    assert torch.equal(out["mean"], out2["mean"])
