@@ -1,19 +1,24 @@
 """Benchmark: batched local-GP SDF regression on one MI355X.
 
-One step is one pass of the whole hot path over the indoor-room workload:
-  fit      every cell of the room (FP32 with FP64 refit of ill-conditioned cells),
-  query    mean + gradient + softmin variance + GP variance at the 256^3 grid
-           (16,777,216 points),
-  backward collision-cost VJP at 4,096 trajectories x 64 waypoints (262,144 points)
-           to the points and to (length-scale, noise), when the adjoint is built.
-Inputs are generated once, seeded, and resident in HBM before timing.  The plain
-per-cell FP64 path (one block per cell, one thread per query) is timed on the
-same inputs as the comparison leg, and the FP64 CPU oracle on a bounded sample as
-the CPU baseline.  Prints one JSON line.
+One step is one pass of the whole hot path over the indoor-room workload
+(10 x 8 x 3 m room, 20 boxes + 10 cylinders, 2 cm sampling, 0.25 m cells, m <= 64):
+  fit + query  every cell fitted (FP32, FP64 refit of ill-conditioned cells, adjoint
+               vectors for the backward) and mean + gradient + softmin variance + GP
+               variance + sign at the 256^3 grid (16,777,216 points), in the fused
+               persistent launch or as separate launches, as the autotuner picked;
+  backward     the collision cost sum softplus(0.3 - d + sqrt(var)) over 4,096
+               trajectories x 64 waypoints (262,144 points): forward query, cost
+               cotangents, adjoint to the waypoints and to (length-scale, noise).
+Inputs are generated once, seeded, and resident in HBM before timing.  value = query
+points of one step (grid + trajectory) / step time.  Kernel durations come from HIP
+events the library records around each phase's kernel on its launch stream.  The
+plain per-cell FP64 GPU path is timed on the same inputs as the comparison leg, and
+the FP64 CPU oracle on a bounded sample as the CPU baseline.  Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,13 +29,82 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector (packed) peak
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 vector peak (published, packed issue)
 PEAK_VALU_TSLOTS = 39.32      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instructions/s
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_room_grid.txt")
+KERNEL_SOURCES = {
+    "query_fast": ["query_fast.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
+    "fused": ["fused.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
+}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2603_29227_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE per dispatch, each scaled by the same counter's reading on a plain copy of
+    known size); None when there is none or the kernel's sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel") != kernel or kv.get("source_hash") != source_hash(kernel):
+        return None
+    try:
+        fetch = float(kv["fetch_kib_per_dispatch"]) * 1024 * float(kv["copy_scale_fetch"])
+        write = float(kv["write_kib_per_dispatch"]) * 1024 * float(kv["copy_scale_write"])
+    except (KeyError, ValueError):
+        return None
+    return fetch + write
+
+
+def copy_calibration(torch, dev):
+    """A plain copy of 1 GiB, launched 3 times, for scaling the HBM byte counters."""
+    x = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log("copy calibration: 3 x copy of 1073741824 bytes (read 1 GiB, write 1 GiB)")
+    del x, y
+
+
+def query_flops(m_mean: float, k: int) -> tuple[float, float]:
+    """Algorithmic work of one forward query (independent of the kernel): per sample of
+    each of the K candidate cells z^2 (3 sub + 3 FMA: 9 flop), the exponent (2), exp (1),
+    a e accumulation (2); at the chosen cell gradient (6 per sample), sqrt (1), softmin
+    variance (8), forward substitution for the GP variance (m^2) and the recomputed k*
+    (14 per sample).  Returns (flop, transcendental count)."""
+    m = m_mean
+    return 14 * k * m + 30 * m + m * m, (k + 2) * m + m
+
+
+def backward_flops(m_mean: float) -> float:
+    """One VJP point at its argmin cell: recompute k* (14 m), gradient and its Jacobian
+    (20 m), the variance adjoint by a forward and a backward substitution (2 m^2), the
+    hyperparameter terms (6 m)."""
+    m = m_mean
+    return 40 * m + 2 * m * m
+
+
+def fit_flops(m: np.ndarray) -> float:
+    """Per cell: assembly of the lower triangle (5 m^2), Cholesky (m^3 / 3), the two
+    triangular solves for a (2 m^2)."""
+    m = m.astype(np.float64)
+    return float(np.sum(m ** 3 / 3 + 7 * m * m))
 
 
 def main():
@@ -39,134 +113,232 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--grid", type=int, default=256)
-    ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-queries", type=int, default=16384)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 GPU leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-tune", action="store_true", help="use the cached tuning, do not time")
+    ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="also run a plain 1 GiB copy (scale for the HBM byte counters)")
+    ap.add_argument("--cpu-queries", type=int, default=1 << 20)
+    ap.add_argument("--cpu-vjp", type=int, default=1 << 16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU sharding is described, not built)"}))
+                                   "(the multi-GPU sharding is described, not built)"}), flush=True)
         sys.exit(2)
 
     import torch
-    from paper_2603_29227_amd import ksdf, scenes
+    from paper_2603_29227_amd import ksdf, scenes, tune
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     t0 = time.time()
     wl = scenes.room_workload("grid", grid_n=args.grid)
-    log(f"room workload: {len(wl.points)} samples, {len(wl.queries)} queries ({time.time() - t0:.1f}s)")
+    tq_np, tsg_np = scenes.room_trajectories(wl)
+    log(f"room workload: {len(wl.points)} samples, {len(wl.queries)} grid queries, "
+        f"{len(tq_np)} trajectory points ({time.time() - t0:.1f}s)")
     cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
                              wl.m_cap_grid, wl.key_lo)
     m = cells.m
     log(f"cells: {cells.n}, m mean {m.mean():.1f}, max {m.max()}")
     qbox = (np.zeros(3), np.array([10.0, 8.0, 3.0]))
     model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
-                       precision="fp32", query_box=qbox)
+                       precision="fp32", query_box=qbox, adjoint=True)
     info = model.info()
     pts = torch.from_numpy(wl.points).to(dev)
     q = torch.from_numpy(wl.queries).to(dev)
     sg = torch.from_numpy(wl.sign).to(dev)
-    Q = len(q)
+    tq = torch.from_numpy(tq_np).to(dev)
+    tsg = torch.from_numpy(tsg_np).to(dev)
+    Q, QT = len(q), len(tq)
+
+    if args.no_tune:
+        tuning = tune.apply(model, Q)
+        tuned = {"source": "cache" if tuning else "default", "tuning": model.tuning()}
+    else:
+        t1 = time.time()
+        res = tune.tune(model, pts, q, sg, reps=2, cache_path=None)
+        tuned = {"source": "timed", "tuning": res["tuning"], "ms": res["ms"],
+                 "candidates": len(res["table"]), "seconds": round(time.time() - t1, 1)}
+        log(f"autotuner: {res['tuning']} {res['ms']:.3f} ms ({len(res['table'])} candidates)")
+    fused = model.tuning()["fused"] == 1
+
+    out = model._out(Q, dev)
+    tout = model._out(QT, dev, status=False)
+    d_mean = torch.empty(QT, dtype=torch.float32, device=dev)
+    d_var = torch.empty(QT, dtype=torch.float32, device=dev)
     cst = torch.zeros(cells.n, dtype=torch.uint8, device=dev)
-    out = None
-    stream = torch.cuda.current_stream()
+    grads = {}
 
     def step():
-        nonlocal out
-        model.fit(pts, cell_status=cst)
-        out = model.query(q, sg, argmin=True, status=True, out=out)
+        model.fit_query(pts, q, sg, cell_status=cst, out=out)
+        model.query(tq, tsg, out=tout)
+        # cost c = sum softplus(0.3 - d + sqrt(var)): dc/dd = -sigmoid(t), dc/dvar = sigmoid(t) / (2 sqrt(var))
+        sd = torch.sqrt(torch.clamp_min(tout["var"], 1e-30))
+        s = torch.sigmoid(0.3 - tout["mean"] + sd)
+        torch.neg(s, out=d_mean)
+        torch.div(s, 2 * sd, out=d_var)
+        grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
+                                                         argmin=tout["argmin"])
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: K whole steps
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    fit_ms, qry_ms = [], []
+    if args.copy_calib:
+        copy_calibration(torch, dev)
+
+    # timed region: K whole steps; the library's events time each phase's kernel
+    model.set_timing(True)
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    step_ms, fwd_ms = [], []
+    kern = {"fused": [], "fit": [], "query": [], "query_traj": [], "backward": []}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for _ in range(args.steps):
         ev[0].record(stream)
-        model.fit(pts, cell_status=cst)
+        model.fit_query(pts, q, sg, cell_status=cst, out=out)
         ev[1].record(stream)
-        out = model.query(q, sg, argmin=True, status=True, out=out)
+        model.query(tq, tsg, out=tout)
+        sd = torch.sqrt(torch.clamp_min(tout["var"], 1e-30))
+        s = torch.sigmoid(0.3 - tout["mean"] + sd)
+        torch.neg(s, out=d_mean)
+        torch.div(s, 2 * sd, out=d_var)
+        grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
+                                                         argmin=tout["argmin"])
         ev[2].record(stream)
-        torch.cuda.synchronize()
-        fit_ms.append(ev[0].elapsed_time(ev[1]))
-        qry_ms.append(ev[1].elapsed_time(ev[2]))
+        ev[2].synchronize()
+        step_ms.append(ev[0].elapsed_time(ev[2]))
+        fwd_ms.append(ev[0].elapsed_time(ev[1]))
+        for k in ["fused"] if fused else ["fit"]:
+            kern[k] += model.timer_read(k)
+        qt = model.timer_read("query")   # grid (when not fused), then trajectory
+        if not fused:
+            kern["query"].append(qt[0])
+        kern["query_traj"].append(qt[-1])
+        kern["backward"] += model.timer_read("backward")
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t_start) / args.steps * 1e3
-    fit_med, qry_med = float(np.median(fit_ms)), float(np.median(qry_ms))
-    step_ms = fit_med + qry_med
+    model.set_timing(False)
+    step_avg = float(np.mean(step_ms))
+    kavg = {k: float(np.mean(v)) for k, v in kern.items() if v}
     n_fp64 = int(((cst.cpu().numpy() & ksdf.C_FP64) != 0).sum())
     st = out["status"].cpu().numpy()
-    log(f"fit {fit_med:.3f} ms, query {qry_med:.3f} ms, wall/step {wall:.3f} ms, fp64 cells {n_fp64}")
+    log(f"step {step_avg:.3f} ms (wall {wall:.3f}), grid fit+query {np.mean(fwd_ms):.3f} ms, "
+        f"kernels {kavg}, fp64 cells {n_fp64}")
 
-    # algorithmic work of the query (per the method, independent of the kernel):
-    # per candidate sample: z^2 (3 sub + 3 FMA = 9 flop), exponent (2), exp (1), a*e acc (2)
-    # per argmin sample: recompute (14) + gradient (6) + sqrt (1) + softmin (8) + forward
-    # substitution row (2 per entry, m^2 total) ; transcendentals: (K+2) m exps + m sqrt.
-    mm = float(m.mean())
-    k = 8
-    flops_q = 14 * k * mm + 30 * mm + mm * mm
-    trans_q = (k + 2) * mm + mm
-    flops = flops_q * Q
-    achieved_tflops = flops / (qry_med * 1e-3) / 1e12
-    slots = (flops_q / 2 + trans_q * 4) * Q   # FMA-slot equivalents, transcendental = 4 slots
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "kernel": "query_fwd",
-                "issue_frac": round(slots / (qry_med * 1e-3) / (PEAK_VALU_TSLOTS * 1e12), 4)}
+    # graph-replayed step (same work, launches captured once)
+    graph = None
+    if not args.no_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            g.replay()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        graph = round(e0.elapsed_time(e1) / args.steps, 4)
+        log(f"graph replay: {graph:.3f} ms/step")
+        del g
+
+    # roofline of the dominant kernel (algorithmic flops over its measured duration)
+    k_fuse = int(model.hyper.k_fuse)
+    fq, tr = query_flops(float(m.mean()), k_fuse)
+    if fused:
+        dom, dom_ms, flops = "fused", kavg["fused"], fq * Q + fit_flops(m)
+    else:
+        dom, dom_ms, flops = "query_fast", kavg["query"], fq * Q
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    slots = (fq / 2 + tr * 4) * Q   # FMA-slot equivalents; a transcendental takes 4 slots
+    traffic = measured_traffic(dom)
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "kernel": dom, "kernel_ms": round(dom_ms, 4), "flop_per_launch": round(flops),
+                "issue_frac": round(slots / (kavg["query" if not fused else "fused"] * 1e-3)
+                                    / (PEAK_VALU_TSLOTS * 1e12), 4)}
+    bflops = backward_flops(float(m.mean())) * QT
+    roof_bwd = {"kernel": "bwd_wave", "kernel_ms": round(kavg["backward"], 4),
+                "achieved": round(bflops / (kavg["backward"] * 1e-3) / 1e12, 3),
+                "frac": round(bflops / (kavg["backward"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
 
     result = {
         "metric": "SDF queries/s (mean+grad+var) + backward queries/s vs plain path, at tolerance",
-        "value": round(Q / (step_ms * 1e-3), 1),
+        "value": round((Q + QT) / (step_avg * 1e-3), 1),
         "unit": "queries/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(step_ms, 4),
+        "ms_per_step": round(step_avg, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"indoor room 10x8x3 m, 20 boxes + 10 cylinders, 2 cm spacing, "
-                               f"{len(wl.points)} samples, {cells.n} cells (h 0.25 m, m<=64), "
-                               f"{args.grid}^3 query grid", "queries": Q, "k_fuse": k,
-                   "ell": wl.ell, "noise_var": wl.noise_var},
-        "fit_ms": round(fit_med, 4), "query_ms": round(qry_med, 4),
-        "query_only_qps": round(Q / (qry_med * 1e-3), 1),
+        "config": {"workload": f"indoor room 10x8x3 m, 20 boxes + 10 cylinders, 2 cm sampling, "
+                               f"{len(wl.points)} samples, {cells.n} cells (h 0.25 m, m<=64); "
+                               f"{args.grid}^3 grid queries + backward of the softplus collision "
+                               f"cost at 4096 x 64 trajectory points", "grid_queries": Q,
+                   "trajectory_points": QT, "k_fuse": k_fuse, "ell": wl.ell,
+                   "noise_var": wl.noise_var, "tuning": tuned},
+        "fwd_qps": round(Q / (np.mean(fwd_ms) * 1e-3), 1),
+        "bwd_qps": round(QT / ((step_avg - np.mean(fwd_ms)) * 1e-3), 1),
+        "kernel_ms": {k: round(v, 4) for k, v in kavg.items()},
+        "graph_ms_per_step": graph,
         "fp64_cells": n_fp64, "no_valid_queries": int(((st & 1) != 0).sum()),
         "model_device_bytes": info["device_bytes"],
-        "roofline": roofline,
+        "roofline": roofline, "roofline_backward": roof_bwd,
     }
 
     if not args.no_plain:
+        # the plain per-cell FP64 GPU path: one thread per query, every candidate cell in
+        # FP64, the plain backward; same inputs
         plain = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell,
-                           noise_var=wl.noise_var, precision="fp64", query_box=qbox)
-        p64 = pts.double()
-        q64 = q.double()
-        pout = None
-        for _ in range(1):
+                           noise_var=wl.noise_var, precision="fp64", query_box=qbox, adjoint=True)
+        p64, q64, tq64 = pts.double(), q.double(), tq.double()
+        pout = plain._out(Q, dev)
+        ptout = plain._out(QT, dev, status=False)
+        dm64, dv64 = d_mean.double(), d_var.double()
+
+        def plain_step(ev=None):
+            if ev:
+                ev[0].record(stream)
             plain.fit(p64)
-            pout = plain.query(q64, sg, out=pout)
+            plain.query(q64, sg, out=pout)
+            if ev:
+                ev[1].record(stream)
+            plain.query(tq64, tsg, out=ptout)
+            plain.backward(tq64, tsg, dm64, None, dv64, None, argmin=ptout["argmin"])
+            if ev:
+                ev[2].record(stream)
+
+        plain_step()
         torch.cuda.synchronize()
-        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        plain.fit(p64)
-        e1.record(stream)
-        pout = plain.query(q64, sg, out=pout)
-        e2.record(stream)
+        pe = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        plain_step(pe)
         torch.cuda.synchronize()
-        pf, pq = e0.elapsed_time(e1), e1.elapsed_time(e2)
-        result["plain_fp64"] = {"fit_ms": round(pf, 3), "query_ms": round(pq, 3),
-                                "qps": round(Q / ((pf + pq) * 1e-3), 1),
-                                "speedup_step": round((pf + pq) / step_ms, 2),
-                                "speedup_query": round(pq / qry_med, 2)}
-        log(f"plain fp64: fit {pf:.3f} ms, query {pq:.3f} ms")
+        pf, pb = pe[0].elapsed_time(pe[1]), pe[1].elapsed_time(pe[2])
+        ours_b = step_avg - float(np.mean(fwd_ms))
+        result["plain_fp64"] = {"fit_query_ms": round(pf, 3), "traj_query_backward_ms": round(pb, 3),
+                                "step_ms": round(pf + pb, 3),
+                                "value": round((Q + QT) / ((pf + pb) * 1e-3), 1),
+                                "speedup_step": round((pf + pb) / step_avg, 2),
+                                "speedup_grid_fit_query": round(pf / float(np.mean(fwd_ms)), 2),
+                                "speedup_trajectory_query_backward": round(pb / ours_b, 2)}
+        log(f"plain fp64: grid fit+query {pf:.3f} ms, trajectory query+backward {pb:.3f} ms")
         plain.close()
 
     if not args.no_cpu:
         import oracle
-        nthreads = os.cpu_count() or 1
+        nthreads = oracle.threads()
         rng = np.random.default_rng(0)
         sel = np.sort(rng.choice(Q, size=min(args.cpu_queries, Q), replace=False))
+        tsel = np.sort(rng.choice(QT, size=min(args.cpu_vjp, QT), replace=False))
         oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
                           np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
         t1 = time.perf_counter()
@@ -175,14 +347,30 @@ def main():
         oracle.query(wl.points, oc, f, wl.queries[sel], wl.ell, wl.noise_var, cand_prec=32,
                      sign=wl.sign[sel])
         t3 = time.perf_counter()
-        per_q = (t3 - t2) / len(sel)
-        cpu_qps = 1.0 / ((t2 - t1) / Q + per_q)
-        result["cpu_baseline"] = {"value": round(cpu_qps, 1), "unit": "queries/s", "cores": nthreads,
-                                  "kind": "oracle",
-                                  "sample": f"full FP64 fit ({cells.n} cells, {t2 - t1:.2f} s) + "
-                                            f"{len(sel)} seeded grid queries ({t3 - t2:.2f} s); "
-                                            f"rate = Q / (fit + Q * per-query time)"}
-        log(f"cpu oracle: fit {t2 - t1:.2f}s, {len(sel)} queries {t3 - t2:.2f}s")
+        # the VJP refits every cell with dual numbers (its hyperparameter derivative), a
+        # fixed cost per call: two sample sizes separate it from the per-point cost
+        small = tsel[:64]
+        oracle.vjp(wl.points, oc, tq_np[small], wl.ell, wl.noise_var, cand_prec=32,
+                   sign=tsg_np[small], mode=1)
+        t4 = time.perf_counter()
+        oracle.vjp(wl.points, oc, tq_np[tsel], wl.ell, wl.noise_var, cand_prec=32,
+                   sign=tsg_np[tsel], mode=1)
+        t5 = time.perf_counter()
+        per_vjp = max((t5 - t4) - (t4 - t3), 0.0) / (len(tsel) - len(small))
+        fixed_vjp = max((t4 - t3) - per_vjp * len(small), 0.0)
+        cpu_step = (t2 - t1) + (t3 - t2) / len(sel) * Q + fixed_vjp + per_vjp * QT
+        result["cpu_baseline"] = {
+            "value": round((Q + QT) / cpu_step, 1), "unit": "queries/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"full FP64 fit of {cells.n} cells ({t2 - t1:.2f} s), {len(sel)} seeded grid "
+                      f"queries ({t3 - t2:.2f} s), trajectory VJPs of the softplus cost at "
+                      f"{len(small)} and {len(tsel)} points ({t4 - t3:.2f} s, {t5 - t4:.2f} s: "
+                      f"dual-number refit {fixed_vjp:.2f} s + {per_vjp * 1e3:.3f} ms/point); "
+                      f"step time = fit + grid queries + refit + trajectory points, scaled to "
+                      f"{Q} grid and {QT} trajectory points"}
+        log(f"cpu oracle: fit {t2 - t1:.2f}s, {len(sel)} queries {t3 - t2:.2f}s, "
+            f"vjps {t4 - t3:.2f}s / {t5 - t4:.2f}s, {nthreads} threads")
+    model.close()
     print(json.dumps(result), flush=True)
 
 

@@ -127,6 +127,46 @@ int ksdf_model_create(int n_cells, const int* offsets, const int* samples, const
                       const double origin[3], double h, long n_points, const ksdf_hyper* hyper,
                       const double query_lo[3], const double query_hi[3], ksdf_model** out);
 void ksdf_model_destroy(ksdf_model* model);
+/* Launch-shape knobs (host struct), picked per workload by the autotuner.
+ * query_sub: index boxes are split into query_sub^3 sub-boxes (1, 2 or 4) for the
+ *   counting sort that groups a wave's queries; 0 = finest that keeps <= 8M bins.
+ * query_block: threads per block of the FP32 query kernel (64 or 256; 0 = 256).
+ * fused: ksdf_fit_query uses the persistent fused launch (1) or the per-bucket fit
+ *   launches followed by the query launch (0).
+ * fit_min_bucket: FP32 cells with m <= this run in the fit kernel sized for it
+ *   (16, 32 or 64): larger values merge small cells into fewer launches. */
+typedef struct ksdf_tuning {
+  int query_sub;
+  int query_block;
+  int fused;
+  int fit_min_bucket;
+} ksdf_tuning;
+int ksdf_model_set_tuning(ksdf_model* model, const ksdf_tuning* tuning);
+int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);
+
+/* Kernel timing, for benchmarks and profiles.  With timing on, each launch records a
+ * pair of HIP events on its own stream around the main kernel(s) of its phase:
+ *   KSDF_TIMER_FIT       the FP32 bucket fits and the FP64 refit (ksdf_fit_cells);
+ *   KSDF_TIMER_QUERY     the query kernel, after the query bucketing;
+ *   KSDF_TIMER_BACKWARD  the adjoint kernel (after the argmin sort, before the
+ *                        hyperparameter reduction);
+ *   KSDF_TIMER_FUSED     the persistent fused fit+query kernel.
+ * Each phase keeps the pairs of its last KSDF_TIMER_SLOTS launches.
+ * ksdf_model_timer_read waits for the phase's launches since the previous read (or since
+ * timing was turned on), writes their durations in ms, in launch order, to ms[0..*n)
+ * (at most max_n), and starts a new count.  KSDF_ERR_INVALID_ARGUMENT when timing is off
+ * or more than KSDF_TIMER_SLOTS launches happened since the previous read (the oldest
+ * pairs were reused).  Timing must be off while a stream that the model launches on is
+ * being captured into a graph. */
+#define KSDF_TIMER_FIT 0
+#define KSDF_TIMER_QUERY 1
+#define KSDF_TIMER_BACKWARD 2
+#define KSDF_TIMER_FUSED 3
+#define KSDF_TIMER_COUNT 4
+#define KSDF_TIMER_SLOTS 8
+int ksdf_model_set_timing(ksdf_model* model, int on);
+int ksdf_model_timer_read(ksdf_model* model, int timer, float* ms, int max_n, int* n);
+
 /* Host-side facts about a model: n_cells, nnz, largest m, index entries, device bytes. */
 int ksdf_model_info(const ksdf_model* model, int* n_cells, long* nnz, int* max_m,
                     long* index_entries, size_t* device_bytes);

@@ -66,6 +66,11 @@ def lib():
     return _lib
 
 
+def threads() -> int:
+    """Worker threads the oracle's parallel loops use."""
+    return int(lib().oracle_threads())
+
+
 def _p(a, t):
     if a is None:
         return None

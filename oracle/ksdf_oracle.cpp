@@ -34,6 +34,8 @@
 #include <tuple>
 #include <vector>
 
+#include <omp.h>
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -465,6 +467,9 @@ template <int N> Dual<N> softplus(const Dual<N>& t) {
 }  // namespace
 
 extern "C" {
+
+// Worker threads the parallel loops below use.
+int oracle_threads() { return omp_get_max_threads(); }
 
 // Fit every cell in FP64.  a: [nnz]; L: concatenated row-major m_c x m_c factors.
 int oracle_fit(const double* pts, const double* svar, int n_cells, const int* offsets,

@@ -63,6 +63,10 @@ void free_model(ksdf_model* m) {
                   m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  for (auto& phase : m->tev)
+    for (auto& pair : phase)
+      for (hipEvent_t e : pair)
+        if (e) (void)hipEventDestroy(e);
   delete m;
 }
 
@@ -134,6 +138,7 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
   }
   auto* m = new ksdf_model;
   (void)hipGetDevice(&m->device);
+  (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
   m->precision = hyper->precision;
   m->k_fuse = hyper->k_fuse;
   m->cond_thr = hyper->cond_fp64_threshold;
@@ -326,10 +331,69 @@ extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype,
     return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
                         ws_bytes, s);
   }
+  if (!m->tuning.fused) {
+    r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
+    if (r) return r;
+    m->fitted = true;
+    return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+                        ws_bytes, s);
+  }
   r = launch_fit_query_fused(m, surface_pts, dtype, sample_var, cell_status, points, Q, sign,
                              mean, grad, var, var_f, argmin, q_status, workspace, ws_bytes, s);
   if (r == KSDF_OK) m->fitted = true;
   return r;
+}
+
+extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
+  if (!m || !t || (t->query_sub != 0 && t->query_sub != 1 && t->query_sub != 2 && t->query_sub != 4) ||
+      (t->query_block != 0 && t->query_block != 64 && t->query_block != 256) ||
+      (t->fused != 0 && t->fused != 1) ||
+      (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64)) {
+    set_error("ksdf_model_set_tuning: invalid tuning");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  m->tuning = *t;
+  if (m->tuning.query_block == 0) m->tuning.query_block = 256;
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_model_set_timing(ksdf_model* m, int on) {
+  if (!m) return KSDF_ERR_INVALID_ARGUMENT;
+  int r = check_device(m);
+  if (r) return r;
+  if (on && !m->tev[0][0][0]) {
+    for (auto& phase : m->tev)
+      for (auto& pair : phase)
+        for (hipEvent_t& e : pair) KSDF_HIP_TRY(hipEventCreate(&e));
+  }
+  m->timing = on != 0;
+  for (int& c : m->tcount) c = 0;
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_model_timer_read(ksdf_model* m, int which, float* ms, int max_n, int* n) {
+  if (!m || !n || (max_n > 0 && !ms) || which < 0 || which >= KSDF_TIMER_COUNT || !m->timing) {
+    set_error("ksdf_model_timer_read: timing off or bad arguments");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const int cnt = m->tcount[which];
+  m->tcount[which] = 0;
+  if (cnt > KSDF_TIMER_SLOTS) {
+    set_error("ksdf_model_timer_read: more launches than timer slots since the last read");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  *n = cnt < max_n ? cnt : max_n;
+  for (int i = 0; i < *n; ++i) {
+    KSDF_HIP_TRY(hipEventSynchronize(m->tev[which][i][1]));
+    KSDF_HIP_TRY(hipEventElapsedTime(ms + i, m->tev[which][i][0], m->tev[which][i][1]));
+  }
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_model_get_tuning(const ksdf_model* m, ksdf_tuning* t) {
+  if (!m || !t) return KSDF_ERR_INVALID_ARGUMENT;
+  *t = m->tuning;
+  return KSDF_OK;
 }
 
 extern "C" size_t ksdf_query_workspace_bytes(const ksdf_model* m, long Q) {

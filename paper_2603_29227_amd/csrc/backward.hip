@@ -66,10 +66,12 @@ __device__ __forceinline__ T aabb_d2(const float* bx, T x, T y, T z) {
 
 // One query's VJP on its argmin cell, per-thread loops (the plain path; also the
 // FP32 path, where the wave calls it with a wave-uniform cell so the per-cell data
-// arrive through scalar loads).  v is per-thread storage for k, then L^{-1} k, then
-// beta = A^{-1} k.
-template <class T>
-__device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3], double out_th[2]) {
+// arrive through scalar loads).  With VARF (a var_f cotangent is given), v is
+// per-thread storage for k, then L^{-1} k, then beta = A^{-1} k; without it the two
+// triangular solves and v are not needed.
+template <class T, bool VARF>
+__device__ __forceinline__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
+                                          double out_th[2]) {
   const T lt = A.ell;
   const T x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
   const T s = A.sign ? (T)A.sign[q] : T(1);
@@ -78,7 +80,7 @@ __device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
   const T gv = A.d_var ? A.d_var[q] : T(0);
-  const T gf = A.d_var_f ? A.d_var_f[q] : T(0);
+  const T gf = VARF && A.d_var_f ? A.d_var_f[q] : T(0);
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const T* p = A.ps + 4L * b;
   const T* sv = A.sv + b;
@@ -112,22 +114,24 @@ __device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
     S += sm;
     M1 += sm * t;
     M2 += sm * t * t;
-    v[i] = e * ginv;
+    if constexpr (VARF) v[i] = e * ginv;
   }
-  // forward substitution: v <- L^{-1} k
   T vv = 0;
-  for (int i = 0; i < m; ++i) {
-    const T* row = Lc + (long)i * (i + 1) / 2;
-    T t = v[i];
-    for (int j = 0; j < i; ++j) t -= row[j] * v[j];
-    v[i] = t * row[i];
-    vv += v[i] * v[i];
-  }
-  // backward substitution: v <- L^{-T} v = A^{-1} k (row-oriented, last row first)
-  for (int i = m - 1; i >= 0; --i) {
-    const T* row = Lc + (long)i * (i + 1) / 2;
-    v[i] *= row[i];
-    for (int j = 0; j < i; ++j) v[j] -= row[j] * v[i];
+  if constexpr (VARF) {
+    // forward substitution: v <- L^{-1} k
+    for (int i = 0; i < m; ++i) {
+      const T* row = Lc + (long)i * (i + 1) / 2;
+      T t = v[i];
+      for (int j = 0; j < i; ++j) t -= row[j] * v[j];
+      v[i] = t * row[i];
+      vv += v[i] * v[i];
+    }
+    // backward substitution: v <- L^{-T} v = A^{-1} k (row-oriented, last row first)
+    for (int i = m - 1; i >= 0; --i) {
+      const T* row = Lc + (long)i * (i + 1) / 2;
+      v[i] *= row[i];
+      for (int j = 0; j < i; ++j) v[j] -= row[j] * v[i];
+    }
   }
   const T u2 = f > T(0) ? d2 - A.two_l2 * log(f) : T(-1);
   const bool mean_live = u2 > T(0);
@@ -138,7 +142,7 @@ __device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
     const T gw = (gg[0] * w[0] + gg[1] * w[1] + gg[2] * w[2]) / wn;
     for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * w[d] / wn) / wn;
   }
-  const bool varf_live = (T(1) - vv) > T(0);
+  const bool varf_live = VARF && (T(1) - vv) > T(0);
   const T m1 = M1 / S;
   const T h = zmin + m1;
   const T Vz = M2 / S - m1 * m1;
@@ -168,22 +172,25 @@ __device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
     const T ci = si * (A.alpha * (h - z) + T(1));
     const T dvdz = T(2) * A.alpha * (-sv[i] * ci * (ci + si) + si * V + ci * P);
     const T dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
-    const T kb = v[i] * e * ginv;
+    T kb = 0;
+    if constexpr (VARF) kb = v[i] * e * ginv;
     for (int d = 0; d < 3; ++d) {
       if (z > T(0)) dxv[d] += dvdz * di[d] / z;
       Hy[d] += ae * dy * di[d];
       Wz[d] += ae * z2 * di[d];
-      bk[d] += kb * di[d];
+      if constexpr (VARF) bk[d] += kb * di[d];
       Eld[d] += e * xi[2 * i] * di[d];
       Esd[d] += e * xi[2 * i + 1] * di[d];
     }
-    bkz += kb * z2;
-    bb += v[i] * v[i];
+    if constexpr (VARF) {
+      bkz += kb * z2;
+      bb += v[i] * v[i];
+    }
     El += e * xi[2 * i];
     Es += e * xi[2 * i + 1];
   }
   T bDb = 0;
-  if (A.D && gf != T(0) && varf_live) {
+  if (VARF && A.D && gf != T(0) && varf_live) {
     const T* Dc = A.D + A.loff[c];
     for (int i = 1; i < m; ++i) {
       const T* row = Dc + (long)i * (i + 1) / 2;
@@ -223,7 +230,7 @@ __device__ void query_vjp(const BwdArgs<T>& A, long q, int c, T* v, T out_dx[3],
   out_th[1] = ds;
 }
 
-template <class T>
+template <class T, bool VARF>
 __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
   const long q = (long)blockIdx.x * BT + threadIdx.x;
   if (q >= A.Q) return;
@@ -232,20 +239,27 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
   T dx[3] = {T(0), T(0), T(0)};
   double th[2] = {0.0, 0.0};
   if (c >= 0) {
-    T v[KSDF_MAX_M];
-    query_vjp<T>(A, q, c, v, dx, th);
+    if constexpr (VARF) {
+      T v[KSDF_MAX_M];
+      query_vjp<T, true>(A, q, c, v, dx, th);
+    } else {
+      query_vjp<T, false>(A, q, c, nullptr, dx, th);
+    }
   }
   for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = dx[d];
   A.part[2 * q] = th[0];
   A.part[2 * q + 1] = th[1];
 }
 
-// FP32: one wave walks the distinct argmin cells of its lanes, so the cell index is
-// wave-uniform and the cell's samples, factor and adjoint vectors are read through
-// scalar loads.
-__global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A) {
-  const long q = (long)blockIdx.x * BT + threadIdx.x;
-  const bool active = q < A.Q;
+// FP32: lanes take queries in argmin-cell order (perm), and each wave walks the
+// distinct argmin cells of its lanes -- after the sort usually one or two -- so the
+// cell index is wave-uniform and the cell's samples, factor and adjoint vectors are
+// read through scalar loads.
+template <bool VARF>
+__global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const int* perm) {
+  const long sq = (long)blockIdx.x * BT + threadIdx.x;
+  const bool active = sq < A.Q;
+  const long q = active ? perm[sq] : 0;
   int bc = active ? A.argmin[q] : -1;
   if (bc >= A.n_cells) bc = -1;
   float dx[3] = {0.f, 0.f, 0.f};
@@ -259,8 +273,12 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A) {
     if (key == 0xffffffffu) break;
     const int c = (int)key;
     if (todo && bc == c) {
-      float v[KSDF_MAX_M];
-      query_vjp<float>(A, q, c, v, dx, th);
+      if constexpr (VARF) {
+        float v[KSDF_MAX_M];
+        query_vjp<float, true>(A, q, c, v, dx, th);
+      } else {
+        query_vjp<float, false>(A, q, c, nullptr, dx, th);
+      }
       todo = false;
     }
   }
@@ -270,18 +288,57 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A) {
   A.part[2 * q + 1] = th[1];
 }
 
-// Fixed-order FP64 reduction of the per-query hyperparameter partials (one block).
-constexpr int RT = 1024;
-__global__ void __launch_bounds__(RT) theta_reduce_kernel(const double* part, long Q, double* out) {
-  __shared__ double r0[RT], r1[RT];
-  const long per = (Q + RT - 1) / RT;
-  const long beg = (long)threadIdx.x * per;
-  const long end = beg + per < Q ? beg + per : Q;
-  double a = 0.0, b = 0.0;
-  for (long i = beg; i < end; ++i) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
+// Counting sort of the queries by argmin cell (queries without a cell go last).
+constexpr int ST = 256;
+__global__ void fill_int_kernel(int* p, long n, int v) {
+  const long i = (long)blockIdx.x * ST + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void __launch_bounds__(ST) argmin_count_kernel(const int* argmin, long Q, int n_cells,
+                                                          int* key, int* count) {
+  const long q = (long)blockIdx.x * ST + threadIdx.x;
+  if (q >= Q) return;
+  int c = argmin[q];
+  if (c < 0 || c >= n_cells) c = n_cells;
+  key[q] = c;
+  atomicAdd(count + c, 1);
+}
+// exclusive scan of count[0..n) into start (one block; n is a cell count)
+__global__ void __launch_bounds__(1024) scan_counts_kernel(const int* count, int n, int* start) {
+  __shared__ int part[1024];
+  const int per = (n + 1023) / 1024;
+  const int beg = threadIdx.x * per;
+  const int end = beg + per < n ? beg + per : n;
+  int t = 0;
+  for (int i = beg; i < end; ++i) t += count[i];
+  part[threadIdx.x] = t;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int add = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += add;
+    __syncthreads();
   }
+  int run = threadIdx.x ? part[threadIdx.x - 1] : 0;
+  for (int i = beg; i < end; ++i) {
+    start[i] = run;
+    run += count[i];
+  }
+}
+__global__ void __launch_bounds__(ST) argmin_scatter_kernel(long Q, const int* key, int* cursor,
+                                                            int* perm) {
+  const long q = (long)blockIdx.x * ST + threadIdx.x;
+  if (q >= Q) return;
+  perm[atomicAdd(cursor + key[q], 1)] = (int)q;
+}
+
+// Deterministic FP64 reduction of the per-query hyperparameter partials: RB blocks each
+// sum a fixed contiguous chunk (coalesced, fixed tree), then one block sums the RB
+// partials in a fixed tree.  The order depends on Q only.
+constexpr int RT = 256;
+constexpr int RB = 256;
+__device__ void block_sum2(double a, double b, double* out) {
+  __shared__ double r0[RT], r1[RT];
   r0[threadIdx.x] = a;
   r1[threadIdx.x] = b;
   __syncthreads();
@@ -297,6 +354,20 @@ __global__ void __launch_bounds__(RT) theta_reduce_kernel(const double* part, lo
     out[1] = r1[0];
   }
 }
+__global__ void __launch_bounds__(RT) theta_partial_kernel(const double* part, long Q, double* red) {
+  const long per = (Q + RB - 1) / RB;
+  const long beg = (long)blockIdx.x * per;
+  const long end = beg + per < Q ? beg + per : Q;
+  double a = 0.0, b = 0.0;
+  for (long i = beg + threadIdx.x; i < end; i += RT) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  block_sum2(a, b, red + 2 * blockIdx.x);
+}
+__global__ void __launch_bounds__(RT) theta_final_kernel(const double* red, double* out) {
+  block_sum2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1], out);
+}
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -304,9 +375,12 @@ size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 size_t backward_workspace_bytes(const ksdf_model* m, long Q) {
   const size_t fb = m->precision == KSDF_FP64 ? sizeof(double) : sizeof(float);
-  // per-query theta partials, and (when no argmin is passed) a forward pass
-  return al256(2 * Q * sizeof(double)) + al256(Q * sizeof(int)) + al256(Q * 5 * fb) +
-         al256(query_workspace_bytes(m, Q));
+  const size_t nc = (size_t)m->n_cells + 1;
+  // per-query theta partials, block partials, the argmin sort (key, perm, count,
+  // cursor), and (when no argmin is passed) a forward pass
+  return al256(2 * Q * sizeof(double)) + al256(2 * RB * sizeof(double)) +
+         2 * al256(Q * sizeof(int)) + 2 * al256(nc * sizeof(int)) + al256(Q * sizeof(int)) +
+         al256(Q * 5 * fb) + al256(query_workspace_bytes(m, Q));
 }
 
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
@@ -322,27 +396,43 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   const size_t fb = m->precision == KSDF_FP64 ? sizeof(double) : sizeof(float);
+  const long nc = (long)m->n_cells + 1;
   char* w = static_cast<char*>(ws);
   double* part = reinterpret_cast<double*>(w);
   w += al256(2 * Q * sizeof(double));
+  double* red = reinterpret_cast<double*>(w);
+  w += al256(2 * RB * sizeof(double));
+  int* key = reinterpret_cast<int*>(w);
+  w += al256(Q * sizeof(int));
+  int* perm = reinterpret_cast<int*>(w);
+  w += al256(Q * sizeof(int));
+  int* count = reinterpret_cast<int*>(w);
+  w += al256(nc * sizeof(int));
+  int* cursor = reinterpret_cast<int*>(w);
+  w += al256(nc * sizeof(int));
   int* am = reinterpret_cast<int*>(w);
   w += al256(Q * sizeof(int));
   char* fwd = w;
   w += al256(Q * 5 * fb);
   void* fws = w;
-  if (Q == 0) {
-    hipLaunchKernelGGL(theta_reduce_kernel, dim3(1), dim3(RT), 0, s, part, 0L, d_hyper);
-    KSDF_HIP_TRY(hipGetLastError());
-    return KSDF_OK;
-  }
-  if (!argmin) {
+  if (!argmin && Q > 0) {
     // recover each query's argmin cell with a forward pass into the workspace
     int r = launch_query(m, points, Q, sign, fwd, fwd + Q * fb, fwd + 4 * Q * fb, nullptr, am,
                          nullptr, fws, query_workspace_bytes(m, Q), s);
     if (r != KSDF_OK) return r;
     argmin = am;
   }
+  if (Q > 0 && m->precision != KSDF_FP64) {
+    const unsigned gq = (unsigned)((Q + ST - 1) / ST);
+    hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((nc + ST - 1) / ST)), dim3(ST), 0, s, count,
+                       nc, 0);
+    hipLaunchKernelGGL(argmin_count_kernel, dim3(gq), dim3(ST), 0, s, argmin, Q, m->n_cells, key,
+                       count);
+    hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(1024), 0, s, count, (int)nc, cursor);
+    hipLaunchKernelGGL(argmin_scatter_kernel, dim3(gq), dim3(ST), 0, s, Q, key, cursor, perm);
+  }
   const unsigned grid = (unsigned)((Q + BT - 1) / BT);
+  const bool varf = d_var_f != nullptr;
   const double two_l2 = 2.0 * m->ell * m->ell;
   if (m->precision == KSDF_FP64) {
     BwdArgs<double> A{};
@@ -361,7 +451,12 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.centre64 = m->centre64; A.box = m->box32;
     A.ell = m->ell; A.two_l2 = two_l2; A.alpha = m->alpha;
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
-    hipLaunchKernelGGL(bwd_plain_kernel<double>, dim3(grid), dim3(BT), 0, s, A);
+    timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
+    if (Q > 0) {
+      if (varf) hipLaunchKernelGGL((bwd_plain_kernel<double, true>), dim3(grid), dim3(BT), 0, s, A);
+      else hipLaunchKernelGGL((bwd_plain_kernel<double, false>), dim3(grid), dim3(BT), 0, s, A);
+    }
+    timer_mark(m, KSDF_TIMER_BACKWARD, 1, s);
   } else {
     BwdArgs<float> A{};
     A.pts = static_cast<const float*>(points);
@@ -379,9 +474,15 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.centre64 = m->centre64; A.box = m->box32;
     A.ell = (float)m->ell; A.two_l2 = (float)two_l2; A.alpha = (float)m->alpha;
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
-    hipLaunchKernelGGL(bwd_wave_kernel, dim3(grid), dim3(BT), 0, s, A);
+    timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
+    if (Q > 0) {
+      if (varf) hipLaunchKernelGGL(bwd_wave_kernel<true>, dim3(grid), dim3(BT), 0, s, A, perm);
+      else hipLaunchKernelGGL(bwd_wave_kernel<false>, dim3(grid), dim3(BT), 0, s, A, perm);
+    }
+    timer_mark(m, KSDF_TIMER_BACKWARD, 1, s);
   }
-  hipLaunchKernelGGL(theta_reduce_kernel, dim3(1), dim3(RT), 0, s, part, Q, d_hyper);
+  hipLaunchKernelGGL(theta_partial_kernel, dim3(RB), dim3(RT), 0, s, part, Q, red);
+  hipLaunchKernelGGL(theta_final_kernel, dim3(1), dim3(RT), 0, s, red, d_hyper);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

@@ -46,17 +46,24 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
   if (m->precision == KSDF_FP64) {
     A.list = nullptr;
     A.emit32 = 0;
+    timer_mark(m, KSDF_TIMER_FIT, 0, s);
     hipLaunchKernelGGL(fit64_kernel, dim3(m->n_cells), dim3(FIT_THREADS), 0, s, A);
+    timer_mark(m, KSDF_TIMER_FIT, 1, s);
   } else {
     hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, m->fb_count, 0);
+    timer_mark(m, KSDF_TIMER_FIT, 0, s);
+    // m buckets: cells below the tuned smallest bucket merge into it
     const int* lists = m->bucket_cells;
     const int* bs = m->bucket_start;
-    if (bs[1] > bs[0])
+    const int minb = m->tuning.fit_min_bucket;
+    const int lo32 = minb >= 32 ? bs[0] : bs[1];
+    const int lo64 = minb >= 64 ? bs[0] : bs[2];
+    if (minb < 32 && bs[1] > bs[0])
       hipLaunchKernelGGL(fit32_kernel<16>, dim3(bs[1] - bs[0]), dim3(FIT_THREADS), 0, s, A, lists + bs[0]);
-    if (bs[2] > bs[1])
-      hipLaunchKernelGGL(fit32_kernel<32>, dim3(bs[2] - bs[1]), dim3(FIT_THREADS), 0, s, A, lists + bs[1]);
-    if (bs[3] > bs[2])
-      hipLaunchKernelGGL(fit32_kernel<64>, dim3(bs[3] - bs[2]), dim3(FIT_THREADS), 0, s, A, lists + bs[2]);
+    if (minb < 64 && bs[2] > lo32)
+      hipLaunchKernelGGL(fit32_kernel<32>, dim3(bs[2] - lo32), dim3(FIT_THREADS), 0, s, A, lists + lo32);
+    if (bs[3] > lo64)
+      hipLaunchKernelGGL(fit32_kernel<64>, dim3(bs[3] - lo64), dim3(FIT_THREADS), 0, s, A, lists + lo64);
     if (bs[4] > bs[3])
       hipLaunchKernelGGL(fit32_kernel<128>, dim3(bs[4] - bs[3]), dim3(FIT_THREADS), 0, s, A, lists + bs[3]);
     A.list = m->fb_list;
@@ -64,6 +71,7 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
     A.emit32 = 1;
     const int grid = m->n_cells < 2048 ? m->n_cells : 2048;
     hipLaunchKernelGGL(fit64_kernel, dim3(grid), dim3(FIT_THREADS), 0, s, A);
+    timer_mark(m, KSDF_TIMER_FIT, 1, s);
   }
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;

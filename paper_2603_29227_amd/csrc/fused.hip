@@ -106,17 +106,24 @@ int launch_fused_t(ksdf_model* m, FitArgs& F, FastArgs& A, FusedCtl& C, hipStrea
   const size_t smem = std::max(fit32_smem_floats<MF>() * sizeof(float),
                                FIT64_SMEM_DOUBLES * sizeof(double));
   auto kern = fused_kernel<KM, MB, MF>;
-  KSDF_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
-  int per_cu = 0;
-  KSDF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, FT, smem));
-  int cus = 0;
-  KSDF_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, m->device));
+  // attribute and occupancy are taken once per kernel, so that a launch made under
+  // stream capture issues no device-attribute calls
+  static int per_cu = -1;
+  if (per_cu < 0) {
+    KSDF_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    int occ = 0;
+    KSDF_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, FT, smem));
+    per_cu = std::max(occ, 1);
+  }
+  const int cus = std::max(m->n_cu, 1);
   const long tasks = C.n_fit + C.n_qtasks;
-  long grid = (long)std::max(per_cu, 1) * cus;
+  long grid = (long)per_cu * cus;
   if (grid > tasks) grid = tasks;
   if (grid < 1) grid = 1;
+  timer_mark(m, KSDF_TIMER_FUSED, 0, s);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(FT), smem, s, F, A, C);
+  timer_mark(m, KSDF_TIMER_FUSED, 1, s);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

@@ -46,6 +46,7 @@ struct CandidateIndex {
 // The model: per-cell store and candidate index (device memory owned by the model).
 struct ksdf_model {
   int device = 0;
+  int n_cu = 0;  // compute units of the device
   int precision = KSDF_FP32;
   int k_fuse = 8;
   int n_cells = 0;
@@ -53,6 +54,7 @@ struct ksdf_model {
   int max_m = 0;
   long n_points = 0;
   double origin[3] = {0, 0, 0};
+
   double h = 0;
   double ell = 0, noise_var = 0, alpha = 0;   // of the last fit
   double cond_thr = 1e6;
@@ -101,8 +103,22 @@ struct ksdf_model {
   int bucket_start[5] = {0, 0, 0, 0, 0};
 
   ksdf::CandidateIndex index;
+  ksdf_tuning tuning{0, 256, 1, 16};
+  // kernel timing: one event pair per phase, recorded when timing is on
+  bool timing = false;
+  hipEvent_t tev[KSDF_TIMER_COUNT][KSDF_TIMER_SLOTS][2] = {};
+  mutable int tcount[KSDF_TIMER_COUNT] = {};   // launches since the last read
   size_t device_bytes = 0;
 };
+
+namespace ksdf {
+// record the start (end=0) or end (end=1) event of a timed phase
+inline void timer_mark(const ksdf_model* m, int which, int end, hipStream_t s) {
+  if (!m->timing) return;
+  (void)hipEventRecord(m->tev[which][m->tcount[which] % KSDF_TIMER_SLOTS][end], s);
+  if (end) ++m->tcount[which];
+}
+}  // namespace ksdf
 
 namespace ksdf {
 

@@ -189,7 +189,7 @@ __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int
 // One wave answers the 64 sorted queries sq .. (lanes pass their own sq); every
 // lane of the wave must call it together (wave-uniform loops inside).
 template <int KM, int MB>
-__device__ void query_tile(const FastArgs& A, long sq) {
+__device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
   const bool active = sq < A.Q;
   const long qi = active ? A.perm[sq] : 0;
   const float qx = A.pts[3 * qi], qy = A.pts[3 * qi + 1], qz = A.pts[3 * qi + 2];
@@ -581,9 +581,12 @@ __global__ void scatter_kernel(long Q, const int* keys, int* cursor, int* perm) 
   perm[pos] = (int)q;
 }
 
-// finest bucketing (sub-boxes per edge) that keeps the bin count near 8M
+// bucketing granularity (sub-boxes per box edge): the tuned value, else the finest
+// that keeps the bin count near 8M
 int sub_of(const ksdf_model* m) {
   const long nb = m->index.n_boxes;
+  const int t = m->tuning.query_sub;
+  if ((t == 1 || t == 2 || t == 4) && nb * t * t * t <= (16L << 20)) return t;
   return nb * 64 <= (8L << 20) ? 4 : (nb * 8 <= (8L << 20) ? 2 : 1);
 }
 long n_bins_of(const ksdf_model* m) {

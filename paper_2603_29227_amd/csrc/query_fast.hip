@@ -28,9 +28,20 @@
 namespace ksdf {
 namespace {
 
-template <int KM, int MB>
-__global__ void __launch_bounds__(FQ) query_fast_kernel(FastArgs A) {
-  query_tile<KM, MB>(A, (long)blockIdx.x * FQ + threadIdx.x);
+template <int KM, int MB, int NT>
+__global__ void __launch_bounds__(NT) query_fast_kernel(FastArgs A) {
+  query_tile<KM, MB>(A, (long)blockIdx.x * NT + threadIdx.x);
+}
+
+template <int NT>
+void launch_query_nt(const ksdf_model* m, const FastArgs& A, hipStream_t s) {
+  const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
+  const bool k8 = m->k_fuse <= 8;
+  const bool m64 = m->max_m <= 64;
+  if (k8 && m64) hipLaunchKernelGGL((query_fast_kernel<8, 64, NT>), dim3(g), dim3(NT), 0, s, A);
+  else if (k8) hipLaunchKernelGGL((query_fast_kernel<8, 128, NT>), dim3(g), dim3(NT), 0, s, A);
+  else if (m64) hipLaunchKernelGGL((query_fast_kernel<16, 64, NT>), dim3(g), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL((query_fast_kernel<16, 128, NT>), dim3(g), dim3(NT), 0, s, A);
 }
 
 }  // namespace
@@ -50,13 +61,10 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
   FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
   int r = launch_bucketing(m, A, ws, s);
   if (r != KSDF_OK) return r;
-  const unsigned gq = (unsigned)((Q + FQ - 1) / FQ);
-  const bool k8 = m->k_fuse <= 8;
-  const bool m64 = m->max_m <= 64;
-  if (k8 && m64) hipLaunchKernelGGL((query_fast_kernel<8, 64>), dim3(gq), dim3(FQ), 0, s, A);
-  else if (k8) hipLaunchKernelGGL((query_fast_kernel<8, 128>), dim3(gq), dim3(FQ), 0, s, A);
-  else if (m64) hipLaunchKernelGGL((query_fast_kernel<16, 64>), dim3(gq), dim3(FQ), 0, s, A);
-  else hipLaunchKernelGGL((query_fast_kernel<16, 128>), dim3(gq), dim3(FQ), 0, s, A);
+  timer_mark(m, KSDF_TIMER_QUERY, 0, s);
+  if (m->tuning.query_block == 64) launch_query_nt<64>(m, A, s);
+  else launch_query_nt<256>(m, A, s);
+  timer_mark(m, KSDF_TIMER_QUERY, 1, s);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

@@ -33,11 +33,25 @@ EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_c
            "ksdf_model_create", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
            "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
-           "ksdf_status_string", "ksdf_last_error"]
+           "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
+           "ksdf_model_timer_read", "ksdf_status_string",
+           "ksdf_last_error"]
 
 
 class KsdfError(RuntimeError):
     pass
+
+
+TIMERS = {"fit": 0, "query": 1, "backward": 2, "fused": 3}
+TIMER_SLOTS = 8
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("query_sub", ctypes.c_int), ("query_block", ctypes.c_int),
+                ("fused", ctypes.c_int), ("fit_min_bucket", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Hyper(ctypes.Structure):
@@ -85,6 +99,11 @@ def lib():
         L.ksdf_fit_query_workspace_bytes.restype = sz
         L.ksdf_fit_query.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp, l, _vp, _vp, _vp, _vp, _vp,
                                      _vp, _vp, _vp, sz, _vp]
+        L.ksdf_model_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
+        L.ksdf_model_get_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
+        L.ksdf_model_set_timing.argtypes = [_vp, i]
+        L.ksdf_model_timer_read.argtypes = [_vp, i, ctypes.POINTER(ctypes.c_float), i,
+                                            ctypes.POINTER(ctypes.c_int)]
         L.ksdf_status_string.argtypes = [i]
         L.ksdf_status_string.restype = ctypes.c_char_p
         L.ksdf_last_error.argtypes = []
@@ -202,6 +221,28 @@ class Model:
                "ksdf_model_info")
         return dict(n_cells=n.value, nnz=nnz.value, max_m=mm.value, index_entries=ie.value,
                     device_bytes=db.value)
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        _check(self._lib.ksdf_model_get_tuning(self._h, ctypes.byref(t)), "ksdf_model_get_tuning")
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.tuning(), **kw})
+        _check(self._lib.ksdf_model_set_tuning(self._h, ctypes.byref(t)), "ksdf_model_set_tuning")
+
+    def set_timing(self, on: bool = True):
+        """Record HIP events around each phase's main kernel (off under graph capture)."""
+        _check(self._lib.ksdf_model_set_timing(self._h, int(bool(on))), "ksdf_model_set_timing")
+
+    def timer_read(self, phase: str) -> list:
+        """Durations (ms, in launch order) of the launches of 'fit', 'query', 'backward'
+        or 'fused' since the previous read."""
+        buf = (ctypes.c_float * TIMER_SLOTS)()
+        n = ctypes.c_int()
+        _check(self._lib.ksdf_model_timer_read(self._h, TIMERS[phase], buf, TIMER_SLOTS,
+                                               ctypes.byref(n)), "ksdf_model_timer_read")
+        return [buf[i] for i in range(n.value)]
 
     def set_hyper(self, ell=None, noise_var=None, alpha=None):
         if ell is not None:

@@ -438,6 +438,13 @@ def room_workload(variant="grid", grid_n=256, n_random=4_194_304, n_traj=4096, n
                     traj_shape=traj, scene=scene)
 
 
+def room_trajectories(wl: Workload, n_traj=4096, n_way=64):
+    """The trajectory queries of the 'traj' room workload, for a room workload already
+    built (same scene and samples), without sampling the surfaces again."""
+    q = _trajectories(_rng(4, _S_TRAJ), wl.scene, n_traj, n_way, ROOM_LO, ROOM_HI, np.float32)
+    return q, _sign(wl.scene.free(q.astype(np.float64)))
+
+
 def terrain_workload(grid_n=256, n_traj=16384, n_way=64, spacing=0.03, cfg_id=5,
                      size_scale=1.0, with_grid=True):
     """Large outdoor: value-noise terrain with buildings and trees; 3 cm spacing."""

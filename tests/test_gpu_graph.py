@@ -1,0 +1,192 @@
+"""HIP-graph capture of whole steps, and the launch-shape knobs.
+
+A captured step (fit + query + backward, or the fused fit+query) is replayed several
+times with new input values copied into its static inputs, with eager work of the
+same model between the replays; every replay must equal, bit for bit, the eager call
+made on the same inputs.  Every tuning of the launch shape must give the same outputs
+as the default one, bit for bit, and pass parity against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _model(wl, precision="fp32", adjoint=False):
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    return ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                      precision=precision, adjoint=adjoint), cells
+
+
+def _equal(a: dict, b: dict, keys=("mean", "grad", "var", "var_f", "argmin", "status")):
+    for k in keys:
+        assert torch.equal(a[k], b[k]), f"{k} differs"
+
+
+def _clone(d):
+    return {k: v.clone() for k, v in d.items()}
+
+
+def test_graph_fit_query_backward_replays_match_eager():
+    _say("graph: fit + query + backward, 3 replays with eager work between")
+    wl = scenes.small_room_workload(n_queries=20000, cfg_id=41, uneven=True)
+    model, _ = _model(wl, adjoint=True)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    rng = np.random.default_rng(5)
+    dm = torch.from_numpy(rng.normal(size=len(q))).to(dev, torch.float32)
+    dv = torch.from_numpy(rng.normal(size=len(q))).to(dev, torch.float32)
+    out = model._out(len(q), dev)
+
+    def step():
+        model.fit(P)
+        model.query(q, sg, out=out)
+        return model.backward(q, sg, dm, None, dv, None, argmin=out["argmin"])
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()  # warm-up: sizes the workspace, takes the launch attributes
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dpg, dhg = step()
+    shift = torch.tensor([0.0, 0.0, 0.0], device=dev)
+    P0, q0 = P.clone(), q.clone()
+    for rep in range(3):
+        # new inputs in the static buffers: a small rigid shift of samples and queries
+        shift.uniform_(-0.01, 0.01)
+        P.copy_(P0 + shift)
+        q.copy_(q0 + 0.5 * shift)
+        g.replay()
+        torch.cuda.synchronize()
+        got = _clone(out)
+        gdp, gdh = dpg.clone(), dhg.clone()
+        # eager work of the same model between replays (refits, other queries)
+        model.fit(P0)
+        model.query(q0[:1000].contiguous(), sg[:1000].contiguous())
+        ref_out = model._out(len(q), dev)
+        model.fit(P)
+        model.query(q, sg, out=ref_out)
+        rdp, rdh = model.backward(q, sg, dm, None, dv, None, argmin=ref_out["argmin"])
+        torch.cuda.synchronize()
+        _equal(got, ref_out)
+        assert torch.equal(gdp, rdp), f"replay {rep}: d_points differ"
+        assert torch.equal(gdh, rdh), f"replay {rep}: d_hyper differ"
+    model.close()
+
+
+def test_graph_fused_fit_query_replays_match_eager():
+    _say("graph: fused fit_query, 3 replays")
+    wl = scenes.small_room_workload(n_queries=30000, cfg_id=42, uneven=True)
+    model, _ = _model(wl)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    out = model._out(len(q), dev)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        model.fit_query(P, q, sg, out=out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        model.fit_query(P, q, sg, out=out)
+    gen = torch.Generator(device=dev).manual_seed(3)
+    lo = torch.tensor(wl.queries.min(0), device=dev, dtype=torch.float32)
+    hi = torch.tensor(wl.queries.max(0), device=dev, dtype=torch.float32)
+    for rep in range(3):
+        q.copy_(lo + (hi - lo) * torch.rand(q.shape, device=dev, generator=gen))
+        g.replay()
+        torch.cuda.synchronize()
+        got = _clone(out)
+        model.query(q[:500].contiguous(), None)
+        ref = model.fit_query(P, q, sg)
+        torch.cuda.synchronize()
+        _equal(got, ref)
+    model.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(query_sub=1, query_block=256, fused=1, fit_min_bucket=16),
+    dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=32),
+    dict(query_sub=4, query_block=64, fused=1, fit_min_bucket=64),
+])
+def test_tuning_preserves_outputs(tuning):
+    _say(f"tuning {tuning}")
+    wl = scenes.small_room_workload(n_queries=12000, cfg_id=43, uneven=True)
+    model, cells = _model(wl)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    base = model.fit_query(P, q, sg)
+    torch.cuda.synchronize()
+    base = _clone(base)
+    model.set_tuning(**tuning)
+    assert model.tuning() == tuning
+    a = model.fit_query(P, q, sg)
+    model.fit(P)
+    b = model.query(q, sg)
+    torch.cuda.synchronize()
+    _equal(a, base)
+    _equal(b, base)
+    oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                      np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+                     sign=wl.sign, all_candidates=True)
+    assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
+                  label=str(tuning))
+    model.close()
+
+
+def test_tuning_rejects_invalid_values():
+    _say("tuning validation")
+    wl = scenes.sphere_workload(n_queries=16)
+    model, _ = _model(wl, precision="fp64")
+    for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8)):
+        with pytest.raises(ksdf.KsdfError):
+            model.set_tuning(**bad)
+    model.close()
+
+
+def test_kernel_timers_report_each_launch():
+    _say("kernel timers")
+    wl = scenes.small_room_workload(n_queries=5000, cfg_id=44)
+    model, _ = _model(wl, adjoint=True)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    with pytest.raises(ksdf.KsdfError):
+        model.timer_read("query")  # timing is off
+    model.set_timing(True)
+    model.fit(P)
+    out = model.query(q)
+    model.query(q[:100].contiguous())
+    model.backward(q, None, torch.ones(len(q), device=dev), argmin=out["argmin"])
+    fits, qs, bw = model.timer_read("fit"), model.timer_read("query"), model.timer_read("backward")
+    assert len(fits) == 1 and len(qs) == 2 and len(bw) == 1
+    assert all(t > 0 for t in fits + qs + bw)
+    assert model.timer_read("query") == []
+    for _ in range(ksdf.TIMER_SLOTS + 1):
+        model.query(q[:64].contiguous())
+    with pytest.raises(ksdf.KsdfError):
+        model.timer_read("query")  # more launches than slots since the last read
+    model.set_timing(False)
+    model.close()
