@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 GPU leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-tune", action="store_true", help="use the cached tuning, do not time")
+    ap.add_argument("--tune-cache", default=None, help="write the autotuner's choice to this cache")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (scale for the HBM byte counters)")
@@ -157,7 +158,7 @@ def main():
         tuned = {"source": "cache" if tuning else "default", "tuning": model.tuning()}
     else:
         t1 = time.time()
-        res = tune.tune(model, pts, q, sg, reps=2, cache_path=None)
+        res = tune.tune(model, pts, q, sg, reps=2, cache_path=args.tune_cache)
         tuned = {"source": "timed", "tuning": res["tuning"], "ms": res["ms"],
                  "candidates": len(res["table"]), "seconds": round(time.time() - t1, 1)}
         log(f"autotuner: {res['tuning']} {res['ms']:.3f} ms ({len(res['table'])} candidates)")

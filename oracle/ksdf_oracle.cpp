@@ -535,7 +535,7 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
                   int k_fuse, int cand_prec, const double* q, long nq, const int8_t* sign,
                   int mode, double margin, double weight, const double* d_mean,
                   const double* d_grad, const double* d_var, const double* d_var_f,
-                  double* d_points, double* d_hyper) {
+                  double* d_points, double* d_hyper, double* d_hyper_pp) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs);
   QueryOpts o{ell, 0, k_fuse, cand_prec, 0, alpha_fixed <= 0};
@@ -560,9 +560,16 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
     D2 qd[3] = {D2(q[3 * p]), D2(q[3 * p + 1]), D2(q[3 * p + 2])};
     PointOut<D2> r = query_point<D2>(in, qd, sign ? sign[p] : 1, a2.data(), L2.data(), ell2,
                                      noise2, alpha2, o);
-    if (r.status & ST_NO_VALID) continue;
+    if (r.status & ST_NO_VALID) {
+      if (d_hyper_pp) d_hyper_pp[2 * p] = d_hyper_pp[2 * p + 1] = 0.0;
+      continue;
+    }
     D2 l = loss_of(p, r.mean, r.grad, r.var, r.var_f);
     total += l.v; dh0 += l.d[0]; dh1 += l.d[1];
+    if (d_hyper_pp) {
+      d_hyper_pp[2 * p] = l.d[0];
+      d_hyper_pp[2 * p + 1] = l.d[1];
+    }
   }
   d_hyper[0] = dh0; d_hyper[1] = dh1;
   // (2) query points: fit fixed in double, queries in Dual<3>.

@@ -60,7 +60,7 @@ void free_model(ksdf_model* m) {
   if (!m) return;
   void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
                   m->L32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
-                  m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list};
+                  m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list, m->index.box_rank};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (auto& phase : m->tev)
@@ -176,7 +176,7 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
   m->adjoint_alloc = (hyper->flags & (KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) != 0;
   m->adjoint_varf_alloc = (hyper->flags & KSDF_FIT_ADJOINT_VARF) != 0;
   if (m->adjoint_alloc) {
-    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->xi32, 2L * (nnz + KSDF_PAD_SAMPLES)));
+    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->xi32, 4L * (nnz + KSDF_PAD_SAMPLES)));
     else TRY(dalloc(m, &m->xi64, 2L * nnz));
     // the FP64 refit of an FP32 model writes its xi in FP32 too
   }

@@ -31,7 +31,7 @@ constexpr int BT = 256;
 
 template <class T>
 struct BwdArgs {
-  const T* pts;
+  const T* __restrict__ pts;
   long Q;
   const int8_t* sign;
   const int* argmin;
@@ -45,13 +45,15 @@ struct BwdArgs {
   const int* offsets;
   const long* loff;
   const T* ps;             // [nnz,4] (px,py,pz,a) cell-local
+  const float* plo;        // FP32 store: float-float low parts of ps
   const T* sv;
   const T* L;              // packed rows, reciprocal diagonal
-  const T* xi;             // [nnz,2]
+  const T* xi;             // [nnz,2] (FP64) or [nnz+pad,4] float-float (FP32)
   const T* D;              // packed dA/dl or null
   const double* centre64;
   const float* box;        // [n,8] sample AABB (cell-local)
   T ell, two_l2, alpha;
+  double ell_d, alpha_d;   // the same in FP64
   int alpha_tied;
   int uniform_noise;
 };
@@ -85,7 +87,8 @@ __device__ __forceinline__ void query_vjp(const BwdArgs<T>& A, long q, int c, T*
   const T* p = A.ps + 4L * b;
   const T* sv = A.sv + b;
   const T* Lc = A.L + A.loff[c];
-  const T* xi = A.xi + 2L * b;
+  constexpr int XS = sizeof(T) == 4 ? 4 : 2;   // FP32 store: float-float pairs, hi first
+  const T* xi = A.xi + XS * (long)b;
   const double* cc = A.centre64 + 3L * c;
   const T l0 = x0 - (T)cc[0], l1 = x1 - (T)cc[1], l2 = x2 - (T)cc[2];
   const T inv2l2 = T(1) / A.two_l2;
@@ -179,15 +182,15 @@ __device__ __forceinline__ void query_vjp(const BwdArgs<T>& A, long q, int c, T*
       Hy[d] += ae * dy * di[d];
       Wz[d] += ae * z2 * di[d];
       if constexpr (VARF) bk[d] += kb * di[d];
-      Eld[d] += e * xi[2 * i] * di[d];
-      Esd[d] += e * xi[2 * i + 1] * di[d];
+      Eld[d] += e * xi[XS * i] * di[d];
+      Esd[d] += e * xi[XS * i + 1] * di[d];
     }
     if constexpr (VARF) {
       bkz += kb * z2;
       bb += v[i] * v[i];
     }
-    El += e * xi[2 * i];
-    Es += e * xi[2 * i + 1];
+    El += e * xi[XS * i];
+    Es += e * xi[XS * i + 1];
   }
   T bDb = 0;
   if (VARF && A.D && gf != T(0) && varf_live) {
@@ -251,6 +254,163 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
   A.part[2 * q + 1] = th[1];
 }
 
+// VJP without a var_f cotangent for an FP32 model (the terms of query_vjp<T, false>),
+// for a wave-uniform cell: every lane of the wave runs it, so the per-cell data are
+// read by scalar loads, BCH samples per load group, outside divergent control flow; a
+// lane keeps the result only when c is its own argmin cell.  The arithmetic is FP64 on
+// the store's float-float values (samples, weights, adjoint vectors): the sums
+// f' = sum a_i e_i and sum e_i xi_i cancel strongly in ill-conditioned cells, which
+// FP32 would turn into errors of 1e-3 in the hyperparameter gradient, while FP64
+// issues at the rate of unpacked FP32 on this hardware.
+constexpr int BCH = 2;
+
+__device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, double x1, double x2,
+                                         double s, double gm, const double gg[3], double gv, int c,
+                                         double out_dx[3], double out_th[2]) {
+  const float4* __restrict__ P4 = reinterpret_cast<const float4*>(A.ps);
+  const float4* __restrict__ PL = reinterpret_cast<const float4*>(A.plo);
+  const float4* __restrict__ X4 = reinterpret_cast<const float4*>(A.xi);
+  const float* __restrict__ SV = A.sv;
+  const int b = __builtin_amdgcn_readfirstlane(A.offsets[c]);
+  const int m = __builtin_amdgcn_readfirstlane(A.offsets[c + 1]) - b;
+  const double lt = A.ell_d, two_l2 = 2.0 * lt * lt, inv2l2 = 1.0 / two_l2, al = A.alpha_d;
+  const double l0 = x0 - A.centre64[3L * c], l1 = x1 - A.centre64[3L * c + 1],
+               l2 = x2 - A.centre64[3L * c + 2];
+  // sample i in FP64: coordinates and weight from the float-float pair
+  auto load = [&](int i, double& px, double& py, double& pz, double& pa) {
+    const float4 h = P4[b + i], lo = PL[b + i];
+    px = (double)h.x + (double)lo.x;
+    py = (double)h.y + (double)lo.y;
+    pz = (double)h.z + (double)lo.z;
+    pa = (double)h.w + (double)lo.w;
+  };
+  double d2 = INFINITY;
+  for (int i0 = 0; i0 < m; i0 += BCH) {
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+      double px, py, pz, pa;
+      load(i0 + j, px, py, pz, pa);   // the store is padded
+      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
+      const double z2 = dx * dx + dy * dy + dz * dz;
+      if (i0 + j < m) d2 = fmin(d2, z2);
+    }
+  }
+  const double zmin = sqrt(d2);
+  // pass A: f', w', Z, softmin moments
+  double f = 0, w[3] = {0, 0, 0}, Za = 0, S = 0, M1 = 0, M2 = 0;
+  for (int i0 = 0; i0 < m; i0 += BCH) {
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+      const bool ok = i0 + j < m;
+      double px, py, pz, pa;
+      load(i0 + j, px, py, pz, pa);
+      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
+      const double z2 = dx * dx + dy * dy + dz * dz;
+      const double e = ok ? exp(-(z2 - d2) * inv2l2) : 0.0;
+      const double ae = pa * e;
+      f += ae;
+      w[0] += ae * dx;
+      w[1] += ae * dy;
+      w[2] += ae * dz;
+      Za += ae * z2;
+      const double t = sqrt(z2) - zmin;
+      const double sm = ok ? exp(-al * t) : 0.0;
+      S += sm;
+      M1 += sm * t;
+      M2 += sm * t * t;
+    }
+  }
+  const double u2 = f > 0.0 ? d2 - two_l2 * log(f) : -1.0;
+  const bool mean_live = u2 > 0.0;
+  const double u = mean_live ? sqrt(u2) : 0.0;
+  const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  double y[3] = {0, 0, 0};
+  if (wn > 0.0) {
+    const double gw = (gg[0] * w[0] + gg[1] * w[1] + gg[2] * w[2]) / wn;
+    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * w[d] / wn) / wn;
+  }
+  const double iS = 1.0 / S;
+  const double m1 = M1 * iS;
+  const double h = zmin + m1;
+  const double Vz = M2 * iS - m1 * m1;
+  // pass B: softmin coefficients c_i; V, P, d var / d alpha, sum c^2
+  double V = 0, Pp = 0, dVa = 0, C2 = 0;
+  for (int i0 = 0; i0 < m; i0 += BCH) {
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+      const bool ok = i0 + j < m;
+      double px, py, pz, pa;
+      load(i0 + j, px, py, pz, pa);
+      const double svj = ok ? (double)SV[b + i0 + j] : 0.0;
+      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
+      const double z = sqrt(dx * dx + dy * dy + dz * dz);
+      const double si = ok ? exp(-al * (z - zmin)) * iS : 0.0;
+      const double Bi = al * (h - z) + 1.0;
+      const double ci = si * Bi;
+      V += svj * ci * ci;
+      Pp += svj * ci * si;
+      C2 += ci * ci;
+      dVa += 2.0 * svj * ci * (si * (h - z) * (Bi + 1.0) - al * si * Vz);
+    }
+  }
+  // pass C: per-sample accumulations
+  double dxv[3] = {0, 0, 0}, Hy[3] = {0, 0, 0}, Wz[3] = {0, 0, 0};
+  double El = 0, Es = 0, Eld[3] = {0, 0, 0}, Esd[3] = {0, 0, 0};
+  for (int i0 = 0; i0 < m; i0 += BCH) {
+#pragma unroll
+    for (int j = 0; j < BCH; ++j) {
+      const bool ok = i0 + j < m;
+      double px, py, pz, pa;
+      load(i0 + j, px, py, pz, pa);
+      const float4 xq = X4[b + i0 + j];
+      const double svj = ok ? (double)SV[b + i0 + j] : 0.0;
+      const double x0j = ok ? (double)xq.x + (double)xq.z : 0.0;
+      const double x1j = ok ? (double)xq.y + (double)xq.w : 0.0;
+      const double di[3] = {l0 - px, l1 - py, l2 - pz};
+      const double z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
+      const double z = sqrt(z2);
+      const double e = ok ? exp(-(z2 - d2) * inv2l2) : 0.0;
+      const double ae = pa * e;
+      const double si = ok ? exp(-al * (z - zmin)) * iS : 0.0;
+      const double ci = si * (al * (h - z) + 1.0);
+      const double dvdz = 2.0 * al * (-svj * ci * (ci + si) + si * V + ci * Pp);
+      const double rz = z > 0.0 ? 1.0 / z : 0.0;
+      const double dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        dxv[d] += dvdz * di[d] * rz;
+        Hy[d] += ae * dy * di[d];
+        Wz[d] += ae * z2 * di[d];
+        Eld[d] += e * x0j * di[d];
+        Esd[d] += e * x1j * di[d];
+      }
+      El += e * x0j;
+      Es += e * x1j;
+    }
+  }
+  const double l3 = lt * lt * lt;
+  for (int d = 0; d < 3; ++d) {
+    double r = s * (f * y[d] - Hy[d] / (lt * lt)) + gv * dxv[d];
+    if (mean_live) r += s * gm * w[d] / (f * u);
+    out_dx[d] = r;
+  }
+  double aXl = s * (y[0] * Eld[0] + y[1] * Eld[1] + y[2] * Eld[2]);
+  double aXs = s * (y[0] * Esd[0] + y[1] * Esd[1] + y[2] * Esd[2]);
+  if (mean_live) {
+    const double cm = -s * gm * lt * lt / (u * f);
+    aXl += cm * El;
+    aXs += cm * Es;
+  }
+  double dl = 0, ds = 0;
+  if (mean_live) dl += s * gm * (u2 - Za / f) / (lt * u);
+  dl += s * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]) / l3;
+  if (A.alpha_tied) dl += gv * dVa * (-2.0 * al / lt);
+  dl -= aXl;
+  if (A.uniform_noise) ds += gv * C2 - aXs;
+  out_th[0] = dl;
+  out_th[1] = ds;
+}
+
 // FP32: lanes take queries in argmin-cell order (perm), and each wave walks the
 // distinct argmin cells of its lanes -- after the sort usually one or two -- so the
 // cell index is wave-uniform and the cell's samples, factor and adjoint vectors are
@@ -265,6 +425,14 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
   float dx[3] = {0.f, 0.f, 0.f};
   double th[2] = {0.0, 0.0};
   bool todo = bc >= 0;
+  // per-lane inputs (the no-var_f path reads them once for all its cells)
+  const double x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
+  const double sgn = A.sign ? (double)A.sign[q] : 1.0;
+  const double gm = A.d_mean ? (double)A.d_mean[q] : 0.0;
+  double gg[3] = {0.0, 0.0, 0.0};
+  if (A.d_grad)
+    for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
+  const double gv = A.d_var ? (double)A.d_var[q] : 0.0;
   while (true) {
     unsigned key = todo ? (unsigned)bc : 0xffffffffu;
 #pragma unroll
@@ -272,14 +440,21 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
     key = (unsigned)__builtin_amdgcn_readfirstlane((int)key);
     if (key == 0xffffffffu) break;
     const int c = (int)key;
-    if (todo && bc == c) {
-      if constexpr (VARF) {
+    if constexpr (VARF) {
+      if (todo && bc == c) {
         float v[KSDF_MAX_M];
         query_vjp<float, true>(A, q, c, v, dx, th);
-      } else {
-        query_vjp<float, false>(A, q, c, nullptr, dx, th);
+        todo = false;
       }
-      todo = false;
+    } else {
+      double tdx[3], tth[2];
+      vjp_ff64(A, x0, x1, x2, sgn, gm, gg, gv, c, tdx, tth);
+      if (todo && bc == c) {
+        for (int d = 0; d < 3; ++d) dx[d] = (float)tdx[d];
+        th[0] = tth[0];
+        th[1] = tth[1];
+        todo = false;
+      }
     }
   }
   if (!active) return;
@@ -473,6 +648,7 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.D = m->adjoint_varf ? m->D32 : nullptr;
     A.centre64 = m->centre64; A.box = m->box32;
     A.ell = (float)m->ell; A.two_l2 = (float)two_l2; A.alpha = (float)m->alpha;
+    A.ell_d = m->ell; A.alpha_d = m->alpha; A.plo = m->plo32;
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
     if (Q > 0) {

@@ -180,7 +180,7 @@ struct FitArgs {
   float inv2l2_ff[2];
   float inv_l3_ff[2];
   int adjoint;           // also prepare the adjoint vectors xi (and D when non-null)
-  float* xi32;           // [nnz,2] (xi_l, xi_s)
+  float* xi32;           // [nnz+pad,4] (xi_l, xi_s) as float-float: hi_l, hi_s, lo_l, lo_s
   float* D32;            // packed dA/dl or null
   double* xi64;
   double* D64;
@@ -311,13 +311,19 @@ __device__ void write_cell(const T* Lp, const T* xs, const T* sv, const WVec<T>&
 }
 
 // Solve A x = rhs for the cell (block-cooperative): an FP32 solve with the factor,
-// then three refinement steps whose residuals rhs - A x are evaluated in
-// float-float from (Ahi, Alo).  rhs (rh, rl) and x (xh, xl) are float-float
-// arrays in LDS; res is scratch.  Ends with a barrier.
+// then refinement steps whose residuals rhs - A x are evaluated in float-float from
+// (Ahi, Alo), until a correction is below REFINE_TOL of |x| or no longer shrinks
+// (the float-float residual's own accuracy is reached), at most REFINE_MAX steps;
+// each step shrinks the error by about cond(A) * 2^-24.  rhs (rh, rl) and
+// x (xh, xl) are float-float arrays in LDS; res is scratch.  Ends with a barrier.
+constexpr int REFINE_MAX = 10;
+constexpr float REFINE_TOL = 1e-13f;
 __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float* Lf, int m,
                                  const float* rh, const float* rl, float* xh, float* xl,
                                  float* res) {
   const int lane = threadIdx.x & 63;
+  __shared__ int converged;
+  float prev = INFINITY;   // last correction (wave 0)
   __syncthreads();
   if (threadIdx.x < 64) {
     WVec<float> rv, y, x0;
@@ -338,7 +344,7 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
     }
   }
   __syncthreads();
-  for (int it = 0; it < 3; ++it) {
+  for (int it = 0; it < REFINE_MAX; ++it) {
     for (int i = threadIdx.x; i < m; i += blockDim.x) {
       ff acc{0.f, 0.f};
       for (int k = 0; k < m; ++k) {
@@ -358,6 +364,7 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
       }
       wave_forward<float>(Lf, m, rv, y);
       wave_backward<float>(Lf, m, y, dlt);
+      float dn = 0.f, xn = 0.f;
 #pragma unroll
       for (int t = 0; t < SLOTS; ++t) {
         const int i = t * 64 + lane;
@@ -365,10 +372,17 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
           const ff x2 = ff_add(ff{xh[i], xl[i]}, ff{dlt.s[t], 0.f});
           xh[i] = x2.hi;
           xl[i] = x2.lo;
+          dn = fmaxf(dn, fabsf(dlt.s[t]));
+          xn = fmaxf(xn, fabsf(x2.hi));
         }
       }
+      dn = wave_max(dn);
+      xn = wave_max(xn);
+      if (threadIdx.x == 0) converged = !(dn > REFINE_TOL * xn) || !(dn < 0.5f * prev);
+      prev = dn;
     }
     __syncthreads();
+    if (converged) break;
   }
 }
 
@@ -376,9 +390,9 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
 // float-float (about 44 bits: exact cell-local differences, a float-float exp),
 // its leading float part is factored in FP32, and a = A^{-1} 1 is refined with
 // residuals r = 1 - A a evaluated in float-float and corrections solved with the
-// FP32 factor.  Each step shrinks the error by about cond(A) * 2^-24, so three
-// steps bring a to the accuracy of its float-float residual before it is rounded
-// to FP32.  MB is the bucket's largest m and sizes the LDS arrays.
+// FP32 factor.  Each step shrinks the error by about cond(A) * 2^-24; the steps
+// continue until a reaches the accuracy of its float-float residual, and a is kept
+// as a float-float pair.  MB is the bucket's largest m and sizes the LDS arrays.
 template <int MB>
 __host__ __device__ constexpr int fit32_smem_floats() {
   return 3 * (MB * (MB + 1) / 2) + 6 * MB + 10 * MB + 4;
@@ -496,7 +510,10 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
         rl[i] = g.lo;
       }
       ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
-      for (int i = threadIdx.x; i < m; i += blockDim.x) A.xi32[2L * (b + i)] = xih[i] + xil[i];
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        A.xi32[4L * (b + i)] = xih[i];
+        A.xi32[4L * (b + i) + 2] = xil[i];
+      }
       if (!A.svar) {
         __syncthreads();
         for (int i = threadIdx.x; i < m; i += blockDim.x) {
@@ -505,8 +522,10 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
         }
         ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
       }
-      for (int i = threadIdx.x; i < m; i += blockDim.x)
-        A.xi32[2L * (b + i) + 1] = A.svar ? 0.f : xih[i] + xil[i];
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        A.xi32[4L * (b + i) + 1] = A.svar ? 0.f : xih[i];
+        A.xi32[4L * (b + i) + 3] = A.svar ? 0.f : xil[i];
+      }
       if (A.D32) {
         const float il3f = A.inv_l3_ff[0];
         for (int e = threadIdx.x; e < m * (m + 1) / 2; e += blockDim.x) {
@@ -618,8 +637,11 @@ __device__ void fit64_cell(const FitArgs& A, int c, double* smem) {
           if (i < m) {
             const double xsv = A.svar ? 0.0 : xs_.s[t2];
             if (A.emit32) {
-              A.xi32[2L * (b + i)] = (float)xl_.s[t2];
-              A.xi32[2L * (b + i) + 1] = (float)xsv;
+              const float hl = (float)xl_.s[t2], hs = (float)xsv;
+              A.xi32[4L * (b + i)] = hl;
+              A.xi32[4L * (b + i) + 1] = hs;
+              A.xi32[4L * (b + i) + 2] = (float)(xl_.s[t2] - (double)hl);
+              A.xi32[4L * (b + i) + 3] = (float)(xsv - (double)hs);
             } else {
               A.xi64[2L * (b + i)] = xl_.s[t2];
               A.xi64[2L * (b + i) + 1] = xsv;

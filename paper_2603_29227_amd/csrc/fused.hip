@@ -1,10 +1,10 @@
 // Persistent fused fit + query launch (FP32 models, cells with uneven m).
 //
-// One launch of resident workgroups (512 threads) drains a task queue:
+// One launch of resident workgroups (256 threads) drains a task queue:
 //   tasks [0, n_fit)            fit one cell with the whole workgroup, largest m first
 //                               (fit32_cell of the cell's m bucket, FP64 refit in place
 //                               when the condition estimate asks for it);
-//   tasks [n_fit, n_fit + n_q)  8 query tiles of 64 bucketed queries, one per wave.
+//   tasks [n_fit, n_fit + n_q)  4 query tiles of 64 bucketed queries, one per wave.
 // Every fit task is dequeued before any query task, so a workgroup that holds a query
 // task waits (acquire) only for fit tasks that other running workgroups already hold:
 // the wait always ends.  No query reads cell data before every fit has released its
@@ -16,7 +16,7 @@
 namespace ksdf {
 namespace {
 
-constexpr int FT = 512;
+constexpr int FT = 256;
 constexpr int WAVES = FT / 64;
 
 struct FusedCtl {
@@ -28,73 +28,69 @@ struct FusedCtl {
   long n_qtasks;
 };
 
-// Separate (not inlined) bodies keep the register allocation of the fit and query
-// parts apart; the kernel then needs the larger of the two, not their union.
+// Fit tasks and query tiles run in two consecutive loops (a workgroup's first query
+// task ends its fit loop), so values that the compiler keeps live across one loop are
+// not live in the other and the kernel needs the registers of the larger part, not of
+// both.
 template <int MB>
-__device__ __noinline__ bool fit32_task(const FitArgs& F, int c, float* smem) {
+__device__ __forceinline__ bool fit32_task(const FitArgs& F, int c, float* smem) {
   return fit32_cell<MB>(F, c, smem);
-}
-__device__ __noinline__ void fit64_task(const FitArgs& F, int c, double* smem) {
-  fit64_cell(F, c, smem);
-}
-template <int KM, int MB>
-__device__ __noinline__ void query_task(const FastArgs& Q, long sq) {
-  query_tile<KM, MB>(Q, sq);
 }
 
 template <int KM, int MB, int MF>
 __global__ void __launch_bounds__(FT) fused_kernel(FitArgs F, FastArgs Q, FusedCtl C) {
   extern __shared__ float smem[];
   __shared__ long task_sh;
-  bool fits_seen = false;
-  while (true) {
+  const long n_total = C.n_fit + C.n_qtasks;
+  auto grab = [&]() -> long {
     __syncthreads();
     if (threadIdx.x == 0) task_sh = atomicAdd(C.next, 1);
     __syncthreads();
-    const long t = task_sh;
-    if (t < C.n_fit) {
-      const int c = C.order[t];
-      const int m = F.offsets[c + 1] - F.offsets[c];
-      bool need64;
-      if (m <= 16) {
-        need64 = fit32_task<16>(F, c, smem);
-      } else if (m <= 32 || MF <= 32) {
-        need64 = fit32_task<32>(F, c, smem);
-      } else if (m <= 64 || MF <= 64) {
-        if constexpr (MF >= 64) need64 = fit32_task<64>(F, c, smem);
-        else need64 = true;
-      } else {
-        if constexpr (MF >= 128) need64 = fit32_task<128>(F, c, smem);
-        else need64 = true;
-      }
-      if (need64) fit64_task(F, c, reinterpret_cast<double*>(smem));
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(C.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else if (t < C.n_fit + C.n_qtasks) {
-      if (!fits_seen) {
-        if (threadIdx.x == 0) {
-          long spins = 0;
-          while (__hip_atomic_load(C.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < C.n_fit) {
-            __builtin_amdgcn_s_sleep(8);
-            if (++spins > (1L << 26)) {
-              atomicExch(C.timeout, 1);
-              break;
-            }
-          }
-        }
-        __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        fits_seen = true;
-      }
-      const int wave = threadIdx.x / 64;
-      const long sq = ((t - C.n_fit) * WAVES + wave) * 64 + (threadIdx.x & 63);
-      query_tile<KM, MB>(Q, sq);
+    return task_sh;
+  };
+  long t = grab();
+  while (t < C.n_fit) {
+    const int c = C.order[t];
+    const int m = F.offsets[c + 1] - F.offsets[c];
+    bool need64;
+    if (m <= 16) {
+      need64 = fit32_task<16>(F, c, smem);
+    } else if (m <= 32 || MF <= 32) {
+      need64 = fit32_task<32>(F, c, smem);
+    } else if (m <= 64 || MF <= 64) {
+      if constexpr (MF >= 64) need64 = fit32_task<64>(F, c, smem);
+      else need64 = true;
     } else {
-      break;
+      if constexpr (MF >= 128) need64 = fit32_task<128>(F, c, smem);
+      else need64 = true;
+    }
+    if (need64) fit64_cell(F, c, reinterpret_cast<double*>(smem));
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_add(C.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    t = grab();
+  }
+  if (t >= n_total) return;
+  // every fit task has been taken: wait until they have all been released
+  if (threadIdx.x == 0) {
+    long spins = 0;
+    while (__hip_atomic_load(C.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < C.n_fit) {
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins > (1L << 26)) {
+        atomicExch(C.timeout, 1);
+        break;
+      }
     }
   }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const int wave = threadIdx.x / 64;
+  do {
+    const long sq = ((t - C.n_fit) * WAVES + wave) * 64 + (threadIdx.x & 63);
+    query_tile<KM, MB>(Q, sq);
+    t = grab();
+  } while (t < n_total);
 }
 
 __global__ void fused_reset_kernel(int* ctl) {

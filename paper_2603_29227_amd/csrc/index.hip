@@ -13,6 +13,7 @@
 // prefix writes the list in id order.  Built once per model (structure only).
 #include <algorithm>
 #include <cmath>
+#include <utility>
 
 #include "ksdf_internal.h"
 
@@ -223,7 +224,23 @@ int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi) {
     KSDF_HIP_TRY(hipDeviceSynchronize());
     (void)hipFree(bound);
     (void)hipFree(counts);
-    m->device_bytes += (n_boxes + 1 + std::max<long>(total, 1)) * sizeof(int);
+    // Z-order rank of every box: query bucketing orders its bins by it, so that the
+    // queries of one wave stay spatially compact also where they are sparse
+    std::vector<std::pair<uint64_t, int>> z(n_boxes);
+    for (long b = 0; b < n_boxes; ++b) {
+      const long bx = b % X.dims[0], by = (b / X.dims[0]) % X.dims[1], bz = b / ((long)X.dims[0] * X.dims[1]);
+      uint64_t code = 0;
+      for (int bit = 0; bit < 21; ++bit)
+        code |= (((uint64_t)(bx >> bit) & 1) << (3 * bit)) | (((uint64_t)(by >> bit) & 1) << (3 * bit + 1)) |
+                (((uint64_t)(bz >> bit) & 1) << (3 * bit + 2));
+      z[b] = {code, (int)b};
+    }
+    std::sort(z.begin(), z.end());
+    std::vector<int> rank(n_boxes);
+    for (long r = 0; r < n_boxes; ++r) rank[z[r].second] = (int)r;
+    KSDF_HIP_TRY(hipMalloc(&X.box_rank, n_boxes * sizeof(int)));
+    KSDF_HIP_TRY(hipMemcpy(X.box_rank, rank.data(), n_boxes * sizeof(int), hipMemcpyHostToDevice));
+    m->device_bytes += (2 * n_boxes + 1 + std::max<long>(total, 1)) * sizeof(int);
   }
   return KSDF_OK;
 }

@@ -38,6 +38,7 @@ struct CandidateIndex {
   long entries = 0;
   int* box_off = nullptr;      // [n_boxes+1]
   int* box_list = nullptr;     // [entries] cell ids, ascending within a box
+  int* box_rank = nullptr;     // [n_boxes] position of each box in Z (Morton) order
   int max_list = 0;
 };
 
@@ -94,7 +95,7 @@ struct ksdf_model {
   bool adjoint_varf_alloc = false;
   bool adjoint = false;         // xi vectors prepared by the last fit
   bool adjoint_varf = false;    // packed dA/dl prepared by the last fit
-  float* xi32 = nullptr;        // [nnz+pad,2] xi_l = A^{-1}(dA/dl)a, xi_s = A^{-1}a
+  float* xi32 = nullptr;        // [nnz+pad,4] xi_l = A^{-1}(dA/dl)a, xi_s = A^{-1}a (float-float)
   double* xi64 = nullptr;       // [nnz,2] (FP64 models)
   float* D32 = nullptr;         // packed dA/dl (FP32 models)
   double* D64 = nullptr;        // packed dA/dl (FP64 models)

@@ -44,12 +44,14 @@ struct FastArgs {
   int dims[3];
   long n_boxes;
   const int* __restrict__ box_off;
+  const int* __restrict__ box_rank;
   const int* __restrict__ box_list;
   float c2;          // log2(e) / (2 l^2)
   float two_l2;      // 2 l^2
   float alpha_l2e;   // alpha * log2(e)
   float alpha;
   float inv2l2_ff[2];
+  float far2;        // |x - centre|^2 beyond which pass 2 takes the far-field exponent
 };
 
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
@@ -92,9 +94,16 @@ __device__ __forceinline__ long box_key(const FastArgs& A, float qx, float qy, f
 // ---------------------------------------------------------------------------
 // float-float re-evaluation of one cell's u^2 for one lane (rare path)
 // ---------------------------------------------------------------------------
-__device__ float cell_u2_ff(const FastArgs& A, int c, float qx, float qy, float qz, float d2ref) {
+__device__ float cell_u2_ff(const FastArgs& A, int c, float qx, float qy, float qz) {
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const float4 ctr = A.centre[c];
+  // scaling reference: the nearest sample (FP32), so that no term underflows
+  float d2ref = INFINITY;
+  for (int i = 0; i < m; ++i) {
+    const float4 p = A.ps[b + i];
+    const float dx = (qx - ctr.x) - p.x, dy = (qy - ctr.y) - p.y, dz = (qz - ctr.z) - p.z;
+    d2ref = fminf(d2ref, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+  }
   const ff lx = ff_two_sum(qx, -ctr.x), ly = ff_two_sum(qy, -ctr.y), lz = ff_two_sum(qz, -ctr.z);
   const ff inv{A.inv2l2_ff[0], A.inv2l2_ff[1]};
   ff f{0.f, 0.f};
@@ -247,11 +256,12 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
   }
 
   // ---- pass 1: per-candidate u^2 with error bounds, wave-uniform over the union
-  float cu2[KM], cdl[KM];
+  float cu2[KM], cdl[KM], cref[KM];
 #pragma unroll
   for (int r = 0; r < KM; ++r) {
     cu2[r] = INFINITY;
     cdl[r] = 0.f;
+    cref[r] = 0.f;
   }
   unsigned pending = active ? ((1u << n) - 1u) : 0u;
   float best = INFINITY, best_del = 0.f;
@@ -287,6 +297,7 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
       float f = 0.f, R = 0.f, RZ = 0.f;
       for (int pass = 0; pass < 2; ++pass) {
         const float c2d = c2 * d2ref;
+        float emax = 0.f;
         f = 0.f;
         R = 0.f;
         RZ = 0.f;
@@ -296,20 +307,28 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
           for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
 #pragma unroll
           for (int j = 0; j < CH; ++j) {
-            const float aw = (i0 + j < m) ? P[j].w : 0.f;
+            // entries past m belong to the next cell (the store is padded): their
+            // offsets from this cell's centre can be far nearer than d2ref, and exp2
+            // would overflow, so their term is masked, not weighted by 0
+            const bool in = i0 + j < m;
+            const float aw = P[j].w;
             const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
             const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float e = __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d));
+            const float e = in ? __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d)) : 0.f;
             const float ae = fabsf(aw) * e;
             f = fmaf(aw, e, f);
             R += ae;
             RZ = fmaf(ae, z2, RZ);
+            emax = fmaxf(emax, e);
           }
         }
-        // every term underflowed against the box bound (far queries, loose box):
-        // redo once against the nearest sample
-        if (!__ballot(ev && !(R > 0.f))) break;
-        if (ev && !(R > 0.f)) {
+        // far from the cell, the nearest sample can lie so much farther than the box's
+        // nearest point that every term is tiny against the box reference and the
+        // smaller ones underflow (FP32 exponents end at -126): redo once against the
+        // nearest sample, which gives its own term 1
+        const bool low = ev && !(emax >= 0x1p-24f);
+        if (!__ballot(low)) break;
+        if (low) {
           float d2 = INFINITY;
           for (int i = 0; i < m; ++i) {
             const float4 p = A.ps[b + i];
@@ -333,6 +352,9 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
           cu2[r] = u2;
           cdl[r] = del;
         }
+#pragma unroll
+      for (int r = 0; r < KM; ++r)
+        if (r == slot) cref[r] = d2ref;
       pending &= ~(1u << slot);
       if (u2 < best) {
         best = u2;
@@ -363,10 +385,7 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
 #pragma unroll
         for (int r = 0; r < KM; ++r)
           if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
-            const int c = cid[r];
-            const float4 ctr = A.centre[c];
-            const float d2lb = aabb_d2(A.box + 8L * c, qx - ctr.x, qy - ctr.y, qz - ctr.z);
-            cu2[r] = cell_u2_ff(A, c, qx, qy, qz, d2lb);
+            cu2[r] = cell_u2_ff(A, cid[r], qx, qy, qz);
           }
         bu = INFINITY;
         bc = -1;
@@ -380,6 +399,12 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
       best = bu;
     }
   }
+  // the argmin cell's scaling reference from pass 1 (box bound, or its nearest sample
+  // where the box bound would have underflowed the terms)
+  float bref = 0.f;
+#pragma unroll
+  for (int r = 0; r < KM; ++r)
+    if (r < n && cid[r] == bc) bref = cref[r];
 
   // ---- pass 2: argmin cell outputs, wave-uniform over the distinct argmin cells
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, vv = 0.f, var = 0.f;
@@ -395,10 +420,18 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
     const float* Lc = A.L + A.loff[c];
     const float4 ctr = A.centre[c];
     const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
-    const float d2lb = aabb_d2(A.box + 8L * c, lx, ly, lz);
-    const float c2d = c2 * d2lb;
+    const float c2d = c2 * bref;
     const float ginv = __builtin_amdgcn_exp2f(-c2d);     // exp(-d^2 / 2 l^2)
-    const float zref = __builtin_amdgcn_sqrtf(d2lb);
+    const float zref = __builtin_amdgcn_sqrtf(bref);
+    // Far from the cell the exponent c2 (d^2 - z_i^2) is a small difference of large
+    // squares, and its FP32 rounding (about eps c2 z^2 per sample) tilts the direction
+    // w/|w|.  There it is formed as c2 (d^2 - |l|^2) + c2 (2 l.p_i - |p_i|^2): the
+    // first part's rounding is common to every sample and cancels in the direction,
+    // the per-sample part is small.  Near the cell the direct form is the accurate one.
+    const float ll = fmaf(lz, lz, fmaf(ly, ly, lx * lx));
+    const bool farl = ll > A.far2;
+    const float k0 = c2 * (bref - ll);
+    const float tx = 2.f * c2 * lx, ty = 2.f * c2 * ly, tz = 2.f * c2 * lz;
     if (mine) {
       float v[MB];
       float S = 0.f, T1 = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
@@ -416,10 +449,13 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
 #pragma unroll
           for (int j = 0; j < CH; ++j) {
             const bool in = i0 + j < m;
-            const float aw = in ? P[j].w : 0.f;
+            const float aw = P[j].w;
             const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
             const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float e = __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d));
+            const float pp = fmaf(P[j].z, P[j].z, fmaf(P[j].y, P[j].y, P[j].x * P[j].x));
+            const float arg_far = fmaf(tx, P[j].x, fmaf(ty, P[j].y, fmaf(tz, P[j].z, fmaf(-c2, pp, k0))));
+            const float arg = farl ? arg_far : fmaf(z2, -c2, c2d);
+            const float e = in ? __builtin_amdgcn_exp2f(arg) : 0.f;   // see pass 1
             const float ae = aw * e;
             a0 = fmaf(ae, dx, a0);
             a1 = fmaf(ae, dy, a1);
@@ -497,7 +533,7 @@ __global__ void bin_kernel(FastArgs A, int* keys, int* counts, long n_bins) {
   if (q >= A.Q) return;
   int sub;
   const long b = box_key(A, A.pts[3 * q], A.pts[3 * q + 1], A.pts[3 * q + 2], &sub);
-  const int key = b < 0 ? (int)(n_bins - 1) : (int)(b * A.sub * A.sub * A.sub + sub);
+  const int key = b < 0 ? (int)(n_bins - 1) : (int)((long)A.box_rank[b] * A.sub * A.sub * A.sub + sub);
   keys[q] = key;
   atomicAdd(&counts[key], 1);
 }
@@ -630,12 +666,14 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   A.sub = sub_of(m);
   A.n_boxes = m->index.n_boxes;
   A.box_off = m->index.box_off;
+  A.box_rank = m->index.box_rank;
   A.box_list = m->index.box_list;
   const double two_l2 = 2.0 * m->ell * m->ell;
   A.c2 = (float)(1.4426950408889634 / two_l2);
   A.two_l2 = (float)two_l2;
   A.alpha = (float)m->alpha;
   A.alpha_l2e = (float)(m->alpha * 1.4426950408889634);
+  A.far2 = (float)(4.0 * m->h * m->h);
   const double inv = 1.0 / two_l2;
   A.inv2l2_ff[0] = (float)inv;
   A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);

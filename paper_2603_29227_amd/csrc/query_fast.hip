@@ -1,9 +1,10 @@
 // Query forward, FP32 model: the per-point SDF prediction of Sec. IV-B laid out for
 // 64-wide wavefronts.
 //
-// 1. Bucket.  Queries are counting-sorted by (candidate-index box, Morton index of
-//    a sub-box of it) so the 64 queries of a wave sit in one small region and
-//    mostly share their K nearest cells (Sec. IV-B.1, "K nearest GPs").
+// 1. Bucket.  Queries are counting-sorted by (Z-order rank of their candidate-index
+//    box, Morton index of a sub-box of it) so the 64 queries of a wave sit in one
+//    small region and mostly share their K nearest cells (Sec. IV-B.1, "K nearest
+//    GPs"), also where queries are sparse.
 // 2. Candidates.  Each lane keeps the K nearest occupied cell centres of its box's
 //    list (fixed FP32 rounding sequence, ties by id).
 // 3. Per-candidate UDF (eq. log_gp_posterior_mean with App. D scaling, Table I).

@@ -88,6 +88,9 @@ class Box:
     def inside(self, p, tol=1e-9):
         return np.all((p >= self.lo - tol) & (p <= self.hi + tol), axis=-1)
 
+    def bounds(self):
+        return np.asarray(self.lo, np.float64), np.asarray(self.hi, np.float64)
+
 
 @dataclasses.dataclass
 class Cylinder:        # vertical
@@ -100,6 +103,10 @@ class Cylinder:        # vertical
     def inside(self, p, tol=1e-9):
         d2 = (p[..., 0] - self.cx) ** 2 + (p[..., 1] - self.cy) ** 2
         return (d2 <= (self.r + tol) ** 2) & (p[..., 2] >= self.z0 - tol) & (p[..., 2] <= self.z1 + tol)
+
+    def bounds(self):
+        return (np.array([self.cx - self.r, self.cy - self.r, self.z0]),
+                np.array([self.cx + self.r, self.cy + self.r, self.z1]))
 
 
 @dataclasses.dataclass
@@ -214,14 +221,34 @@ def _cyl_surface(rng, c: Cylinder, spacing, bottom=False):
     return np.concatenate(ps), np.concatenate(ns)
 
 
+def _inside_any(p, solids, tol=1e-9):
+    """Mask of the points of p inside any of the solids (each solid's own test, with
+    its tolerance); solids with an axis-aligned bound only test the points whose x
+    falls in that bound (points sorted by x once)."""
+    out = np.zeros(len(p), bool)
+    bounded = [s for s in solids if hasattr(s, "bounds")]
+    for s in solids:
+        if not hasattr(s, "bounds"):
+            out |= s.inside(p, tol=tol)
+    if bounded and len(p):
+        order = np.argsort(p[:, 0], kind="stable")
+        xs = p[order, 0]
+        pad = tol + 1e-6
+        for s in bounded:
+            lo, hi = s.bounds()
+            a = np.searchsorted(xs, lo[0] - pad, "left")
+            b = np.searchsorted(xs, hi[0] + pad, "right")
+            idx = order[a:b]
+            if len(idx):
+                out[idx[s.inside(p[idx], tol=tol)]] = True
+    return out
+
+
 def _drop_inside(parts, solids):
     """Union surface: drop each part's samples that lie in another part's solid."""
     keep_p, keep_n = [], []
     for k, (p, n) in enumerate(parts):
-        mask = np.ones(len(p), bool)
-        for j, s in enumerate(solids):
-            if j != k:
-                mask &= ~s.inside(p)
+        mask = ~_inside_any(p, [s for j, s in enumerate(solids) if j != k])
         keep_p.append(p[mask])
         keep_n.append(n[mask])
     return keep_p, keep_n
@@ -262,10 +289,7 @@ class RoomScene:
 
     def free(self, p):
         """True where p lies in free space (inside the room, outside every object)."""
-        f = ~self.walls.inside(p, tol=0.0)
-        for s in self.boxes + self.cyls:
-            f &= ~s.inside(p, tol=0.0)
-        return f
+        return ~_inside_any(p, [self.walls] + self.boxes + self.cyls, tol=0.0)
 
     def sample(self, rng_j, rng_n, spacing, noise_std, density=None):
         """density: optional per-object multiplier (room faces first, then boxes, cylinders)."""
@@ -309,10 +333,7 @@ class TerrainScene:
         return [self.terrain] + self.boxes + self.cyls
 
     def free(self, p):
-        f = ~self.terrain.inside(p, tol=0.0)
-        for s in self.boxes + self.cyls:
-            f &= ~s.inside(p, tol=0.0)
-        return f
+        return ~_inside_any(p, [self.terrain] + self.boxes + self.cyls, tol=0.0)
 
     def sample(self, rng_j, rng_n, spacing, noise_std):
         n1 = int(np.ceil(100.0 / spacing))

@@ -6,7 +6,8 @@ launch or per-bucket fits followed by the query launch, and the smallest fit m b
 (16, 32, 64: cells below it run in the kernel sized for it).  ``tune`` times every
 combination on the caller's own data (the fit+query step, median of a few runs, after
 a warm-up) and keeps the fastest; the outputs do not depend on the choice.  Results
-are cached in a JSON file keyed by device name and a workload signature (cell count,
+are cached in a JSON file keyed by device (architecture and compute-unit count) and a
+workload signature (cell count,
 m histogram, query count to a power of two, precision, K), so a later process
 applies them without timing (``apply``).
 """
@@ -31,7 +32,8 @@ def signature(model, n_queries: int) -> str:
     hist = [int(np.sum(m <= 16)), int(np.sum((m > 16) & (m <= 32))), int(np.sum((m > 32) & (m <= 64))),
             int(np.sum(m > 64))]
     qb = 1 << max(int(n_queries) - 1, 0).bit_length()
-    name = torch.cuda.get_device_name(model.device).replace(" ", "_")
+    props = torch.cuda.get_device_properties(model.device)
+    name = f"{props.gcnArchName.split(':')[0]}x{props.multi_processor_count}"
     return (f"{name}|cells={model.n_cells}|mhist={'/'.join(map(str, hist))}|q<={qb}|"
             f"prec={model.precision}|k={model.hyper.k_fuse}")
 

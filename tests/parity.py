@@ -7,6 +7,9 @@ Tolerances (the parity contract):
   grad   |d| <= tau where the oracle's cancellation ratio sum|a_i| e_i |x*-x_i| / |w|
          is <= 1e3 (elsewhere the direction is ill-conditioned for FP32 weights: the
          measured FP32 error grows as about 3e-8 x ratio; counted, not compared).
+         More than 2 m from the surface the limit is 2.5e2: there the per-sample
+         spread of the kernel exponent grows like |x*-c| h / l^2, its FP32 rounding
+         adds to the cancellation, and the measured error is about 4e-7 x ratio.
   var    |d| <= 1e-3 |ref| (FP32) / 1e-10 |ref| (FP64).
   var_f  |d| <= 1e-3 (FP32) / 1e-10 (FP64), relative to the prior variance k(x,x) = 1.
 Near-ties of the min-fusion: the GPU's argmin cell is accepted when it is one of
@@ -19,9 +22,10 @@ from __future__ import annotations
 import numpy as np
 
 TOL = {
-    "fp32": dict(tau=1e-4, tau_sq=1e-5, var=1e-3, var_f=1e-3, ratio=1e3),
-    "fp64": dict(tau=1e-10, tau_sq=1e-11, var=1e-10, var_f=1e-10, ratio=1e6),
+    "fp32": dict(tau=1e-4, tau_sq=1e-5, var=1e-3, var_f=1e-3, ratio=1e3, ratio_far=2.5e2),
+    "fp64": dict(tau=1e-10, tau_sq=1e-11, var=1e-10, var_f=1e-10, ratio=1e6, ratio_far=1e6),
 }
+FAR = 2.0   # metres from the surface where the far-field ratio limit applies
 
 
 def _mean_ok(d, ref, ell, t):
@@ -69,7 +73,8 @@ def compare(gpu: dict, ora: dict, ell: float, precision: str, sign=None) -> dict
     crat = ora["cratio"][idx, c]
     gg = np.asarray(gpu["grad"], np.float64)[idx]
     gerr = np.linalg.norm(gg - cg, axis=1)
-    well = crat <= t["ratio"]
+    far = np.abs(ora["mean"][idx]) > FAR
+    well = crat <= np.where(far, t["ratio_far"], t["ratio"])
     rep["exempt_grad"] = int(np.sum(~well))
     m_grad = np.ones(Q, bool)
     m_grad[idx] = ~well | (gerr <= t["tau"])
@@ -99,3 +104,13 @@ def assert_parity(gpu, ora, ell, precision, sign=None, label=""):
     rep = compare(gpu, ora, ell, precision, sign)
     assert not rep["failures"], f"{label} parity failures {rep['failures']} report {rep}"
     return rep
+
+
+def hyper_within(dh, odh, pp_abs, rel=1e-3, per_term=1e-4):
+    """d_hyper against the oracle.  d_hyper is a sum over queries of terms that can
+    cancel; each term carries the FP32 error of its own query, so the sum is held to
+    rel x |sum| or, where the terms cancel, per_term x sum_q |term_q| (per_term = the
+    forward tolerance).  Returns (ok per component, |error|, allowed)."""
+    err = np.abs(np.asarray(dh) - np.asarray(odh))
+    allowed = np.maximum(rel * np.abs(odh), per_term * np.asarray(pp_abs))
+    return err <= allowed, err, allowed

@@ -2,7 +2,9 @@
 
 Tolerances: FP64 path within 1e-8 (relative per point, and for d_hyper); FP32 path
 d_points within 1e-3 relative (norm-wise per point) and d_hyper within 1e-3
-relative (with a var_f cotangent 3e-3 per point and 5e-3 for d_hyper: beta = A^{-1} k
+relative, or, where the per-query terms of that sum cancel, within 1e-4 of
+sum_q |term_q| (tests/parity.py hyper_within; the oracle gives the terms)
+(with a var_f cotangent 3e-3 per point and 5e-3 for d_hyper: beta = A^{-1} k
 comes from FP32 triangular solves with cond(A) up to 1e6, and the noise derivative
 carries |beta|^2).  Excluded and counted: points whose argmin cell differs between GPU and
 oracle (a near-tie of the min-fusion, where the derivative is that of another
@@ -19,6 +21,7 @@ import torch
 
 import oracle
 from paper_2603_29227_amd import ksdf, scenes
+from tests.parity import hyper_within
 
 pytestmark = pytest.mark.gpu
 
@@ -65,8 +68,8 @@ def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, ma
     oc = _ocells(wl, cells)
     cp = 64 if prec == "fp64" else 32
     kw = {} if mode == 1 else cot
-    _, odp, odh = oracle.vjp(wl.points, oc, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign,
-                             mode=mode, **kw)
+    _, odp, odh, opp = oracle.vjp(wl.points, oc, q, wl.ell, wl.noise_var, cand_prec=cp,
+                                  sign=sign, mode=mode, per_point=True, **kw)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
     o = oracle.query(wl.points, oc, f, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign)
     ok = (am == o["argmin"]) & (o["status"] & 3 == 0) & (o["u_best"] > 1e-3) & (o["ratio"] <= max_ratio)
@@ -77,10 +80,14 @@ def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, ma
     err = np.linalg.norm(dp - odp, axis=1) / scale
     bad = np.where(ok & (err > tol_p))[0]
     assert len(bad) == 0, f"{len(bad)} points over tolerance, worst {err[ok].max():.3g} at {bad[:5]}"
-    # d_hyper sums every query, the excluded ones included: compare as a whole
+    # d_hyper sums every query, the excluded ones included: compare as a whole, with
+    # the allowance for cancelling per-query terms (tests/parity.py hyper_within)
     rel = np.abs(dh - odh) / np.maximum(np.abs(odh), 1e-12)
+    hok, herr, hallow = hyper_within(dh, odh, np.abs(opp).sum(0), rel=tol_h, per_term=tol_h / 10)
+    print(f"d_hyper {dh} oracle {odh} sum|term| {np.abs(opp).sum(0)} err {herr} allowed {hallow}",
+          flush=True)
     if check_hyper:
-        assert np.all(rel <= tol_h), f"d_hyper {dh} vs oracle {odh} rel {rel}"
+        assert np.all(hok), f"d_hyper {dh} vs oracle {odh}: error {herr} over {hallow}"
     return err[ok].max(), rel
 
 

@@ -1,0 +1,170 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark uses.
+
+The GPU answers every query of the workload; the oracle recomputes a seeded sample
+of them one by one (the whole fit, then the sampled queries), and the sample is
+compared element by element with tests/parity.py's tolerances.  Samples mix uniform
+picks with queries near the surface, where the square root and cancellation make the
+FP32 path hardest.  The backward is checked against the oracle's dual-number VJP on
+the first 1,024 trajectory points.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes, tune
+from tests.parity import assert_parity, hyper_within
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _ocells(wl, cells):
+    return oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                        np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+
+
+def _model(wl, query_box=None, adjoint=False):
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       precision="fp32", query_box=query_box, adjoint=adjoint)
+    return model, cells
+
+
+def _sample(out, n_uniform, n_near, seed):
+    rng = np.random.default_rng(seed)
+    mean = out["mean"].cpu().numpy()
+    Q = len(mean)
+    uni = rng.choice(Q, size=min(n_uniform, Q), replace=False)
+    near = np.where(np.abs(mean) < 0.05)[0]
+    near = rng.choice(near, size=min(n_near, len(near)), replace=False) if len(near) else near
+    return np.unique(np.concatenate([uni, near]))
+
+
+def _check_sample(wl, cells, out, idx, label):
+    oc = _ocells(wl, cells)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, wl.queries[idx], wl.ell, wl.noise_var, cand_prec=32,
+                     sign=wl.sign[idx], all_candidates=True)
+    g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
+    rep = assert_parity(g, o, wl.ell, "fp32", wl.sign[idx], label=label)
+    print(f"{label}: {len(idx)} sampled queries, mean err max {rep['mean_err_max']:.3g}, "
+          f"grad exempt {rep['exempt_grad']}, near ties {rep['near_tie']}", flush=True)
+    return rep
+
+
+def test_room_grid_full_size():
+    _say("room 256^3 grid, 16,777,216 queries, sampled oracle check")
+    wl = scenes.room_workload("grid")
+    model, cells = _model(wl, query_box=(np.zeros(3), np.array([10.0, 8.0, 3.0])))
+    tune.apply(model, len(wl.queries))
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    out = model.fit_query(pts, q, sg)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    assert int(((st & 1) != 0).sum()) == 0
+    idx = _sample(out, 12000, 4000, 20)
+    _check_sample(wl, cells, out, idx, "room grid")
+    model.close()
+
+
+def test_room_batch_uneven_full_size():
+    _say("room batch, uneven m on [8,128], 4,194,304 random queries")
+    wl = scenes.room_workload("batch")
+    model, cells = _model(wl, query_box=(np.zeros(3), np.array([10.0, 8.0, 3.0])))
+    m = cells.m
+    assert m.min() >= 8 and m.max() > 100, (m.min(), m.max())
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    model.set_tuning(fused=1)
+    fused = model.fit_query(pts, q, sg)
+    torch.cuda.synchronize()
+    fused = {k: v.clone() for k, v in fused.items()}
+    model.set_tuning(fused=0)
+    sep = model.fit_query(pts, q, sg)
+    torch.cuda.synchronize()
+    for k in fused:
+        assert torch.equal(fused[k], sep[k]), f"fused and separate launches differ in {k}"
+    idx = _sample(sep, 12000, 4000, 21)
+    _check_sample(wl, cells, sep, idx, "room batch")
+    model.close()
+
+
+def _softplus_cotangents(out):
+    sd = torch.sqrt(torch.clamp_min(out["var"], 1e-30))
+    s = torch.sigmoid(0.3 - out["mean"] + sd)
+    return -s, s / (2 * sd)
+
+
+def _backward_check(wl, cells, model, tq, tsg, label):
+    q = torch.from_numpy(tq).cuda()
+    sg = torch.from_numpy(tsg).cuda()
+    out = model.query(q, sg)
+    dm, dv = _softplus_cotangents(out)
+    dp, _ = model.backward(q, sg, dm.contiguous(), None, dv.contiguous(), None, argmin=out["argmin"])
+    torch.cuda.synchronize()
+    assert torch.isfinite(dp).all()
+    # FP64 check on the first 1,024 points: their own backward (d_hyper of that set)
+    n = 1024
+    q1, s1 = q[:n].contiguous(), sg[:n].contiguous()
+    o1 = model.query(q1, s1)
+    dm1, dv1 = _softplus_cotangents(o1)
+    dp1, dh1 = model.backward(q1, s1, dm1.contiguous(), None, dv1.contiguous(), None,
+                              argmin=o1["argmin"])
+    torch.cuda.synchronize()
+    assert torch.equal(dp1, dp[:n]), "a point's VJP depends on the batch it is in"
+    oc = _ocells(wl, cells)
+    _, odp, odh, opp = oracle.vjp(wl.points, oc, tq[:n], wl.ell, wl.noise_var, cand_prec=32,
+                                  sign=tsg[:n], mode=1, per_point=True)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, tq[:n], wl.ell, wl.noise_var, cand_prec=32, sign=tsg[:n])
+    am = o1["argmin"].cpu().numpy()
+    ok = (am == o["argmin"]) & (o["status"] & 3 == 0) & (o["u_best"] > 1e-3) & (o["ratio"] <= 1e3)
+    assert ok.mean() > 0.8, ok.mean()
+    g = dp1.cpu().numpy().astype(np.float64)
+    nr = np.linalg.norm(odp, axis=1)
+    err = np.linalg.norm(g - odp, axis=1) / np.maximum(nr, 1e-3 * np.median(nr[ok]))
+    bad = np.where(ok & (err > 1e-3))[0]
+    assert len(bad) == 0, f"{label}: {len(bad)} points over tolerance, worst {err[ok].max():.3g}"
+    hok, herr, hallow = hyper_within(dh1.cpu().numpy(), odh, np.abs(opp).sum(0))
+    print(f"{label}: {len(tq)} points; checked {ok.sum()} of {n}, max err {err[ok].max():.3g}; "
+          f"d_hyper {dh1.cpu().numpy()} oracle {odh} sum|term| {np.abs(opp).sum(0)} "
+          f"err {herr} allowed {hallow}", flush=True)
+    assert np.all(hok), f"{label}: d_hyper error {herr} over {hallow}"
+
+
+def test_room_trajectory_backward_full_size():
+    _say("room trajectories 4,096 x 64, softplus cost backward, FP64 check on 1,024 points")
+    wl = scenes.room_workload("grid", grid_n=4)
+    model, cells = _model(wl, query_box=(np.zeros(3), np.array([10.0, 8.0, 3.0])), adjoint=True)
+    model.fit(torch.from_numpy(wl.points).cuda())
+    tq, tsg = scenes.room_trajectories(wl)
+    _backward_check(wl, cells, model, tq, tsg, "room trajectories")
+    model.close()
+
+
+def test_terrain_full_size():
+    _say("outdoor terrain, 256^3 grid + 16,384 x 64 trajectory backward, sampled oracle checks")
+    wl = scenes.terrain_workload(grid_n=256)
+    print(f"terrain: {len(wl.points)} samples", flush=True)
+    model, cells = _model(wl, query_box=(np.zeros(3), np.array([100.0, 100.0, 25.0])), adjoint=True)
+    m = cells.m
+    print(f"cells {cells.n}, m {m.min()}..{m.max()}, mean {m.mean():.1f}", flush=True)
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    model.fit(pts)
+    out = model.query(q, sg)
+    torch.cuda.synchronize()
+    idx = _sample(out, 12000, 4000, 22)
+    _check_sample(wl, cells, out, idx, "terrain grid")
+    tq, tsg = scenes.terrain_trajectories(wl)
+    _backward_check(wl, cells, model, tq, tsg, "terrain trajectories")
+    model.close()

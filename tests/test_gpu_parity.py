@@ -152,3 +152,25 @@ def test_empty_query_and_argument_errors():
     bad.samples[0] = len(wl.points) + 5
     with pytest.raises(ksdf.KsdfError):
         ksdf.Model(bad, len(wl.points), wl.origin, wl.h, precision="fp64")
+
+
+def test_far_queries_over_sloped_patches_fp32():
+    """Far from a sloped patch, the corner of the samples' bounding box can be much
+    nearer than any sample; against that reference every kernel term is tiny and the
+    smaller ones underflow in FP32.  Regression for the nearest-sample fallback."""
+    _say("far queries over sloped patches (FP32 underflow regression)")
+    rng = np.random.default_rng(5)
+    n1 = 100
+    xy = (np.stack(np.meshgrid(np.arange(n1), np.arange(n1), indexing="ij"), -1).reshape(-1, 2)
+          + rng.random((n1 * n1, 2))) * 0.03
+    z = 0.6 * xy[:, 0] + 0.35 * xy[:, 1] + rng.normal(0, 0.005, len(xy))
+    pts = np.column_stack([xy, z]).astype(np.float32)
+    q = np.column_stack([rng.uniform(0, 3, 4000), rng.uniform(0, 3, 4000),
+                         rng.uniform(6, 16, 4000)]).astype(np.float32)
+    wl = scenes.Workload(90, "sloped_patch", pts, (0.0, 0.0, 0.0), 0.5, 0.25, 32, 1, q,
+                         np.ones(len(q), np.int8))
+    model, cells, res = gpu_run(wl)
+    ora = oracle_run(wl, cells, q, wl.sign, "fp32")
+    rep = assert_parity(res, ora, wl.ell, "fp32", wl.sign, label="sloped far")
+    assert np.all(np.isfinite(res["mean"]))
+    print("sloped far:", rep["mean_err_max"], flush=True)
