@@ -61,7 +61,7 @@ def lib():
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp,
-                                  _dp, _dp, _dp])
+                                  _dp, _dp, _dp, _ip])
         _lib = L
     return _lib
 
@@ -186,10 +186,11 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
 
 def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_prec=64, sign=None,
         mode=0, margin=0.3, weight=1.0, d_mean=None, d_grad=None, d_var=None, d_var_f=None,
-        per_point=False):
+        per_point=False, force_argmin=None):
     """Dual-number VJP.  mode 0: given cotangents; mode 1: softplus collision cost.
     Returns (loss, d_points [Q,3], d_hyper [2] = d/d(l, sigma^2)), and with per_point
-    also each query's own contribution to d_hyper [Q,2]."""
+    also each query's own contribution to d_hyper [Q,2].  force_argmin [Q] (optional):
+    differentiate at that candidate cell where it is valid (near-tie resolution)."""
     L = lib()
     pts = _f64(points)
     q = _f64(queries).reshape(-1, 3)
@@ -197,12 +198,14 @@ def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_pr
     dp = np.zeros((len(q), 3))
     dh = np.zeros(2)
     pp = np.zeros((len(q), 2)) if per_point else None
+    fa = None if force_argmin is None else np.ascontiguousarray(force_argmin, dtype=np.int32)
     cot = [None if c is None else _f64(c) for c in (d_mean, d_grad, d_var, d_var_f)]
     ctr = _f64(cells.centres)
     loss = L.oracle_vjp(_p(pts, _dp), cells.n, _p(cells.offsets, _ip), _p(cells.samples, _ip),
                         _p(ctr, _dp), ell, noise, -1.0 if alpha is None else alpha, k_fuse,
                         cand_prec, _p(q, _dp), len(q), _p(sg, _i8p), mode, margin, weight,
-                        *[_p(c, _dp) for c in cot], _p(dp, _dp), _p(dh, _dp), _p(pp, _dp))
+                        *[_p(c, _dp) for c in cot], _p(dp, _dp), _p(dh, _dp), _p(pp, _dp),
+                        _p(fa, _ip))
     return (loss, dp, dh, pp) if per_point else (loss, dp, dh)
 
 

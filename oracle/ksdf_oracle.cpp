@@ -385,7 +385,7 @@ enum { ST_NO_VALID = 1, ST_CLAMPED = 2, ST_GRAD_ZERO = 4 };
 template <class T>
 PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, const T* L,
                         const T& ell, const T& noise, const T& alpha, const QueryOpts& o,
-                        bool all_candidates = false) {
+                        bool all_candidates = false, int forced = -1) {
   double qv[3] = {val(q[0]), val(q[1]), val(q[2])};
   PointOut<T> r;
   r.status = 0;
@@ -416,11 +416,17 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
     r.var = T(inf); r.var_f = T(1.0);
     return r;
   }
-  r.argmin = std::get<1>(us[0]);
-  r.u_best = std::get<0>(us[0]);
-  if (std::get<3>(us[0])) r.status |= ST_CLAMPED;
+  // a forced cell (a near-tie of the min-fusion resolved the other way, which the
+  // parity contract accepts) replaces the minimum when it is a valid candidate
+  size_t pick = 0;
+  if (forced >= 0)
+    for (size_t k = 0; k < us.size(); ++k)
+      if (std::get<1>(us[k]) == forced && std::get<0>(us[k]) < inf) pick = k;
+  r.argmin = std::get<1>(us[pick]);
+  r.u_best = std::get<0>(us[pick]);
+  if (std::get<3>(us[pick])) r.status |= ST_CLAMPED;
   // d = s * u; grad d = s * grad u; V[d] = V[u] (deterministic sign).
-  r.mean = T((double)sign) * std::get<2>(us[0]);
+  r.mean = T((double)sign) * std::get<2>(us[pick]);
   CellOut<T> co = cell_outputs(in, r.argmin, q, a, L, ell, noise, alpha, o);
   for (int d = 0; d < 3; ++d) r.grad[d] = T((double)sign) * co.grad[d];
   r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio;
@@ -535,7 +541,8 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
                   int k_fuse, int cand_prec, const double* q, long nq, const int8_t* sign,
                   int mode, double margin, double weight, const double* d_mean,
                   const double* d_grad, const double* d_var, const double* d_var_f,
-                  double* d_points, double* d_hyper, double* d_hyper_pp) {
+                  double* d_points, double* d_hyper, double* d_hyper_pp,
+                  const int* force_argmin) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs);
   QueryOpts o{ell, 0, k_fuse, cand_prec, 0, alpha_fixed <= 0};
@@ -559,7 +566,7 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
   for (long p = 0; p < nq; ++p) {
     D2 qd[3] = {D2(q[3 * p]), D2(q[3 * p + 1]), D2(q[3 * p + 2])};
     PointOut<D2> r = query_point<D2>(in, qd, sign ? sign[p] : 1, a2.data(), L2.data(), ell2,
-                                     noise2, alpha2, o);
+                                     noise2, alpha2, o, false, force_argmin ? force_argmin[p] : -1);
     if (r.status & ST_NO_VALID) {
       if (d_hyper_pp) d_hyper_pp[2 * p] = d_hyper_pp[2 * p + 1] = 0.0;
       continue;
@@ -584,7 +591,7 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
     D3 qd[3];
     for (int d = 0; d < 3; ++d) { qd[d] = D3(q[3 * p + d]); qd[d].d[d] = 1.0; }
     PointOut<D3> r = query_point<D3>(in, qd, sign ? sign[p] : 1, a3.data(), L3.data(), ell3,
-                                     noise3, alpha3, o);
+                                     noise3, alpha3, o, false, force_argmin ? force_argmin[p] : -1);
     if (r.status & ST_NO_VALID) {
       for (int d = 0; d < 3; ++d) d_points[3 * p + d] = 0;
       continue;

@@ -263,6 +263,17 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
 // FP32 would turn into errors of 1e-3 in the hyperparameter gradient, while FP64
 // issues at the rate of unpacked FP32 on this hardware.
 constexpr int BCH = 2;
+constexpr double LOG2E_D = 1.4426950408889634;
+
+// exp(x) for x <= 0 from the hardware 2^r on the fraction r in [0, 1) of x log2(e):
+// relative error about 1e-7 (the FP32 rounding of r and the instruction's ulp)
+// instead of the library's FP64 exp, which costs several times more.
+__device__ __forceinline__ double exp_neg(double x) {
+  const double t = x * LOG2E_D;
+  const double n = floor(t);
+  if (n < -1000.0) return 0.0;
+  return ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
+}
 
 __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, double x1, double x2,
                                          double s, double gm, const double gg[3], double gv, int c,
@@ -306,7 +317,7 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
       load(i0 + j, px, py, pz, pa);
       const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
       const double z2 = dx * dx + dy * dy + dz * dz;
-      const double e = ok ? exp(-(z2 - d2) * inv2l2) : 0.0;
+      const double e = ok ? exp_neg(-(z2 - d2) * inv2l2) : 0.0;
       const double ae = pa * e;
       f += ae;
       w[0] += ae * dx;
@@ -314,7 +325,7 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
       w[2] += ae * dz;
       Za += ae * z2;
       const double t = sqrt(z2) - zmin;
-      const double sm = ok ? exp(-al * t) : 0.0;
+      const double sm = ok ? exp_neg(-al * t) : 0.0;
       S += sm;
       M1 += sm * t;
       M2 += sm * t * t;
@@ -333,28 +344,12 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
   const double m1 = M1 * iS;
   const double h = zmin + m1;
   const double Vz = M2 * iS - m1 * m1;
-  // pass B: softmin coefficients c_i; V, P, d var / d alpha, sum c^2
+  // pass B: every per-sample sum at once.  d var / d z_j = 2 alpha (-sigma_j^2 c_j
+  // (c_j + s_j) + s_j V + c_j P) needs V and P of the same pass, so the point
+  // derivative keeps its three parts apart (Q1, Q2, Q3) and combines them after.
   double V = 0, Pp = 0, dVa = 0, C2 = 0;
-  for (int i0 = 0; i0 < m; i0 += BCH) {
-#pragma unroll
-    for (int j = 0; j < BCH; ++j) {
-      const bool ok = i0 + j < m;
-      double px, py, pz, pa;
-      load(i0 + j, px, py, pz, pa);
-      const double svj = ok ? (double)SV[b + i0 + j] : 0.0;
-      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
-      const double z = sqrt(dx * dx + dy * dy + dz * dz);
-      const double si = ok ? exp(-al * (z - zmin)) * iS : 0.0;
-      const double Bi = al * (h - z) + 1.0;
-      const double ci = si * Bi;
-      V += svj * ci * ci;
-      Pp += svj * ci * si;
-      C2 += ci * ci;
-      dVa += 2.0 * svj * ci * (si * (h - z) * (Bi + 1.0) - al * si * Vz);
-    }
-  }
-  // pass C: per-sample accumulations
-  double dxv[3] = {0, 0, 0}, Hy[3] = {0, 0, 0}, Wz[3] = {0, 0, 0};
+  double Q1[3] = {0, 0, 0}, Q2[3] = {0, 0, 0}, Q3[3] = {0, 0, 0}, Hy[3] = {0, 0, 0},
+         Wz[3] = {0, 0, 0};
   double El = 0, Es = 0, Eld[3] = {0, 0, 0}, Esd[3] = {0, 0, 0};
   for (int i0 = 0; i0 < m; i0 += BCH) {
 #pragma unroll
@@ -369,16 +364,23 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
       const double di[3] = {l0 - px, l1 - py, l2 - pz};
       const double z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
       const double z = sqrt(z2);
-      const double e = ok ? exp(-(z2 - d2) * inv2l2) : 0.0;
+      const double e = ok ? exp_neg(-(z2 - d2) * inv2l2) : 0.0;
       const double ae = pa * e;
-      const double si = ok ? exp(-al * (z - zmin)) * iS : 0.0;
-      const double ci = si * (al * (h - z) + 1.0);
-      const double dvdz = 2.0 * al * (-svj * ci * (ci + si) + si * V + ci * Pp);
+      const double si = ok ? exp_neg(-al * (z - zmin)) * iS : 0.0;
+      const double Bi = al * (h - z) + 1.0;
+      const double ci = si * Bi;
+      V += svj * ci * ci;
+      Pp += svj * ci * si;
+      C2 += ci * ci;
+      dVa += 2.0 * svj * ci * (si * (h - z) * (Bi + 1.0) - al * si * Vz);
       const double rz = z > 0.0 ? 1.0 / z : 0.0;
+      const double q1 = -svj * ci * (ci + si) * rz, q2 = si * rz, q3 = ci * rz;
       const double dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        dxv[d] += dvdz * di[d] * rz;
+        Q1[d] += q1 * di[d];
+        Q2[d] += q2 * di[d];
+        Q3[d] += q3 * di[d];
         Hy[d] += ae * dy * di[d];
         Wz[d] += ae * z2 * di[d];
         Eld[d] += e * x0j * di[d];
@@ -390,7 +392,8 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
   }
   const double l3 = lt * lt * lt;
   for (int d = 0; d < 3; ++d) {
-    double r = s * (f * y[d] - Hy[d] / (lt * lt)) + gv * dxv[d];
+    const double dxv = 2.0 * al * (Q1[d] + V * Q2[d] + Pp * Q3[d]);
+    double r = s * (f * y[d] - Hy[d] / (lt * lt)) + gv * dxv;
     if (mean_live) r += s * gm * w[d] / (f * u);
     out_dx[d] = r;
   }

@@ -39,52 +39,79 @@ struct WVec {
   T s[SLOTS];
 };
 
+// Element k of v (k the same in every lane) broadcast to every lane by v_readlane.
+__device__ __forceinline__ float readlane(float x, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+}
+__device__ __forceinline__ double readlane(double x, int l) {
+  const long long u = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
 template <class T>
 __device__ __forceinline__ T wget(const WVec<T>& v, int k) {
-  // broadcast element k to every lane
   T x = v.s[0];
 #pragma unroll
   for (int t = 1; t < SLOTS; ++t)
     if (k / 64 == t) x = v.s[t];
-  return __shfl(x, k % 64, 64);
+  return readlane(x, k % 64);
 }
 
-// Solve L y = b (L packed lower with its true diagonal), wave-cooperative.
+// Solve L y = b (L packed lower with its true diagonal), wave-cooperative, column
+// by column: y_j leaves the residual's lane j by v_readlane, and every lane i > j
+// subtracts L_ij y_j from its own entry, so a step costs one broadcast and one FMA
+// per slot instead of a cross-lane reduction.
 template <class T>
 __device__ void wave_forward(const T* Lp, int m, const WVec<T>& b, WVec<T>& y) {
   const int lane = threadIdx.x & 63;
+  WVec<T> r = b;
 #pragma unroll
   for (int t = 0; t < SLOTS; ++t) y.s[t] = T(0);
-  for (int i = 0; i < m; ++i) {
-    const T* row = Lp + pk(i, 0);
-    T acc = T(0);
+  for (int j = 0; j < m; ++j) {
+    const T yj = wget(r, j) / Lp[pk(j, j)];
+    if (lane == j % 64) y.s[j / 64] = yj;
 #pragma unroll
     for (int t = 0; t < SLOTS; ++t) {
-      const int k = t * 64 + lane;
-      if (k < i) acc += row[k] * y.s[t];
+      const int i = t * 64 + lane;
+      if (i > j && i < m) r.s[t] -= Lp[pk(i, j)] * yj;
     }
-    acc = wave_sum(acc);
-    const T yi = (wget(b, i) - acc) / row[i];
-    if (lane == i % 64) y.s[i / 64] = yi;
   }
 }
 
-// Solve L^T x = y, wave-cooperative.
+// Solve L^T x = y, wave-cooperative, last unknown first: x_i leaves lane i by
+// v_readlane and every lane k < i subtracts L_ik x_i (row i of L, contiguous).
 template <class T>
 __device__ void wave_backward(const T* Lp, int m, const WVec<T>& y, WVec<T>& x) {
   const int lane = threadIdx.x & 63;
+  WVec<T> r = y;
 #pragma unroll
   for (int t = 0; t < SLOTS; ++t) x.s[t] = T(0);
   for (int i = m - 1; i >= 0; --i) {
-    T acc = T(0);
+    const T* row = Lp + pk(i, 0);
+    const T xi = wget(r, i) / row[i];
+    if (lane == i % 64) x.s[i / 64] = xi;
 #pragma unroll
     for (int t = 0; t < SLOTS; ++t) {
       const int k = t * 64 + lane;
-      if (k > i && k < m) acc += Lp[pk(k, i)] * x.s[t];
+      if (k < i) r.s[t] -= row[k] * xi;
     }
-    acc = wave_sum(acc);
-    const T xi = (wget(y, i) - acc) / Lp[pk(i, i)];
-    if (lane == i % 64) x.s[i / 64] = xi;
+  }
+}
+
+// y = A x for the packed symmetric A, wave-cooperative, column by column.
+template <class T>
+__device__ void wave_matvec(const T* Ap, int m, const WVec<T>& x, WVec<T>& y) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int t = 0; t < SLOTS; ++t) y.s[t] = T(0);
+  for (int j = 0; j < m; ++j) {
+    const T xj = wget(x, j);
+#pragma unroll
+    for (int t = 0; t < SLOTS; ++t) {
+      const int i = t * 64 + lane;
+      if (i < m) y.s[t] += (i >= j ? Ap[pk(i, j)] : Ap[pk(j, i)]) * xj;
+    }
   }
 }
 
@@ -93,18 +120,6 @@ __device__ void wave_backward(const T* Lp, int m, const WVec<T>& y, WVec<T>& x) 
 // close to the Perron vector), lambda_min by inverse iteration through the factor
 // from an alternating-sign start.  Both converge from below, so the estimate is a
 // lower bound of cond_2(A) that tightens with the step count.
-template <class T>
-__device__ T wave_matvec_elem(const T* Ap, int m, const WVec<T>& x, int i) {
-  const int lane = threadIdx.x & 63;
-  T acc = T(0);
-#pragma unroll
-  for (int t = 0; t < SLOTS; ++t) {
-    const int k = t * 64 + lane;
-    if (k < m) acc += (k <= i ? Ap[pk(i, k)] : Ap[pk(k, i)]) * x.s[t];
-  }
-  return wave_sum(acc);
-}
-
 template <class T>
 __device__ T cond2_estimate(const T* Ap, const T* Lp, int m) {
   const int lane = threadIdx.x & 63;
@@ -120,10 +135,7 @@ __device__ T cond2_estimate(const T* Ap, const T* Lp, int m) {
       y.s[t] = T(0);   // entries k >= m stay zero
     }
     nx = sqrt(wave_sum(nx));
-    for (int i = 0; i < m; ++i) {
-      const T yi = wave_matvec_elem(Ap, m, x, i);
-      if (lane == i % 64) y.s[i / 64] = yi;
-    }
+    wave_matvec(Ap, m, x, y);
     T xy = T(0), yy = T(0);
 #pragma unroll
     for (int t = 0; t < SLOTS; ++t) {
@@ -310,6 +322,32 @@ __device__ void write_cell(const T* Lp, const T* xs, const T* sv, const WVec<T>&
   }
 }
 
+// Block-cooperative float-float row sums: row i of the m rows is shared by G
+// consecutive threads (G = blockDim / (rows rounded up to a power of two), at most
+// 16, a divisor of 64), each summing the terms k = part, part + G, ...; the G
+// partials are combined by lane shuffles.  term(i, k) returns the ff term; every
+// thread of the block must call it.  The row's sum goes to out(i, sum) on part 0.
+template <class Term, class Out>
+__device__ __forceinline__ void ff_row_sums(int m, Term term, Out out) {
+  int mp = 1;
+  while (mp < m) mp <<= 1;
+  int G = (int)blockDim.x / mp;
+  G = G < 1 ? 1 : (G > 16 ? 16 : G);
+  const int part = threadIdx.x % G;
+  const int rows_per_pass = blockDim.x / G;
+  for (int base = 0; base < m; base += rows_per_pass) {
+    const int i = base + (int)threadIdx.x / G;
+    ff acc{0.f, 0.f};
+    if (i < m)
+      for (int k = part; k < m; k += G) acc = ff_add(acc, term(i, k));
+    for (int o = 1; o < G; o <<= 1) {
+      const ff other{__shfl_xor(acc.hi, o, 64), __shfl_xor(acc.lo, o, 64)};
+      acc = ff_add(acc, other);
+    }
+    if (i < m && part == 0) out(i, acc);
+  }
+}
+
 // Solve A x = rhs for the cell (block-cooperative): an FP32 solve with the factor,
 // then refinement steps whose residuals rhs - A x are evaluated in float-float from
 // (Ahi, Alo), until a correction is below REFINE_TOL of |x| or no longer shrinks
@@ -317,7 +355,7 @@ __device__ void write_cell(const T* Lp, const T* xs, const T* sv, const WVec<T>&
 // each step shrinks the error by about cond(A) * 2^-24.  rhs (rh, rl) and
 // x (xh, xl) are float-float arrays in LDS; res is scratch.  Ends with a barrier.
 constexpr int REFINE_MAX = 10;
-constexpr float REFINE_TOL = 1e-13f;
+constexpr float REFINE_TOL = 1e-10f;
 __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float* Lf, int m,
                                  const float* rh, const float* rl, float* xh, float* xl,
                                  float* res) {
@@ -345,15 +383,16 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
   }
   __syncthreads();
   for (int it = 0; it < REFINE_MAX; ++it) {
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      ff acc{0.f, 0.f};
-      for (int k = 0; k < m; ++k) {
-        const long e = k <= i ? pk(i, k) : pk(k, i);
-        acc = ff_add(acc, ff_mul(ff{Ahi[e], Alo[e]}, ff{xh[k], xl[k]}));
-      }
-      const ff r = ff_add(ff{rh[i], rl[i]}, ff_neg(acc));
-      res[i] = r.hi + r.lo;
-    }
+    ff_row_sums(
+        m,
+        [&](int i, int k) {
+          const long e = k <= i ? pk(i, k) : pk(k, i);
+          return ff_mul(ff{Ahi[e], Alo[e]}, ff{xh[k], xl[k]});
+        },
+        [&](int i, ff acc) {
+          const ff r = ff_add(ff{rh[i], rl[i]}, ff_neg(acc));
+          res[i] = r.hi + r.lo;
+        });
     __syncthreads();
     if (threadIdx.x < 64) {
       WVec<float> rv, y, dlt;
@@ -492,23 +531,24 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
       // adjoint vectors of the fit: xi_l = A^{-1} (dA/dl) a with dA_ij/dl = K_ij r_ij^2 / l^3,
       // and xi_s = A^{-1} a (dA/dsigma^2 = I for the uniform noise variance)
       const ff il3{A.inv_l3_ff[0], A.inv_l3_ff[1]};
-      for (int i = threadIdx.x; i < m; i += blockDim.x) {
-        ff acc{0.f, 0.f};
-        for (int k = 0; k < m; ++k) {
-          if (k == i) continue;
-          const long e = k <= i ? pk(i, k) : pk(k, i);
-          ff r2{0.f, 0.f};
+      ff_row_sums(
+          m,
+          [&](int i, int k) {
+            if (k == i) return ff{0.f, 0.f};
+            const long e = k <= i ? pk(i, k) : pk(k, i);
+            ff r2{0.f, 0.f};
 #pragma unroll
-          for (int d = 0; d < 3; ++d) {
-            const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
-            r2 = ff_add(r2, ff_mul(dd, dd));
-          }
-          acc = ff_add(acc, ff_mul(ff_mul(ff{Ahi[e], Alo[e]}, r2), ff{ah[k], al[k]}));
-        }
-        const ff g = ff_mul(acc, il3);
-        rh[i] = g.hi;
-        rl[i] = g.lo;
-      }
+            for (int d = 0; d < 3; ++d) {
+              const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
+              r2 = ff_add(r2, ff_mul(dd, dd));
+            }
+            return ff_mul(ff_mul(ff{Ahi[e], Alo[e]}, r2), ff{ah[k], al[k]});
+          },
+          [&](int i, ff acc) {
+            const ff g = ff_mul(acc, il3);
+            rh[i] = g.hi;
+            rl[i] = g.lo;
+          });
       ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
       for (int i = threadIdx.x; i < m; i += blockDim.x) {
         A.xi32[4L * (b + i)] = xih[i];

@@ -68,8 +68,10 @@ def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, ma
     oc = _ocells(wl, cells)
     cp = 64 if prec == "fp64" else 32
     kw = {} if mode == 1 else cot
+    # differentiate at the GPU's argmin cells: near-ties of the min-fusion may resolve
+    # either way, and d_hyper sums every point
     _, odp, odh, opp = oracle.vjp(wl.points, oc, q, wl.ell, wl.noise_var, cand_prec=cp,
-                                  sign=sign, mode=mode, per_point=True, **kw)
+                                  sign=sign, mode=mode, per_point=True, force_argmin=am, **kw)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
     o = oracle.query(wl.points, oc, f, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign)
     ok = (am == o["argmin"]) & (o["status"] & 3 == 0) & (o["u_best"] > 1e-3) & (o["ratio"] <= max_ratio)
@@ -80,8 +82,9 @@ def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, ma
     err = np.linalg.norm(dp - odp, axis=1) / scale
     bad = np.where(ok & (err > tol_p))[0]
     assert len(bad) == 0, f"{len(bad)} points over tolerance, worst {err[ok].max():.3g} at {bad[:5]}"
-    # d_hyper sums every query, the excluded ones included: compare as a whole, with
-    # the allowance for cancelling per-query terms (tests/parity.py hyper_within)
+    # d_hyper sums every query, the excluded ones included (at the GPU's cells):
+    # compare as a whole, with the allowance for cancelling per-query terms
+    # (tests/parity.py hyper_within)
     rel = np.abs(dh - odh) / np.maximum(np.abs(odh), 1e-12)
     hok, herr, hallow = hyper_within(dh, odh, np.abs(opp).sum(0), rel=tol_h, per_term=tol_h / 10)
     print(f"d_hyper {dh} oracle {odh} sum|term| {np.abs(opp).sum(0)} err {herr} allowed {hallow}",

@@ -103,3 +103,27 @@ def test_vjp_alpha_is_tied_to_length_scale():
     assert dh_fixed[0] == 0.0
     assert dh_tied[0] != 0.0
     assert dh_tied[1] == pytest.approx(dh_fixed[1], rel=1e-12)
+
+
+def test_forced_argmin_matches_free_choice_and_switches_cell():
+    """force_argmin: the oracle's own argmin reproduces the free VJP exactly; another
+    valid candidate changes exactly the forced points."""
+    wl = scenes.small_room_workload(n_queries=300, cfg_id=35)
+    oc = oracle.cells_for(wl)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, sign=wl.sign)
+    base = oracle.vjp(wl.points, oc, wl.queries, wl.ell, wl.noise_var, sign=wl.sign, mode=1,
+                      per_point=True)
+    same = oracle.vjp(wl.points, oc, wl.queries, wl.ell, wl.noise_var, sign=wl.sign, mode=1,
+                      per_point=True, force_argmin=o["argmin"])
+    assert np.array_equal(base[1], same[1]) and np.array_equal(base[3], same[3])
+    forced = o["argmin"].copy()
+    second = np.where(np.isfinite(o["u_second"]))[0][:20]
+    for p in second:  # the second-best candidate
+        u = o["ucand"][p]
+        order = np.argsort(u, kind="stable")
+        forced[p] = o["cand"][p][order[1]]
+    alt = oracle.vjp(wl.points, oc, wl.queries, wl.ell, wl.noise_var, sign=wl.sign, mode=1,
+                     per_point=True, force_argmin=forced)
+    changed = np.where(np.any(alt[1] != base[1], axis=1))[0]
+    assert set(changed) <= set(second) and len(changed) > 0
