@@ -134,12 +134,15 @@ void ksdf_model_destroy(ksdf_model* model);
  * fused: ksdf_fit_query uses the persistent fused launch (1) or the per-bucket fit
  *   launches followed by the query launch (0).
  * fit_min_bucket: FP32 cells with m <= this run in the fit kernel sized for it
- *   (16, 32 or 64): larger values merge small cells into fewer launches. */
+ *   (16, 32 or 64): larger values merge small cells into fewer launches.
+ * query_split: the FP32 query runs as two kernels with the queries regrouped by
+ *   argmin cell between them (1), or as one kernel (0).  Outputs are identical. */
 typedef struct ksdf_tuning {
   int query_sub;
   int query_block;
   int fused;
   int fit_min_bucket;
+  int query_split;
 } ksdf_tuning;
 int ksdf_model_set_tuning(ksdf_model* model, const ksdf_tuning* tuning);
 int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);

@@ -348,7 +348,8 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
   if (!m || !t || (t->query_sub != 0 && t->query_sub != 1 && t->query_sub != 2 && t->query_sub != 4) ||
       (t->query_block != 0 && t->query_block != 64 && t->query_block != 256) ||
       (t->fused != 0 && t->fused != 1) ||
-      (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64)) {
+      (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64) ||
+      (t->query_split != 0 && t->query_split != 1)) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
   }

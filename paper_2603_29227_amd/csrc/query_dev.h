@@ -195,10 +195,21 @@ __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int
   return vv;
 }
 
-// One wave answers the 64 sorted queries sq .. (lanes pass their own sq); every
-// lane of the wave must call it together (wave-uniform loops inside).
-template <int KM, int MB>
-__device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
+// What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
+// cell (-1: none valid), the minimum u^2 and the scaling reference used for that
+// cell.  32 bytes, the record the split query passes between its two kernels.
+struct Pass1 {
+  float qx, qy, qz, best;
+  int qi, bc;
+  float bref;
+  int flags;   // bit 0: query outside the candidate index; bit 1: active lane
+};
+
+// Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
+// of a wave (lanes pass their own sq); every lane of the wave must call it together
+// (wave-uniform loops inside).
+template <int KM>
+__device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   const bool active = sq < A.Q;
   const long qi = active ? A.perm[sq] : 0;
   const float qx = A.pts[3 * qi], qy = A.pts[3 * qi + 1], qz = A.pts[3 * qi + 2];
@@ -405,6 +416,28 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
 #pragma unroll
   for (int r = 0; r < KM; ++r)
     if (r < n && cid[r] == bc) bref = cref[r];
+  Pass1 r;
+  r.qx = qx;
+  r.qy = qy;
+  r.qz = qz;
+  r.best = best;
+  r.qi = (int)qi;
+  r.bc = bc;
+  r.bref = bref;
+  r.flags = (outside ? 1 : 0) | (active ? 2 : 0);
+  return r;
+}
+
+// The argmin cell's outputs (gradient, GP variance, softmin variance) and every
+// output of the query; all lanes of the wave call it together.
+template <int MB>
+__device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1) {
+  const bool active = (p1.flags & 2) != 0, outside = (p1.flags & 1) != 0;
+  const long qi = p1.qi;
+  const float qx = p1.qx, qy = p1.qy, qz = p1.qz;
+  const int bc = p1.bc;
+  const float best = p1.best, bref = p1.bref;
+  const float c2 = A.c2;
 
   // ---- pass 2: argmin cell outputs, wave-uniform over the distinct argmin cells
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, vv = 0.f, var = 0.f;
@@ -518,6 +551,43 @@ __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
   if (A.var_f) A.var_f[qi] = fmaxf(1.f - vv, 0.f);
   if (A.argmin) A.argmin[qi] = bc;
   if (A.qst) A.qst[qi] = st;
+}
+
+// The whole query for one wave of sorted queries.
+template <int KM, int MB>
+__device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
+  query_finish<MB>(A, query_pass1<KM>(A, sq));
+}
+
+// Wave-aggregated counting-sort steps over small integer keys: the lanes that share
+// a key take one atomic between them (the lowest lane issues it).
+__device__ __forceinline__ void wave_count(int* count, int key, bool valid) {
+  unsigned long long pending = __ballot(valid);
+  const int lane = threadIdx.x & 63;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int k = __builtin_amdgcn_readlane(key, leader);
+    const unsigned long long mask = __ballot(valid && key == k);
+    if (lane == leader) atomicAdd(count + k, (int)__popcll(mask));
+    pending &= ~mask;
+  }
+}
+// position of each valid lane in its key's range (cursor: running start per key)
+__device__ __forceinline__ int wave_slot(int* cursor, int key, bool valid) {
+  unsigned long long pending = __ballot(valid);
+  const int lane = threadIdx.x & 63;
+  int pos = -1;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int k = __builtin_amdgcn_readlane(key, leader);
+    const unsigned long long mask = __ballot(valid && key == k);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(cursor + k, (int)__popcll(mask));
+    base = __builtin_amdgcn_readlane(base, leader);
+    if (valid && key == k) pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+    pending &= ~mask;
+  }
+  return pos;
 }
 
 // ---------------------------------------------------------------------------

@@ -2,8 +2,9 @@
 
 The knobs (``ksdf_tuning``): query bucketing granularity (sub-boxes per index-box
 edge: 1, 2, 4), query block size (64 or 256 threads), persistent fused fit+query
-launch or per-bucket fits followed by the query launch, and the smallest fit m bucket
-(16, 32, 64: cells below it run in the kernel sized for it).  ``tune`` times every
+launch or per-bucket fits followed by the query launch, the smallest fit m bucket
+(16, 32, 64: cells below it run in the kernel sized for it), and the query in one
+kernel or in two with the queries regrouped by argmin cell between them.  ``tune`` times every
 combination on the caller's own data (the fit+query step, median of a few runs, after
 a warm-up) and keeps the fastest; the outputs do not depend on the choice.  Results
 are cached in a JSON file keyed by device (architecture and compute-unit count) and a
@@ -23,7 +24,8 @@ import torch
 
 from .ksdf import FP64
 
-KNOBS = dict(query_sub=(1, 2, 4), query_block=(64, 256), fused=(0, 1), fit_min_bucket=(16, 32, 64))
+KNOBS = dict(query_sub=(1, 2, 4), query_block=(64, 256), fused=(0, 1), fit_min_bucket=(16, 32, 64),
+             query_split=(0, 1))
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
@@ -78,8 +80,11 @@ def tune(model, points: torch.Tensor, queries: torch.Tensor, sign=None, reps: in
     table = []
     for combo in itertools.product(*(KNOBS[k] for k in keys)):
         t = dict(zip(keys, combo))
-        if model.precision == FP64 and (t["fused"] == 1 or t["fit_min_bucket"] != 16):
+        if model.precision == FP64 and (t["fused"] == 1 or t["fit_min_bucket"] != 16 or
+                                        t["query_split"] == 1):
             continue  # FP64 models fit per cell and query on the plain path
+        if t["fused"] == 1 and t["query_split"] == 1:
+            continue  # the fused launch runs the query in one pass
         model.set_tuning(**t)
         ms = _time_step(model, points, queries, sign, out, reps)
         table.append((ms, t))

@@ -123,9 +123,10 @@ def test_graph_fused_fit_query_replays_match_eager():
 
 
 @pytest.mark.parametrize("tuning", [
-    dict(query_sub=1, query_block=256, fused=1, fit_min_bucket=16),
-    dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=32),
-    dict(query_sub=4, query_block=64, fused=1, fit_min_bucket=64),
+    dict(query_sub=1, query_block=256, fused=1, fit_min_bucket=16, query_split=0),
+    dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=32, query_split=0),
+    dict(query_sub=4, query_block=64, fused=1, fit_min_bucket=64, query_split=1),
+    dict(query_sub=4, query_block=256, fused=0, fit_min_bucket=16, query_split=1),
 ])
 def test_tuning_preserves_outputs(tuning):
     _say(f"tuning {tuning}")
@@ -160,7 +161,8 @@ def test_tuning_rejects_invalid_values():
     _say("tuning validation")
     wl = scenes.sphere_workload(n_queries=16)
     model, _ = _model(wl, precision="fp64")
-    for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8)):
+    for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8),
+                dict(query_split=2)):
         with pytest.raises(ksdf.KsdfError):
             model.set_tuning(**bad)
     model.close()
