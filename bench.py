@@ -153,32 +153,57 @@ def main():
     tsg = torch.from_numpy(tsg_np).to(dev)
     Q, QT = len(q), len(tq)
 
-    if args.no_tune:
-        tuning = tune.apply(model, Q)
-        tuned = {"source": "cache" if tuning else "default", "tuning": model.tuning()}
-    else:
-        t1 = time.time()
-        res = tune.tune(model, pts, q, sg, reps=2, cache_path=args.tune_cache)
-        tuned = {"source": "timed", "tuning": res["tuning"], "ms": res["ms"],
-                 "candidates": len(res["table"]), "seconds": round(time.time() - t1, 1)}
-        log(f"autotuner: {res['tuning']} {res['ms']:.3f} ms ({len(res['table'])} candidates)")
-    fused = model.tuning()["fused"] == 1
-
     out = model._out(Q, dev)
     tout = model._out(QT, dev, status=False)
     d_mean = torch.empty(QT, dtype=torch.float32, device=dev)
     d_var = torch.empty(QT, dtype=torch.float32, device=dev)
-    cst = torch.zeros(cells.n, dtype=torch.uint8, device=dev)
-    grads = {}
 
-    def step():
-        model.fit_query(pts, q, sg, cell_status=cst, out=out)
-        model.query(tq, tsg, out=tout)
+    def cotangents():
         # cost c = sum softplus(0.3 - d + sqrt(var)): dc/dd = -sigmoid(t), dc/dvar = sigmoid(t) / (2 sqrt(var))
         sd = torch.sqrt(torch.clamp_min(tout["var"], 1e-30))
         s = torch.sigmoid(0.3 - tout["mean"] + sd)
         torch.neg(s, out=d_mean)
         torch.div(s, 2 * sd, out=d_var)
+
+    # launch shapes: the fit+query step, the trajectory query and the backward are tuned
+    # (or taken from the cache) separately
+    t1 = time.time()
+    if args.no_tune:
+        tg = tune.cached(model, Q) or {}
+        model.set_tuning(**tg)
+        tg = model.tuning()
+        tq_t = tune.cached(model, QT, "query") or {}
+        tb_t = tune.cached(model, QT, "backward") or {}
+        source = "cache"
+    else:
+        res = tune.tune(model, pts, q, sg, reps=2, cache_path=args.tune_cache)
+        tg = res["tuning"]
+        log(f"autotuner fit+query: {tg} {res['ms']:.3f} ms ({len(res['table'])} candidates)")
+        rq = tune.tune_query(model, tq, tsg, reps=3, cache_path=args.tune_cache)
+        tq_t = rq["tuning"]
+        model.query(tq, tsg, out=tout)
+        cotangents()
+        rb = tune.tune_backward(model, tq, tsg, dict(d_mean=d_mean, d_var=d_var), tout["argmin"],
+                                reps=3, cache_path=args.tune_cache)
+        tb_t = rb["tuning"]
+        log(f"autotuner trajectory query: {tq_t} {rq['ms']:.3f} ms; backward: {tb_t} {rb['ms']:.3f} ms")
+        source = "timed"
+    t_grid = dict(tg)
+    t_traj = {**t_grid, **tq_t}
+    t_bwd = {**t_traj, **tb_t}
+    tuned = {"source": source, "fit_query": t_grid, "trajectory_query": tq_t, "backward": tb_t,
+             "seconds": round(time.time() - t1, 1)}
+    fused = t_grid["fused"] == 1
+    cst = torch.zeros(cells.n, dtype=torch.uint8, device=dev)
+    grads = {}
+
+    def step():
+        model.set_tuning(**t_grid)
+        model.fit_query(pts, q, sg, cell_status=cst, out=out)
+        model.set_tuning(**t_traj)
+        model.query(tq, tsg, out=tout)
+        cotangents()
+        model.set_tuning(**t_bwd)
         grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
                                                          argmin=tout["argmin"])
 
@@ -198,13 +223,13 @@ def main():
     t_start = time.perf_counter()
     for _ in range(args.steps):
         ev[0].record(stream)
+        model.set_tuning(**t_grid)
         model.fit_query(pts, q, sg, cell_status=cst, out=out)
         ev[1].record(stream)
+        model.set_tuning(**t_traj)
         model.query(tq, tsg, out=tout)
-        sd = torch.sqrt(torch.clamp_min(tout["var"], 1e-30))
-        s = torch.sigmoid(0.3 - tout["mean"] + sd)
-        torch.neg(s, out=d_mean)
-        torch.div(s, 2 * sd, out=d_var)
+        cotangents()
+        model.set_tuning(**t_bwd)
         grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
                                                          argmin=tout["argmin"])
         ev[2].record(stream)

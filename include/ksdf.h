@@ -136,13 +136,19 @@ void ksdf_model_destroy(ksdf_model* model);
  * fit_min_bucket: FP32 cells with m <= this run in the fit kernel sized for it
  *   (16, 32 or 64): larger values merge small cells into fewer launches.
  * query_split: the FP32 query runs as two kernels with the queries regrouped by
- *   argmin cell between them (1), or as one kernel (0).  Outputs are identical. */
+ *   argmin cell between them (1), or as one kernel (0).  Outputs are identical.
+ * query_lanes, backward_lanes: each lane reads its own cells (1) instead of the
+ *   wave sharing a cell through scalar loads (0); for sparse query sets, whose waves
+ *   span many cells.  query_lanes applies to the two-kernel query.  Outputs are
+ *   identical. */
 typedef struct ksdf_tuning {
   int query_sub;
   int query_block;
   int fused;
   int fit_min_bucket;
   int query_split;
+  int query_lanes;
+  int backward_lanes;
 } ksdf_tuning;
 int ksdf_model_set_tuning(ksdf_model* model, const ksdf_tuning* tuning);
 int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);

@@ -349,7 +349,8 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
       (t->query_block != 0 && t->query_block != 64 && t->query_block != 256) ||
       (t->fused != 0 && t->fused != 1) ||
       (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64) ||
-      (t->query_split != 0 && t->query_split != 1)) {
+      (t->query_split != 0 && t->query_split != 1) || (t->query_lanes != 0 && t->query_lanes != 1) ||
+      (t->backward_lanes != 0 && t->backward_lanes != 1)) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
   }

@@ -275,6 +275,7 @@ __device__ __forceinline__ double exp_neg(double x) {
   return ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
 }
 
+template <bool UNI>
 __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, double x1, double x2,
                                          double s, double gm, const double gg[3], double gv, int c,
                                          double out_dx[3], double out_th[2]) {
@@ -282,8 +283,8 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
   const float4* __restrict__ PL = reinterpret_cast<const float4*>(A.plo);
   const float4* __restrict__ X4 = reinterpret_cast<const float4*>(A.xi);
   const float* __restrict__ SV = A.sv;
-  const int b = __builtin_amdgcn_readfirstlane(A.offsets[c]);
-  const int m = __builtin_amdgcn_readfirstlane(A.offsets[c + 1]) - b;
+  const int b = UNI ? __builtin_amdgcn_readfirstlane(A.offsets[c]) : A.offsets[c];
+  const int m = (UNI ? __builtin_amdgcn_readfirstlane(A.offsets[c + 1]) : A.offsets[c + 1]) - b;
   const double lt = A.ell_d, two_l2 = 2.0 * lt * lt, inv2l2 = 1.0 / two_l2, al = A.alpha_d;
   const double l0 = x0 - A.centre64[3L * c], l1 = x1 - A.centre64[3L * c + 1],
                l2 = x2 - A.centre64[3L * c + 2];
@@ -418,7 +419,7 @@ __device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, dou
 // distinct argmin cells of its lanes -- after the sort usually one or two -- so the
 // cell index is wave-uniform and the cell's samples, factor and adjoint vectors are
 // read through scalar loads.
-template <bool VARF>
+template <bool VARF, bool LANE>
 __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const int* perm) {
   const long sq = (long)blockIdx.x * BT + threadIdx.x;
   const bool active = sq < A.Q;
@@ -436,6 +437,19 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
   const double gv = A.d_var ? (double)A.d_var[q] : 0.0;
+  if constexpr (LANE && !VARF) {
+    // per lane (sparse queries): every lane its own argmin cell, in one round
+    if (__ballot(todo)) {
+      double tdx[3], tth[2];
+      vjp_ff64<false>(A, x0, x1, x2, sgn, gm, gg, gv, todo ? bc : 0, tdx, tth);
+      if (todo) {
+        for (int d = 0; d < 3; ++d) dx[d] = (float)tdx[d];
+        th[0] = tth[0];
+        th[1] = tth[1];
+        todo = false;
+      }
+    }
+  }
   while (true) {
     unsigned key = todo ? (unsigned)bc : 0xffffffffu;
 #pragma unroll
@@ -451,7 +465,7 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
       }
     } else {
       double tdx[3], tth[2];
-      vjp_ff64(A, x0, x1, x2, sgn, gm, gg, gv, c, tdx, tth);
+      vjp_ff64<true>(A, x0, x1, x2, sgn, gm, gg, gv, c, tdx, tth);
       if (todo && bc == c) {
         for (int d = 0; d < 3; ++d) dx[d] = (float)tdx[d];
         th[0] = tth[0];
@@ -655,8 +669,10 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
     if (Q > 0) {
-      if (varf) hipLaunchKernelGGL(bwd_wave_kernel<true>, dim3(grid), dim3(BT), 0, s, A, perm);
-      else hipLaunchKernelGGL(bwd_wave_kernel<false>, dim3(grid), dim3(BT), 0, s, A, perm);
+      if (varf) hipLaunchKernelGGL((bwd_wave_kernel<true, false>), dim3(grid), dim3(BT), 0, s, A, perm);
+      else if (m->tuning.backward_lanes)
+        hipLaunchKernelGGL((bwd_wave_kernel<false, true>), dim3(grid), dim3(BT), 0, s, A, perm);
+      else hipLaunchKernelGGL((bwd_wave_kernel<false, false>), dim3(grid), dim3(BT), 0, s, A, perm);
     }
     timer_mark(m, KSDF_TIMER_BACKWARD, 1, s);
   }

@@ -156,15 +156,14 @@ __host__ __device__ constexpr int row_of(int e) {
 }
 
 // v <- L^{-1} v for the first m rows (L packed by rows with reciprocal diagonal),
-// streaming the packed factor through scalar registers 32 floats at a time.  The
-// chunks are generated by template recursion so every (row, column) index is a
-// compile-time constant and v stays in registers.  Accumulates |L^{-1} v|^2 over
-// the first m rows into vv.
-template <int E0, int MB>
+// streaming the packed factor LC floats at a time (through scalar registers when the
+// cell is wave-uniform).  The chunks are generated by template recursion so every
+// (row, column) index is a compile-time constant and v stays in registers.
+// Accumulates |L^{-1} v|^2 over the first m rows into vv.
+template <int E0, int MB, int LC>
 __device__ __forceinline__ void fsub_chunk(const float* __restrict__ Lc, int m, float (&v)[MB],
                                            float& vv, float& t) {
   constexpr int NP = MB * (MB + 1) / 2;
-  constexpr int LC = 32;
   if constexpr (E0 < NP) {
     if (row_of(E0) >= m) return;
     float buf[LC];
@@ -184,14 +183,16 @@ __device__ __forceinline__ void fsub_chunk(const float* __restrict__ Lc, int m, 
         }
       }
     }
-    fsub_chunk<E0 + LC, MB>(Lc, m, v, vv, t);
+    fsub_chunk<E0 + LC, MB, LC>(Lc, m, v, vv, t);
   }
 }
 
-template <int MB>
+// LC: factor entries per load group (32 through scalar registers when the cell is
+// wave-uniform; fewer when every lane loads its own cell into vector registers)
+template <int MB, int LC = 32>
 __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int m, float (&v)[MB]) {
   float vv = 0.f, t = 0.f;
-  fsub_chunk<0, MB>(Lc, m, v, vv, t);
+  fsub_chunk<0, MB, LC>(Lc, m, v, vv, t);
   return vv;
 }
 
@@ -208,7 +209,7 @@ struct Pass1 {
 // Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
 // of a wave (lanes pass their own sq); every lane of the wave must call it together
 // (wave-uniform loops inside).
-template <int KM>
+template <int KM, bool LANE = false>
 __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   const bool active = sq < A.Q;
   const long qi = active ? A.perm[sq] : 0;
@@ -274,9 +275,10 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     cdl[r] = 0.f;
     cref[r] = 0.f;
   }
-  unsigned pending = active ? ((1u << n) - 1u) : 0u;
   float best = INFINITY, best_del = 0.f;
   const float c2 = A.c2;
+  if constexpr (!LANE) {
+  unsigned pending = active ? ((1u << n) - 1u) : 0u;
   while (true) {
     unsigned key = 0xffffffffu;
     if (pending) {
@@ -373,6 +375,66 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
       }
     }
   }
+  } else {
+    // per lane: each lane walks its own candidates, nearest centre first, with its
+    // own (vector) loads; for sparse queries, whose waves would share few cells.
+    // The same arithmetic in the same order as the wave-uniform walk, so the same
+    // results.
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+      if (active && r < n) {
+        const int c = cid[r];
+        const int b = A.offsets[c];
+        const int m = A.offsets[c + 1] - b;
+        const float4 ctr = A.centre[c];
+        const float* bx = A.box + 8L * c;
+        const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
+        float d2ref = aabb_d2(bx, lx, ly, lz);
+        const float lb = d2ref - A.two_l2 * logf(fmaxf(bx[3], 1.f));
+        float u2 = INFINITY, del = 0.f;
+        if (!(lb > best + 2.f * best_del + 1e-6f)) {
+          float f = 0.f, R = 0.f, RZ = 0.f;
+          for (int pass = 0; pass < 2; ++pass) {
+            const float c2d = c2 * d2ref;
+            float emax = 0.f;
+            f = 0.f;
+            R = 0.f;
+            RZ = 0.f;
+            for (int i = 0; i < m; ++i) {
+              const float4 P = A.ps[b + i];
+              const float dx = lx - P.x, dy = ly - P.y, dz = lz - P.z;
+              const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+              const float e = __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d));
+              const float ae = fabsf(P.w) * e;
+              f = fmaf(P.w, e, f);
+              R += ae;
+              RZ = fmaf(ae, z2, RZ);
+              emax = fmaxf(emax, e);
+            }
+            if (emax >= 0x1p-24f) break;
+            float d2 = INFINITY;
+            for (int i = 0; i < m; ++i) {
+              const float4 p = A.ps[b + i];
+              const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
+              d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+            }
+            d2ref = d2;
+          }
+          if (f > 0.f) {
+            u2 = d2ref - A.two_l2 * LN2 * __log2f(f);
+            del = A.two_l2 * EPS32 * (6.f * R + 3.5f * c2 * RZ) / f;
+          }
+        }
+        cu2[r] = u2;
+        cdl[r] = del;
+        cref[r] = d2ref;
+        if (u2 < best) {
+          best = u2;
+          best_del = del;
+        }
+      }
+    }
+  }
 
   // ---- resolve the minimum; re-evaluate uncertain cells in float-float
   int bc = -1;
@@ -430,7 +492,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
 
 // The argmin cell's outputs (gradient, GP variance, softmin variance) and every
 // output of the query; all lanes of the wave call it together.
-template <int MB>
+template <int MB, bool LANE = false>
 __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1) {
   const bool active = (p1.flags & 2) != 0, outside = (p1.flags & 1) != 0;
   const long qi = p1.qi;
@@ -443,13 +505,20 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, vv = 0.f, var = 0.f;
   bool todo = bc >= 0;
   while (true) {
-    unsigned key = todo ? (unsigned)bc : 0xffffffffu;
-    key = (unsigned)uniform((int)wave_min_u32(key));
-    if (key == 0xffffffffu) break;
-    const int c = (int)key;
+    int c;
+    if constexpr (LANE) {
+      // per lane (sparse queries): every lane its own argmin cell, in one round
+      if (!__ballot(todo)) break;
+      c = todo ? bc : 0;
+    } else {
+      unsigned key = todo ? (unsigned)bc : 0xffffffffu;
+      key = (unsigned)uniform((int)wave_min_u32(key));
+      if (key == 0xffffffffu) break;
+      c = (int)key;
+    }
     const bool mine = todo && bc == c;
-    const int b = uniform(A.offsets[c]);
-    const int m = uniform(A.offsets[c + 1]) - b;
+    const int b = LANE ? A.offsets[c] : uniform(A.offsets[c]);
+    const int m = (LANE ? A.offsets[c + 1] : uniform(A.offsets[c + 1])) - b;
     const float* Lc = A.L + A.loff[c];
     const float4 ctr = A.centre[c];
     const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
@@ -466,21 +535,24 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
     const float k0 = c2 * (bref - ll);
     const float tx = 2.f * c2 * lx, ty = 2.f * c2 * ly, tz = 2.f * c2 * lz;
     if (mine) {
+      // samples per load group: 8 through scalar registers, 2 when each lane loads
+      // its own cell into vector registers
+      constexpr int CHP = LANE ? 2 : CH;
       float v[MB];
       float S = 0.f, T1 = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-      for (int i0 = 0; i0 < MB; i0 += CH) {
+      for (int i0 = 0; i0 < MB; i0 += CHP) {
         if (i0 < m) {
-          float4 P[CH];
-          float SV[CH];
+          float4 P[CHP];
+          float SV[CHP];
 #pragma unroll
-          for (int j = 0; j < CH; ++j) {
+          for (int j = 0; j < CHP; ++j) {
             P[j] = A.ps[b + i0 + j];
             SV[j] = A.sv[b + i0 + j];
           }
 #pragma unroll
-          for (int j = 0; j < CH; ++j) {
+          for (int j = 0; j < CHP; ++j) {
             const bool in = i0 + j < m;
             const float aw = P[j].w;
             const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
@@ -507,7 +579,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
           }
         }
       }
-      vv = forward_subst<MB>(Lc, m, v);
+      vv = forward_subst<MB, LANE ? 16 : 32>(Lc, m, v);
       const float Tb = 1.f + T1 / S;
       var = (Tb * Tb * X0 - 2.f * Tb * X1 + X2) / (S * S);
       w0 = a0;

@@ -50,10 +50,10 @@ void launch_query_nt(const ksdf_model* m, const FastArgs& A, hipStream_t s) {
 // argmin cell; pass 2 then meets one or two argmin cells per wave instead of the
 // two to three of a spatial bucket, so the per-cell work (gradient, GP variance by
 // forward substitution, softmin variance) is not repeated for lanes that idle.
-template <int KM, int NT>
+template <int KM, int NT, bool LANE>
 __global__ void __launch_bounds__(NT) query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
-  const Pass1 r = query_pass1<KM>(A, sq);
+  const Pass1 r = query_pass1<KM, LANE>(A, sq);
   const bool active = (r.flags & 2) != 0;
   if (active) rec[sq] = r;
   wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
@@ -69,31 +69,31 @@ __global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, lo
   if (active) rec2[pos] = r;
 }
 
-template <int MB, int NT>
+template <int MB, int NT, bool LANE>
 __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   Pass1 r{};
   r.bc = -1;
   if (sq < A.Q) r = rec2[sq];
-  query_finish<MB>(A, r);
+  query_finish<MB, LANE>(A, r);
 }
 
-template <int NT>
+template <int NT, bool LANE>
 void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2, int* count,
                      int* cursor, int* tsum, hipStream_t s) {
   const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
   const long nc = (long)m->n_cells + 1;
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
-  if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT>), dim3(g), dim3(NT), 0, s, A, rec, count);
-  else hipLaunchKernelGGL((query_p1_kernel<16, NT>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  else hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
   hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);
   hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum, cursor);
   hipLaunchKernelGGL(query_regroup_kernel, dim3((unsigned)((A.Q + 255) / 256)), dim3(256), 0, s, rec,
                      A.Q, m->n_cells, cursor, rec2);
-  if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT>), dim3(g), dim3(NT), 0, s, A, rec2);
-  else hipLaunchKernelGGL((query_p2_kernel<128, NT>), dim3(g), dim3(NT), 0, s, A, rec2);
+  if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+  else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
 }
 
 size_t bucketing_bytes(const ksdf_model* m, long Q) {
@@ -137,8 +137,14 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
       set_error("query: too many cells for the argmin regrouping");
       return KSDF_ERR_UNSUPPORTED;
     }
-    if (m->tuning.query_block == 64) launch_split_nt<64>(m, A, rec, rec2, count, cursor, tsum, s);
-    else launch_split_nt<256>(m, A, rec, rec2, count, cursor, tsum, s);
+    const bool lane = m->tuning.query_lanes != 0;
+    if (m->tuning.query_block == 64) {
+      if (lane) launch_split_nt<64, true>(m, A, rec, rec2, count, cursor, tsum, s);
+      else launch_split_nt<64, false>(m, A, rec, rec2, count, cursor, tsum, s);
+    } else {
+      if (lane) launch_split_nt<256, true>(m, A, rec, rec2, count, cursor, tsum, s);
+      else launch_split_nt<256, false>(m, A, rec, rec2, count, cursor, tsum, s);
+    }
   } else if (m->tuning.query_block == 64) {
     launch_query_nt<64>(m, A, s);
   } else {

@@ -175,3 +175,19 @@ def test_backward_requires_adjoint_fit():
     q = torch.from_numpy(wl.queries).cuda()
     with pytest.raises(ksdf.KsdfError, match="ADJOINT"):
         model.backward(q, None, torch.ones(16, dtype=torch.float64, device="cuda"))
+
+
+def test_backward_lane_mode_is_identical():
+    _say("backward per-lane cells == wave-shared cells")
+    wl = scenes.small_room_workload(n_queries=5000, cfg_id=36)
+    model, cells, dt = _setup(wl, "fp32")
+    cot = _cotangents(len(wl.queries), 4, grad=True, var_f=False)
+    qt = torch.from_numpy(wl.queries).cuda()
+    st = torch.from_numpy(wl.sign).cuda()
+    c = {k: (None if v is None else torch.from_numpy(v).to("cuda", dt)) for k, v in cot.items()}
+    am = model.query(qt, st)["argmin"]
+    r1 = model.backward(qt, st, c["d_mean"], c["d_grad"], c["d_var"], None, argmin=am)
+    model.set_tuning(backward_lanes=1)
+    r2 = model.backward(qt, st, c["d_mean"], c["d_grad"], c["d_var"], None, argmin=am)
+    torch.cuda.synchronize()
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])

@@ -127,6 +127,8 @@ def test_graph_fused_fit_query_replays_match_eager():
     dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=32, query_split=0),
     dict(query_sub=4, query_block=64, fused=1, fit_min_bucket=64, query_split=1),
     dict(query_sub=4, query_block=256, fused=0, fit_min_bucket=16, query_split=1),
+    dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=16, query_split=1, query_lanes=1,
+         backward_lanes=1),
 ])
 def test_tuning_preserves_outputs(tuning):
     _say(f"tuning {tuning}")
@@ -140,7 +142,7 @@ def test_tuning_preserves_outputs(tuning):
     torch.cuda.synchronize()
     base = _clone(base)
     model.set_tuning(**tuning)
-    assert model.tuning() == tuning
+    assert all(model.tuning()[k] == v for k, v in tuning.items())
     a = model.fit_query(P, q, sg)
     model.fit(P)
     b = model.query(q, sg)
@@ -162,7 +164,7 @@ def test_tuning_rejects_invalid_values():
     wl = scenes.sphere_workload(n_queries=16)
     model, _ = _model(wl, precision="fp64")
     for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8),
-                dict(query_split=2)):
+                dict(query_split=2), dict(query_lanes=2), dict(backward_lanes=-1)):
         with pytest.raises(ksdf.KsdfError):
             model.set_tuning(**bad)
     model.close()
