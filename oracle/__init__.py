@@ -56,7 +56,8 @@ def lib():
         L.oracle_query.argtypes = ([_dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp] +
                                    [ctypes.c_double] * 3 + [ctypes.c_int] * 3 +
                                    [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
-                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp])
+                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp])
+        L.oracle_softmin.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.oracle_vjp.restype = ctypes.c_double
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
@@ -64,6 +65,16 @@ def lib():
                                   _dp, _dp, _dp, _ip])
         _lib = L
     return _lib
+
+
+def softmin(q, x, alpha):
+    """Softmin distance h and its gradient g with respect to the query (App. C)."""
+    q = _f64(q).reshape(3)
+    x = _f64(x).reshape(-1, 3)
+    h = np.zeros(1)
+    g = np.zeros(3)
+    lib().oracle_softmin(_p(q, _dp), _p(x, _dp), len(x), float(alpha), _p(h, _dp), _p(g, _dp))
+    return float(h[0]), g
 
 
 def threads() -> int:
@@ -153,7 +164,8 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
           cand_prec=64, d_mode=0, sign=None, svar=None, all_candidates=False) -> dict:
     """All outputs of the back-end at each query (see ``oracle_query``).  With
     all_candidates, also every candidate cell's gradient, variances and ratio
-    (keys cgrad [Q,K,3], cvar, cvar_f, cratio [Q,K])."""
+    (keys cgrad [Q,K,3], cgrad_var [Q,K,3], cvar, cvar_f, cratio [Q,K]).  grad_var [Q,3]
+    is the SDF gradient variance V[grad_k u] of App. C."""
     L = lib()
     pts = _f64(points)
     q = _f64(queries).reshape(-1, 3)
@@ -163,12 +175,14 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
     sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.int8)
     out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "ratio")}
     out["grad"] = np.zeros((nq, 3))
+    out["grad_var"] = np.zeros((nq, 3))
     out["argmin"] = np.zeros(nq, np.int32)
     out["status"] = np.zeros(nq, np.int32)
     out["cand"] = np.zeros((nq, k_fuse), np.int32)
     out["ucand"] = np.zeros((nq, k_fuse))
     if all_candidates:
         out["cgrad"] = np.zeros((nq, k_fuse, 3))
+        out["cgrad_var"] = np.zeros((nq, k_fuse, 3))
         for k in ("cvar", "cvar_f", "cratio"):
             out[k] = np.zeros((nq, k_fuse))
     g = out.get
@@ -180,7 +194,8 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
                    _p(out["var_f"], _dp), _p(out["argmin"], _ip), _p(out["status"], _ip),
                    _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["ratio"], _dp),
                    _p(out["cand"], _ip), _p(out["ucand"], _dp), _p(g("cgrad"), _dp),
-                   _p(g("cvar"), _dp), _p(g("cvar_f"), _dp), _p(g("cratio"), _dp))
+                   _p(g("cvar"), _dp), _p(g("cvar_f"), _dp), _p(g("cratio"), _dp),
+                   _p(out["grad_var"], _dp), _p(g("cgrad_var"), _dp))
     return out
 
 

@@ -304,6 +304,7 @@ template <class T>
 struct CellOut {
   T grad[3];
   T var, var_f;
+  T grad_var[3];         // V[grad_k u] of App. C
   double ratio;          // cancellation ratio sum|a_i| e_i |x*-x_i| / |w|
   bool grad_zero;
 };
@@ -366,12 +367,48 @@ CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T
     var = var + ci * ci * sample_var(in, in.samples[b + i], noise);
   }
   r.var = var;
+  // SDF gradient variance (App. C, the variance of the softmin gradient): with
+  // v_i = (x* - x_i)/z_i, l_i = s_i (alpha h - alpha z_i + 1) and g = sum_i l_i v_i,
+  // the derivative of g with respect to sample x_i (rows: components of g) is
+  //   J_i = alpha w_i v_i^T + (l_i / z_i)(v_i v_i^T - I),  w_i = l_i (v_i - V s) + s_i (v_i - g)
+  // (App. C prints its transpose, the gradient layout), and
+  //   V[grad_k u] = sum_i sigma_i^2 |row k of J_i|^2.
+  // A sample at the query itself (z_i = 0) has no direction and contributes nothing.
+  std::vector<T> vdir(3 * (size_t)m, T(0.0));
+  T Vs[3] = {T(0.0), T(0.0), T(0.0)}, gs[3] = {T(0.0), T(0.0), T(0.0)};
+  std::vector<T> li(m);
+  for (int i = 0; i < m; ++i) {
+    li[i] = s[i] * (alpha * hval - alpha * z[i] + T(1.0));
+    if (val(z[i]) > 0)
+      for (int d = 0; d < 3; ++d) vdir[3 * i + d] = diff[3 * i + d] / z[i];
+    for (int d = 0; d < 3; ++d) {
+      Vs[d] = Vs[d] + s[i] * vdir[3 * i + d];
+      gs[d] = gs[d] + li[i] * vdir[3 * i + d];
+    }
+  }
+  for (int k = 0; k < 3; ++k) r.grad_var[k] = T(0.0);
+  for (int i = 0; i < m; ++i) {
+    if (!(val(z[i]) > 0)) continue;
+    T wv[3];
+    for (int d = 0; d < 3; ++d)
+      wv[d] = li[i] * (vdir[3 * i + d] - Vs[d]) + s[i] * (vdir[3 * i + d] - gs[d]);
+    const T sv2 = sample_var(in, in.samples[b + i], noise);
+    for (int k = 0; k < 3; ++k) {
+      T row2 = T(0.0);
+      for (int j = 0; j < 3; ++j) {
+        const T Jkj = alpha * wv[k] * vdir[3 * i + j] +
+                      (li[i] / z[i]) * (vdir[3 * i + k] * vdir[3 * i + j] - T(k == j ? 1.0 : 0.0));
+        row2 = row2 + Jkj * Jkj;
+      }
+      r.grad_var[k] = r.grad_var[k] + sv2 * row2;
+    }
+  }
   return r;
 }
 
 template <class T>
 struct PointOut {
-  T mean, grad[3], var, var_f;
+  T mean, grad[3], var, var_f, grad_var[3];
   int argmin;
   double u_best, u_second, ratio;
   int status;
@@ -414,6 +451,7 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
     r.mean = T(inf);
     for (int d = 0; d < 3; ++d) r.grad[d] = T(0.0);
     r.var = T(inf); r.var_f = T(1.0);
+    for (int d = 0; d < 3; ++d) r.grad_var[d] = T(inf);
     return r;
   }
   // a forced cell (a near-tie of the min-fusion resolved the other way, which the
@@ -430,6 +468,7 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
   CellOut<T> co = cell_outputs(in, r.argmin, q, a, L, ell, noise, alpha, o);
   for (int d = 0; d < 3; ++d) r.grad[d] = T((double)sign) * co.grad[d];
   r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio;
+  for (int d = 0; d < 3; ++d) r.grad_var[d] = co.grad_var[d];
   if (co.grad_zero) r.status |= ST_GRAD_ZERO;
   return r;
 }
@@ -474,6 +513,29 @@ template <int N> Dual<N> softplus(const Dual<N>& t) {
 
 extern "C" {
 
+// Softmin distance h = s^T z (s = softmax(-alpha z), z_i = |q - x_i|) of a sample set and
+// its gradient g = grad_q h = sum_i l_i v_i (Sec. IV-B.3, App. C), for tests of the
+// gradient variance by finite differences.
+void oracle_softmin(const double* q, const double* x, int m, double alpha, double* h, double* g) {
+  std::vector<double> z(m), sm(m);
+  double zmin = 0, ssum = 0, hv = 0;
+  for (int i = 0; i < m; ++i) {
+    double d2 = 0;
+    for (int d = 0; d < 3; ++d) d2 += (q[d] - x[3 * i + d]) * (q[d] - x[3 * i + d]);
+    z[i] = std::sqrt(d2);
+    if (i == 0 || z[i] < zmin) zmin = z[i];
+  }
+  for (int i = 0; i < m; ++i) { sm[i] = std::exp(-alpha * (z[i] - zmin)); ssum += sm[i]; }
+  for (int i = 0; i < m; ++i) { sm[i] /= ssum; hv += sm[i] * z[i]; }
+  *h = hv;
+  for (int d = 0; d < 3; ++d) g[d] = 0;
+  for (int i = 0; i < m; ++i) {
+    const double li = sm[i] * (alpha * hv - alpha * z[i] + 1.0);
+    if (z[i] > 0)
+      for (int d = 0; d < 3; ++d) g[d] += li * (q[d] - x[3 * i + d]) / z[i];
+  }
+}
+
 // Worker threads the parallel loops below use.
 int oracle_threads() { return omp_get_max_threads(); }
 
@@ -500,7 +562,8 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
                   int cand_prec, int d_mode, const double* q, long nq, const int8_t* sign,
                   double* mean, double* grad, double* var, double* var_f, int* argmin,
                   int* status, double* u_best, double* u_second, double* ratio, int* cand,
-                  double* ucand, double* cgrad, double* cvar, double* cvar_f, double* cratio) {
+                  double* ucand, double* cgrad, double* cvar, double* cvar_f, double* cratio,
+                  double* grad_var, double* cgrad_var) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs);
   QueryOpts o{ell, alpha, k_fuse, cand_prec, d_mode, false};
@@ -511,6 +574,8 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
                                              ell, noise, alpha, o, cgrad != nullptr);
     mean[p] = r.mean; var[p] = r.var; var_f[p] = r.var_f;
     for (int d = 0; d < 3; ++d) grad[3 * p + d] = r.grad[d];
+    if (grad_var)
+      for (int d = 0; d < 3; ++d) grad_var[3 * p + d] = r.grad_var[d];
     argmin[p] = r.argmin; status[p] = r.status;
     if (u_best) u_best[p] = r.u_best;
     if (u_second) u_second[p] = r.u_second;
@@ -525,6 +590,8 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
         cvar[j] = have ? r.cout[i].var : inf;
         cvar_f[j] = have ? r.cout[i].var_f : 1.0;
         cratio[j] = have ? r.cout[i].ratio : inf;
+        if (cgrad_var)
+          for (int d = 0; d < 3; ++d) cgrad_var[3 * j + d] = have ? r.cout[i].grad_var[d] : inf;
       }
     }
   }
