@@ -20,6 +20,8 @@ _SRC = os.path.join(_HERE, "ksdf_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
+KERNELS = {"rbf": 0, "matern32": 1}   # Table I
+
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
 _lp = ctypes.POINTER(ctypes.c_long)
@@ -52,17 +54,17 @@ def lib():
         L.oracle_cells_free.argtypes = [ctypes.c_void_p]
         L.oracle_fit.restype = ctypes.c_int
         L.oracle_fit.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, ctypes.c_double, ctypes.c_double,
-                                 _dp, _dp, _ip]
+                                 _dp, _dp, _ip, ctypes.c_int]
         L.oracle_query.argtypes = ([_dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp] +
                                    [ctypes.c_double] * 3 + [ctypes.c_int] * 3 +
                                    [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
-                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp])
+                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int])
         L.oracle_softmin.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.oracle_vjp.restype = ctypes.c_double
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp,
-                                  _dp, _dp, _dp, _ip])
+                                  _dp, _dp, _dp, _ip, ctypes.c_int])
         _lib = L
     return _lib
 
@@ -146,7 +148,7 @@ class Fit:
         return self.L[self.lofs[c]:self.lofs[c + 1]].reshape(m, m)
 
 
-def fit(points, cells: Cells, ell, noise, svar=None) -> Fit:
+def fit(points, cells: Cells, ell, noise, svar=None, kernel="rbf") -> Fit:
     L = lib()
     pts = _f64(points)
     sv = None if svar is None else _f64(svar)
@@ -156,12 +158,14 @@ def fit(points, cells: Cells, ell, noise, svar=None) -> Fit:
     Lf = np.zeros(int(lofs[-1]), np.float64)
     ok = np.zeros(cells.n, np.int32)
     nf = L.oracle_fit(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
-                      _p(cells.samples, _ip), ell, noise, _p(a, _dp), _p(Lf, _dp), _p(ok, _ip))
+                      _p(cells.samples, _ip), ell, noise, _p(a, _dp), _p(Lf, _dp), _p(ok, _ip),
+                      KERNELS[kernel])
     return Fit(a, Lf, lofs, ok, nf)
 
 
 def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=8,
-          cand_prec=64, d_mode=0, sign=None, svar=None, all_candidates=False) -> dict:
+          cand_prec=64, d_mode=0, sign=None, svar=None, all_candidates=False,
+          kernel="rbf") -> dict:
     """All outputs of the back-end at each query (see ``oracle_query``).  With
     all_candidates, also every candidate cell's gradient, variances and ratio
     (keys cgrad [Q,K,3], cgrad_var [Q,K,3], cvar, cvar_f, cratio [Q,K]).  grad_var [Q,3]
@@ -195,13 +199,13 @@ def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=
                    _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["ratio"], _dp),
                    _p(out["cand"], _ip), _p(out["ucand"], _dp), _p(g("cgrad"), _dp),
                    _p(g("cvar"), _dp), _p(g("cvar_f"), _dp), _p(g("cratio"), _dp),
-                   _p(out["grad_var"], _dp), _p(g("cgrad_var"), _dp))
+                   _p(out["grad_var"], _dp), _p(g("cgrad_var"), _dp), KERNELS[kernel])
     return out
 
 
 def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_prec=64, sign=None,
         mode=0, margin=0.3, weight=1.0, d_mean=None, d_grad=None, d_var=None, d_var_f=None,
-        per_point=False, force_argmin=None):
+        per_point=False, force_argmin=None, kernel="rbf"):
     """Dual-number VJP.  mode 0: given cotangents; mode 1: softplus collision cost.
     Returns (loss, d_points [Q,3], d_hyper [2] = d/d(l, sigma^2)), and with per_point
     also each query's own contribution to d_hyper [Q,2].  force_argmin [Q] (optional):
@@ -220,11 +224,11 @@ def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_pr
                         _p(ctr, _dp), ell, noise, -1.0 if alpha is None else alpha, k_fuse,
                         cand_prec, _p(q, _dp), len(q), _p(sg, _i8p), mode, margin, weight,
                         *[_p(c, _dp) for c in cot], _p(dp, _dp), _p(dh, _dp), _p(pp, _dp),
-                        _p(fa, _ip))
+                        _p(fa, _ip), KERNELS[kernel])
     return (loss, dp, dh, pp) if per_point else (loss, dp, dh)
 
 
 def run(points, cells: Cells, queries, ell, noise, **kw):
     """Fit then query, returning (fit, outputs)."""
-    f = fit(points, cells, ell, noise, svar=kw.get("svar"))
+    f = fit(points, cells, ell, noise, svar=kw.get("svar"), kernel=kw.get("kernel", "rbf"))
     return f, query(points, cells, f, queries, ell, noise, **kw)

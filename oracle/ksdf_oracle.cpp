@@ -10,8 +10,9 @@
 //   Sec. IV-B.1  log-GP posterior mean, gradient and variance (eq. log_gp_posterior_mean),
 //                kernel vector / matrix / noise, UDF gradient, local GPs per octant with
 //                overlapping collection boxes, min-fusion of the K nearest GPs
-//   Table I      RBF kernel and its inverse transform r(f)
-//   App. D       adaptive scaling (gamma = exp(d^2 / 2 l^2), r(f') = sqrt(-2 l^2 log f' + d^2))
+//   Table I      RBF and Matern 3/2 kernels and their inverse transforms r(f)
+//   App. D       adaptive scaling (RBF: gamma = exp(d^2 / 2 l^2), r(f') = sqrt(-2 l^2 log f' + d^2);
+//                Matern 3/2: gamma = exp(sqrt(3) d / l), r(f') = -(l / sqrt(3)) log f' + d)
 //   Sec. IV-B.3  softmin SDF variance V[u] = sum_i |grad_{x_i} h|^2 sigma_i^2
 //   Sec. IV-B.1  sign decomposition d = s * u
 //
@@ -19,8 +20,8 @@
 //   cells: collection box = cell box grown by `margin` per side; up to m_c samples
 //   nearest the cell centre (ties by lower sample index); candidate GPs = the
 //   K nearest occupied cell centres (ties by id); d in App. D = nearest sample;
-//   f' <= 0 excludes the cell (u = +inf); u^2 < 0 clamps u to 0; softmin
-//   temperature alpha = 1/(2 l^2) unless given.
+//   f' <= 0 excludes the cell (u = +inf); u^2 < 0 (RBF) or u < 0 (Matern) clamps
+//   u to 0; softmin temperature alpha = 1/(2 l^2) unless given, for both kernels.
 //
 // Scalar type T is double for the forward pass and Dual<N> (forward-mode
 // automatic differentiation) for the vector-Jacobian products.
@@ -176,9 +177,28 @@ void oracle_cells_free(void* hdl) { delete static_cast<CellSet*>(hdl); }
 namespace {
 
 // ---------------------------------------------------------------------------
+// kernels of Table I as functions of the squared distance
+// ---------------------------------------------------------------------------
+enum { KERNEL_RBF = 0, KERNEL_MATERN32 = 1 };
+
+// Matern 3/2 rate c = sqrt(3) / l: k(r) = (1 + c r) exp(-c r).
+template <class T>
+T matern_rate(const T& ell) { return T(std::sqrt(3.0)) / ell; }
+
+// k(r) from r^2.  RBF: exp(-r^2 / 2 l^2); Matern 3/2: (1 + c r) exp(-c r), which is
+// 1 at r = 0 (taken exactly there, where the square root has no derivative).
+template <class T>
+T kernel_r2(int kernel, const T& r2, const T& ell) {
+  if (kernel == KERNEL_RBF) return exp(-r2 / (T(2.0) * ell * ell));
+  if (!(val(r2) > 0)) return T(1.0);
+  const T t = matern_rate(ell) * sqrt(r2);
+  return (T(1.0) + t) * exp(-t);
+}
+
+// ---------------------------------------------------------------------------
 // fit: A = K + Sigma (eq. log_gp_posterior_mean with K_ij = k(x_i, x_j), Sigma_ii =
-// sigma_i^2), RBF k(r) = exp(-r^2 / 2 l^2) (Table I); A = L L^T (textbook
-// Cholesky); a = A^{-1} 1 (all labels equal exp(-lambda * 0) = 1).
+// sigma_i^2), k from Table I; A = L L^T (textbook Cholesky); a = A^{-1} 1 (all
+// labels equal exp(-lambda * 0) = 1).
 // ---------------------------------------------------------------------------
 struct Inputs {
   const double* pts;        // [N,3] surface samples
@@ -188,6 +208,7 @@ struct Inputs {
   const int* samples;       // [nnz]
   const double* centres;    // [n_cells,3]
   const long* lofs;         // [n_cells] offset of each cell's m x m factor
+  int kernel;               // KERNEL_RBF or KERNEL_MATERN32
 };
 
 template <class T>
@@ -206,7 +227,7 @@ bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L)
       const double* xj = in.pts + 3 * (long)in.samples[b + j];
       double dx = xi[0] - xj[0], dy = xi[1] - xj[1], dz = xi[2] - xj[2];
       double r2 = dx * dx + dy * dy + dz * dz;
-      A[(size_t)i * m + j] = exp(T(-r2) / (T(2.0) * ell * ell));
+      A[(size_t)i * m + j] = i == j ? T(1.0) : kernel_r2(in.kernel, T(r2), ell);
       if (i == j) A[(size_t)i * m + j] = A[(size_t)i * m + j] + sample_var(in, in.samples[b + i], noise);
     }
   for (int i = 0; i < m * m; ++i) L[i] = T(0.0);
@@ -292,6 +313,21 @@ T cell_udf(const Inputs& in, int c, const T* q, const T* a, const T& ell, const 
     d2 = z2[0];
   }
   T f = T(0.0);
+  if (in.kernel == KERNEL_MATERN32) {
+    // f' = gamma f with gamma = exp(c d): sum a_i (1 + c z_i) exp(-c (z_i - d));
+    // u = d - log(f') / c (App. D, Table I)
+    const T c = matern_rate(ell);
+    const T d = sqrt(d2);
+    for (int i = 0; i < m; ++i) {
+      const T z = sqrt(z2[i]);
+      f = f + a[b + i] * (T(1.0) + c * z) * exp(-c * (z - d));
+    }
+    if (!(val(f) > 0)) return T(std::numeric_limits<double>::infinity());
+    T u = d - log(f) / c;
+    if (val(u) < 0) { if (clamped) *clamped = true; return T(0.0); }
+    if (clamped) *clamped = false;
+    return u;
+  }
   for (int i = 0; i < m; ++i) f = f + a[b + i] * exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
   if (!(val(f) > 0)) return T(std::numeric_limits<double>::infinity());
   T u2 = d2 - T(2.0) * ell * ell * log(f);
@@ -325,12 +361,17 @@ CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T
   if (o.d_mode == 1) d2 = z2[0];
   if (o.d_mode == 2) d2 = T(0.0);
   CellOut<T> r;
-  // gradient: grad f = -(1/l^2) sum a_i k_i (x* - x_i); the UDF gradient is
-  // -grad f / |grad f| = w / |w| with w = sum a_i k_i (x* - x_i) (scaled by gamma).
+  // gradient.  RBF: grad f = -(1/l^2) sum a_i k_i (x* - x_i); Matern 3/2: dk/dr =
+  // -c^2 r exp(-c r), so grad f = -c^2 sum a_i exp(-c z_i) (x* - x_i).  Either way the
+  // UDF gradient is -grad f / |grad f| = w / |w| with w = sum a_i e_i (x* - x_i),
+  // e_i = k_i (RBF) or exp(-c z_i) (Matern), both scaled by gamma.
+  const bool matern = in.kernel == KERNEL_MATERN32;
+  const T cm = matern_rate(ell);
+  const T dref = matern ? sqrt(d2) : T(0.0);
   T w[3] = {T(0.0), T(0.0), T(0.0)};
   double absum = 0;
   for (int i = 0; i < m; ++i) {
-    T e = exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
+    T e = matern ? exp(-cm * (sqrt(z2[i]) - dref)) : exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
     for (int d = 0; d < 3; ++d) w[d] = w[d] + a[b + i] * e * diff[3 * i + d];
     absum += std::fabs(val(a[b + i]) * val(e)) * std::sqrt(val(z2[i]));
   }
@@ -342,7 +383,7 @@ CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T
   std::vector<T> v(m);
   T vv = T(0.0);
   for (int i = 0; i < m; ++i) {
-    T t = exp(-z2[i] / (T(2.0) * ell * ell));
+    T t = kernel_r2(in.kernel, z2[i], ell);
     for (int k = 0; k < i; ++k) t = t - L[in.lofs[c] + (long)i * m + k] * v[k];
     v[i] = t / L[in.lofs[c] + (long)i * m + i];
     vv = vv + v[i] * v[i];
@@ -474,13 +515,14 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
 }
 
 Inputs make_inputs(const double* pts, const double* svar, int n_cells, const int* offsets,
-                   const int* samples, const double* centres, std::vector<long>& lofs) {
+                   const int* samples, const double* centres, std::vector<long>& lofs,
+                   int kernel) {
   lofs.assign(n_cells + 1, 0);
   for (int c = 0; c < n_cells; ++c) {
     long m = offsets[c + 1] - offsets[c];
     lofs[c + 1] = lofs[c] + m * m;
   }
-  return Inputs{pts, svar, n_cells, offsets, samples, centres, lofs.data()};
+  return Inputs{pts, svar, n_cells, offsets, samples, centres, lofs.data(), kernel};
 }
 
 template <class T>
@@ -540,11 +582,12 @@ void oracle_softmin(const double* q, const double* x, int m, double alpha, doubl
 int oracle_threads() { return omp_get_max_threads(); }
 
 // Fit every cell in FP64.  a: [nnz]; L: concatenated row-major m_c x m_c factors.
+// kernel: KERNEL_RBF (0) or KERNEL_MATERN32 (1), here and below.
 int oracle_fit(const double* pts, const double* svar, int n_cells, const int* offsets,
                const int* samples, double ell, double noise, double* a_out, double* L_out,
-               int* ok) {
+               int* ok, int kernel) {
   std::vector<long> lofs;
-  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, nullptr, lofs);
+  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, nullptr, lofs, kernel);
   std::vector<double> a, L;
   int nfail = fit_all<double>(in, ell, noise, a, L, ok);
   std::copy(a.begin(), a.end(), a_out);
@@ -563,9 +606,9 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
                   double* mean, double* grad, double* var, double* var_f, int* argmin,
                   int* status, double* u_best, double* u_second, double* ratio, int* cand,
                   double* ucand, double* cgrad, double* cvar, double* cvar_f, double* cratio,
-                  double* grad_var, double* cgrad_var) {
+                  double* grad_var, double* cgrad_var, int kernel) {
   std::vector<long> lofs;
-  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs);
+  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs, kernel);
   QueryOpts o{ell, alpha, k_fuse, cand_prec, d_mode, false};
   const double inf = std::numeric_limits<double>::infinity();
 #pragma omp parallel for schedule(dynamic, 64)
@@ -609,9 +652,9 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
                   int mode, double margin, double weight, const double* d_mean,
                   const double* d_grad, const double* d_var, const double* d_var_f,
                   double* d_points, double* d_hyper, double* d_hyper_pp,
-                  const int* force_argmin) {
+                  const int* force_argmin, int kernel) {
   std::vector<long> lofs;
-  Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs);
+  Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs, kernel);
   QueryOpts o{ell, 0, k_fuse, cand_prec, 0, alpha_fixed <= 0};
   auto loss_of = [&](long p, auto mean, auto* g, auto var, auto var_f) {
     using T = decltype(mean);
