@@ -34,7 +34,8 @@ PEAK_VALU_TSLOTS = 39.32      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instru
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_room_grid.txt")
 KERNEL_SOURCES = {
-    "query_fast": ["query_fast.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
+    "query_fast": ["query_fast.hip", "query_split.h", "query_split64.hip", "query_split256.hip",
+                   "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
     "fused": ["fused.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
 }
 
@@ -114,6 +115,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 GPU leg")
+    ap.add_argument("--no-matern", action="store_true", help="skip the Matern 3/2 leg")
+    ap.add_argument("--no-grad-var", action="store_true",
+                    help="skip timing the gradient-variance output")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-tune", action="store_true", help="use the cached tuning, do not time")
     ap.add_argument("--tune-cache", default=None, help="write the autotuner's choice to this cache")
@@ -277,6 +281,52 @@ def main():
         log(f"graph replay: {graph:.3f} ms/step")
         del g
 
+    # cost of the optional gradient-variance output (App. C), not part of the step: the
+    # grid query alone, without and with it
+    model.set_tuning(**{**t_grid, "fused": 0})
+    gv_out = model._out(Q, dev, grad_var=True)
+    gv_ms = {}
+    for name, o in () if args.no_grad_var else (("query_ms", out), ("query_with_grad_var_ms", gv_out)):
+        model.query(q, sg, out=o)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(3):
+            model.query(q, sg, out=o)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gv_ms[name] = round(e0.elapsed_time(e1) / 3, 4)
+    del gv_out
+    gv_ms = gv_ms or None
+    log(f"grid query without / with grad_var: {gv_ms}")
+
+    # the Matern 3/2 variant (Table I) on the same room and grid, its own FP32 model:
+    # float-float fit as for the RBF, the plain one-thread-per-query kernel in FP32
+    matern = None
+    if not args.no_matern:
+        mat = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell,
+                         noise_var=wl.noise_var, precision="fp32", query_box=qbox,
+                         kernel="matern32")
+        mout = mat._out(Q, dev)
+        mat.fit(pts)
+        mat.query(q, sg, out=mout)
+        torch.cuda.synchronize()
+        mat.set_timing(True)
+        mf, mq = [], []
+        for _ in range(2):
+            mat.fit(pts)
+            mat.query(q, sg, out=mout)
+            torch.cuda.synchronize()
+            mf += mat.timer_read("fit")
+            mq += mat.timer_read("query")
+        mat.set_timing(False)
+        mst = mout["status"].cpu().numpy()
+        matern = {"fit_ms": round(float(np.mean(mf)), 4), "query_ms": round(float(np.mean(mq)), 4),
+                  "query_qps": round(Q / (float(np.mean(mq)) * 1e-3), 1),
+                  "no_valid_queries": int(((mst & 1) != 0).sum())}
+        log(f"matern32: {matern}")
+        del mout
+        mat.close()
+
     # roofline of the dominant kernel (algorithmic flops over its measured duration)
     k_fuse = int(model.hyper.k_fuse)
     fq, tr = query_flops(float(m.mean()), k_fuse)
@@ -319,6 +369,8 @@ def main():
         "fp64_cells": n_fp64, "no_valid_queries": int(((st & 1) != 0).sum()),
         "model_device_bytes": info["device_bytes"],
         "roofline": roofline, "roofline_backward": roof_bwd,
+        "grad_var_cost": gv_ms,
+        "matern32": matern,
     }
 
     if not args.no_plain:

@@ -62,7 +62,17 @@ enum { KSDF_C_FP64 = 1, KSDF_C_FAILED = 2 };
 #define KSDF_MAX_M 128     /* samples per cell */
 #define KSDF_MAX_K 16      /* fused cells per query */
 
-/* Hyperparameters (host struct).  ell: RBF length-scale l (m), > 0.  noise_var:
+/* Kernels of Table I.  KSDF_KERNEL_RBF: k(r) = exp(-r^2 / 2 l^2), u = sqrt(d^2 - 2 l^2
+ * ln f') (App. D scaling by the nearest sample d).  KSDF_KERNEL_MATERN32: k(r) =
+ * (1 + c r) exp(-c r) with c = sqrt(3) / l, u = d - ln(f') / c; u < 0 clamps to 0.
+ * The UDF gradient is w/|w| with w = sum a_i e_i (x* - x_i), e_i the scaled k_i (RBF)
+ * or exp(-c (z_i - d)) (Matern 3/2).  Matern 3/2 models: FP32 queries run the plain
+ * one-thread-per-query kernel in FP32 (the wave-cooperative kernels carry RBF-specific
+ * error bounds), ksdf_fit_query runs fit and query as separate launches, and the
+ * backward and the adjoint flags are not supported (KSDF_ERR_UNSUPPORTED). */
+enum { KSDF_KERNEL_RBF = 0, KSDF_KERNEL_MATERN32 = 1 };
+
+/* Hyperparameters (host struct).  ell: length-scale l (m), > 0.  noise_var:
  * uniform surface-sample variance sigma^2 >= 0 (used where no per-sample variance is
  * given).  alpha: softmin temperature; <= 0 ties it to the length-scale as
  * alpha = 1/(2 l^2), which the backward then differentiates through.  k_fuse:
@@ -78,6 +88,7 @@ typedef struct ksdf_hyper {
   int precision;
   double cond_fp64_threshold;
   int flags;          /* KSDF_FIT_* bits */
+  int kernel;         /* KSDF_KERNEL_*; fixed at ksdf_model_create */
 } ksdf_hyper;
 
 /* flags: KSDF_FIT_ADJOINT makes every fit also prepare the per-cell adjoint vectors
@@ -202,15 +213,17 @@ int ksdf_fit_cells(ksdf_model* model, const void* surface_pts, int dtype, long n
  * points: device [Q,3].  sign: device int8 [Q] (+1/-1) or NULL (all +1).
  * Outputs (device, overwritten): mean [Q] = s*u; grad [Q,3] = s*w/|w| (unit); var [Q]
  * = softmin V[u] (m^2) of the argmin cell; var_f [Q] = GP variance 1 - |L^{-1} k*|^2 of
- * the argmin cell, or NULL; argmin [Q] int32 cell id or NULL; q_status [Q] uint8 or
- * NULL.  A query with no valid cell gets mean = +inf, grad = 0, var = +inf, var_f = 1.
+ * the argmin cell, or NULL; grad_var [Q,3] = V[grad_k u], the variance of the softmin
+ * gradient of the argmin cell from the sample variances (Sec. IV-B.3, App. C), or NULL;
+ * argmin [Q] int32 cell id or NULL; q_status [Q] uint8 or NULL.  A query with no valid
+ * cell gets mean = +inf, grad = 0, var = +inf, var_f = 1, grad_var = +inf.
  * workspace: device scratch of at least ksdf_query_workspace_bytes(model, Q) bytes
  * (may be NULL when that is 0).  Asynchronous; allocates nothing.
  * ------------------------------------------------------------------------- */
 size_t ksdf_query_workspace_bytes(const ksdf_model* model, long Q);
 int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
-               void* mean, void* grad, void* var, void* var_f, int* argmin, uint8_t* q_status,
-               void* workspace, size_t ws_bytes, void* stream);
+               void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
+               uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * ksdf_fit_query — ksdf_fit_cells followed by ksdf_query, with the same arguments
@@ -226,8 +239,8 @@ size_t ksdf_fit_query_workspace_bytes(const ksdf_model* model, long Q);
 int ksdf_fit_query(ksdf_model* model, const void* surface_pts, int dtype, long n_points,
                    const void* sample_var, const ksdf_hyper* hyper, uint8_t* cell_status,
                    const void* points, long Q, const int8_t* sign, void* mean, void* grad,
-                   void* var, void* var_f, int* argmin, uint8_t* q_status, void* workspace,
-                   size_t ws_bytes, void* stream);
+                   void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status,
+                   void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * ksdf_query_backward — vector-Jacobian product of ksdf_query.

@@ -27,10 +27,15 @@ int check_hyper(const ksdf_hyper* hp) {
   }
   if (!(hp->ell > 0) || hp->noise_var < 0 || hp->k_fuse < 1 || hp->k_fuse > KSDF_MAX_K ||
       (hp->precision != KSDF_FP64 && hp->precision != KSDF_FP32) ||
-      !(hp->cond_fp64_threshold > 0) || (hp->flags & ~(KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF))) {
+      !(hp->cond_fp64_threshold > 0) || (hp->flags & ~(KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) ||
+      (hp->kernel != KSDF_KERNEL_RBF && hp->kernel != KSDF_KERNEL_MATERN32)) {
     set_error("hyperparameter out of range (ell > 0, noise_var >= 0, 1 <= k_fuse <= 16, "
-              "precision KSDF_FP64|KSDF_FP32, cond threshold > 0)");
+              "precision KSDF_FP64|KSDF_FP32, cond threshold > 0, kernel KSDF_KERNEL_*)");
     return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (hp->kernel != KSDF_KERNEL_RBF && hp->flags) {
+    set_error("the adjoint (backward) is implemented for the RBF kernel only");
+    return KSDF_ERR_UNSUPPORTED;
   }
   return KSDF_OK;
 }
@@ -140,6 +145,7 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
   (void)hipGetDevice(&m->device);
   (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
   m->precision = hyper->precision;
+  m->kernel = hyper->kernel;
   m->k_fuse = hyper->k_fuse;
   m->cond_thr = hyper->cond_fp64_threshold;
   m->n_cells = n_cells;
@@ -262,8 +268,10 @@ int prepare_fit(ksdf_model* m, const void* surface_pts, int dtype, long n_points
   int r = check_hyper(hyper);
   if (r) return r;
   if ((m->n_cells > 0 && !surface_pts) || (dtype != KSDF_DTYPE_F32 && dtype != KSDF_DTYPE_F64) ||
-      n_points != m->n_points || hyper->k_fuse != m->k_fuse || hyper->precision != m->precision) {
-    set_error("ksdf_fit_cells: arguments do not match the model (n_points, dtype, k_fuse, precision)");
+      n_points != m->n_points || hyper->k_fuse != m->k_fuse || hyper->precision != m->precision ||
+      hyper->kernel != m->kernel) {
+    set_error("ksdf_fit_cells: arguments do not match the model (n_points, dtype, k_fuse, precision, "
+              "kernel)");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   if ((r = check_device(m))) return r;
@@ -312,7 +320,7 @@ extern "C" size_t ksdf_fit_query_workspace_bytes(const ksdf_model* m, long Q) {
 extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
                               const void* sample_var, const ksdf_hyper* hyper,
                               uint8_t* cell_status, const void* points, long Q,
-                              const int8_t* sign, void* mean, void* grad, void* var, void* var_f,
+                              const int8_t* sign, void* mean, void* grad, void* var, void* var_f, void* grad_var,
                               int* argmin, uint8_t* q_status, void* workspace, size_t ws_bytes,
                               void* stream) {
   int r = prepare_fit(m, surface_pts, dtype, n_points, sample_var, hyper);
@@ -328,18 +336,18 @@ extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype,
     r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
     if (r) return r;
     m->fitted = true;
-    return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+    return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
                         ws_bytes, s);
   }
-  if (!m->tuning.fused) {
+  if (!m->tuning.fused || m->kernel != KSDF_KERNEL_RBF) {
     r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
     if (r) return r;
     m->fitted = true;
-    return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+    return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
                         ws_bytes, s);
   }
   r = launch_fit_query_fused(m, surface_pts, dtype, sample_var, cell_status, points, Q, sign,
-                             mean, grad, var, var_f, argmin, q_status, workspace, ws_bytes, s);
+                             mean, grad, var, var_f, grad_var, argmin, q_status, workspace, ws_bytes, s);
   if (r == KSDF_OK) m->fitted = true;
   return r;
 }
@@ -403,7 +411,7 @@ extern "C" size_t ksdf_query_workspace_bytes(const ksdf_model* m, long Q) {
 }
 
 extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                          void* mean, void* grad, void* var, void* var_f, int* argmin,
+                          void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                           uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
   if (int r0 = check_query_args(m, points, Q, mean, grad, var)) return r0;
   if (!m->fitted) {
@@ -417,7 +425,7 @@ extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const
   }
   int r = check_device(m);
   if (r) return r;
-  return launch_query(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, workspace,
+  return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
                       ws_bytes, (hipStream_t)stream);
 }
 
@@ -437,6 +445,10 @@ extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long
   if (!m->fitted) {
     set_error("ksdf_query_backward: the model has not been fitted");
     return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (m->kernel != KSDF_KERNEL_RBF) {
+    set_error("ksdf_query_backward: implemented for the RBF kernel only");
+    return KSDF_ERR_UNSUPPORTED;
   }
   const size_t need = backward_workspace_bytes(m, Q);
   if (ws_bytes < need || (need > 0 && !workspace)) {

@@ -609,8 +609,8 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
   void* fws = w;
   if (!argmin && Q > 0) {
     // recover each query's argmin cell with a forward pass into the workspace
-    int r = launch_query(m, points, Q, sign, fwd, fwd + Q * fb, fwd + 4 * Q * fb, nullptr, am,
-                         nullptr, fws, query_workspace_bytes(m, Q), s);
+    int r = launch_query(m, points, Q, sign, fwd, fwd + Q * fb, fwd + 4 * Q * fb, nullptr, nullptr,
+                         am, nullptr, fws, query_workspace_bytes(m, Q), s);
     if (r != KSDF_OK) return r;
     argmin = am;
   }

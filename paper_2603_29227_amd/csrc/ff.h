@@ -152,4 +152,15 @@ __host__ __device__ __forceinline__ ff ff_exp_neg_tab(ff t) {
   return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
 }
 
+// Square root of a float-float a >= 0: the float root s of the leading part, then one
+// Newton step on the exact residual a - s^2 (s^2 by TwoProduct), which doubles the
+// number of correct bits.
+__host__ __device__ __forceinline__ ff ff_sqrt(ff a) {
+#pragma clang fp contract(off)
+  if (!(a.hi > 0.f)) return {0.f, 0.f};
+  const float s = sqrtf(a.hi);
+  const ff r = ff_add(a, ff_neg(ff_two_prod(s, s)));
+  return ff_fast_two_sum(s, r.hi / (2.f * s));
+}
+
 }  // namespace ksdf

@@ -191,6 +191,8 @@ struct FitArgs {
   float noise_ff[2];     // sigma^2, 1/(2 l^2) and 1/l^3 as float-float pairs
   float inv2l2_ff[2];
   float inv_l3_ff[2];
+  int kernel;            // KSDF_KERNEL_* (Table I)
+  float mc_ff[2];        // Matern 3/2 rate c = sqrt(3) / l, float-float
   int adjoint;           // also prepare the adjoint vectors xi (and D when non-null)
   float* xi32;           // [nnz+pad,4] (xi_l, xi_s) as float-float: hi_l, hi_s, lo_l, lo_s
   float* D32;            // packed dA/dl or null
@@ -244,8 +246,9 @@ __device__ bool block_cholesky(T* Ap, int m) {
 }
 
 // Assemble A = K + Sigma (packed lower) from cell-local coordinates xs.
+// Matern 3/2 kernels take k = (1 + c r) exp(-c r) (mc = c); RBF exp(-r^2 inv2l2).
 template <class T>
-__device__ void assemble(T* Ap, const T* xs, const T* sv, int m, T inv2l2) {
+__device__ void assemble(T* Ap, const T* xs, const T* sv, int m, T inv2l2, int kernel, T mc) {
   const int n = m * (m + 1) / 2;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     // invert the packed index: row i with i(i+1)/2 <= e
@@ -255,7 +258,13 @@ __device__ void assemble(T* Ap, const T* xs, const T* sv, int m, T inv2l2) {
     const int k = e - i * (i + 1) / 2;
     const T dx = xs[3 * i] - xs[3 * k], dy = xs[3 * i + 1] - xs[3 * k + 1], dz = xs[3 * i + 2] - xs[3 * k + 2];
     const T r2 = dx * dx + dy * dy + dz * dz;
-    T v = exp(-r2 * inv2l2);
+    T v;
+    if (kernel == KSDF_KERNEL_MATERN32) {
+      const T t = mc * sqrt(r2);
+      v = (T(1) + t) * exp(-t);
+    } else {
+      v = exp(-r2 * inv2l2);
+    }
     if (i == k) v += sv[i];
     Ap[e] = v;
   }
@@ -489,6 +498,7 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
   __syncthreads();
   // A = K + Sigma in float-float
   const ff inv2l2{A.inv2l2_ff[0], A.inv2l2_ff[1]};
+  const ff mc{A.mc_ff[0], A.mc_ff[1]};
   for (int e = threadIdx.x; e < m * (m + 1) / 2; e += blockDim.x) {
     int i = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
     while (i * (i + 1) / 2 > e) --i;
@@ -500,7 +510,14 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
       const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
       r2 = ff_add(r2, ff_mul(dd, dd));
     }
-    ff v = ff_exp_neg_tab(ff_mul(r2, inv2l2));
+    ff v;
+    if (A.kernel == KSDF_KERNEL_MATERN32) {
+      // (1 + c r) exp(-c r), exactly 1 at r = 0
+      const ff t = ff_mul(ff_sqrt(r2), mc);
+      v = ff_mul(ff_add(ff{1.f, 0.f}, t), ff_exp_neg_tab(t));
+    } else {
+      v = ff_exp_neg_tab(ff_mul(r2, inv2l2));
+    }
     if (i == k) v = ff_add(v, ff{sv[i], svl[i]});
     Ahi[e] = v.hi;
     Alo[e] = v.lo;
@@ -621,7 +638,7 @@ __device__ void fit64_cell(const FitArgs& A, int c, double* smem) {
     }
     __syncthreads();
     double* Ap = A.L64 + A.loff[c];   // the factor is computed in place in global memory
-    assemble<double>(Ap, xs, sv, m, 1.0 / (2.0 * A.ell * A.ell));
+    assemble<double>(Ap, xs, sv, m, 1.0 / (2.0 * A.ell * A.ell), A.kernel, std::sqrt(3.0) / A.ell);
     __threadfence_block();
     const bool ok = block_cholesky<double>(Ap, m);
     __threadfence_block();
@@ -733,6 +750,7 @@ inline FitArgs make_fit_args(ksdf_model* m, const void* pts, int dtype, const vo
   A.loff = m->loff;
   A.centre64 = m->centre64;
   A.ell = m->ell;
+  A.kernel = m->kernel;
   A.noise = m->noise_var;
   A.cond_thr = m->cond_thr;
   A.user_status = user_status;
@@ -753,6 +771,9 @@ inline FitArgs make_fit_args(ksdf_model* m, const void* pts, int dtype, const vo
     const double inv = 1.0 / (2.0 * m->ell * m->ell);
     A.inv2l2_ff[0] = (float)inv;
     A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);
+    const double mc = std::sqrt(3.0) / m->ell;
+    A.mc_ff[0] = (float)mc;
+    A.mc_ff[1] = (float)(mc - (double)(float)mc);
     A.noise_ff[0] = (float)m->noise_var;
     A.noise_ff[1] = (float)(m->noise_var - (double)(float)m->noise_var);
   }

@@ -132,13 +132,13 @@ size_t fused_workspace_bytes(const ksdf_model* m, long Q) {
 
 int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void* svar,
                            uint8_t* cell_status, const void* points, long Q, const int8_t* sign,
-                           void* mean, void* grad, void* var, void* var_f, int* argmin,
+                           void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                            uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
   (void)ws_bytes;
   FitArgs F = make_fit_args(m, pts, dtype, svar, cell_status);
   F.emit32 = 1;
   F.list = nullptr;
-  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
+  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
   int* ctl = reinterpret_cast<int*>(static_cast<char*>(ws) + query_fast_workspace_bytes(m, Q));
   hipLaunchKernelGGL(fused_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
   if (Q > 0) {

@@ -49,6 +49,7 @@ struct ksdf_model {
   int device = 0;
   int n_cu = 0;  // compute units of the device
   int precision = KSDF_FP32;
+  int kernel = KSDF_KERNEL_RBF;
   int k_fuse = 8;
   int n_cells = 0;
   long nnz = 0;
@@ -128,11 +129,11 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
                hipStream_t s);
 int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
-                 void* grad, void* var, void* var_f, int* argmin, uint8_t* q_status, void* ws,
+                 void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
                  size_t ws_bytes, hipStream_t s);
 size_t query_workspace_bytes(const ksdf_model* m, long Q);
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                      void* mean, void* grad, void* var, void* var_f, int* argmin,
+                      void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
 size_t query_fast_workspace_bytes(const ksdf_model* m, long Q);
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
@@ -143,7 +144,7 @@ size_t backward_workspace_bytes(const ksdf_model* m, long Q);
 size_t fused_workspace_bytes(const ksdf_model* m, long Q);
 int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void* svar,
                            uint8_t* cell_status, const void* points, long Q, const int8_t* sign,
-                           void* mean, void* grad, void* var, void* var_f, int* argmin,
+                           void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                            uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
 
 }  // namespace ksdf

@@ -8,9 +8,14 @@
 // variance 1 - |L^{-1} k*|^2 by forward substitution, and the softmin variance
 // sum_i c_i^2 sigma_i^2, c_i = s_i (alpha h - alpha z_i + 1).  d = s u (sign input).
 //
-// This file holds the plain path of the FP64 model: one thread per query, every
-// read straight from the per-cell store (no staging, no bucketing).  FP32 models
-// use the wave-cooperative kernel of query_fast.hip.
+// The Matern 3/2 kernel of Table I replaces k by (1 + c r) exp(-c r), c = sqrt(3)/l,
+// the transform by u = d - ln(f')/c (App. D scaling gamma = exp(c d)) and e_i in w
+// by exp(-c (z_i - d)), since dk/dr = -c^2 r exp(-c r); u < 0 clamps to 0.
+//
+// This file holds the plain path: one thread per query, every read straight from
+// the per-cell store (no staging, no bucketing), in the model's precision.  It serves
+// FP64 models and FP32 Matern models; FP32 RBF models use the wave-cooperative
+// kernels of query_fast.hip.
 #include <cmath>
 
 #include "ksdf_internal.h"
@@ -26,6 +31,7 @@ struct QueryArgs {
   T* grad;
   T* var;
   T* var_f;
+  T* grad_var;
   int* argmin;
   uint8_t* qst;
   int n_cells;
@@ -47,6 +53,8 @@ struct QueryArgs {
   T inv2l2;           // 1/(2 l^2)
   T two_l2;           // 2 l^2
   T alpha;            // softmin temperature
+  int kernel;         // KSDF_KERNEL_*
+  T mc;               // Matern 3/2 rate sqrt(3) / l
 };
 
 namespace {
@@ -120,12 +128,27 @@ __device__ T cell_udf(const QueryArgs<T>& A, int c, T qx, T qy, T qz, bool* clam
     d2 = min(d2, dx * dx + dy * dy + dz * dz);
   }
   T f = T(0);
+  *clamped = false;
+  if (A.kernel == KSDF_KERNEL_MATERN32) {
+    const T d = sqrt(d2);
+    for (int i = 0; i < m; ++i) {
+      const T dx = lx - p[4 * i], dy = ly - p[4 * i + 1], dz = lz - p[4 * i + 2];
+      const T z = sqrt(dx * dx + dy * dy + dz * dz);
+      f += p[4 * i + 3] * (T(1) + A.mc * z) * exp(-A.mc * (z - d));
+    }
+    if (!(f > T(0))) return (T)INFINITY;
+    const T u = d - log(f) / A.mc;
+    if (u < T(0)) {
+      *clamped = true;
+      return T(0);
+    }
+    return u;
+  }
   for (int i = 0; i < m; ++i) {
     const T dx = lx - p[4 * i], dy = ly - p[4 * i + 1], dz = lz - p[4 * i + 2];
     const T z2 = dx * dx + dy * dy + dz * dz;
     f += p[4 * i + 3] * exp(-(z2 - d2) * A.inv2l2);
   }
-  *clamped = false;
   if (!(f > T(0))) return (T)INFINITY;
   const T u2 = d2 - A.two_l2 * log(f);
   if (u2 < T(0)) {
@@ -162,6 +185,8 @@ __global__ void __launch_bounds__(QT) query_plain_kernel(QueryArgs<T> A) {
     for (int d = 0; d < 3; ++d) A.grad[3 * q + d] = T(0);
     A.var[q] = (T)INFINITY;
     if (A.var_f) A.var_f[q] = T(1);
+    if (A.grad_var)
+      for (int d = 0; d < 3; ++d) A.grad_var[3 * q + d] = (T)INFINITY;
     if (A.argmin) A.argmin[q] = -1;
     if (A.qst) A.qst[q] = st | KSDF_Q_NO_VALID_CELL;
     return;
@@ -185,33 +210,73 @@ __global__ void __launch_bounds__(QT) query_plain_kernel(QueryArgs<T> A) {
   const T g = exp(-d2 * A.inv2l2);   // 1/gamma: k_i = e_i / gamma
   const T zmin = sqrt(d2);
   T S = 0, H = 0;
+  const bool matern = A.kernel == KSDF_KERNEL_MATERN32;
   for (int i = 0; i < m; ++i) {
     const T dx = lx - p[4 * i], dy = ly - p[4 * i + 1], dz = lz - p[4 * i + 2];
     const T z2 = dx * dx + dy * dy + dz * dz;
-    const T e = exp(-(z2 - d2) * A.inv2l2);
+    const T z = sqrt(z2);
+    // e_i of the gradient (scaled) and the unscaled kernel value k_i
+    T e, t;
+    if (matern) {
+      e = exp(-A.mc * (z - zmin));
+      t = (T(1) + A.mc * z) * exp(-A.mc * z);
+    } else {
+      e = exp(-(z2 - d2) * A.inv2l2);
+      t = e * g;
+    }
     const T ae = p[4 * i + 3] * e;
     w0 += ae * dx;
     w1 += ae * dy;
     w2 += ae * dz;
-    // forward substitution L v = k, k_i = exp(-z_i^2 / 2 l^2)
-    T t = e * g;
+    // forward substitution L v = k
     const T* row = L + (long)i * (i + 1) / 2;
     for (int j = 0; j < i; ++j) t -= row[j] * v[j];
     v[i] = t * row[i];
     vv += v[i] * v[i];
-    const T z = sqrt(z2);
     const T s = exp(-A.alpha * (z - zmin));
     S += s;
     H += s * z;
   }
   const T h = H / S;
   T var = 0;
+  // sums for the gradient variance: Vs = sum s_i v_i, g = sum l_i v_i (l_i = c_i)
+  T Vs[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
   for (int i = 0; i < m; ++i) {
     const T dx = lx - p[4 * i], dy = ly - p[4 * i + 1], dz = lz - p[4 * i + 2];
     const T z = sqrt(dx * dx + dy * dy + dz * dz);
     const T s = exp(-A.alpha * (z - zmin)) / S;
     const T ci = s * (A.alpha * h - A.alpha * z + T(1));
     var += ci * ci * sv[i];
+    if (z > T(0)) {
+      const T vd[3] = {dx / z, dy / z, dz / z};
+      for (int d = 0; d < 3; ++d) {
+        Vs[d] += s * vd[d];
+        gs[d] += ci * vd[d];
+      }
+    }
+  }
+  if (A.grad_var) {
+    // V[grad_k u] = sum_i sigma_i^2 |row k of J_i|^2 with J_i the derivative of the
+    // softmin gradient g with respect to sample i (App. C):
+    //   J_i = alpha w_i v_i^T + (l_i / z_i)(v_i v_i^T - I),
+    //   w_i = l_i (v_i - Vs) + s_i (v_i - g).
+    // As |v_i| = 1 the cross term of row k vanishes and
+    //   |row k|^2 = alpha^2 w_ik^2 + (l_i / z_i)^2 (1 - v_ik^2).
+    T gv[3] = {0, 0, 0};
+    for (int i = 0; i < m; ++i) {
+      const T dx = lx - p[4 * i], dy = ly - p[4 * i + 1], dz = lz - p[4 * i + 2];
+      const T z = sqrt(dx * dx + dy * dy + dz * dz);
+      if (!(z > T(0))) continue;   // a sample at the query has no direction
+      const T s = exp(-A.alpha * (z - zmin)) / S;
+      const T li = s * (A.alpha * h - A.alpha * z + T(1));
+      const T vd[3] = {dx / z, dy / z, dz / z};
+      const T lz2 = (li / z) * (li / z);
+      for (int d = 0; d < 3; ++d) {
+        const T w = li * (vd[d] - Vs[d]) + s * (vd[d] - gs[d]);
+        gv[d] += sv[i] * (A.alpha * A.alpha * w * w + lz2 * (T(1) - vd[d] * vd[d]));
+      }
+    }
+    for (int d = 0; d < 3; ++d) A.grad_var[3 * q + d] = gv[d];
   }
   const T wn = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
   T gx = 0, gy = 0, gz = 0;
@@ -234,7 +299,7 @@ __global__ void __launch_bounds__(QT) query_plain_kernel(QueryArgs<T> A) {
 
 template <class T>
 QueryArgs<T> make_args(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                       void* mean, void* grad, void* var, void* var_f, int* argmin,
+                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                        uint8_t* q_status) {
   QueryArgs<T> A{};
   A.pts = static_cast<const T*>(points);
@@ -244,6 +309,7 @@ QueryArgs<T> make_args(const ksdf_model* m, const void* points, long Q, const in
   A.grad = static_cast<T*>(grad);
   A.var = static_cast<T*>(var);
   A.var_f = static_cast<T*>(var_f);
+  A.grad_var = static_cast<T*>(grad_var);
   A.argmin = argmin;
   A.qst = q_status;
   A.n_cells = m->n_cells;
@@ -264,6 +330,8 @@ QueryArgs<T> make_args(const ksdf_model* m, const void* points, long Q, const in
   A.inv2l2 = (T)(1.0 / (2.0 * m->ell * m->ell));
   A.two_l2 = (T)(2.0 * m->ell * m->ell);
   A.alpha = (T)m->alpha;
+  A.kernel = m->kernel;
+  A.mc = (T)(std::sqrt(3.0) / m->ell);
   return A;
 }
 
@@ -274,18 +342,28 @@ size_t query_workspace_bytes(const ksdf_model* m, long Q) {
 }
 
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
-                 void* grad, void* var, void* var_f, int* argmin, uint8_t* q_status, void* ws,
+                 void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
                  size_t ws_bytes, hipStream_t s) {
   if (Q == 0) return KSDF_OK;
   const unsigned grid = (unsigned)((Q + QT - 1) / QT);
   if (m->precision == KSDF_FP64) {
-    QueryArgs<double> A = make_args<double>(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
+    QueryArgs<double> A = make_args<double>(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
     A.ps = m->ps64;
     A.sv = m->sv64;
     A.L = m->L64;
+    timer_mark(m, KSDF_TIMER_QUERY, 0, s);
     hipLaunchKernelGGL(query_plain_kernel<double>, dim3(grid), dim3(QT), 0, s, A);
+    timer_mark(m, KSDF_TIMER_QUERY, 1, s);
+  } else if (m->kernel != KSDF_KERNEL_RBF) {
+    QueryArgs<float> A = make_args<float>(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
+    A.ps = m->ps32;
+    A.sv = m->sv32;
+    A.L = m->L32;
+    timer_mark(m, KSDF_TIMER_QUERY, 0, s);
+    hipLaunchKernelGGL(query_plain_kernel<float>, dim3(grid), dim3(QT), 0, s, A);
+    timer_mark(m, KSDF_TIMER_QUERY, 1, s);
   } else {
-    return launch_query_fast(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status, ws,
+    return launch_query_fast(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, ws,
                              ws_bytes, s);
   }
   KSDF_HIP_TRY(hipGetLastError());

@@ -8,14 +8,9 @@
 #include "ksdf_internal.h"
 
 namespace ksdf {
-namespace {
 
-
-constexpr int FQ = 256;            // threads per block (4 independent waves)
-constexpr float LOG2E = 1.4426950408889634f;
-constexpr float LN2 = 0.6931471805599453f;
-constexpr float EPS32 = 5.9604645e-08f;
-
+// Arguments of the FP32 query kernels (shared by the translation units that launch
+// them, hence outside the file-local namespace).
 struct FastArgs {
   const float* pts;
   long Q;
@@ -24,6 +19,7 @@ struct FastArgs {
   float* grad;
   float* var;
   float* var_f;
+  float* grad_var;
   int* argmin;
   uint8_t* qst;
   const int* perm;
@@ -53,6 +49,32 @@ struct FastArgs {
   float inv2l2_ff[2];
   float far2;        // |x - centre|^2 beyond which pass 2 takes the far-field exponent
 };
+
+// What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
+// cell (-1: none valid), the minimum u^2 and the scaling reference used for that
+// cell.  32 bytes, the record the split query passes between its two kernels.
+struct Pass1 {
+  float qx, qy, qz, best;
+  int qi, bc;
+  float bref;
+  int flags;   // bit 0: query outside the candidate index; bit 1: active lane
+};
+
+// two-kernel query launches (query_split64.hip, query_split256.hip)
+void launch_query_split_64(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                           int* count, int* cursor, int* tsum, bool lane, hipStream_t s);
+void launch_query_split_256(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                            int* count, int* cursor, int* tsum, bool lane, hipStream_t s);
+
+namespace {
+
+
+constexpr int FQ = 256;            // threads per block (4 independent waves)
+constexpr float LOG2E = 1.4426950408889634f;
+constexpr float LN2 = 0.6931471805599453f;
+constexpr float EPS32 = 5.9604645e-08f;
+
+
 
 __device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
 #pragma unroll
@@ -195,16 +217,6 @@ __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int
   fsub_chunk<0, MB, LC>(Lc, m, v, vv, t);
   return vv;
 }
-
-// What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
-// cell (-1: none valid), the minimum u^2 and the scaling reference used for that
-// cell.  32 bytes, the record the split query passes between its two kernels.
-struct Pass1 {
-  float qx, qy, qz, best;
-  int qi, bc;
-  float bref;
-  int flags;   // bit 0: query outside the candidate index; bit 1: active lane
-};
 
 // Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
 // of a wave (lanes pass their own sq); every lane of the wave must call it together
@@ -490,6 +502,60 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   return r;
 }
 
+// Variance of the softmin gradient g = sum_i l_i v_i of one cell (App. C): the
+// derivative of g with respect to sample i is
+//   J_i = alpha w_i v_i^T + (l_i / z_i)(v_i v_i^T - I),  w_i = l_i (v_i - Vs) + s_i (v_i - g),
+// with v_i the unit vector from sample i to the query, s the normalised softmin
+// weights, l_i = s_i (alpha h - alpha z_i + 1) and Vs = sum s_i v_i.  As |v_i| = 1,
+// row k of J_i has squared norm alpha^2 w_ik^2 + (l_i / z_i)^2 (1 - v_ik^2), and
+// V[grad_k u] = sum_i sigma_i^2 |row k of J_i|^2.  With t_i = alpha (z_i - zref) and
+// the unnormalised weights e^{-t_i}: s_i = e^{-t_i} / S and l_i = s_i (Tb - t_i).
+// Two more passes over the cell's samples (the sums Vs and g first); called only
+// when the caller asks for the output.
+__device__ __forceinline__ float3 grad_var_cell(const FastArgs& A, int b, int m, float lx,
+                                                float ly, float lz, float zref, float S,
+                                                float Tb) {
+  const float invS = 1.f / S;
+  float V0 = 0.f, V1 = 0.f, V2 = 0.f, G0 = 0.f, G1 = 0.f, G2 = 0.f;
+  for (int i = 0; i < m; ++i) {
+    const float4 P = A.ps[b + i];
+    const float dx = lx - P.x, dy = ly - P.y, dz = lz - P.z;
+    const float z = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    if (!(z > 0.f)) continue;
+    const float s = __builtin_amdgcn_exp2f(-A.alpha_l2e * (z - zref)) * invS;
+    const float l = s * (Tb - A.alpha * (z - zref));
+    const float iz = 1.f / z;
+    const float v0 = dx * iz, v1 = dy * iz, v2 = dz * iz;
+    V0 = fmaf(s, v0, V0);
+    V1 = fmaf(s, v1, V1);
+    V2 = fmaf(s, v2, V2);
+    G0 = fmaf(l, v0, G0);
+    G1 = fmaf(l, v1, G1);
+    G2 = fmaf(l, v2, G2);
+  }
+  const float a2 = A.alpha * A.alpha;
+  float r0 = 0.f, r1 = 0.f, r2 = 0.f;
+  for (int i = 0; i < m; ++i) {
+    const float4 P = A.ps[b + i];
+    const float dx = lx - P.x, dy = ly - P.y, dz = lz - P.z;
+    const float z = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    if (!(z > 0.f)) continue;
+    const float s = __builtin_amdgcn_exp2f(-A.alpha_l2e * (z - zref)) * invS;
+    const float l = s * (Tb - A.alpha * (z - zref));
+    const float iz = 1.f / z;
+    const float v0 = dx * iz, v1 = dy * iz, v2 = dz * iz;
+    const float sv = A.sv[b + i];
+    const float lz2 = (l * iz) * (l * iz);
+    const float x0 = l * (v0 - V0) + s * (v0 - G0);
+    const float x1 = l * (v1 - V1) + s * (v1 - G1);
+    const float x2 = l * (v2 - V2) + s * (v2 - G2);
+    r0 = fmaf(sv, fmaf(a2 * x0, x0, lz2 * (1.f - v0 * v0)), r0);
+    r1 = fmaf(sv, fmaf(a2 * x1, x1, lz2 * (1.f - v1 * v1)), r1);
+    r2 = fmaf(sv, fmaf(a2 * x2, x2, lz2 * (1.f - v2 * v2)), r2);
+  }
+  return make_float3(r0, r1, r2);
+}
+
 // The argmin cell's outputs (gradient, GP variance, softmin variance) and every
 // output of the query; all lanes of the wave call it together.
 template <int MB, bool LANE = false>
@@ -503,6 +569,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
 
   // ---- pass 2: argmin cell outputs, wave-uniform over the distinct argmin cells
   float w0 = 0.f, w1 = 0.f, w2 = 0.f, vv = 0.f, var = 0.f;
+  float gv0 = 0.f, gv1 = 0.f, gv2 = 0.f;
   bool todo = bc >= 0;
   while (true) {
     int c;
@@ -585,6 +652,12 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
       w0 = a0;
       w1 = a1;
       w2 = a2;
+      if (A.grad_var) {
+        const float3 g = grad_var_cell(A, b, m, lx, ly, lz, zref, S, Tb);
+        gv0 = g.x;
+        gv1 = g.y;
+        gv2 = g.z;
+      }
       todo = false;
     }
   }
@@ -593,6 +666,11 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   const float sgn = A.sign ? (float)A.sign[qi] : 1.f;
   uint8_t st = outside ? KSDF_Q_OUTSIDE_INDEX : 0;
   if (bc < 0) {
+    if (A.grad_var) {
+      A.grad_var[3 * qi] = INFINITY;
+      A.grad_var[3 * qi + 1] = INFINITY;
+      A.grad_var[3 * qi + 2] = INFINITY;
+    }
     A.mean[qi] = INFINITY;
     A.grad[3 * qi] = 0.f;
     A.grad[3 * qi + 1] = 0.f;
@@ -621,6 +699,11 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   A.grad[3 * qi + 2] = sgn * gz;
   A.var[qi] = var;
   if (A.var_f) A.var_f[qi] = fmaxf(1.f - vv, 0.f);
+  if (A.grad_var) {
+    A.grad_var[3 * qi] = gv0;
+    A.grad_var[3 * qi + 1] = gv1;
+    A.grad_var[3 * qi + 2] = gv2;
+  }
   if (A.argmin) A.argmin[qi] = bc;
   if (A.qst) A.qst[qi] = st;
 }
@@ -777,7 +860,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Query arguments of an FP32 model (outputs set by the caller's launch).
 inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                               void* mean, void* grad, void* var, void* var_f, int* argmin,
+                               void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                                uint8_t* q_status) {
   FastArgs A{};
   A.pts = static_cast<const float*>(points);
@@ -787,6 +870,7 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   A.grad = static_cast<float*>(grad);
   A.var = static_cast<float*>(var);
   A.var_f = static_cast<float*>(var_f);
+  A.grad_var = static_cast<float*>(grad_var);
   A.argmin = argmin;
   A.qst = q_status;
   A.n_cells = m->n_cells;

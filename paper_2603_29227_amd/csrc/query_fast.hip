@@ -45,57 +45,6 @@ void launch_query_nt(const ksdf_model* m, const FastArgs& A, hipStream_t s) {
   else hipLaunchKernelGGL((query_fast_kernel<16, 128, NT>), dim3(g), dim3(NT), 0, s, A);
 }
 
-// Split query: pass 1 (candidates, min-fusion) writes one record per query in wave
-// order and counts the queries of each argmin cell; the records are regrouped by
-// argmin cell; pass 2 then meets one or two argmin cells per wave instead of the
-// two to three of a spatial bucket, so the per-cell work (gradient, GP variance by
-// forward substitution, softmin variance) is not repeated for lanes that idle.
-template <int KM, int NT, bool LANE>
-__global__ void __launch_bounds__(NT) query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
-  const long sq = (long)blockIdx.x * NT + threadIdx.x;
-  const Pass1 r = query_pass1<KM, LANE>(A, sq);
-  const bool active = (r.flags & 2) != 0;
-  if (active) rec[sq] = r;
-  wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
-}
-
-__global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, long Q, int n_cells,
-                                                            int* cursor, Pass1* rec2) {
-  const long sq = (long)blockIdx.x * 256 + threadIdx.x;
-  const bool active = sq < Q;
-  Pass1 r{};
-  if (active) r = rec[sq];
-  const int pos = wave_slot(cursor, r.bc < 0 ? n_cells : r.bc, active);
-  if (active) rec2[pos] = r;
-}
-
-template <int MB, int NT, bool LANE>
-__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
-  const long sq = (long)blockIdx.x * NT + threadIdx.x;
-  Pass1 r{};
-  r.bc = -1;
-  if (sq < A.Q) r = rec2[sq];
-  query_finish<MB, LANE>(A, r);
-}
-
-template <int NT, bool LANE>
-void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2, int* count,
-                     int* cursor, int* tsum, hipStream_t s) {
-  const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
-  const long nc = (long)m->n_cells + 1;
-  const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
-  if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
-  else hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum, cursor);
-  hipLaunchKernelGGL(query_regroup_kernel, dim3((unsigned)((A.Q + 255) / 256)), dim3(256), 0, s, rec,
-                     A.Q, m->n_cells, cursor, rec2);
-  if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
-  else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
-}
-
 size_t bucketing_bytes(const ksdf_model* m, long Q) {
   const long nb = n_bins_of(m);
   const long tiles = (nb + SCAN_TILE - 1) / SCAN_TILE;
@@ -113,11 +62,11 @@ size_t query_fast_workspace_bytes(const ksdf_model* m, long Q) {
 }
 
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                      void* mean, void* grad, void* var, void* var_f, int* argmin,
+                      void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
   (void)ws_bytes;   // checked by the caller against query_workspace_bytes
   if (Q == 0) return KSDF_OK;
-  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, argmin, q_status);
+  FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
   int r = launch_bucketing(m, A, ws, s);
   if (r != KSDF_OK) return r;
   timer_mark(m, KSDF_TIMER_QUERY, 0, s);
@@ -138,13 +87,8 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
       return KSDF_ERR_UNSUPPORTED;
     }
     const bool lane = m->tuning.query_lanes != 0;
-    if (m->tuning.query_block == 64) {
-      if (lane) launch_split_nt<64, true>(m, A, rec, rec2, count, cursor, tsum, s);
-      else launch_split_nt<64, false>(m, A, rec, rec2, count, cursor, tsum, s);
-    } else {
-      if (lane) launch_split_nt<256, true>(m, A, rec, rec2, count, cursor, tsum, s);
-      else launch_split_nt<256, false>(m, A, rec, rec2, count, cursor, tsum, s);
-    }
+    if (m->tuning.query_block == 64) launch_query_split_64(m, A, rec, rec2, count, cursor, tsum, lane, s);
+    else launch_query_split_256(m, A, rec, rec2, count, cursor, tsum, lane, s);
   } else if (m->tuning.query_block == 64) {
     launch_query_nt<64>(m, A, s);
   } else {

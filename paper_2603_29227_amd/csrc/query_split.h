@@ -1,0 +1,66 @@
+// Two-kernel form of the FP32 query (a launch choice with the same outputs as the
+// one-kernel form of query_fast.hip).
+//
+// Pass 1 (candidates, min-fusion) writes one record per query in wave order and
+// counts the queries of each argmin cell; the records are regrouped by argmin cell;
+// pass 2 then meets one or two argmin cells per wave instead of the two to three of
+// a spatial bucket, so the per-cell work (gradient, GP variance by forward
+// substitution, softmin variance) is not repeated for lanes that idle.
+//
+// The kernels are instantiated per block size in query_split64.hip and
+// query_split256.hip, which compile in parallel.
+#pragma once
+
+#include "query_dev.h"
+
+namespace ksdf {
+namespace {
+
+template <int KM, int NT, bool LANE>
+__global__ void __launch_bounds__(NT) query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
+  const long sq = (long)blockIdx.x * NT + threadIdx.x;
+  const Pass1 r = query_pass1<KM, LANE>(A, sq);
+  const bool active = (r.flags & 2) != 0;
+  if (active) rec[sq] = r;
+  wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
+}
+
+__global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, long Q, int n_cells,
+                                                            int* cursor, Pass1* rec2) {
+  const long sq = (long)blockIdx.x * 256 + threadIdx.x;
+  const bool active = sq < Q;
+  Pass1 r{};
+  if (active) r = rec[sq];
+  const int pos = wave_slot(cursor, r.bc < 0 ? n_cells : r.bc, active);
+  if (active) rec2[pos] = r;
+}
+
+template <int MB, int NT, bool LANE>
+__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
+  const long sq = (long)blockIdx.x * NT + threadIdx.x;
+  Pass1 r{};
+  r.bc = -1;
+  if (sq < A.Q) r = rec2[sq];
+  query_finish<MB, LANE>(A, r);
+}
+
+template <int NT, bool LANE>
+void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2, int* count,
+                     int* cursor, int* tsum, hipStream_t s) {
+  const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
+  const long nc = (long)m->n_cells + 1;
+  const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
+  if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  else hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum, cursor);
+  hipLaunchKernelGGL(query_regroup_kernel, dim3((unsigned)((A.Q + 255) / 256)), dim3(256), 0, s, rec,
+                     A.Q, m->n_cells, cursor, rec2);
+  if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+  else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+}
+
+}  // namespace
+}  // namespace ksdf

@@ -56,11 +56,14 @@ class Tuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+KERNELS = {"rbf": 0, "matern32": 1}   # KSDF_KERNEL_* (Table I)
+
+
 class Hyper(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_double), ("noise_var", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("k_fuse", ctypes.c_int),
                 ("precision", ctypes.c_int), ("cond_fp64_threshold", ctypes.c_double),
-                ("flags", ctypes.c_int)]
+                ("flags", ctypes.c_int), ("kernel", ctypes.c_int)]
 
 
 _lib = None
@@ -92,7 +95,8 @@ def lib():
         L.ksdf_fit_cells.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp]
         L.ksdf_query_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_query_workspace_bytes.restype = sz
-        L.ksdf_query.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz, _vp]
+        L.ksdf_query.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
+                                 _vp]
         L.ksdf_backward_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -100,7 +104,7 @@ def lib():
         L.ksdf_fit_query_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_fit_query_workspace_bytes.restype = sz
         L.ksdf_fit_query.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp, l, _vp, _vp, _vp, _vp, _vp,
-                                     _vp, _vp, _vp, sz, _vp]
+                                     _vp, _vp, _vp, _vp, sz, _vp]
         L.ksdf_model_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_get_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_set_timing.argtypes = [_vp, i]
@@ -182,7 +186,7 @@ class Model:
     def __init__(self, cells: CellSet, n_points: int, origin, h: float, ell: float = 0.2,
                  noise_var: float = 1e-4, k_fuse: int = 8, precision: str = "fp32",
                  alpha: Optional[float] = None, cond_threshold: float = 1e6, query_box=None,
-                 adjoint: bool = False, adjoint_var_f: bool = False):
+                 adjoint: bool = False, adjoint_var_f: bool = False, kernel: str = "rbf"):
         if not torch.cuda.is_available():
             raise KsdfError("no GPU: libksdf needs a gfx950 device")
         self._lib = lib()
@@ -193,8 +197,12 @@ class Model:
         self.precision = FP64 if precision == "fp64" else FP32
         self.dtype = torch.float64 if self.precision == FP64 else torch.float32
         flags = (FIT_ADJOINT if adjoint or adjoint_var_f else 0) | (FIT_ADJOINT_VARF if adjoint_var_f else 0)
+        if kernel not in KERNELS:
+            raise ValueError(f"kernel must be one of {sorted(KERNELS)}")
+        self.kernel = kernel
         self.hyper = Hyper(float(ell), float(noise_var), -1.0 if alpha is None else float(alpha),
-                           int(k_fuse), self.precision, float(cond_threshold), flags)
+                           int(k_fuse), self.precision, float(cond_threshold), flags,
+                           KERNELS[kernel])
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._h = ctypes.c_void_p()
         qlo = qhi = None
@@ -279,7 +287,10 @@ class Model:
         return self._ws
 
     def query(self, points: torch.Tensor, sign: Optional[torch.Tensor] = None, var_f=True,
-              argmin=True, status=True, out: Optional[dict] = None, stream=None) -> dict:
+              argmin=True, status=True, grad_var=False, out: Optional[dict] = None,
+              stream=None) -> dict:
+        """Per-query outputs: mean, grad [Q,3], var, and optionally var_f, argmin, status
+        and grad_var [Q,3] (the variance of each gradient component, App. C)."""
         if points.dtype != self.dtype or not points.is_cuda or not points.is_contiguous() \
                 or points.dim() != 2 or points.shape[1] != 3:
             raise ValueError(f"points must be a contiguous [Q,3] CUDA {self.dtype} tensor")
@@ -287,25 +298,16 @@ class Model:
             raise ValueError("sign must be int8 [Q]")
         Q = len(points)
         if out is None:
-            dev, dt = points.device, self.dtype
-            out = dict(mean=torch.empty(Q, dtype=dt, device=dev),
-                       grad=torch.empty(Q, 3, dtype=dt, device=dev),
-                       var=torch.empty(Q, dtype=dt, device=dev))
-            if var_f:
-                out["var_f"] = torch.empty(Q, dtype=dt, device=dev)
-            if argmin:
-                out["argmin"] = torch.empty(Q, dtype=torch.int32, device=dev)
-            if status:
-                out["status"] = torch.empty(Q, dtype=torch.uint8, device=dev)
+            out = self._out(Q, points.device, var_f, argmin, status, grad_var)
         nb = self._lib.ksdf_query_workspace_bytes(self._h, Q)
         ws = self._workspace(nb)
         _check(self._lib.ksdf_query(self._h, _ptr(points), Q, _ptr(sign), _ptr(out["mean"]),
                                     _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
-                                    _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
+                                    _ptr(out.get("grad_var")), _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
                                     _stream(stream)), "ksdf_query")
         return out
 
-    def _out(self, Q, device, var_f=True, argmin=True, status=True):
+    def _out(self, Q, device, var_f=True, argmin=True, status=True, grad_var=False):
         dt = self.dtype
         out = dict(mean=torch.empty(Q, dtype=dt, device=device),
                    grad=torch.empty(Q, 3, dtype=dt, device=device),
@@ -316,10 +318,13 @@ class Model:
             out["argmin"] = torch.empty(Q, dtype=torch.int32, device=device)
         if status:
             out["status"] = torch.empty(Q, dtype=torch.uint8, device=device)
+        if grad_var:
+            out["grad_var"] = torch.empty(Q, 3, dtype=dt, device=device)
         return out
 
     def fit_query(self, points: torch.Tensor, queries: torch.Tensor, sign=None, sample_var=None,
-                  cell_status=None, out: Optional[dict] = None, stream=None) -> dict:
+                  cell_status=None, grad_var=False, out: Optional[dict] = None,
+                  stream=None) -> dict:
         """Fit and query in one persistent fused launch (FP32 models)."""
         if not points.is_cuda or points.dim() != 2 or points.shape[1] != 3 or not points.is_contiguous():
             raise ValueError("points must be a contiguous [N,3] CUDA tensor")
@@ -327,14 +332,14 @@ class Model:
             raise ValueError(f"queries must be a contiguous [Q,3] CUDA {self.dtype} tensor")
         dt = DTYPE_F64 if points.dtype == torch.float64 else DTYPE_F32
         Q = len(queries)
-        out = out if out is not None else self._out(Q, queries.device)
+        out = out if out is not None else self._out(Q, queries.device, grad_var=grad_var)
         nb = self._lib.ksdf_fit_query_workspace_bytes(self._h, Q)
         ws = self._workspace(nb)
         _check(self._lib.ksdf_fit_query(self._h, _ptr(points), dt, len(points), _ptr(sample_var),
                                         ctypes.byref(self.hyper), _ptr(cell_status), _ptr(queries), Q,
                                         _ptr(sign), _ptr(out["mean"]), _ptr(out["grad"]),
                                         _ptr(out["var"]), _ptr(out.get("var_f")),
-                                        _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
+                                        _ptr(out.get("grad_var")), _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
                                         _stream(stream)), "ksdf_fit_query")
         self.points = points
         self.sample_var = sample_var

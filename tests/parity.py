@@ -12,6 +12,9 @@ Tolerances (the parity contract):
          adds to the cancellation, and the measured error is about 4e-7 x ratio.
   var    |d| <= 1e-3 |ref| (FP32) / 1e-10 |ref| (FP64).
   var_f  |d| <= 1e-3 (FP32) / 1e-10 (FP64), relative to the prior variance k(x,x) = 1.
+  grad_var (when the GPU output holds it) |d_k| <= 1e-3 (FP32) / 1e-10 (FP64) x max_k
+         |ref_k|: the three components share one scale, and a component can be near 0
+         (the (1 - v_k^2) factor of the dominant direction) while the others are not.
 Near-ties of the min-fusion: the GPU's argmin cell is accepted when it is one of
 the oracle's candidates and its oracle u is within the mean tolerance of the
 oracle's minimum; grad / var / var_f are then compared with the oracle's values
@@ -88,6 +91,17 @@ def compare(gpu: dict, ora: dict, ell: float, precision: str, sign=None) -> dict
         m_vf = np.ones(Q, bool)
         m_vf[idx] = np.abs(gf - cvf) <= t["var_f"]
         fail("var_f", m_vf)
+    if gpu.get("grad_var") is not None:
+        ggv = np.asarray(gpu["grad_var"], np.float64)[idx]
+        cgv = ora["cgrad_var"][idx, c]
+        scale = np.abs(cgv).max(1)
+        gverr = np.abs(ggv - cgv).max(1)
+        m_gv = np.ones(Q, bool)
+        m_gv[idx] = gverr <= t["var"] * scale
+        fail("grad_var", m_gv)
+        rep["grad_var_relerr_max"] = float((gverr / np.maximum(scale, 1e-300)).max()) if idx.size else 0.0
+        # no-valid queries report +inf
+        fail("grad_var_no_valid", ~novalid | np.isinf(np.asarray(gpu["grad_var"])).all(1))
     # error statistics (for reports)
     mv = v & np.isfinite(gmean)
     rel = np.abs(gmean[mv] - ora["mean"][mv]) / np.maximum(np.abs(ora["mean"][mv]), 1.0)

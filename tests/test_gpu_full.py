@@ -65,7 +65,7 @@ def test_room_grid_full_size():
     pts = torch.from_numpy(wl.points).cuda()
     q = torch.from_numpy(wl.queries).cuda()
     sg = torch.from_numpy(wl.sign).cuda()
-    out = model.fit_query(pts, q, sg)
+    out = model.fit_query(pts, q, sg, grad_var=True)
     torch.cuda.synchronize()
     st = out["status"].cpu().numpy()
     assert int(((st & 1) != 0).sum()) == 0
@@ -162,7 +162,7 @@ def test_terrain_full_size():
     q = torch.from_numpy(wl.queries).cuda()
     sg = torch.from_numpy(wl.sign).cuda()
     model.fit(pts)
-    out = model.query(q, sg)
+    out = model.query(q, sg, grad_var=True)
     torch.cuda.synchronize()
     idx = _sample(out, 12000, 4000, 22)
     _check_sample(wl, cells, out, idx, "terrain grid")

@@ -1,0 +1,88 @@
+"""GPU parity of the Matern 3/2 kernel variant (Table I, App. D) against the FP64
+oracle, element by element (tests/parity.py's tolerances), for FP64 and FP32 models,
+with every output including the gradient variance; and the variant's limits (no
+backward, fused fit+query served by separate launches)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes
+from tests.parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _cells(wl):
+    return ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                            wl.m_cap_grid, wl.key_lo)
+
+
+def _ocells(wl, cells):
+    return oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                        np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+
+
+def _run(wl, precision):
+    cells = _cells(wl)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       precision=precision, kernel="matern32")
+    st = torch.zeros(max(cells.n, 1), dtype=torch.uint8, device="cuda")
+    model.fit(torch.from_numpy(np.ascontiguousarray(wl.points)).to("cuda", dt), cell_status=st)
+    out = model.query(torch.from_numpy(np.ascontiguousarray(wl.queries)).to("cuda", dt),
+                      torch.from_numpy(wl.sign).cuda(), grad_var=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in out.items()}
+    oc = _ocells(wl, cells)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel="matern32")
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, kernel="matern32",
+                     cand_prec=64 if precision == "fp64" else 32, sign=wl.sign, all_candidates=True)
+    return model, cells, g, o, st.cpu().numpy()[:cells.n]
+
+
+def test_matern_sphere_fp64():
+    _say("matern32 sphere fp64, 10k queries")
+    wl = scenes.sphere_workload()
+    model, _, g, o, _ = _run(wl, "fp64")
+    rep = assert_parity(g, o, wl.ell, "fp64", wl.sign, label="matern sphere fp64")
+    assert rep["mean_err_max"] < 1e-10
+    model.close()
+
+
+@pytest.mark.parametrize("uneven", [False, True])
+def test_matern_small_room_fp32(uneven):
+    _say(f"matern32 small room fp32 uneven={uneven}")
+    wl = scenes.small_room_workload(n_queries=4096, uneven=uneven)
+    model, _, g, o, _ = _run(wl, "fp32")
+    rep = assert_parity(g, o, wl.ell, "fp32", wl.sign, label=f"matern room uneven={uneven}")
+    print(rep, flush=True)
+    model.close()
+
+
+def test_matern_fit_query_and_limits():
+    _say("matern32 fit_query (fused tuning) vs fit + query; unsupported backward")
+    wl = scenes.small_room_workload(n_queries=2048)
+    cells = _cells(wl)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       kernel="matern32")
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    model.set_tuning(fused=1)
+    a = {k: v.clone() for k, v in model.fit_query(pts, q, sg).items()}
+    model.fit(pts)
+    b = model.query(q, sg)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], b[k]), f"fit_query and fit + query differ in {k}"
+    with pytest.raises(ksdf.KsdfError):
+        model.backward(q, sg, torch.ones_like(b["mean"]))
+    with pytest.raises(ksdf.KsdfError):
+        ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, kernel="matern32",
+                   adjoint=True)
+    model.close()

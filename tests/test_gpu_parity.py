@@ -30,7 +30,7 @@ def gpu_run(wl, queries=None, sign=None, precision="fp32", k_fuse=8, query_box=N
     model.fit(pts, sample_var=sv, cell_status=st)
     qt = torch.from_numpy(np.ascontiguousarray(q)).to("cuda", dt)
     sg = None if s is None else torch.from_numpy(np.ascontiguousarray(s)).to("cuda")
-    out = model.query(qt, sg)
+    out = model.query(qt, sg, grad_var=True)
     torch.cuda.synchronize()
     res = {k: v.cpu().numpy() for k, v in out.items()}
     res["cell_status"] = st.cpu().numpy()[:cells.n]
@@ -120,6 +120,7 @@ def test_failed_cells_are_excluded_and_reported():
     assert np.all(g["cell_status"] & ksdf.C_FAILED)
     assert np.all(g["status"] & ksdf.Q_NO_VALID_CELL)
     assert np.all(np.isinf(g["mean"])) and np.all(g["var_f"] == 1.0) and np.all(g["grad"] == 0)
+    assert np.all(np.isposinf(g["grad_var"]))
 
 
 def test_ill_conditioned_cells_fall_back_to_fp64():
