@@ -35,6 +35,7 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_room_grid.txt")
 KERNEL_SOURCES = {
     "query_fast": ["query_fast.hip", "query_split.h", "query_split64.hip", "query_split256.hip",
+                   "query_pairs.hip",
                    "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
     "fused": ["fused.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
 }

@@ -151,7 +151,14 @@ void ksdf_model_destroy(ksdf_model* model);
  * query_lanes, backward_lanes: each lane reads its own cells (1) instead of the
  *   wave sharing a cell through scalar loads (0); for sparse query sets, whose waves
  *   span many cells.  query_lanes applies to the two-kernel query.  Outputs are
- *   identical. */
+ *   identical.
+ * query_pairs: the first kernel of the two-kernel query evaluates each (query,
+ *   candidate cell) pair once, with the pairs grouped by cell (1), instead of each
+ *   wave walking the union of its lanes' candidates (0).  Every candidate is then
+ *   evaluated (no lower-bound pruning), which can change which near-tied cells are
+ *   re-evaluated in float-float: outputs agree within the parity tolerance, not
+ *   always bit for bit.  Applies to the two-kernel query when Q * (8 or 16) < 2^31;
+ *   the workspace grows by about 24 bytes per (query, candidate). */
 typedef struct ksdf_tuning {
   int query_sub;
   int query_block;
@@ -160,6 +167,7 @@ typedef struct ksdf_tuning {
   int query_split;
   int query_lanes;
   int backward_lanes;
+  int query_pairs;
 } ksdf_tuning;
 int ksdf_model_set_tuning(ksdf_model* model, const ksdf_tuning* tuning);
 int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);

@@ -358,7 +358,7 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
       (t->fused != 0 && t->fused != 1) ||
       (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64) ||
       (t->query_split != 0 && t->query_split != 1) || (t->query_lanes != 0 && t->query_lanes != 1) ||
-      (t->backward_lanes != 0 && t->backward_lanes != 1)) {
+      (t->backward_lanes != 0 && t->backward_lanes != 1) || (t->query_pairs != 0 && t->query_pairs != 1)) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
   }

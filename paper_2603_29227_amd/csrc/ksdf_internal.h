@@ -105,7 +105,7 @@ struct ksdf_model {
   int bucket_start[5] = {0, 0, 0, 0, 0};
 
   ksdf::CandidateIndex index;
-  ksdf_tuning tuning{0, 256, 1, 16, 1, 0, 0};
+  ksdf_tuning tuning{0, 256, 1, 16, 1, 0, 0, 0};
   // kernel timing: one event pair per phase, recorded when timing is on
   bool timing = false;
   hipEvent_t tev[KSDF_TIMER_COUNT][KSDF_TIMER_SLOTS][2] = {};

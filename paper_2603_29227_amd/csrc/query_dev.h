@@ -62,9 +62,14 @@ struct Pass1 {
 
 // two-kernel query launches (query_split64.hip, query_split256.hip)
 void launch_query_split_64(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
-                           int* count, int* cursor, int* tsum, bool lane, hipStream_t s);
+                           int* count, int* cursor, int* tsum, bool lane, void* pws, hipStream_t s);
 void launch_query_split_256(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
-                            int* count, int* cursor, int* tsum, bool lane, hipStream_t s);
+                            int* count, int* cursor, int* tsum, bool lane, void* pws, hipStream_t s);
+// pair form of pass 1 (query_pairs.hip): usable for Q queries, its workspace, launch
+bool query_pairs_usable(const ksdf_model* m, long Q);
+size_t query_pairs_workspace_bytes(const ksdf_model* m, long Q);
+void launch_pass1_pairs(const ksdf_model* m, const FastArgs& A, Pass1* rec, int* count, void* ws,
+                        hipStream_t s);
 
 namespace {
 
@@ -218,19 +223,14 @@ __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int
   return vv;
 }
 
-// Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
-// of a wave (lanes pass their own sq); every lane of the wave must call it together
-// (wave-uniform loops inside).
-template <int KM, bool LANE = false>
-__device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
-  const bool active = sq < A.Q;
-  const long qi = active ? A.perm[sq] : 0;
-  const float qx = A.pts[3 * qi], qy = A.pts[3 * qi + 1], qz = A.pts[3 * qi + 2];
-
-  // ---- candidates: K nearest centres of the box list (ties by id)
+// K nearest occupied cell centres of the candidate-index box list of (qx,qy,qz), ties
+// by id (Sec. IV-B.1): the first n entries of cid, nearest first.  outside: the point
+// lies outside the index lattice (then every cell is scanned).
+template <int KM>
+__device__ __forceinline__ void query_candidates(const FastArgs& A, bool active, float qx, float qy,
+                                                 float qz, int (&cid)[KM], int& n, bool& outside) {
   // sorted top-KM of (distance, id); ids arrive ascending, so a later equal distance
   // never moves ahead of an earlier one; the first k entries are the K nearest
-  int cid[KM];
   float cd[KM];
 #pragma unroll
   for (int r = 0; r < KM; ++r) {
@@ -239,8 +239,8 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   }
   int subkey;
   const long bkey = box_key(A, qx, qy, qz, &subkey);
-  const bool outside = bkey < 0;
-  int n = 0;
+  outside = bkey < 0;
+  n = 0;
   if (active) {
     int beg = 0, end = A.n_cells;
     if (!outside) {
@@ -278,6 +278,129 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     }
     n = min(A.k, end - beg);
   }
+}
+
+// u^2 of one cell at the cell-local point (lx,ly,lz) for the lanes with ev set, with
+// its rounding-error bound del, against the scaling reference d2ref (in: the sample
+// box's lower bound; out: the reference used).  Wave-uniform: every lane of the wave
+// calls it for the same cell (b, m), whose samples come through scalar loads.
+__device__ __forceinline__ void cell_u2_wave(const FastArgs& A, int b, int m, float lx, float ly,
+                                             float lz, bool ev, float& d2ref, float& u2,
+                                             float& del) {
+  const float c2 = A.c2;
+  u2 = INFINITY;
+  del = 0.f;
+  if (!__ballot(ev)) return;
+  float f = 0.f, R = 0.f, RZ = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    const float c2d = c2 * d2ref;
+    float emax = 0.f;
+    f = 0.f;
+    R = 0.f;
+    RZ = 0.f;
+    for (int i0 = 0; i0 < m; i0 += CH) {
+      float4 P[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
+#pragma unroll
+      for (int j = 0; j < CH; ++j) {
+        // entries past m belong to the next cell (the store is padded): their
+        // offsets from this cell's centre can be far nearer than d2ref, and exp2
+        // would overflow, so their term is masked, not weighted by 0
+        const bool in = i0 + j < m;
+        const float aw = P[j].w;
+        const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
+        const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const float e = in ? __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d)) : 0.f;
+        const float ae = fabsf(aw) * e;
+        f = fmaf(aw, e, f);
+        R += ae;
+        RZ = fmaf(ae, z2, RZ);
+        emax = fmaxf(emax, e);
+      }
+    }
+    // far from the cell, the nearest sample can lie so much farther than the box's
+    // nearest point that every term is tiny against the box reference and the
+    // smaller ones underflow (FP32 exponents end at -126): redo once against the
+    // nearest sample, which gives its own term 1
+    const bool low = ev && !(emax >= 0x1p-24f);
+    if (!__ballot(low)) break;
+    if (low) {
+      float d2 = INFINITY;
+      for (int i = 0; i < m; ++i) {
+        const float4 p = A.ps[b + i];
+        const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
+        d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      }
+      d2ref = d2;
+    }
+  }
+  if (ev && f > 0.f) {
+    u2 = d2ref - A.two_l2 * LN2 * __log2f(f);
+    // |d f| <= eps * sum_i |a_i| e_i (2 + (5 ln 2) c2 z_i^2) + summation error
+    del = A.two_l2 * EPS32 * (6.f * R + 3.5f * c2 * RZ) / f;
+  }
+}
+
+// Min-fusion of the candidates' u^2 (ties to the lower id); where the error bounds of
+// the best and of a rival overlap by more than the budget, the overlapping cells are
+// re-evaluated in float-float.  Returns the argmin cell (-1: none valid); best = its u^2.
+template <int KM>
+__device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float qx, float qy,
+                                           float qz, const int (&cid)[KM], int n, float (&cu2)[KM],
+                                           const float (&cdl)[KM], float& best) {
+  int bc = -1;
+  if (active) {
+    float bu = INFINITY, bd = 0.f;
+#pragma unroll
+    for (int r = 0; r < KM; ++r)
+      if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
+        bu = cu2[r];
+        bd = cdl[r];
+        bc = cid[r];
+      }
+    if (bc >= 0) {
+      const float budget = u2_budget(bu, A.two_l2);
+      bool redo = false;
+#pragma unroll
+      for (int r = 0; r < KM; ++r)
+        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
+          redo = true;
+      if (redo) {
+#pragma unroll
+        for (int r = 0; r < KM; ++r)
+          if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
+            cu2[r] = cell_u2_ff(A, cid[r], qx, qy, qz);
+          }
+        bu = INFINITY;
+        bc = -1;
+#pragma unroll
+        for (int r = 0; r < KM; ++r)
+          if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
+            bu = cu2[r];
+            bc = cid[r];
+          }
+      }
+      best = bu;
+    }
+  }
+  return bc;
+}
+
+// Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
+// of a wave (lanes pass their own sq); every lane of the wave must call it together
+// (wave-uniform loops inside).
+template <int KM, bool LANE = false>
+__device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
+  const bool active = sq < A.Q;
+  const long qi = active ? A.perm[sq] : 0;
+  const float qx = A.pts[3 * qi], qy = A.pts[3 * qi + 1], qz = A.pts[3 * qi + 2];
+
+  // ---- candidates: K nearest centres of the box list (ties by id)
+  int cid[KM];
+  int n = 0;
+  bool outside = false;
+  query_candidates<KM>(A, active, qx, qy, qz, cid, n, outside);
 
   // ---- pass 1: per-candidate u^2 with error bounds, wave-uniform over the union
   float cu2[KM], cdl[KM], cref[KM];
@@ -318,57 +441,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     const bool part = slot >= 0;
     const bool ev = part && !(lb > best + 2.f * best_del + 1e-6f);
     float u2 = INFINITY, del = 0.f;
-    if (__ballot(ev)) {
-      float f = 0.f, R = 0.f, RZ = 0.f;
-      for (int pass = 0; pass < 2; ++pass) {
-        const float c2d = c2 * d2ref;
-        float emax = 0.f;
-        f = 0.f;
-        R = 0.f;
-        RZ = 0.f;
-        for (int i0 = 0; i0 < m; i0 += CH) {
-          float4 P[CH];
-#pragma unroll
-          for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
-#pragma unroll
-          for (int j = 0; j < CH; ++j) {
-            // entries past m belong to the next cell (the store is padded): their
-            // offsets from this cell's centre can be far nearer than d2ref, and exp2
-            // would overflow, so their term is masked, not weighted by 0
-            const bool in = i0 + j < m;
-            const float aw = P[j].w;
-            const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
-            const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-            const float e = in ? __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d)) : 0.f;
-            const float ae = fabsf(aw) * e;
-            f = fmaf(aw, e, f);
-            R += ae;
-            RZ = fmaf(ae, z2, RZ);
-            emax = fmaxf(emax, e);
-          }
-        }
-        // far from the cell, the nearest sample can lie so much farther than the box's
-        // nearest point that every term is tiny against the box reference and the
-        // smaller ones underflow (FP32 exponents end at -126): redo once against the
-        // nearest sample, which gives its own term 1
-        const bool low = ev && !(emax >= 0x1p-24f);
-        if (!__ballot(low)) break;
-        if (low) {
-          float d2 = INFINITY;
-          for (int i = 0; i < m; ++i) {
-            const float4 p = A.ps[b + i];
-            const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
-            d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
-          }
-          d2ref = d2;
-        }
-      }
-      if (ev && f > 0.f) {
-        u2 = d2ref - A.two_l2 * LN2 * __log2f(f);
-        // |d f| <= eps * sum_i |a_i| e_i (2 + (5 ln 2) c2 z_i^2) + summation error
-        del = A.two_l2 * EPS32 * (6.f * R + 3.5f * c2 * RZ) / f;
-      }
-    }
+    cell_u2_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
     if (part) {
       if (!ev) u2 = INFINITY;   // pruned: provably not the minimum
 #pragma unroll
@@ -449,41 +522,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   }
 
   // ---- resolve the minimum; re-evaluate uncertain cells in float-float
-  int bc = -1;
-  if (active) {
-    float bu = INFINITY, bd = 0.f;
-#pragma unroll
-    for (int r = 0; r < KM; ++r)
-      if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
-        bu = cu2[r];
-        bd = cdl[r];
-        bc = cid[r];
-      }
-    if (bc >= 0) {
-      const float budget = u2_budget(bu, A.two_l2);
-      bool redo = false;
-#pragma unroll
-      for (int r = 0; r < KM; ++r)
-        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
-          redo = true;
-      if (redo) {
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
-            cu2[r] = cell_u2_ff(A, cid[r], qx, qy, qz);
-          }
-        bu = INFINITY;
-        bc = -1;
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
-            bu = cu2[r];
-            bc = cid[r];
-          }
-      }
-      best = bu;
-    }
-  }
+  const int bc = resolve_min<KM>(A, active, qx, qy, qz, cid, n, cu2, cdl, best);
   // the argmin cell's scaling reference from pass 1 (box bound, or its nearest sample
   // where the box bound would have underflowed the terms)
   float bref = 0.f;

@@ -57,8 +57,9 @@ size_t bucketing_bytes(const ksdf_model* m, long Q) {
 size_t query_fast_workspace_bytes(const ksdf_model* m, long Q) {
   const long nc = (long)m->n_cells + 1;
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
+  const bool pairs = m->tuning.query_split && m->tuning.query_pairs && query_pairs_usable(m, Q);
   return bucketing_bytes(m, Q) + 2 * align256(Q * sizeof(Pass1)) + 2 * align256(nc * sizeof(int)) +
-         align256(tiles * sizeof(int));
+         align256(tiles * sizeof(int)) + (pairs ? query_pairs_workspace_bytes(m, Q) : 0);
 }
 
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
@@ -82,13 +83,17 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
     int* cursor = reinterpret_cast<int*>(w);
     w += align256(nc * sizeof(int));
     int* tsum = reinterpret_cast<int*>(w);
+    w += align256(((nc + SCAN_TILE - 1) / SCAN_TILE) * sizeof(int));
+    void* pws = (m->tuning.query_pairs && query_pairs_usable(m, Q)) ? w : nullptr;
     if ((nc + SCAN_TILE - 1) / SCAN_TILE > (long)SCAN_TILE) {
       set_error("query: too many cells for the argmin regrouping");
       return KSDF_ERR_UNSUPPORTED;
     }
     const bool lane = m->tuning.query_lanes != 0;
-    if (m->tuning.query_block == 64) launch_query_split_64(m, A, rec, rec2, count, cursor, tsum, lane, s);
-    else launch_query_split_256(m, A, rec, rec2, count, cursor, tsum, lane, s);
+    if (m->tuning.query_block == 64)
+      launch_query_split_64(m, A, rec, rec2, count, cursor, tsum, lane, pws, s);
+    else
+      launch_query_split_256(m, A, rec, rec2, count, cursor, tsum, lane, pws, s);
   } else if (m->tuning.query_block == 64) {
     launch_query_nt<64>(m, A, s);
   } else {

@@ -46,12 +46,13 @@ __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* r
 
 template <int NT, bool LANE>
 void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2, int* count,
-                     int* cursor, int* tsum, hipStream_t s) {
+                     int* cursor, int* tsum, void* pws, hipStream_t s) {
   const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
   const long nc = (long)m->n_cells + 1;
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
-  if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  if (pws) launch_pass1_pairs(m, A, rec, count, pws, s);
+  else if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
   else hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
   hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum);
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);

@@ -4,9 +4,10 @@
 namespace ksdf {
 
 void launch_query_split_256(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
-                            int* count, int* cursor, int* tsum, bool lane, hipStream_t s) {
-  if (lane) launch_split_nt<256, true>(m, A, rec, rec2, count, cursor, tsum, s);
-  else launch_split_nt<256, false>(m, A, rec, rec2, count, cursor, tsum, s);
+                            int* count, int* cursor, int* tsum, bool lane, void* pws,
+                            hipStream_t s) {
+  if (lane) launch_split_nt<256, true>(m, A, rec, rec2, count, cursor, tsum, pws, s);
+  else launch_split_nt<256, false>(m, A, rec, rec2, count, cursor, tsum, pws, s);
 }
 
 }  // namespace ksdf

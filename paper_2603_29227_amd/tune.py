@@ -28,8 +28,8 @@ import torch
 from .ksdf import FP64
 
 KNOBS = dict(query_sub=(1, 2, 4), query_block=(64, 256), fused=(0, 1), fit_min_bucket=(16, 32, 64),
-             query_split=(0, 1), query_lanes=(0, 1), backward_lanes=(0, 1))
-QUERY_KNOBS = ("query_sub", "query_block", "query_split", "query_lanes")
+             query_split=(0, 1), query_lanes=(0, 1), backward_lanes=(0, 1), query_pairs=(0, 1))
+QUERY_KNOBS = ("query_sub", "query_block", "query_split", "query_lanes", "query_pairs")
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
@@ -100,6 +100,9 @@ def _valid(t: dict, fp64: bool) -> bool:
         return False   # the fused launch runs the query in one pass
     if t.get("query_lanes", 0) == 1 and t.get("query_split", 0) == 0:
         return False   # lanes apply to the two-kernel query
+    if t.get("query_pairs", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or
+                                         t.get("fused", 0) == 1):
+        return False   # pairs apply to the two-kernel FP32 query
     return True
 
 
@@ -126,7 +129,8 @@ def tune(model, points: torch.Tensor, queries: torch.Tensor, sign=None, reps: in
     """Time the launch shapes of this model's fit+query step; keep and cache the
     fastest.  Returns {"tuning", "ms", "table"}."""
     out = model._out(len(queries), queries.device)
-    keys = ["query_sub", "query_block", "fused", "fit_min_bucket", "query_split", "query_lanes"]
+    keys = ["query_sub", "query_block", "fused", "fit_min_bucket", "query_split", "query_lanes",
+            "query_pairs"]
     best, ms, table = _search(model, keys, lambda: model.fit_query(points, queries, sign, out=out),
                               reps, log)
     _store(cache_path, signature(model, len(queries)), best, ms)

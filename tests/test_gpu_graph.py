@@ -159,12 +159,52 @@ def test_tuning_preserves_outputs(tuning):
     model.close()
 
 
+@pytest.mark.parametrize("tuning", [
+    dict(query_sub=4, query_block=64, fused=0, query_split=1, query_pairs=1),
+    dict(query_sub=2, query_block=256, fused=0, query_split=1, query_pairs=1, query_lanes=1),
+])
+def test_query_pairs_matches_wave_walk_and_oracle(tuning):
+    """The pair form of pass 1 evaluates every candidate (no pruning); it must pass
+    parity and agree with the wave-shared walk except where a near-tied cell's
+    float-float re-evaluation is triggered differently."""
+    _say(f"query pairs {tuning}")
+    wl = scenes.small_room_workload(n_queries=12000, cfg_id=44, uneven=True)
+    model, cells = _model(wl)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    model.set_tuning(fused=0, query_split=1, query_pairs=0)
+    model.fit(P)
+    base = _clone(model.query(q, sg, grad_var=True))
+    model.set_tuning(**tuning)
+    b = model.query(q, sg, grad_var=True)
+    again = model.query(q, sg, grad_var=True)
+    torch.cuda.synchronize()
+    _equal(b, again, keys=("mean", "grad", "var", "var_f", "grad_var", "argmin", "status"))
+    diff = torch.zeros(len(q), dtype=torch.bool, device=dev)
+    for k in ("mean", "var", "var_f", "argmin", "status"):
+        diff |= base[k] != b[k]
+    diff |= (base["grad"] != b["grad"]).any(1)
+    print(f"pairs vs wave walk: {int(diff.sum())} of {len(q)} queries differ", flush=True)
+    assert int(diff.sum()) <= len(q) // 100
+    oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                      np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+                     sign=wl.sign, all_candidates=True)
+    assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
+                  label=f"pairs {tuning}")
+    model.close()
+
+
 def test_tuning_rejects_invalid_values():
     _say("tuning validation")
     wl = scenes.sphere_workload(n_queries=16)
     model, _ = _model(wl, precision="fp64")
     for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8),
-                dict(query_split=2), dict(query_lanes=2), dict(backward_lanes=-1)):
+                dict(query_split=2), dict(query_lanes=2), dict(backward_lanes=-1),
+                dict(query_pairs=3)):
         with pytest.raises(ksdf.KsdfError):
             model.set_tuning(**bad)
     model.close()

@@ -175,3 +175,9 @@ def test_far_queries_over_sloped_patches_fp32():
     rep = assert_parity(res, ora, wl.ell, "fp32", wl.sign, label="sloped far")
     assert np.all(np.isfinite(res["mean"]))
     print("sloped far:", rep["mean_err_max"], flush=True)
+    # the pair form of pass 1 takes the same nearest-sample fallback
+    model.set_tuning(query_split=1, query_pairs=1)
+    out = model.query(torch.from_numpy(q).cuda(), torch.from_numpy(wl.sign).cuda(), grad_var=True)
+    torch.cuda.synchronize()
+    res2 = {k: v.cpu().numpy() for k, v in out.items()}
+    assert_parity(res2, ora, wl.ell, "fp32", wl.sign, label="sloped far, pairs")
