@@ -156,7 +156,7 @@ void ksdf_model_destroy(ksdf_model* model);
  *   candidate cell) pair once, with the pairs grouped by cell (1), instead of each
  *   wave walking the union of its lanes' candidates (0).  Every candidate is then
  *   evaluated (no lower-bound pruning), which can change which near-tied cells are
- *   re-evaluated in float-float: outputs agree within the parity tolerance, not
+ *   re-evaluated in FP64: outputs agree within the parity tolerance, not
  *   always bit for bit.  Applies to the two-kernel query when Q * (8 or 16) < 2^31;
  *   the workspace grows by about 24 bytes per (query, candidate). */
 typedef struct ksdf_tuning {
@@ -232,6 +232,36 @@ size_t ksdf_query_workspace_bytes(const ksdf_model* model, long Q);
 int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
                void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * ksdf_refit_cells — streaming update of the fitted cells (Sec. IV-C, App. G "GP
+ * training queue").  dirty [n_cells] (device float, the count c2 of buffer updates
+ * since a cell's last training) and qcount [n_cells] (device float, the query count
+ * c0, see ksdf_count_queries) give each cell with c2 > 0 the priority
+ * s = c2 (1 + eta c0), computed in FP64 as c2 * (1 + (eta * c0)) with each operation
+ * rounded once; the min(budget, #dirty) cells of highest priority (ties to the lower
+ * id) are refitted from surface_pts (and sample_var, or the uniform noise_var) with
+ * the model's current hyperparameters, exactly as ksdf_fit_cells fits them; then
+ * c2 = 0 and c0 = c0 / 2 for those cells.  All other cells keep their fit.
+ * refit_cells (device int, at least min(budget, n_cells)) receives the refitted cell
+ * ids in priority order and n_refit (device int) their number.  cell_status (device
+ * uint8 [n_cells] or NULL) is updated for the refitted cells only.  Requires a prior
+ * ksdf_fit_cells / ksdf_fit_query; budget >= 1; eta >= 0; the counters >= 0.
+ * Asynchronous and free of host synchronisation (capturable in a graph); workspace:
+ * at least ksdf_refit_workspace_bytes(model, budget) bytes.
+ * ------------------------------------------------------------------------- */
+size_t ksdf_refit_workspace_bytes(const ksdf_model* model, int budget);
+int ksdf_refit_cells(ksdf_model* model, const void* surface_pts, int dtype, long n_points,
+                     const void* sample_var, float* dirty, float* qcount, double eta, int budget,
+                     int* refit_cells, int* n_refit, uint8_t* cell_status, void* workspace,
+                     size_t ws_bytes, void* stream);
+
+/* ksdf_count_queries — the query counters of App. G: qcount[argmin[q]] += 1 for every
+ * query with a valid argmin cell (the GP whose prediction was used), then
+ * qcount = min(qcount, cap) (App. G caps at 10000).  argmin: device int [Q] from
+ * ksdf_query; qcount: device float [n_cells].  Asynchronous. */
+int ksdf_count_queries(const ksdf_model* model, const int* argmin, long Q, float* qcount,
+                       float cap, void* stream);
 
 /* ---------------------------------------------------------------------------
  * ksdf_fit_query — ksdf_fit_cells followed by ksdf_query, with the same arguments

@@ -79,6 +79,19 @@ def softmin(q, x, alpha):
     return float(h[0]), g
 
 
+def refit_priority(dirty, qcount, eta, budget):
+    """The GP training queue of App. G: the cells with c2 > 0 ordered by decreasing
+    s = c2 (1 + eta c0), ties to the lower id, the first `budget` of them.  The score
+    is formed in double as c2 * (1 + (eta * c0)), one rounding per operation (the
+    counters are float32)."""
+    c2 = np.asarray(dirty, np.float32).astype(np.float64)
+    c0 = np.asarray(qcount, np.float32).astype(np.float64)
+    ids = [i for i in range(len(c2)) if c2[i] > 0]
+    score = {i: c2[i] * (1.0 + eta * c0[i]) for i in ids}
+    ids.sort(key=lambda i: (-score[i], i))
+    return np.asarray(ids[:budget], np.int32)
+
+
 def threads() -> int:
     """Worker threads the oracle's parallel loops use."""
     return int(lib().oracle_threads())

@@ -312,6 +312,45 @@ extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype,
   return r;
 }
 
+extern "C" size_t ksdf_refit_workspace_bytes(const ksdf_model* m, int budget) {
+  return (m && budget > 0) ? refit_workspace_bytes(m, budget) : 0;
+}
+
+extern "C" int ksdf_refit_cells(ksdf_model* m, const void* surface_pts, int dtype, long n_points,
+                                const void* sample_var, float* dirty, float* qcount, double eta,
+                                int budget, int* refit_cells, int* n_refit, uint8_t* cell_status,
+                                void* workspace, size_t ws_bytes, void* stream) {
+  if (!m || !dirty || !qcount || !refit_cells || !n_refit || budget < 1 || !std::isfinite(eta) ||
+      eta < 0 || (m->n_cells > 0 && !surface_pts) ||
+      (dtype != KSDF_DTYPE_F32 && dtype != KSDF_DTYPE_F64) || n_points != m->n_points) {
+    set_error("ksdf_refit_cells: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!m->fitted) {
+    set_error("ksdf_refit_cells: the model has not been fitted");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (ws_bytes < refit_workspace_bytes(m, budget) || !workspace) {
+    set_error("ksdf_refit_cells: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  return launch_refit(m, surface_pts, dtype, sample_var, dirty, qcount, eta, budget, refit_cells,
+                      n_refit, cell_status, workspace, (hipStream_t)stream);
+}
+
+extern "C" int ksdf_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount,
+                                  float cap, void* stream) {
+  if (!m || Q < 0 || (Q > 0 && !argmin) || !qcount || !(cap >= 0)) {
+    set_error("ksdf_count_queries: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  return launch_count_queries(m, argmin, Q, qcount, cap, (hipStream_t)stream);
+}
+
 extern "C" size_t ksdf_fit_query_workspace_bytes(const ksdf_model* m, long Q) {
   if (!m) return 0;
   return m->precision == KSDF_FP32 ? fused_workspace_bytes(m, Q) : query_workspace_bytes(m, Q);

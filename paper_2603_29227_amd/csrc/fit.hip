@@ -11,6 +11,8 @@
 // m = 128) and estimate cond_2(A) by power and inverse iteration; a cell above the
 // threshold or with a non-positive pivot is queued for the FP64 kernel, which
 // factors in global memory (the plain FP64 path uses that kernel for every cell).
+#include <algorithm>
+
 #include "fit_dev.h"
 
 namespace ksdf {
@@ -18,9 +20,12 @@ namespace {
 
 constexpr int FIT_THREADS = 256;
 
+// list: the cells to fit; count (device, or null for the grid size): how many of them
 template <int MB>
-__global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int* list) {
+__global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int* list,
+                                                            const int* count) {
   __shared__ float smem[fit32_smem_floats<MB>()];
+  if (count && (int)blockIdx.x >= *count) return;
   const int c = list[blockIdx.x];
   const bool need64 = fit32_cell<MB>(A, c, smem);
   if (threadIdx.x == 0 && need64) {
@@ -37,7 +42,165 @@ __global__ void __launch_bounds__(FIT_THREADS) fit64_kernel(FitArgs A) {
   for (int t = blockIdx.x; t < count; t += gridDim.x) fit64_cell(A, A.list ? A.list[t] : t, smem);
 }
 
+// ---- streaming refit (Sec. IV-C, App. G) ----
+
+// Training-queue score of App. G, s = c2 (1 + eta c0), in FP64 with every rounding
+// explicit (no contraction), so that a host computation in the same order agrees.
+__device__ __forceinline__ double refit_score(const float* dirty, const float* qcount, double eta,
+                                              int c) {
+  return __dmul_rn((double)dirty[c], __dadd_rn(1.0, __dmul_rn(eta, (double)qcount[c])));
+}
+
+// Rank of every dirty cell (c2 > 0) by descending score, ties to the lower id, by
+// comparison with every other cell through LDS tiles; the first `budget` ranks name
+// the cells to refit.  n_dirty counts the dirty cells.
+__global__ void __launch_bounds__(256) refit_rank_kernel(const float* dirty, const float* qcount,
+                                                         double eta, int n, int budget, int* sel,
+                                                         int* n_dirty) {
+  __shared__ double ts[256];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const bool mine = i < n && dirty[i] > 0.f;
+  const double si = mine ? refit_score(dirty, qcount, eta, i) : -1.0;
+  int rank = 0;
+  for (int base = 0; base < n; base += 256) {
+    __syncthreads();
+    const int j = base + threadIdx.x;
+    ts[threadIdx.x] = (j < n && dirty[j] > 0.f) ? refit_score(dirty, qcount, eta, j) : -1.0;
+    __syncthreads();
+    const int lim = min(256, n - base);
+    for (int k = 0; k < lim; ++k) {
+      const double sj = ts[k];
+      rank += (sj > si || (sj == si && base + k < i)) ? 1 : 0;
+    }
+  }
+  if (mine) {
+    if (rank < budget) sel[rank] = i;
+    atomicAdd(n_dirty, 1);
+  }
+}
+
+// n_sel = min(budget, n_dirty); clears the per-bucket counts
+__global__ void refit_count_kernel(const int* n_dirty, int budget, int* n_sel, int* bcount) {
+  if (threadIdx.x == 0) *n_sel = min(budget, *n_dirty);
+  if (threadIdx.x < 4) bcount[threadIdx.x] = 0;
+}
+
+// the selected cells into per-m-bucket lists (the bucket sizing of the full fit)
+__global__ void __launch_bounds__(256) refit_bucket_kernel(const int* sel, const int* n_sel,
+                                                           const int* offsets, int minb, int budget,
+                                                           int* blist, int* bcount) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= *n_sel) return;
+  const int c = sel[i];
+  const int mc = offsets[c + 1] - offsets[c];
+  int bk = mc <= 16 ? 0 : mc <= 32 ? 1 : mc <= 64 ? 2 : 3;
+  if (minb >= 32 && bk < 1) bk = 1;
+  if (minb >= 64 && bk < 2) bk = 2;
+  const int pos = atomicAdd(&bcount[bk], 1);
+  blist[(long)bk * budget + pos] = c;
+}
+
+// after the refit: c2 = 0 and c0 halved for the refitted cells (App. G)
+__global__ void __launch_bounds__(256) refit_reset_kernel(const int* sel, const int* n_sel,
+                                                          float* dirty, float* qcount) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= *n_sel) return;
+  const int c = sel[i];
+  dirty[c] = 0.f;
+  qcount[c] = 0.5f * qcount[c];
+}
+
+__global__ void __launch_bounds__(256) count_queries_kernel(const int* argmin, long Q, float* qcount) {
+  const long q = (long)blockIdx.x * 256 + threadIdx.x;
+  if (q >= Q) return;
+  const int c = argmin[q];
+  if (c >= 0) atomicAdd(qcount + c, 1.f);
+}
+
+__global__ void __launch_bounds__(256) cap_kernel(float* qcount, int n, float cap) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < n) qcount[c] = fminf(qcount[c], cap);
+}
+
 }  // namespace
+
+size_t refit_workspace_bytes(const ksdf_model* m, int budget) {
+  const long b = std::min(budget, m->n_cells);
+  return 4 * b * sizeof(int) + 8 * sizeof(int);
+}
+
+int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, float* dirty,
+                 float* qcount, double eta, int budget, int* sel, int* n_sel, uint8_t* user_status,
+                 void* ws, hipStream_t s) {
+  if (m->n_cells == 0) {
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, n_sel, 0);
+    KSDF_HIP_TRY(hipGetLastError());
+    return KSDF_OK;
+  }
+  budget = std::min(budget, m->n_cells);
+  int* blist = static_cast<int*>(ws);
+  int* bcount = blist + 4L * budget;
+  int* n_dirty = bcount + 4;
+  const unsigned gc = (unsigned)((m->n_cells + 255) / 256);
+  const unsigned gb = (unsigned)((budget + 255) / 256);
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, n_dirty, 0);
+  hipLaunchKernelGGL(refit_rank_kernel, dim3(gc), dim3(256), 0, s, dirty, qcount, eta, m->n_cells,
+                     budget, sel, n_dirty);
+  hipLaunchKernelGGL(refit_count_kernel, dim3(1), dim3(64), 0, s, n_dirty, budget, n_sel, bcount);
+  FitArgs A = make_fit_args(m, pts, dtype, svar, user_status);
+  timer_mark(m, KSDF_TIMER_FIT, 0, s);
+  if (m->precision == KSDF_FP64) {
+    A.list = sel;
+    A.list_count = n_sel;
+    A.emit32 = 0;
+    hipLaunchKernelGGL(fit64_kernel, dim3((unsigned)budget), dim3(FIT_THREADS), 0, s, A);
+  } else {
+    const int minb = m->tuning.fit_min_bucket;
+    hipLaunchKernelGGL(refit_bucket_kernel, dim3(gb), dim3(256), 0, s, sel, n_sel, m->offsets, minb,
+                       budget, blist, bcount);
+    hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, m->fb_count, 0);
+    // grid per bucket: at most the budget and at most the cells of that bucket
+    const int* bs = m->bucket_start;
+    const int lo32 = minb >= 32 ? bs[0] : bs[1];
+    const int lo64 = minb >= 64 ? bs[0] : bs[2];
+    const int n16 = minb < 32 ? bs[1] - bs[0] : 0;
+    const int n32 = minb < 64 ? bs[2] - lo32 : 0;
+    const int n64 = bs[3] - lo64, n128 = bs[4] - bs[3];
+    if (n16 > 0)
+      hipLaunchKernelGGL(fit32_kernel<16>, dim3(std::min(n16, budget)), dim3(FIT_THREADS), 0, s, A,
+                         blist, bcount);
+    if (n32 > 0)
+      hipLaunchKernelGGL(fit32_kernel<32>, dim3(std::min(n32, budget)), dim3(FIT_THREADS), 0, s, A,
+                         blist + budget, bcount + 1);
+    if (n64 > 0)
+      hipLaunchKernelGGL(fit32_kernel<64>, dim3(std::min(n64, budget)), dim3(FIT_THREADS), 0, s, A,
+                         blist + 2L * budget, bcount + 2);
+    if (n128 > 0)
+      hipLaunchKernelGGL(fit32_kernel<128>, dim3(std::min(n128, budget)), dim3(FIT_THREADS), 0, s, A,
+                         blist + 3L * budget, bcount + 3);
+    A.list = m->fb_list;
+    A.list_count = m->fb_count;
+    A.emit32 = 1;
+    hipLaunchKernelGGL(fit64_kernel, dim3((unsigned)std::min(budget, 2048)), dim3(FIT_THREADS), 0, s,
+                       A);
+  }
+  timer_mark(m, KSDF_TIMER_FIT, 1, s);
+  hipLaunchKernelGGL(refit_reset_kernel, dim3(gb), dim3(256), 0, s, sel, n_sel, dirty, qcount);
+  KSDF_HIP_TRY(hipGetLastError());
+  return KSDF_OK;
+}
+
+int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount, float cap,
+                         hipStream_t s) {
+  if (Q > 0)
+    hipLaunchKernelGGL(count_queries_kernel, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s,
+                       argmin, Q, qcount);
+  if (m->n_cells > 0)
+    hipLaunchKernelGGL(cap_kernel, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, s,
+                       qcount, m->n_cells, cap);
+  KSDF_HIP_TRY(hipGetLastError());
+  return KSDF_OK;
+}
 
 int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint8_t* user_status,
                hipStream_t s) {
@@ -59,13 +222,13 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
     const int lo32 = minb >= 32 ? bs[0] : bs[1];
     const int lo64 = minb >= 64 ? bs[0] : bs[2];
     if (minb < 32 && bs[1] > bs[0])
-      hipLaunchKernelGGL(fit32_kernel<16>, dim3(bs[1] - bs[0]), dim3(FIT_THREADS), 0, s, A, lists + bs[0]);
+      hipLaunchKernelGGL(fit32_kernel<16>, dim3(bs[1] - bs[0]), dim3(FIT_THREADS), 0, s, A, lists + bs[0], nullptr);
     if (minb < 64 && bs[2] > lo32)
-      hipLaunchKernelGGL(fit32_kernel<32>, dim3(bs[2] - lo32), dim3(FIT_THREADS), 0, s, A, lists + lo32);
+      hipLaunchKernelGGL(fit32_kernel<32>, dim3(bs[2] - lo32), dim3(FIT_THREADS), 0, s, A, lists + lo32, nullptr);
     if (bs[3] > lo64)
-      hipLaunchKernelGGL(fit32_kernel<64>, dim3(bs[3] - lo64), dim3(FIT_THREADS), 0, s, A, lists + lo64);
+      hipLaunchKernelGGL(fit32_kernel<64>, dim3(bs[3] - lo64), dim3(FIT_THREADS), 0, s, A, lists + lo64, nullptr);
     if (bs[4] > bs[3])
-      hipLaunchKernelGGL(fit32_kernel<128>, dim3(bs[4] - bs[3]), dim3(FIT_THREADS), 0, s, A, lists + bs[3]);
+      hipLaunchKernelGGL(fit32_kernel<128>, dim3(bs[4] - bs[3]), dim3(FIT_THREADS), 0, s, A, lists + bs[3], nullptr);
     A.list = m->fb_list;
     A.list_count = m->fb_count;
     A.emit32 = 1;

@@ -128,6 +128,13 @@ namespace ksdf {
 int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint8_t* user_status,
                hipStream_t s);
 int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
+// streaming refit of the highest-priority dirty cells and the query counter update
+size_t refit_workspace_bytes(const ksdf_model* m, int budget);
+int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, float* dirty,
+                 float* qcount, double eta, int budget, int* sel, int* n_sel, uint8_t* user_status,
+                 void* ws, hipStream_t s);
+int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount, float cap,
+                         hipStream_t s);
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
                  void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
                  size_t ws_bytes, hipStream_t s);

@@ -19,7 +19,7 @@
 //    ill-conditioned cells have strongly cancelling weights.  Each lane keeps an
 //    error bound per cell from the cancellation ratio sum|a_i e_i| / |f'|; where
 //    the bound could move the answer by more than a fraction of the tolerance, the
-//    lane re-evaluates those cells in float-float (FP32 instructions only).
+//    lane re-evaluates those cells in FP64.
 // 5. Argmin cell.  The wave loops over the distinct argmin cells of its lanes (one
 //    or two in practice): gradient w/|w|, GP variance 1 - |L^{-1} k*|^2 by forward
 //    substitution with the factor rows in scalar registers, and the softmin

@@ -12,7 +12,7 @@
 //      per-cell ranges;
 //   3. evaluation of u^2, its error bound and its scaling reference per pair, in the
 //      same arithmetic as the wave-shared walk;
-//   4. per query, the min-fusion with float-float re-evaluation of uncertain cells,
+//   4. per query, the min-fusion with FP64 re-evaluation of uncertain cells,
 //      writing the same record as pass 1 for the regrouping and pass 2.
 // Every candidate is evaluated (no lower-bound pruning), as in the method's
 // definition of the min-fusion.

@@ -34,7 +34,8 @@ EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_c
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
            "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
-           "ksdf_model_timer_read", "ksdf_status_string",
+           "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
+           "ksdf_count_queries", "ksdf_status_string",
            "ksdf_last_error"]
 
 
@@ -106,6 +107,11 @@ def lib():
         L.ksdf_fit_query_workspace_bytes.restype = sz
         L.ksdf_fit_query.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp, l, _vp, _vp, _vp, _vp, _vp,
                                      _vp, _vp, _vp, _vp, sz, _vp]
+        L.ksdf_refit_workspace_bytes.argtypes = [_vp, i]
+        L.ksdf_refit_workspace_bytes.restype = sz
+        L.ksdf_refit_cells.argtypes = [_vp, _vp, i, l, _vp, _vp, _vp, ctypes.c_double, i, _vp, _vp,
+                                       _vp, _vp, sz, _vp]
+        L.ksdf_count_queries.argtypes = [_vp, _vp, l, _vp, ctypes.c_float, _vp]
         L.ksdf_model_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_get_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_set_timing.argtypes = [_vp, i]
@@ -364,6 +370,35 @@ class Model:
                                              *[_ptr(t) for t in c], _ptr(d_points), _ptr(d_hyper),
                                              _ptr(ws), nb, _stream(stream)), "ksdf_query_backward")
         return d_points, d_hyper
+
+    def refit(self, points: torch.Tensor, dirty: torch.Tensor, qcount: torch.Tensor, eta: float,
+              budget: int, sample_var=None, cell_status=None, stream=None):
+        """Streaming refit (App. G): refit the min(budget, #dirty) cells of highest
+        priority dirty * (1 + eta * qcount); resets their dirty counts and halves their
+        query counts in place.  Returns (refit_cells int32 [min(budget, n_cells)],
+        n_refit int32 [1]) on the device."""
+        for t in (dirty, qcount):
+            if t.dtype != torch.float32 or not t.is_cuda or t.numel() != self.n_cells:
+                raise ValueError("dirty and qcount must be float32 CUDA tensors of n_cells")
+        dt = DTYPE_F64 if points.dtype == torch.float64 else DTYPE_F32
+        cells = torch.empty(max(min(int(budget), self.n_cells), 1), dtype=torch.int32,
+                            device=points.device)
+        n = torch.empty(1, dtype=torch.int32, device=points.device)
+        nb = self._lib.ksdf_refit_workspace_bytes(self._h, int(budget))
+        ws = self._workspace(nb)
+        _check(self._lib.ksdf_refit_cells(self._h, _ptr(points), dt, len(points), _ptr(sample_var),
+                                          _ptr(dirty), _ptr(qcount), float(eta), int(budget),
+                                          _ptr(cells), _ptr(n), _ptr(cell_status), _ptr(ws), nb,
+                                          _stream(stream)), "ksdf_refit_cells")
+        return cells, n
+
+    def count_queries(self, argmin: torch.Tensor, qcount: torch.Tensor, cap: float = 10000.0,
+                      stream=None):
+        """App. G query counters: qcount[argmin] += 1 (valid argmins), capped at cap."""
+        if argmin.dtype != torch.int32 or qcount.dtype != torch.float32:
+            raise ValueError("argmin must be int32 and qcount float32")
+        _check(self._lib.ksdf_count_queries(self._h, _ptr(argmin), argmin.numel(), _ptr(qcount),
+                                            float(cap), _stream(stream)), "ksdf_count_queries")
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -1,0 +1,118 @@
+"""GPU streaming refit (Sec. IV-C, App. G): the cells refitted are exactly the oracle's
+training-queue choice, the counters are reset as the paper states, and a model whose
+dirty cells have all been refitted (in one call or in several budgeted calls) answers
+every query bit for bit like a model fitted from scratch on the new samples."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2603_29227_amd import ksdf, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _setup(precision="fp32", seed=0):
+    wl = scenes.small_room_workload(n_queries=6000, cfg_id=45, uneven=True)
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    rng = np.random.default_rng(seed)
+    p0 = np.ascontiguousarray(wl.points)
+    p1 = p0.copy()
+    moved = rng.choice(len(p0), size=len(p0) // 30, replace=False)
+    p1[moved] += rng.normal(0, 0.004, (len(moved), 3)).astype(p0.dtype)
+    # cells holding a moved sample must be retrained
+    hit = np.zeros(len(p0), bool)
+    hit[moved] = True
+    owner = np.repeat(np.arange(cells.n), np.diff(cells.offsets))
+    dirty_cells = np.unique(owner[hit[cells.samples]])
+    return wl, cells, dt, p0, p1, dirty_cells
+
+
+def _model(wl, cells, precision):
+    return ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                      precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_refit_all_dirty_equals_fresh_fit(precision):
+    _say(f"refit of every dirty cell vs fresh fit, {precision}")
+    wl, cells, dt, p0, p1, dirty_cells = _setup(precision)
+    assert 0 < len(dirty_cells) < cells.n
+    q = torch.from_numpy(wl.queries).to("cuda", dt)
+    sg = torch.from_numpy(wl.sign).cuda()
+    fresh = _model(wl, cells, precision)
+    fresh.fit(torch.from_numpy(p1).to("cuda", dt))
+    want = {k: v.clone() for k, v in fresh.query(q, sg).items()}
+    model = _model(wl, cells, precision)
+    model.fit(torch.from_numpy(p0).to("cuda", dt))
+    stale = {k: v.clone() for k, v in model.query(q, sg).items()}
+    P1 = torch.from_numpy(p1).to("cuda", dt)
+    dirty = torch.zeros(cells.n, dtype=torch.float32, device="cuda")
+    dirty[torch.from_numpy(dirty_cells).long().cuda()] = 1.0
+    qcount = torch.zeros(cells.n, dtype=torch.float32, device="cuda")
+    model.count_queries(stale["argmin"], qcount)
+    # two budgeted calls, then one for the rest
+    half = max(len(dirty_cells) // 3, 1)
+    done = []
+    for budget in (half, half, cells.n):
+        sel, n = model.refit(P1, dirty, qcount, 0.5, budget)
+        torch.cuda.synchronize()
+        done += sel[:int(n.item())].cpu().tolist()
+    assert sorted(done) == sorted(dirty_cells.tolist())
+    assert float(dirty.abs().sum()) == 0.0
+    got = model.query(q, sg)
+    torch.cuda.synchronize()
+    for k in want:
+        assert torch.equal(got[k], want[k]), f"{k} differs from a fresh fit"
+    assert not torch.equal(stale["mean"], want["mean"])
+    model.close()
+    fresh.close()
+
+
+def test_refit_selection_and_counters_match_oracle():
+    _say("refit selection order and counter updates")
+    wl, cells, dt, p0, p1, _ = _setup()
+    model = _model(wl, cells, "fp32")
+    P0 = torch.from_numpy(p0).cuda()
+    model.fit(P0)
+    rng = np.random.default_rng(7)
+    for budget, eta in ((1, 0.5), (17, 0.25), (cells.n, 1.0), (5, 0.0)):
+        c2 = rng.integers(0, 4, cells.n).astype(np.float32)
+        c2[rng.random(cells.n) < 0.5] = 0
+        c0 = rng.integers(0, 6, cells.n).astype(np.float32)   # many ties
+        dirty = torch.from_numpy(c2).cuda()
+        qcount = torch.from_numpy(c0).cuda()
+        sel, n = model.refit(P0, dirty, qcount, eta, budget)
+        torch.cuda.synchronize()
+        want = oracle.refit_priority(c2, c0, eta, budget)
+        assert int(n.item()) == len(want)
+        assert sel[:len(want)].cpu().numpy().tolist() == want.tolist()
+        d2, q2 = c2.copy(), c0.copy()
+        d2[want] = 0
+        q2[want] *= 0.5
+        assert np.array_equal(dirty.cpu().numpy(), d2)
+        assert np.array_equal(qcount.cpu().numpy(), q2)
+    model.close()
+
+
+def test_count_queries_matches_bincount():
+    _say("query counters")
+    wl, cells, dt, p0, _, _ = _setup()
+    model = _model(wl, cells, "fp32")
+    model.fit(torch.from_numpy(p0).cuda())
+    out = model.query(torch.from_numpy(wl.queries).cuda())
+    qcount = torch.full((cells.n,), 2.0, dtype=torch.float32, device="cuda")
+    model.count_queries(out["argmin"], qcount, cap=30.0)
+    torch.cuda.synchronize()
+    am = out["argmin"].cpu().numpy()
+    want = np.minimum(2.0 + np.bincount(am[am >= 0], minlength=cells.n), 30.0)
+    assert np.array_equal(qcount.cpu().numpy(), want.astype(np.float32))
+    with pytest.raises(ksdf.KsdfError):
+        model.refit(torch.from_numpy(p0).cuda(), qcount, qcount, -1.0, 4)
+    model.close()
