@@ -117,6 +117,7 @@ def main():
     ap.add_argument("--grid", type=int, default=256)
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 GPU leg")
     ap.add_argument("--no-matern", action="store_true", help="skip the Matern 3/2 leg")
+    ap.add_argument("--no-bhm", action="store_true", help="skip the BHM sign leg")
     ap.add_argument("--no-grad-var", action="store_true",
                     help="skip timing the gradient-variance output")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -328,6 +329,29 @@ def main():
         del mout
         mat.close()
 
+    # SDF sign from local BHM weights (synthetic weights from the scene's free-space
+    # test; paper's indoor box, hinge count and kernel scale), for the grid and the
+    # trajectory points
+    bhm = None
+    if not args.no_bhm:
+        b = scenes.bhm_weights(wl)
+        bargs = (b["origin"], b["box"], b["dims"], b["hinges"], b["gamma"],
+                 torch.from_numpy(b["box_bhm"]).to(dev), torch.from_numpy(b["weights"]).to(dev))
+        bhm = {"maps": int((b["box_bhm"] >= 0).sum()), "hinges": b["hinges"]}
+        for name, pts_ in (("grid", q), ("trajectory", tq)):
+            ksdf.bhm_sign(pts_, *bargs)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                sgn = ksdf.bhm_sign(pts_, *bargs)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            bhm[f"{name}_sign_ms"] = round(ms, 4)
+            bhm[f"{name}_sign_qps"] = round(len(pts_) / (ms * 1e-3), 1)
+        del bargs
+        log(f"bhm sign: {bhm}")
+
     # roofline of the dominant kernel (algorithmic flops over its measured duration)
     k_fuse = int(model.hyper.k_fuse)
     fq, tr = query_flops(float(m.mean()), k_fuse)
@@ -372,6 +396,7 @@ def main():
         "roofline": roofline, "roofline_backward": roof_bwd,
         "grad_var_cost": gv_ms,
         "matern32": matern,
+        "bhm_sign": bhm,
     }
 
     if not args.no_plain:

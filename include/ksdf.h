@@ -264,6 +264,37 @@ int ksdf_count_queries(const ksdf_model* model, const int* argmin, long Q, float
                        float cap, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * SDF sign from local Bayesian-Hilbert-map weights (Sec. IV-A, eq. sign_prediction;
+ * App. B features).  The caller's BHM front-end supplies the weights; these calls
+ * only evaluate them.  Local maps sit on a lattice of boxes (edge `box`, dims boxes per
+ * axis from `origin`); box b's map is box_bhm[b] (device int, -1 = none).  A map holds
+ * hinges^3 hinge points at the lattice points of its box (spacing box / (hinges - 1),
+ * 2 <= hinges <= 16) and weights[id * (hinges^3 + 1) + ...] (device double, hinge
+ * (i, j, k) at (i * hinges + j) * hinges + k, the bias last).  The log-odds of a query
+ * in box b is l = mu^T phi with phi = [exp(-gamma |x - h|^2) ..., 1] over its map.
+ * ksdf_bhm_sign: sign[q] (device int8) = +1 where l < tau, -1 otherwise, +1 where the
+ * box has no map (no occupied voxel); logodds[q] (device double, or NULL) = l, or
+ * -inf without a map.  points: device [Q,3], dtype float or double; l in double.
+ * ksdf_bhm_update_tau: tau (device double, in/out) <- (1 - alpha) tau + (alpha / K)
+ * sum_k l(hit_k) (eq. online_surf_logodds), 0 < alpha <= 1, in a fixed summation
+ * order; workspace >= ksdf_bhm_tau_workspace_bytes(K).  Both asynchronous.
+ * ------------------------------------------------------------------------- */
+typedef struct ksdf_bhm_layout {
+  double origin[3];
+  double box;
+  int dims[3];
+  int hinges;
+  double gamma;
+} ksdf_bhm_layout;
+int ksdf_bhm_sign(const ksdf_bhm_layout* layout, const int* box_bhm, const double* weights,
+                  const void* points, int dtype, long Q, double tau, int8_t* sign, double* logodds,
+                  void* stream);
+size_t ksdf_bhm_tau_workspace_bytes(long K);
+int ksdf_bhm_update_tau(const ksdf_bhm_layout* layout, const int* box_bhm, const double* weights,
+                        const void* hits, int dtype, long K, double alpha, double* tau,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------------------
  * ksdf_fit_query — ksdf_fit_cells followed by ksdf_query, with the same arguments
  * and outputs, as ONE persistent fused launch for FP32 models: resident workgroups
  * drain a task queue holding every cell fit (largest m first, FP64 refit in place

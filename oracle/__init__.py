@@ -60,6 +60,8 @@ def lib():
                                    [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
                                     _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int])
         L.oracle_softmin.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp]
+        L.oracle_bhm.argtypes = [_dp, ctypes.c_double, _ip, ctypes.c_int, ctypes.c_double, _ip, _dp,
+                                 _dp, ctypes.c_long, ctypes.c_double, _dp, _ip, _ip]
         L.oracle_vjp.restype = ctypes.c_double
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
@@ -77,6 +79,29 @@ def softmin(q, x, alpha):
     g = np.zeros(3)
     lib().oracle_softmin(_p(q, _dp), _p(x, _dp), len(x), float(alpha), _p(h, _dp), _p(g, _dp))
     return float(h[0]), g
+
+
+def bhm(queries, origin, box, dims, hinges, gamma, box_bhm, weights, tau=0.0):
+    """Log-odds l, has-map flag and SDF sign (+1 free) of local BHMs (eq.
+    sign_prediction, App. B features); see ``oracle_bhm``."""
+    q = _f64(queries).reshape(-1, 3)
+    org = _f64(origin)
+    dm = np.ascontiguousarray(dims, np.int32)
+    bb = np.ascontiguousarray(box_bhm, np.int32)
+    w = _f64(weights)
+    lo = np.zeros(len(q))
+    have = np.zeros(len(q), np.int32)
+    sign = np.zeros(len(q), np.int32)
+    lib().oracle_bhm(_p(org, _dp), float(box), _p(dm, _ip), int(hinges), float(gamma), _p(bb, _ip),
+                     _p(w, _dp), _p(q, _dp), len(q), float(tau), _p(lo, _dp), _p(have, _ip),
+                     _p(sign, _ip))
+    return lo, have, sign
+
+
+def bhm_update_tau(tau, hit_logodds, alpha):
+    """eq. online_surf_logodds: tau <- (1 - alpha) tau + (alpha / K) sum_k l(x_k)."""
+    h = np.asarray(hit_logodds, np.float64)
+    return (1.0 - alpha) * tau + alpha / len(h) * h.sum()
 
 
 def refit_priority(dirty, qcount, eta, budget):

@@ -578,6 +578,48 @@ void oracle_softmin(const double* q, const double* x, int m, double alpha, doubl
   }
 }
 
+// Log-odds of local Bayesian Hilbert maps and the SDF sign (Sec. IV-A, eq.
+// sign_prediction; App. B features): l(x) = mu^T phi(x), phi = [k(x, h_1) .. k(x, h_M), 1]
+// with k(x, h) = exp(-gamma |x - h|^2) over the hinge points of the map of the box
+// holding x (box lattice from `origin`, edge `box`, `dims` boxes per axis; hinges^3
+// points at the box's lattice points, spacing box / (hinges - 1); weights per map
+// hinges^3 + 1 with the bias last).  sign = +1 where l < tau, else -1; +1 and
+// have = 0 where the box has no map.
+void oracle_bhm(const double* origin, double box, const int* dims, int hinges, double gamma,
+                const int* box_bhm, const double* weights, const double* q, long nq, double tau,
+                double* logodds, int* have, int* sign) {
+  const double sp = box / (double)(hinges - 1);
+  const long m = (long)hinges * hinges * hinges;
+  for (long p = 0; p < nq; ++p) {
+    const double* x = q + 3 * p;
+    long key[3];
+    bool in = true;
+    for (int d = 0; d < 3; ++d) {
+      key[d] = (long)std::floor((x[d] - origin[d]) / box);
+      in = in && key[d] >= 0 && key[d] < dims[d];
+    }
+    const int id = in ? box_bhm[(key[0] * dims[1] + key[1]) * dims[2] + key[2]] : -1;
+    have[p] = id >= 0;
+    double l = 0;
+    if (id >= 0) {
+      const double* w = weights + (long)id * (m + 1);
+      for (int i = 0; i < hinges; ++i)
+        for (int j = 0; j < hinges; ++j)
+          for (int k = 0; k < hinges; ++k) {
+            const double h[3] = {origin[0] + (double)key[0] * box + i * sp,
+                                 origin[1] + (double)key[1] * box + j * sp,
+                                 origin[2] + (double)key[2] * box + k * sp};
+            double d2 = 0;
+            for (int d = 0; d < 3; ++d) d2 += (x[d] - h[d]) * (x[d] - h[d]);
+            l += w[((long)i * hinges + j) * hinges + k] * std::exp(-gamma * d2);
+          }
+      l += w[m];
+    }
+    logodds[p] = l;
+    sign[p] = (id < 0 || l < tau) ? 1 : -1;
+  }
+}
+
 // Worker threads the parallel loops below use.
 int oracle_threads() { return omp_get_max_threads(); }
 

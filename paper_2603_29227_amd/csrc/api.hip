@@ -312,6 +312,23 @@ extern "C" int ksdf_fit_cells(ksdf_model* m, const void* surface_pts, int dtype,
   return r;
 }
 
+extern "C" int ksdf_bhm_sign(const ksdf_bhm_layout* layout, const int* box_bhm,
+                             const double* weights, const void* points, int dtype, long Q,
+                             double tau, int8_t* sign, double* logodds, void* stream) {
+  return launch_bhm_sign(layout, box_bhm, weights, points, dtype, Q, tau, sign, logodds,
+                         (hipStream_t)stream);
+}
+
+extern "C" size_t ksdf_bhm_tau_workspace_bytes(long K) { return K > 0 ? bhm_tau_workspace_bytes(K) : 0; }
+
+extern "C" int ksdf_bhm_update_tau(const ksdf_bhm_layout* layout, const int* box_bhm,
+                                   const double* weights, const void* hits, int dtype, long K,
+                                   double alpha, double* tau, void* workspace, size_t ws_bytes,
+                                   void* stream) {
+  return launch_bhm_update_tau(layout, box_bhm, weights, hits, dtype, K, alpha, tau, workspace,
+                               ws_bytes, (hipStream_t)stream);
+}
+
 extern "C" size_t ksdf_refit_workspace_bytes(const ksdf_model* m, int budget) {
   return (m && budget > 0) ? refit_workspace_bytes(m, budget) : 0;
 }

@@ -128,6 +128,14 @@ namespace ksdf {
 int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint8_t* user_status,
                hipStream_t s);
 int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
+// sign from BHM weights
+size_t bhm_tau_workspace_bytes(long K);
+int launch_bhm_sign(const ksdf_bhm_layout* L, const int* box_bhm, const double* weights,
+                    const void* points, int dtype, long Q, double tau, int8_t* sign,
+                    double* logodds, hipStream_t s);
+int launch_bhm_update_tau(const ksdf_bhm_layout* L, const int* box_bhm, const double* weights,
+                          const void* hits, int dtype, long K, double alpha, double* tau, void* ws,
+                          size_t ws_bytes, hipStream_t s);
 // streaming refit of the highest-priority dirty cells and the query counter update
 size_t refit_workspace_bytes(const ksdf_model* m, int budget);
 int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, float* dirty,

@@ -35,7 +35,8 @@ EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_c
            "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
            "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
-           "ksdf_count_queries", "ksdf_status_string",
+           "ksdf_count_queries", "ksdf_bhm_sign", "ksdf_bhm_tau_workspace_bytes",
+           "ksdf_bhm_update_tau", "ksdf_status_string",
            "ksdf_last_error"]
 
 
@@ -59,6 +60,45 @@ class Tuning(ctypes.Structure):
 
 
 KERNELS = {"rbf": 0, "matern32": 1}   # KSDF_KERNEL_* (Table I)
+
+
+class BhmLayout(ctypes.Structure):
+    _fields_ = [("origin", ctypes.c_double * 3), ("box", ctypes.c_double),
+                ("dims", ctypes.c_int * 3), ("hinges", ctypes.c_int), ("gamma", ctypes.c_double)]
+
+
+def _bhm_layout(origin, box, dims, hinges, gamma):
+    return BhmLayout((ctypes.c_double * 3)(*map(float, origin)), float(box),
+                     (ctypes.c_int * 3)(*map(int, dims)), int(hinges), float(gamma))
+
+
+def bhm_sign(points: torch.Tensor, origin, box, dims, hinges, gamma, box_bhm: torch.Tensor,
+             weights: torch.Tensor, tau: float = 0.0, logodds=False, stream=None):
+    """Sign of the SDF from local BHM weights (eq. sign_prediction): int8 [Q] (+1 free),
+    and with logodds=True also the log-odds l [Q] (float64)."""
+    if box_bhm.dtype != torch.int32 or weights.dtype != torch.float64:
+        raise ValueError("box_bhm must be int32 and weights float64")
+    Q = len(points)
+    sign = torch.empty(Q, dtype=torch.int8, device=points.device)
+    lo = torch.empty(Q, dtype=torch.float64, device=points.device) if logodds else None
+    dt = DTYPE_F64 if points.dtype == torch.float64 else DTYPE_F32
+    lay = _bhm_layout(origin, box, dims, hinges, gamma)
+    _check(lib().ksdf_bhm_sign(ctypes.byref(lay), _ptr(box_bhm), _ptr(weights), _ptr(points), dt, Q,
+                               float(tau), _ptr(sign), _ptr(lo), _stream(stream)), "ksdf_bhm_sign")
+    return (sign, lo) if logodds else sign
+
+
+def bhm_update_tau(hits: torch.Tensor, origin, box, dims, hinges, gamma, box_bhm: torch.Tensor,
+                   weights: torch.Tensor, alpha: float, tau: torch.Tensor, stream=None):
+    """tau <- (1 - alpha) tau + alpha * mean l(hits), in place (device float64 [1])."""
+    K = len(hits)
+    nb = lib().ksdf_bhm_tau_workspace_bytes(K)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=hits.device)
+    dt = DTYPE_F64 if hits.dtype == torch.float64 else DTYPE_F32
+    lay = _bhm_layout(origin, box, dims, hinges, gamma)
+    _check(lib().ksdf_bhm_update_tau(ctypes.byref(lay), _ptr(box_bhm), _ptr(weights), _ptr(hits), dt,
+                                     K, float(alpha), _ptr(tau), _ptr(ws), nb, _stream(stream)),
+           "ksdf_bhm_update_tau")
 
 
 class Hyper(ctypes.Structure):
@@ -112,6 +152,11 @@ def lib():
         L.ksdf_refit_cells.argtypes = [_vp, _vp, i, l, _vp, _vp, _vp, ctypes.c_double, i, _vp, _vp,
                                        _vp, _vp, sz, _vp]
         L.ksdf_count_queries.argtypes = [_vp, _vp, l, _vp, ctypes.c_float, _vp]
+        L.ksdf_bhm_sign.argtypes = [ctypes.POINTER(BhmLayout), _vp, _vp, _vp, i, l, d, _vp, _vp, _vp]
+        L.ksdf_bhm_tau_workspace_bytes.argtypes = [l]
+        L.ksdf_bhm_tau_workspace_bytes.restype = sz
+        L.ksdf_bhm_update_tau.argtypes = [ctypes.POINTER(BhmLayout), _vp, _vp, _vp, i, l, d, _vp,
+                                          _vp, sz, _vp]
         L.ksdf_model_set_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_get_tuning.argtypes = [_vp, ctypes.POINTER(Tuning)]
         L.ksdf_model_set_timing.argtypes = [_vp, i]

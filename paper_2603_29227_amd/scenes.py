@@ -508,3 +508,29 @@ def small_room_workload(n_queries=4096, cfg_id=12, spacing=0.04, n_boxes=3, n_cy
     return Workload(cfg_id, "small_room", pts, origin, h, h / 2, m_max, m_min, q,
                     _sign(scene.free(q.astype(np.float64))), m_cap_grid=cap, key_lo=key_lo,
                     scene=scene)
+
+
+def bhm_weights(wl, box=0.16, hinges=7, ell_bhm=0.016, weight=2.0):
+    """Synthetic local Bayesian-Hilbert-map weights standing in for a trained front-end:
+    a map for every box of edge `box` that holds a surface sample, its hinges^3 hinge
+    points at the box's lattice points weighted +weight inside a solid and -weight in
+    free space (the scene's analytic test), bias 0; kernel exp(-gamma |x - h|^2) with
+    gamma = 1 / (2 ell_bhm^2).  Box size, hinge count and kernel scale follow the
+    paper's indoor settings (two 0.08 m voxels, 7 hinges per axis, 0.016 m)."""
+    pts = np.asarray(wl.points, np.float64)
+    origin = pts.min(0) - box
+    dims = np.ceil((pts.max(0) + box - origin) / box).astype(np.int64)
+    keys = np.floor((pts - origin) / box).astype(np.int64)
+    flat = np.unique((keys[:, 0] * dims[1] + keys[:, 1]) * dims[2] + keys[:, 2])
+    box_bhm = np.full(int(np.prod(dims)), -1, np.int32)
+    box_bhm[flat] = np.arange(len(flat), dtype=np.int32)
+    kk = np.stack([flat // (dims[1] * dims[2]), (flat // dims[2]) % dims[1], flat % dims[2]], 1)
+    g = np.arange(hinges) * (box / (hinges - 1))
+    off = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    h = (origin + kk * box)[:, None, :] + off[None, :, :]
+    free = wl.scene.free(h.reshape(-1, 3)).reshape(len(flat), -1)
+    w = np.where(free, -weight, weight)
+    weights = np.concatenate([w, np.zeros((len(flat), 1))], 1)
+    return dict(origin=tuple(origin), box=box, dims=tuple(int(d) for d in dims), hinges=hinges,
+                gamma=1.0 / (2 * ell_bhm * ell_bhm), box_bhm=box_bhm,
+                weights=np.ascontiguousarray(weights.reshape(-1)))
