@@ -34,7 +34,8 @@ PEAK_VALU_TSLOTS = 39.32      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz lane-instru
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_room_grid.txt")
 KERNEL_SOURCES = {
-    "query_fast": ["query_fast.hip", "query_split.h", "query_split64.hip", "query_split256.hip",
+    "query_fast": ["query_fast.hip", "query_split.h", "query_split64_wave.hip",
+                   "query_split64_lane.hip", "query_split256_wave.hip", "query_split256_lane.hip",
                    "query_pairs.hip",
                    "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],
     "fused": ["fused.hip", "query_dev.h", "fit_dev.h", "ff.h", "ksdf_internal.h"],

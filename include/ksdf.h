@@ -69,7 +69,7 @@ enum { KSDF_C_FP64 = 1, KSDF_C_FAILED = 2 };
  * or exp(-c (z_i - d)) (Matern 3/2).  Matern 3/2 models: FP32 queries run the plain
  * one-thread-per-query kernel in FP32 (the wave-cooperative kernels carry RBF-specific
  * error bounds), ksdf_fit_query runs fit and query as separate launches, and the
- * backward and the adjoint flags are not supported (KSDF_ERR_UNSUPPORTED). */
+ * backward runs one thread per query in FP64 for either precision. */
 enum { KSDF_KERNEL_RBF = 0, KSDF_KERNEL_MATERN32 = 1 };
 
 /* Hyperparameters (host struct).  ell: length-scale l (m), > 0.  noise_var:

@@ -33,10 +33,6 @@ int check_hyper(const ksdf_hyper* hp) {
               "precision KSDF_FP64|KSDF_FP32, cond threshold > 0, kernel KSDF_KERNEL_*)");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
-  if (hp->kernel != KSDF_KERNEL_RBF && hp->flags) {
-    set_error("the adjoint (backward) is implemented for the RBF kernel only");
-    return KSDF_ERR_UNSUPPORTED;
-  }
   return KSDF_OK;
 }
 
@@ -501,10 +497,6 @@ extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long
   if (!m->fitted) {
     set_error("ksdf_query_backward: the model has not been fitted");
     return KSDF_ERR_INVALID_ARGUMENT;
-  }
-  if (m->kernel != KSDF_KERNEL_RBF) {
-    set_error("ksdf_query_backward: implemented for the RBF kernel only");
-    return KSDF_ERR_UNSUPPORTED;
   }
   const size_t need = backward_workspace_bytes(m, Q);
   if (ws_bytes < need || (need > 0 && !workspace)) {

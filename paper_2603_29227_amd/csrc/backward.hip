@@ -254,6 +254,221 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
   A.part[2 * q + 1] = th[1];
 }
 
+// VJP of one query on its argmin cell for a Matern 3/2 model (Table I, App. D), in
+// FP64 for either store (the FP32 store's float-float pairs are exact in double).
+// With c = sqrt(3)/l, the nearest sample distance d, e_i = exp(-c (z_i - d)),
+// k'_i = (1 + c z_i) e_i, f' = sum a_i k'_i, w' = sum a_i e_i d_i (d_i = x - x_i):
+//   u = d - ln(f')/c           du/dx = c w'/f',  du/dl|_a = (u - c Z/f')/l, Z = sum a e z^2,
+//                              du/da_i = -k'_i / (c f')
+//   g = w'/|w'|                dw'/dx = (sum a e) I - c sum a e d d^T / z,
+//                              dw'/dc = -sum a e z d (dc/dl = -c/l),  dw'/da_i = e_i d_i
+//   var_f = 1 - k^T A^{-1} k   d/dx = 2 c^2 sum beta_i e^{-c z_i} d_i,
+//                              d/dl|_A = -2 c^2 sum beta_i z_i^2 e^{-c z_i} / l
+// and the softmin variance as for the RBF.  The fit enters through the adjoint
+// vectors xi_l = A^{-1} (dA/dl) a and xi_s = A^{-1} a as in query_vjp.
+template <class T, bool VARF>
+__device__ void vjp_matern(const BwdArgs<T>& A, long q, int c, double* v, double out_dx[3],
+                           double out_th[2]) {
+  constexpr bool F64 = sizeof(T) == 8;
+  const double lt = F64 ? (double)A.ell : A.ell_d;
+  const double al = F64 ? (double)A.alpha : A.alpha_d;
+  const double mc = sqrt(3.0) / lt;
+  const double x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
+  const double s = A.sign ? (double)A.sign[q] : 1.0;
+  const double gm = A.d_mean ? (double)A.d_mean[q] : 0.0;
+  double gg[3] = {0, 0, 0};
+  if (A.d_grad)
+    for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
+  const double gv = A.d_var ? (double)A.d_var[q] : 0.0;
+  const double gf = VARF && A.d_var_f ? (double)A.d_var_f[q] : 0.0;
+  const int b = A.offsets[c], m = A.offsets[c + 1] - b;
+  const T* Lc = A.L + A.loff[c];
+  const double l0 = x0 - A.centre64[3L * c], l1 = x1 - A.centre64[3L * c + 1],
+               l2 = x2 - A.centre64[3L * c + 2];
+  auto load = [&](int i, double di[3], double& pa) {
+    if constexpr (F64) {
+      const T* p = A.ps + 4L * (b + i);
+      di[0] = l0 - p[0];
+      di[1] = l1 - p[1];
+      di[2] = l2 - p[2];
+      pa = p[3];
+    } else {
+      const float* p = A.ps + 4L * (b + i);
+      const float* pl = A.plo + 4L * (b + i);
+      di[0] = l0 - ((double)p[0] + (double)pl[0]);
+      di[1] = l1 - ((double)p[1] + (double)pl[1]);
+      di[2] = l2 - ((double)p[2] + (double)pl[2]);
+      pa = (double)p[3] + (double)pl[3];
+    }
+  };
+  auto xi_l = [&](int i) -> double {
+    if constexpr (F64) return A.xi[2L * (b + i)];
+    else return (double)A.xi[4L * (b + i)] + (double)A.xi[4L * (b + i) + 2];
+  };
+  auto xi_s = [&](int i) -> double {
+    if constexpr (F64) return A.xi[2L * (b + i) + 1];
+    else return (double)A.xi[4L * (b + i) + 1] + (double)A.xi[4L * (b + i) + 3];
+  };
+  double d2 = INFINITY;
+  for (int i = 0; i < m; ++i) {
+    double di[3], pa;
+    load(i, di, pa);
+    d2 = fmin(d2, di[0] * di[0] + di[1] * di[1] + di[2] * di[2]);
+  }
+  const double zmin = sqrt(d2);
+  // pass A: f', sum a e, w', Z, softmin moments, k
+  double f = 0, fe = 0, w[3] = {0, 0, 0}, Za = 0, S = 0, M1 = 0, M2 = 0;
+  for (int i = 0; i < m; ++i) {
+    double di[3], pa;
+    load(i, di, pa);
+    const double z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
+    const double z = sqrt(z2);
+    const double e = exp(-mc * (z - zmin));
+    f += pa * (1.0 + mc * z) * e;
+    fe += pa * e;
+    for (int d = 0; d < 3; ++d) w[d] += pa * e * di[d];
+    Za += pa * e * z2;
+    const double t = z - zmin;
+    const double sm = exp(-al * t);
+    S += sm;
+    M1 += sm * t;
+    M2 += sm * t * t;
+    if constexpr (VARF) v[i] = (1.0 + mc * z) * exp(-mc * z);
+  }
+  double vv = 0;
+  if constexpr (VARF) {
+    for (int i = 0; i < m; ++i) {
+      const T* row = Lc + (long)i * (i + 1) / 2;
+      double t = v[i];
+      for (int j = 0; j < i; ++j) t -= (double)row[j] * v[j];
+      v[i] = t * (double)row[i];
+      vv += v[i] * v[i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      const T* row = Lc + (long)i * (i + 1) / 2;
+      v[i] *= (double)row[i];
+      for (int j = 0; j < i; ++j) v[j] -= (double)row[j] * v[i];
+    }
+  }
+  const double u = f > 0.0 ? zmin - log(f) / mc : -1.0;
+  const bool mean_live = u > 0.0;
+  const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  double y[3] = {0, 0, 0};
+  if (wn > 0.0) {
+    const double gw = (gg[0] * w[0] + gg[1] * w[1] + gg[2] * w[2]) / wn;
+    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * w[d] / wn) / wn;
+  }
+  const bool varf_live = VARF && (1.0 - vv) > 0.0;
+  const double m1 = M1 / S;
+  const double h = zmin + m1;
+  const double Vz = M2 / S - m1 * m1;
+  double V = 0, P = 0, dVa = 0, C2 = 0;
+  for (int i = 0; i < m; ++i) {
+    double di[3], pa;
+    load(i, di, pa);
+    const double z = sqrt(di[0] * di[0] + di[1] * di[1] + di[2] * di[2]);
+    const double si = exp(-al * (z - zmin)) / S;
+    const double Bi = al * (h - z) + 1.0;
+    const double ci = si * Bi;
+    const double svi = A.sv[b + i];
+    V += svi * ci * ci;
+    P += svi * ci * si;
+    C2 += ci * ci;
+    dVa += 2.0 * svi * ci * (si * (h - z) * (Bi + 1.0) - al * si * Vz);
+  }
+  double dxv[3] = {0, 0, 0}, Hy[3] = {0, 0, 0}, Wz[3] = {0, 0, 0}, bk[3] = {0, 0, 0};
+  double bkz = 0, bb = 0, El = 0, Es = 0, Eld[3] = {0, 0, 0}, Esd[3] = {0, 0, 0};
+  for (int i = 0; i < m; ++i) {
+    double di[3], pa;
+    load(i, di, pa);
+    const double z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
+    const double z = sqrt(z2);
+    const double e = exp(-mc * (z - zmin));
+    const double kp = (1.0 + mc * z) * e;
+    const double ae = pa * e;
+    const double si = exp(-al * (z - zmin)) / S;
+    const double ci = si * (al * (h - z) + 1.0);
+    const double svi = A.sv[b + i];
+    const double dvdz = 2.0 * al * (-svi * ci * (ci + si) + si * V + ci * P);
+    const double dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
+    double kb = 0;
+    if constexpr (VARF) kb = v[i] * exp(-mc * z);
+    const double xl = xi_l(i), xs = xi_s(i);
+    for (int d = 0; d < 3; ++d) {
+      if (z > 0.0) {
+        dxv[d] += dvdz * di[d] / z;
+        Hy[d] += ae * dy * di[d] / z;
+      }
+      Wz[d] += ae * z * di[d];
+      if constexpr (VARF) bk[d] += kb * di[d];
+      Eld[d] += e * xl * di[d];
+      Esd[d] += e * xs * di[d];
+    }
+    if constexpr (VARF) {
+      bkz += kb * z2;
+      bb += v[i] * v[i];
+    }
+    El += kp * xl;
+    Es += kp * xs;
+  }
+  double bDb = 0;
+  if (VARF && A.D && gf != 0.0 && varf_live) {
+    const T* Dc = A.D + A.loff[c];
+    for (int i = 1; i < m; ++i) {
+      const T* row = Dc + (long)i * (i + 1) / 2;
+      double t = 0;
+      for (int j = 0; j < i; ++j) t += (double)row[j] * v[j];
+      bDb += 2.0 * v[i] * t;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    double r = s * (fe * y[d] - mc * Hy[d]) + gv * dxv[d];
+    if (mean_live) r += s * gm * mc * w[d] / f;
+    if (varf_live) r += gf * 2.0 * mc * mc * bk[d];
+    out_dx[d] = r;
+  }
+  double aXl = s * (y[0] * Eld[0] + y[1] * Eld[1] + y[2] * Eld[2]);
+  double aXs = s * (y[0] * Esd[0] + y[1] * Esd[1] + y[2] * Esd[2]);
+  if (mean_live) {
+    const double cm = -s * gm / (mc * f);
+    aXl += cm * El;
+    aXs += cm * Es;
+  }
+  double dl = 0, ds = 0;
+  if (mean_live) dl += s * gm * (u - mc * Za / f) / lt;
+  dl += s * (mc / lt) * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]);
+  if (A.alpha_tied) dl += gv * dVa * (-2.0 * al / lt);
+  if (varf_live) dl += gf * (-2.0 * mc * mc * bkz / lt + bDb);
+  dl -= aXl;
+  if (A.uniform_noise) {
+    ds += gv * C2;
+    if (varf_live) ds += gf * bb;
+    ds -= aXs;
+  }
+  out_th[0] = dl;
+  out_th[1] = ds;
+}
+
+template <class T, bool VARF>
+__global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
+  const long q = (long)blockIdx.x * BT + threadIdx.x;
+  if (q >= A.Q) return;
+  int c = A.argmin[q];
+  if (c >= A.n_cells) c = -1;
+  double dx[3] = {0, 0, 0}, th[2] = {0, 0};
+  if (c >= 0) {
+    if constexpr (VARF) {
+      double v[KSDF_MAX_M];
+      vjp_matern<T, true>(A, q, c, v, dx, th);
+    } else {
+      vjp_matern<T, false>(A, q, c, nullptr, dx, th);
+    }
+  }
+  for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = (T)dx[d];
+  A.part[2 * q] = th[0];
+  A.part[2 * q + 1] = th[1];
+}
+
 // VJP without a var_f cotangent for an FP32 model (the terms of query_vjp<T, false>),
 // for a wave-uniform cell: every lane of the wave runs it, so the per-cell data are
 // read by scalar loads, BCH samples per load group, outside divergent control flow; a
@@ -644,7 +859,10 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.ell = m->ell; A.two_l2 = two_l2; A.alpha = m->alpha;
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
-    if (Q > 0) {
+    if (Q > 0 && m->kernel == KSDF_KERNEL_MATERN32) {
+      if (varf) hipLaunchKernelGGL((bwd_matern_kernel<double, true>), dim3(grid), dim3(BT), 0, s, A);
+      else hipLaunchKernelGGL((bwd_matern_kernel<double, false>), dim3(grid), dim3(BT), 0, s, A);
+    } else if (Q > 0) {
       if (varf) hipLaunchKernelGGL((bwd_plain_kernel<double, true>), dim3(grid), dim3(BT), 0, s, A);
       else hipLaunchKernelGGL((bwd_plain_kernel<double, false>), dim3(grid), dim3(BT), 0, s, A);
     }
@@ -668,7 +886,10 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.ell_d = m->ell; A.alpha_d = m->alpha; A.plo = m->plo32;
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
-    if (Q > 0) {
+    if (Q > 0 && m->kernel == KSDF_KERNEL_MATERN32) {
+      if (varf) hipLaunchKernelGGL((bwd_matern_kernel<float, true>), dim3(grid), dim3(BT), 0, s, A);
+      else hipLaunchKernelGGL((bwd_matern_kernel<float, false>), dim3(grid), dim3(BT), 0, s, A);
+    } else if (Q > 0) {
       if (varf) hipLaunchKernelGGL((bwd_wave_kernel<true, false>), dim3(grid), dim3(BT), 0, s, A, perm);
       else if (m->tuning.backward_lanes)
         hipLaunchKernelGGL((bwd_wave_kernel<false, true>), dim3(grid), dim3(BT), 0, s, A, perm);

@@ -193,6 +193,8 @@ struct FitArgs {
   float inv_l3_ff[2];
   int kernel;            // KSDF_KERNEL_* (Table I)
   float mc_ff[2];        // Matern 3/2 rate c = sqrt(3) / l, float-float
+  float mc2_ff[2];       // c^2 and 1 / l, float-float (Matern adjoint)
+  float inv_l_ff[2];
   int adjoint;           // also prepare the adjoint vectors xi (and D when non-null)
   float* xi32;           // [nnz+pad,4] (xi_l, xi_s) as float-float: hi_l, hi_s, lo_l, lo_s
   float* D32;            // packed dA/dl or null
@@ -545,9 +547,12 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
     }
     ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, ah, al, res);
     if (A.adjoint) {
-      // adjoint vectors of the fit: xi_l = A^{-1} (dA/dl) a with dA_ij/dl = K_ij r_ij^2 / l^3,
-      // and xi_s = A^{-1} a (dA/dsigma^2 = I for the uniform noise variance)
-      const ff il3{A.inv_l3_ff[0], A.inv_l3_ff[1]};
+      // adjoint vectors of the fit: xi_l = A^{-1} (dA/dl) a with dA_ij/dl = K_ij r_ij^2 / l^3
+      // (RBF) or c^2 r_ij^2 exp(-c r_ij) / l (Matern 3/2), and xi_s = A^{-1} a
+      // (dA/dsigma^2 = I for the uniform noise variance)
+      const bool matern = A.kernel == KSDF_KERNEL_MATERN32;
+      const ff il3 = matern ? ff{A.inv_l_ff[0], A.inv_l_ff[1]} : ff{A.inv_l3_ff[0], A.inv_l3_ff[1]};
+      const ff mcf{A.mc_ff[0], A.mc_ff[1]}, mc2f{A.mc2_ff[0], A.mc2_ff[1]};
       ff_row_sums(
           m,
           [&](int i, int k) {
@@ -558,6 +563,10 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
             for (int d = 0; d < 3; ++d) {
               const ff dd = ff_add(ff{xh[3 * i + d], xl[3 * i + d]}, ff{-xh[3 * k + d], -xl[3 * k + d]});
               r2 = ff_add(r2, ff_mul(dd, dd));
+            }
+            if (matern) {
+              const ff ecr = ff_exp_neg_tab(ff_mul(ff_sqrt(r2), mcf));
+              return ff_mul(ff_mul(ff_mul(ecr, r2), mc2f), ff{ah[k], al[k]});
             }
             return ff_mul(ff_mul(ff{Ahi[e], Alo[e]}, r2), ff{ah[k], al[k]});
           },
@@ -595,7 +604,12 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
             const float dd = (xh[3 * i + d] - xh[3 * k + d]) + (xl[3 * i + d] - xl[3 * k + d]);
             r2 += dd * dd;
           }
-          A.D32[A.loff[c] + e] = (i == k) ? 0.f : Ahi[e] * r2 * il3f;
+          if (matern) {
+            const float mcv = A.mc_ff[0], r = sqrtf(r2);
+            A.D32[A.loff[c] + e] = (i == k) ? 0.f : A.mc2_ff[0] * r2 * expf(-mcv * r) * A.inv_l_ff[0];
+          } else {
+            A.D32[A.loff[c] + e] = (i == k) ? 0.f : Ahi[e] * r2 * il3f;
+          }
         }
       }
     }
@@ -664,6 +678,13 @@ __device__ void fit64_cell(const FitArgs& A, int c, double* smem) {
       }
       __syncthreads();
       const double inv2l2 = 1.0 / (2.0 * A.ell * A.ell), il3 = 1.0 / (A.ell * A.ell * A.ell);
+      const bool matern = A.kernel == KSDF_KERNEL_MATERN32;
+      const double mcd = std::sqrt(3.0) / A.ell;
+      // dA_ij/dl without the 1/l^3 (RBF) or 1/l (Matern 3/2) factor
+      auto dkl = [&](double r2) {
+        return matern ? mcd * mcd * r2 * exp(-mcd * sqrt(r2)) : exp(-r2 * inv2l2) * r2;
+      };
+      const double lfac = matern ? 1.0 / A.ell : il3;
       for (int i = threadIdx.x; i < m; i += blockDim.x) {
         double acc = 0.0;
         for (int k = 0; k < m; ++k) {
@@ -671,9 +692,9 @@ __device__ void fit64_cell(const FitArgs& A, int c, double* smem) {
           const double dx = xs[3 * i] - xs[3 * k], dy = xs[3 * i + 1] - xs[3 * k + 1],
                        dz = xs[3 * i + 2] - xs[3 * k + 2];
           const double r2 = dx * dx + dy * dy + dz * dz;
-          acc += exp(-r2 * inv2l2) * r2 * a_s[k];
+          acc += dkl(r2) * a_s[k];
         }
-        g_s[i] = acc * il3;
+        g_s[i] = acc * lfac;
       }
       __syncthreads();
       if (threadIdx.x < 64) {
@@ -715,7 +736,7 @@ __device__ void fit64_cell(const FitArgs& A, int c, double* smem) {
           const double dx = xs[3 * i] - xs[3 * k], dy = xs[3 * i + 1] - xs[3 * k + 1],
                        dz = xs[3 * i + 2] - xs[3 * k + 2];
           const double r2 = dx * dx + dy * dy + dz * dz;
-          const double dv = (i == k) ? 0.0 : exp(-r2 * inv2l2) * r2 * il3;
+          const double dv = (i == k) ? 0.0 : dkl(r2) * lfac;
           if (A.emit32) A.D32[A.loff[c] + e] = (float)dv;
           else A.D64[A.loff[c] + e] = dv;
         }
@@ -774,6 +795,11 @@ inline FitArgs make_fit_args(ksdf_model* m, const void* pts, int dtype, const vo
     const double mc = std::sqrt(3.0) / m->ell;
     A.mc_ff[0] = (float)mc;
     A.mc_ff[1] = (float)(mc - (double)(float)mc);
+    const double mc2 = 3.0 / (m->ell * m->ell), il = 1.0 / m->ell;
+    A.mc2_ff[0] = (float)mc2;
+    A.mc2_ff[1] = (float)(mc2 - (double)(float)mc2);
+    A.inv_l_ff[0] = (float)il;
+    A.inv_l_ff[1] = (float)(il - (double)(float)il);
     A.noise_ff[0] = (float)m->noise_var;
     A.noise_ff[1] = (float)(m->noise_var - (double)(float)m->noise_var);
   }

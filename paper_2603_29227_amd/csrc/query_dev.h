@@ -62,11 +62,15 @@ struct Pass1 {
   int flags;   // bit 0: query outside the candidate index; bit 1: active lane
 };
 
-// two-kernel query launches (query_split64.hip, query_split256.hip)
-void launch_query_split_64(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
-                           int* count, int* cursor, int* tsum, bool lane, void* pws, hipStream_t s);
-void launch_query_split_256(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
-                            int* count, int* cursor, int* tsum, bool lane, void* pws, hipStream_t s);
+// two-kernel query launches (query_split{64,256}_{wave,lane}.hip)
+void launch_query_split_64_wave(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                               int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
+void launch_query_split_64_lane(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                               int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
+void launch_query_split_256_wave(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                               int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
+void launch_query_split_256_lane(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+                               int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
 // pair form of pass 1 (query_pairs.hip): usable for Q queries, its workspace, launch
 bool query_pairs_usable(const ksdf_model* m, long Q);
 size_t query_pairs_workspace_bytes(const ksdf_model* m, long Q);

@@ -90,10 +90,13 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
       return KSDF_ERR_UNSUPPORTED;
     }
     const bool lane = m->tuning.query_lanes != 0;
-    if (m->tuning.query_block == 64)
-      launch_query_split_64(m, A, rec, rec2, count, cursor, tsum, lane, pws, s);
-    else
-      launch_query_split_256(m, A, rec, rec2, count, cursor, tsum, lane, pws, s);
+    if (m->tuning.query_block == 64) {
+      if (lane) launch_query_split_64_lane(m, A, rec, rec2, count, cursor, tsum, pws, s);
+      else launch_query_split_64_wave(m, A, rec, rec2, count, cursor, tsum, pws, s);
+    } else {
+      if (lane) launch_query_split_256_lane(m, A, rec, rec2, count, cursor, tsum, pws, s);
+      else launch_query_split_256_wave(m, A, rec, rec2, count, cursor, tsum, pws, s);
+    }
   } else if (m->tuning.query_block == 64) {
     launch_query_nt<64>(m, A, s);
   } else {

@@ -7,8 +7,8 @@
 // a spatial bucket, so the per-cell work (gradient, GP variance by forward
 // substitution, softmin variance) is not repeated for lanes that idle.
 //
-// The kernels are instantiated per block size in query_split64.hip and
-// query_split256.hip, which compile in parallel.
+// The kernels are instantiated per block size and cell mode in
+// query_split{64,256}_{wave,lane}.hip, which compile in parallel.
 #pragma once
 
 #include "query_dev.h"

@@ -30,12 +30,12 @@ def _say(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
 
-def _setup(wl, precision, var_f=False):
+def _setup(wl, precision, var_f=False, kernel="rbf"):
     cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
                              wl.m_cap_grid, wl.key_lo)
     dt = torch.float64 if precision == "fp64" else torch.float32
     model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
-                       precision=precision, adjoint=True, adjoint_var_f=var_f)
+                       precision=precision, adjoint=True, adjoint_var_f=var_f, kernel=kernel)
     model.fit(torch.from_numpy(np.ascontiguousarray(wl.points)).to("cuda", dt))
     return model, cells, dt
 
@@ -64,16 +64,18 @@ def _gpu_vjp(model, q, sign, cot, dt):
 
 
 def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, max_ratio=np.inf,
-             check_hyper=True):
+             check_hyper=True, kernel="rbf"):
     oc = _ocells(wl, cells)
     cp = 64 if prec == "fp64" else 32
     kw = {} if mode == 1 else cot
     # differentiate at the GPU's argmin cells: near-ties of the min-fusion may resolve
     # either way, and d_hyper sums every point
     _, odp, odh, opp = oracle.vjp(wl.points, oc, q, wl.ell, wl.noise_var, cand_prec=cp,
-                                  sign=sign, mode=mode, per_point=True, force_argmin=am, **kw)
-    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
-    o = oracle.query(wl.points, oc, f, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign)
+                                  sign=sign, mode=mode, per_point=True, force_argmin=am,
+                                  kernel=kernel, **kw)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel=kernel)
+    o = oracle.query(wl.points, oc, f, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign,
+                     kernel=kernel)
     ok = (am == o["argmin"]) & (o["status"] & 3 == 0) & (o["u_best"] > 1e-3) & (o["ratio"] <= max_ratio)
     assert ok.mean() > 0.8, ok.mean()
     print(f"compared {ok.sum()} of {len(ok)} points", flush=True)
@@ -127,6 +129,30 @@ def test_fp32_backward_with_gradient_cotangent():
     e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32", 1e-3, 1e-3,
                       max_ratio=3e2, check_hyper=False)
     print("fp32 grad-cotangent max point err", e, "d_hyper rel (reported)", rel, flush=True)
+
+
+def test_matern_fp64_backward_matches_oracle_vjp():
+    _say("matern32 fp64 backward sphere, random cotangents incl. grad and var_f")
+    wl = scenes.sphere_workload(n_queries=2000)
+    model, cells, dt = _setup(wl, "fp64", var_f=True, kernel="matern32")
+    cot = _cotangents(len(wl.queries), 5)
+    dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp64", 1e-8, 1e-8,
+                      kernel="matern32")
+    print("matern fp64 max point err", e, "d_hyper rel", rel, flush=True)
+
+
+@pytest.mark.parametrize("var_f", [False, True])
+def test_matern_fp32_backward_matches_oracle_vjp(var_f):
+    _say(f"matern32 fp32 backward small room var_f={var_f}")
+    wl = scenes.small_room_workload(n_queries=3000, cfg_id=33)
+    model, cells, dt = _setup(wl, "fp32", var_f=var_f, kernel="matern32")
+    cot = _cotangents(len(wl.queries), 6, grad=True, var_f=var_f)
+    dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32",
+                      3e-3 if var_f else 1e-3, 5e-3 if var_f else 1e-3, max_ratio=1e3,
+                      kernel="matern32")
+    print("matern fp32 max point err", e, "d_hyper rel", rel, flush=True)
 
 
 def test_fp32_collision_cost_gradient_via_autograd():

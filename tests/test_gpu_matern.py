@@ -1,7 +1,7 @@
 """GPU parity of the Matern 3/2 kernel variant (Table I, App. D) against the FP64
 oracle, element by element (tests/parity.py's tolerances), for FP64 and FP32 models,
-with every output including the gradient variance; and the variant's limits (no
-backward, fused fit+query served by separate launches)."""
+with every output including the gradient variance, and fused fit+query served by
+separate launches (the backward is tested in test_gpu_backward.py)."""
 import numpy as np
 import pytest
 import torch
@@ -65,7 +65,7 @@ def test_matern_small_room_fp32(uneven):
 
 
 def test_matern_fit_query_and_limits():
-    _say("matern32 fit_query (fused tuning) vs fit + query; unsupported backward")
+    _say("matern32 fit_query (fused tuning) vs fit + query; backward needs the adjoint flag")
     wl = scenes.small_room_workload(n_queries=2048)
     cells = _cells(wl)
     model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
@@ -80,9 +80,7 @@ def test_matern_fit_query_and_limits():
     torch.cuda.synchronize()
     for k in a:
         assert torch.equal(a[k], b[k]), f"fit_query and fit + query differ in {k}"
+    # a model fitted without the adjoint flag has no backward
     with pytest.raises(ksdf.KsdfError):
         model.backward(q, sg, torch.ones_like(b["mean"]))
-    with pytest.raises(ksdf.KsdfError):
-        ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, kernel="matern32",
-                   adjoint=True)
     model.close()
