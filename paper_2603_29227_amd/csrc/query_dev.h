@@ -288,6 +288,29 @@ __device__ __forceinline__ void query_candidates(const FastArgs& A, bool active,
   }
 }
 
+// One chunk of CH samples of the u^2 sums: f = sum a e, R = sum |a| e, RZ = sum |a| e z^2,
+// emax = max e, with e = 2^(c2 (d2ref - z^2)).  With MASK, entries past m belong to the
+// next cell (the store is padded): their offsets from this cell's centre can be far
+// nearer than d2ref, and exp2 would overflow, so their term is masked, not weighted by 0.
+template <bool MASK>
+__device__ __forceinline__ void u2_chunk(const float4 (&P)[CH], int i0, int m, float lx, float ly,
+                                         float lz, float c2, float c2d, float& f, float& R,
+                                         float& RZ, float& emax) {
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const bool in = !MASK || i0 + j < m;
+    const float aw = P[j].w;
+    const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
+    const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+    const float e = in ? __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d)) : 0.f;
+    const float ae = fabsf(aw) * e;
+    f = fmaf(aw, e, f);
+    R += ae;
+    RZ = fmaf(ae, z2, RZ);
+    emax = fmaxf(emax, e);
+  }
+}
+
 // u^2 of one cell at the cell-local point (lx,ly,lz) for the lanes with ev set, with
 // its rounding-error bound del, against the scaling reference d2ref (in: the sample
 // box's lower bound; out: the reference used).  Wave-uniform: every lane of the wave
@@ -310,22 +333,9 @@ __device__ __forceinline__ void cell_u2_wave(const FastArgs& A, int b, int m, fl
       float4 P[CH];
 #pragma unroll
       for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
-#pragma unroll
-      for (int j = 0; j < CH; ++j) {
-        // entries past m belong to the next cell (the store is padded): their
-        // offsets from this cell's centre can be far nearer than d2ref, and exp2
-        // would overflow, so their term is masked, not weighted by 0
-        const bool in = i0 + j < m;
-        const float aw = P[j].w;
-        const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
-        const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        const float e = in ? __builtin_amdgcn_exp2f(fmaf(z2, -c2, c2d)) : 0.f;
-        const float ae = fabsf(aw) * e;
-        f = fmaf(aw, e, f);
-        R += ae;
-        RZ = fmaf(ae, z2, RZ);
-        emax = fmaxf(emax, e);
-      }
+      // only the last chunk of a cell needs the mask (the test is wave-uniform)
+      if (i0 + CH <= m) u2_chunk<false>(P, i0, m, lx, ly, lz, c2, c2d, f, R, RZ, emax);
+      else u2_chunk<true>(P, i0, m, lx, ly, lz, c2, c2d, f, R, RZ, emax);
     }
     // far from the cell, the nearest sample can lie so much farther than the box's
     // nearest point that every term is tiny against the box reference and the
@@ -800,14 +810,19 @@ __global__ void fill_kernel(int* p, long n, int v) {
   if (i < n) p[i] = v;
 }
 
+// The counting sort's count and scatter take one atomic per distinct key of a wave
+// (wave_count, wave_slot): consecutive queries mostly share their bins.
 __global__ void bin_kernel(FastArgs A, int* keys, int* counts, long n_bins) {
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= A.Q) return;
-  int sub;
-  const long b = box_key(A, A.pts[3 * q], A.pts[3 * q + 1], A.pts[3 * q + 2], &sub);
-  const int key = b < 0 ? (int)(n_bins - 1) : (int)((long)A.box_rank[b] * A.sub * A.sub * A.sub + sub);
-  keys[q] = key;
-  atomicAdd(&counts[key], 1);
+  const bool valid = q < A.Q;
+  int key = 0;
+  if (valid) {
+    int sub;
+    const long b = box_key(A, A.pts[3 * q], A.pts[3 * q + 1], A.pts[3 * q + 2], &sub);
+    key = b < 0 ? (int)(n_bins - 1) : (int)((long)A.box_rank[b] * A.sub * A.sub * A.sub + sub);
+    keys[q] = key;
+  }
+  wave_count(counts, key, valid);
 }
 
 constexpr int SCAN_T = 256;
@@ -884,9 +899,9 @@ __global__ void __launch_bounds__(SCAN_T) scan_apply_kernel(const int* in, long 
 
 __global__ void scatter_kernel(long Q, const int* keys, int* cursor, int* perm) {
   const long q = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= Q) return;
-  const int pos = atomicAdd(&cursor[keys[q]], 1);
-  perm[pos] = (int)q;
+  const bool valid = q < Q;
+  const int pos = wave_slot(cursor, valid ? keys[q] : 0, valid);
+  if (valid) perm[pos] = (int)q;
 }
 
 // bucketing granularity (sub-boxes per box edge): the tuned value, else the finest
