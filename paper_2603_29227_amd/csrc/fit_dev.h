@@ -361,15 +361,18 @@ __device__ __forceinline__ void ff_row_sums(int m, Term term, Out out) {
 
 // Solve A x = rhs for the cell (block-cooperative): an FP32 solve with the factor,
 // then refinement steps whose residuals rhs - A x are evaluated in float-float from
-// (Ahi, Alo), until a correction is below REFINE_TOL of |x| or no longer shrinks
+// (Ahi, Alo), until a correction is below tol (REFINE_TOL) of |x| or no longer shrinks
 // (the float-float residual's own accuracy is reached), at most REFINE_MAX steps;
 // each step shrinks the error by about cond(A) * 2^-24.  rhs (rh, rl) and
 // x (xh, xl) are float-float arrays in LDS; res is scratch.  Ends with a barrier.
 constexpr int REFINE_MAX = 10;
 constexpr float REFINE_TOL = 1e-10f;
+// The fit's adjoint vectors enter only the hyperparameter gradient, whose FP32 bound
+// is 1e-3 relative: 1e-7 of |x| is ample there and saves refinement steps.
+constexpr float REFINE_TOL_ADJOINT = 1e-7f;
 __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float* Lf, int m,
                                  const float* rh, const float* rl, float* xh, float* xl,
-                                 float* res) {
+                                 float* res, float tol = REFINE_TOL) {
   const int lane = threadIdx.x & 63;
   __shared__ int converged;
   float prev = INFINITY;   // last correction (wave 0)
@@ -428,7 +431,7 @@ __device__ void ff_refined_solve(const float* Ahi, const float* Alo, const float
       }
       dn = wave_max(dn);
       xn = wave_max(xn);
-      if (threadIdx.x == 0) converged = !(dn > REFINE_TOL * xn) || !(dn < 0.5f * prev);
+      if (threadIdx.x == 0) converged = !(dn > tol * xn) || !(dn < 0.5f * prev);
       prev = dn;
     }
     __syncthreads();
@@ -575,7 +578,7 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
             rh[i] = g.hi;
             rl[i] = g.lo;
           });
-      ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
+      ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res, REFINE_TOL_ADJOINT);
       for (int i = threadIdx.x; i < m; i += blockDim.x) {
         A.xi32[4L * (b + i)] = xih[i];
         A.xi32[4L * (b + i) + 2] = xil[i];
@@ -586,7 +589,7 @@ __device__ bool fit32_cell(const FitArgs& A, int c, float* smem) {
           rh[i] = ah[i];
           rl[i] = al[i];
         }
-        ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res);
+        ff_refined_solve(Ahi, Alo, Lf, m, rh, rl, xih, xil, res, REFINE_TOL_ADJOINT);
       }
       for (int i = threadIdx.x; i < m; i += blockDim.x) {
         A.xi32[4L * (b + i) + 1] = A.svar ? 0.f : xih[i];
