@@ -169,3 +169,51 @@ def test_terrain_full_size():
     tq, tsg = scenes.terrain_trajectories(wl)
     _backward_check(wl, cells, model, tq, tsg, "terrain trajectories")
     model.close()
+
+
+def test_matern_room_grid_full_size():
+    _say("matern32 room 256^3 grid (the bench's Matern leg), sampled oracle check")
+    wl = scenes.room_workload("grid")
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       precision="fp32", query_box=(np.zeros(3), np.array([10.0, 8.0, 3.0])),
+                       kernel="matern32")
+    model.fit(torch.from_numpy(wl.points).cuda())
+    out = model.query(torch.from_numpy(wl.queries).cuda(), torch.from_numpy(wl.sign).cuda(),
+                      grad_var=True)
+    torch.cuda.synchronize()
+    idx = _sample(out, 6000, 2000, 23)
+    oc = _ocells(wl, cells)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel="matern32")
+    o = oracle.query(wl.points, oc, f, wl.queries[idx], wl.ell, wl.noise_var, cand_prec=32,
+                     sign=wl.sign[idx], all_candidates=True, kernel="matern32")
+    g = {k: v.cpu().numpy()[idx] for k, v in out.items()}
+    rep = assert_parity(g, o, wl.ell, "fp32", wl.sign[idx], label="matern room grid")
+    print(f"matern room grid: {len(idx)} sampled, mean err max {rep['mean_err_max']:.3g}", flush=True)
+    model.close()
+
+
+def test_bhm_sign_room_grid_full_size():
+    _say("bhm sign on the room 256^3 grid (the bench's sign leg), sampled oracle check")
+    wl = scenes.room_workload("grid")
+    b = scenes.bhm_weights(wl)
+    q = torch.from_numpy(wl.queries).cuda()
+    sign, lo = ksdf.bhm_sign(q, b["origin"], b["box"], b["dims"], b["hinges"], b["gamma"],
+                             torch.from_numpy(b["box_bhm"]).cuda(),
+                             torch.from_numpy(b["weights"]).cuda(), tau=0.0, logodds=True)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(24)
+    g = lo.cpu().numpy()
+    have = np.where(np.isfinite(g))[0]
+    idx = np.unique(np.concatenate([rng.choice(len(g), 20000, replace=False),
+                                    rng.choice(have, min(20000, len(have)), replace=False)]))
+    olo, oh, osg = oracle.bhm(wl.queries[idx].astype(np.float64), b["origin"], b["box"], b["dims"],
+                              b["hinges"], b["gamma"], b["box_bhm"], b["weights"], tau=0.0)
+    h = oh == 1
+    assert np.array_equal(np.isfinite(g[idx]), h)
+    np.testing.assert_allclose(g[idx][h], olo[h], rtol=0, atol=1e-12)
+    s = sign.cpu().numpy()[idx].astype(np.int32)
+    clear = ~h | (np.abs(olo) > 1e-12)
+    assert np.array_equal(s[clear], osg[clear])
+    print(f"bhm grid: {len(idx)} sampled, {int(h.sum())} inside maps", flush=True)

@@ -116,3 +116,29 @@ def test_count_queries_matches_bincount():
     with pytest.raises(ksdf.KsdfError):
         model.refit(torch.from_numpy(p0).cuda(), qcount, qcount, -1.0, 4)
     model.close()
+
+
+def test_edge_cases_of_the_streaming_and_sign_calls():
+    _say("refit with nothing dirty, empty sign and count calls")
+    wl, cells, dt, p0, _, _ = _setup()
+    model = _model(wl, cells, "fp32")
+    P0 = torch.from_numpy(p0).cuda()
+    model.fit(P0)
+    before = {k: v.clone() for k, v in model.query(torch.from_numpy(wl.queries).cuda()).items()}
+    dirty = torch.zeros(cells.n, dtype=torch.float32, device="cuda")
+    qcount = torch.ones(cells.n, dtype=torch.float32, device="cuda")
+    sel, n = model.refit(P0, dirty, qcount, 0.5, 8)
+    after = model.query(torch.from_numpy(wl.queries).cuda())
+    torch.cuda.synchronize()
+    assert int(n.item()) == 0 and float(qcount.sum()) == cells.n
+    for k in before:
+        assert torch.equal(before[k], after[k])
+    model.count_queries(torch.zeros(0, dtype=torch.int32, device="cuda"), qcount, cap=0.5)
+    torch.cuda.synchronize()
+    assert float(qcount.max()) == 0.5   # the cap alone applies
+    b = scenes.bhm_weights(wl)
+    s = ksdf.bhm_sign(torch.zeros(0, 3, dtype=torch.float32, device="cuda"), b["origin"], b["box"],
+                      b["dims"], b["hinges"], b["gamma"], torch.from_numpy(b["box_bhm"]).cuda(),
+                      torch.from_numpy(b["weights"]).cuda())
+    assert s.numel() == 0
+    model.close()
