@@ -158,7 +158,16 @@ void ksdf_model_destroy(ksdf_model* model);
  *   evaluated (no lower-bound pruning), which can change which near-tied cells are
  *   re-evaluated in FP64: outputs agree within the parity tolerance, not
  *   always bit for bit.  Applies to the two-kernel query when Q * (8 or 16) < 2^31;
- *   the workspace grows by about 24 bytes per (query, candidate). */
+ *   the workspace grows by about 24 bytes per (query, candidate).
+ * query_mfma: the second kernel of the two-kernel query (wave-shared cells) forms
+ *   |L^{-1} k*|^2 of the GP variance on the matrix cores from a dense per-cell L^{-1},
+ *   instead of by forward substitution.  Applies to FP32 models with m <= 64 (else
+ *   ignored).  Setting it allocates the dense factors (16 KiB per cell, held until the
+ *   model is destroyed; KSDF_ERR_OUT_OF_MEMORY if that fails, the model unchanged);
+ *   while it is on, each fit and refit also forms them, and the first query after it
+ *   is turned on forms them if they are stale.  var_f then differs from the other
+ *   launch shapes in the last bits (a different summation order); every other output
+ *   is identical. */
 typedef struct ksdf_tuning {
   int query_sub;
   int query_block;
@@ -168,6 +177,7 @@ typedef struct ksdf_tuning {
   int query_lanes;
   int backward_lanes;
   int query_pairs;
+  int query_mfma;
 } ksdf_tuning;
 int ksdf_model_set_tuning(ksdf_model* model, const ksdf_tuning* tuning);
 int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);

@@ -60,7 +60,7 @@ int dalloc(ksdf_model* m, T** p, size_t n) {
 void free_model(ksdf_model* m) {
   if (!m) return;
   void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
-                  m->L32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
+                  m->L32, m->Linv32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
                   m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list, m->index.box_rank};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -410,9 +410,18 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
       (t->fused != 0 && t->fused != 1) ||
       (t->fit_min_bucket != 16 && t->fit_min_bucket != 32 && t->fit_min_bucket != 64) ||
       (t->query_split != 0 && t->query_split != 1) || (t->query_lanes != 0 && t->query_lanes != 1) ||
-      (t->backward_lanes != 0 && t->backward_lanes != 1) || (t->query_pairs != 0 && t->query_pairs != 1)) {
+      (t->backward_lanes != 0 && t->backward_lanes != 1) || (t->query_pairs != 0 && t->query_pairs != 1) ||
+      (t->query_mfma != 0 && t->query_mfma != 1)) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  // the dense L^{-1} of the matrix-core pass 2, allocated when first asked for
+  if (t->query_mfma && !m->Linv32 && m->precision == KSDF_FP32 && m->max_m <= 64 && m->n_cells > 0) {
+    int r = check_device(m);
+    if (r) return r;
+    r = dalloc(m, &m->Linv32, 4096L * m->n_cells);   // on failure the model is unchanged
+    if (r) return r;
+    m->linv_ok = false;
   }
   m->tuning = *t;
   if (m->tuning.query_block == 0) m->tuning.query_block = 256;

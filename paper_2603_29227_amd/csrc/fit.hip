@@ -122,7 +122,52 @@ __global__ void __launch_bounds__(256) cap_kernel(float* qcount, int n, float ca
   if (c < n) qcount[c] = fminf(qcount[c], cap);
 }
 
+// Dense L^{-1} of each cell (64 x 64, column-major, zero beyond m) from the packed
+// factor rows with reciprocal diagonal: lane j solves L x = e_j by forward
+// substitution, x_i = -(sum_{k<i} L_ik x_k) / L_ii (x_k = 0 for k < j), x_j = 1 / L_jj,
+// with its column in registers and the factor rows read once per wave (uniform
+// loads); each lane stores its column as 16-byte pieces (no LDS, so that occupancy
+// is set by the registers alone).
+__global__ void __launch_bounds__(64) linv_kernel(const int* offsets, const long* loff,
+                                                  const float* L, float* Linv) {
+  const int c = blockIdx.x, j = threadIdx.x;
+  const int m = offsets[c + 1] - offsets[c];
+  const float* Lc = L + loff[c];
+  float x[64];
+#pragma unroll
+  for (int i = 0; i < 64; ++i) {
+    float xi = 0.f;
+    if (i < m) {
+      const float* row = Lc + i * (i + 1) / 2;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+      for (int k = 0; k + 3 < i; k += 4) {
+        a0 = fmaf(row[k], x[k], a0);
+        a1 = fmaf(row[k + 1], x[k + 1], a1);
+        a2 = fmaf(row[k + 2], x[k + 2], a2);
+        a3 = fmaf(row[k + 3], x[k + 3], a3);
+      }
+#pragma unroll
+      for (int k = i & ~3; k < i; ++k) a0 = fmaf(row[k], x[k], a0);
+      const float r = row[i];
+      xi = j == i ? r : (j < i ? -((a0 + a1) + (a2 + a3)) * r : 0.f);
+    }
+    x[i] = xi;
+  }
+  float4* out = reinterpret_cast<float4*>(Linv + (long)c * 4096 + (long)j * 64);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[i] = make_float4(x[4 * i], x[4 * i + 1], x[4 * i + 2], x[4 * i + 3]);
+}
+
 }  // namespace
+
+void launch_linv(const ksdf_model* m, hipStream_t s) {
+  m->linv_ok = false;
+  if (!m->Linv32 || !m->tuning.query_mfma || m->n_cells == 0) return;
+  hipLaunchKernelGGL(linv_kernel, dim3((unsigned)m->n_cells), dim3(64), 0, s, m->offsets, m->loff,
+                     m->L32, m->Linv32);
+  m->linv_ok = true;
+}
 
 size_t refit_workspace_bytes(const ksdf_model* m, int budget) {
   const long b = std::min(budget, m->n_cells);
@@ -185,6 +230,7 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
                        A);
   }
   timer_mark(m, KSDF_TIMER_FIT, 1, s);
+  if (m->precision != KSDF_FP64) launch_linv(m, s);
   hipLaunchKernelGGL(refit_reset_kernel, dim3(gb), dim3(256), 0, s, sel, n_sel, dirty, qcount);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
@@ -235,6 +281,7 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
     const int grid = m->n_cells < 2048 ? m->n_cells : 2048;
     hipLaunchKernelGGL(fit64_kernel, dim3(grid), dim3(FIT_THREADS), 0, s, A);
     timer_mark(m, KSDF_TIMER_FIT, 1, s);
+    launch_linv(m, s);
   }
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;

@@ -120,6 +120,7 @@ int launch_fused_t(ksdf_model* m, FitArgs& F, FastArgs& A, FusedCtl& C, hipStrea
   timer_mark(m, KSDF_TIMER_FUSED, 0, s);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(FT), smem, s, F, A, C);
   timer_mark(m, KSDF_TIMER_FUSED, 1, s);
+  launch_linv(m, s);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

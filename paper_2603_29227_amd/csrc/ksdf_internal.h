@@ -80,6 +80,8 @@ struct ksdf_model {
   float* plo32 = nullptr;       // [nnz,4] float-float low parts of ps32
   float* sv32 = nullptr;        // [nnz] sample variance sigma_i^2
   float* L32 = nullptr;         // packed rows of L; diagonal holds 1/L_jj
+  float* Linv32 = nullptr;      // [n,64,64] dense L^{-1}, column-major, zero-padded (max m <= 64)
+  mutable bool linv_ok = false; // Linv32 holds the inverse of the current L32
   float* box32 = nullptr;       // [n,8] sample AABB lo xyz, A+ (sum of positive a), hi xyz, pad
   float* cond32 = nullptr;      // [n] condition estimate (FP32 factor)
   int* fb_list = nullptr;       // [n] cells to refit in FP64
@@ -105,7 +107,7 @@ struct ksdf_model {
   int bucket_start[5] = {0, 0, 0, 0, 0};
 
   ksdf::CandidateIndex index;
-  ksdf_tuning tuning{0, 256, 1, 16, 1, 0, 0, 0};
+  ksdf_tuning tuning{0, 256, 1, 16, 1, 0, 0, 0, 0};
   // kernel timing: one event pair per phase, recorded when timing is on
   bool timing = false;
   hipEvent_t tev[KSDF_TIMER_COUNT][KSDF_TIMER_SLOTS][2] = {};
@@ -127,6 +129,10 @@ namespace ksdf {
 // launchers (each returns KSDF_OK or an error after setting the message)
 int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint8_t* user_status,
                hipStream_t s);
+// dense L^{-1} per cell from the FP32 store's factor, for the matrix-core pass 2:
+// computed after each fit while query_mfma is on, else marked stale (and then
+// computed by the first query that needs it)
+void launch_linv(const ksdf_model* m, hipStream_t s);
 int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
 // sign from BHM weights
 size_t bhm_tau_workspace_bytes(long K);

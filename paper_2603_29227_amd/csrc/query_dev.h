@@ -31,6 +31,7 @@ struct FastArgs {
   const float4* __restrict__ plo;   // float-float low parts of (px, py, pz, a)
   const float* __restrict__ sv;
   const float* __restrict__ L;
+  const float* __restrict__ Linv;   // [n,64,64] dense L^{-1} (column-major) or null
   const float4* __restrict__ centre;
   const float* __restrict__ box;    // [n,8]: lo xyz, A+, hi xyz, pad
   float origin[3];
@@ -613,9 +614,45 @@ __device__ __forceinline__ float3 grad_var_cell(const FastArgs& A, int b, int m,
   return make_float3(r0, r1, r2);
 }
 
+// |L^{-1} k|^2 of the GP variance for the 64 lanes at once on the matrix cores:
+// V = L^{-1} K with K's columns the lanes' kernel vectors v (zero beyond m, and for
+// lanes that do not use this cell), then each column's squared norm.  The 64 x 64
+// product runs as 2 x 2 tiles of v_mfma_f32_32x32x2f32 (the row tile of rows 0-31
+// needs only k < 32, L^{-1} being lower triangular): lane l supplies A[l mod 32][l div 32]
+// = L^{-1}[row][2t + l div 32] and B[l div 32][l mod 32] = K[2t + l div 32][query], and
+// receives D[8 (r div 4) + 4 (l div 32) + r mod 4][l mod 32] in register r.  The B
+// operand of a k-step comes from the lane's own column or from the other half-wave's
+// (one swap of the half-waves per k-step).
+typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
+__device__ __forceinline__ float mfma_vv(const float* __restrict__ Li, const float (&v)[64]) {
+  const int l = threadIdx.x & 63, hi = l >> 5, col = l & 31;
+  float res0 = 0.f, res1 = 0.f;
+#pragma unroll 1
+  for (int C = 0; C < 2; ++C) {   // query columns 32 C .. 32 C + 31 (one tile pair live)
+    mfma_acc16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const float x = hi ? v[2 * t] : v[2 * t + 1];
+      const float y = __shfl_xor(x, 32, 64);
+      const float bop = C == 0 ? (hi ? y : v[2 * t]) : (hi ? v[2 * t + 1] : y);
+      const float* colp = Li + (2 * t + hi) * 64;
+      if (t < 16) acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(colp[col], bop, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(colp[32 + col], bop, acc1, 0, 0, 0);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s = fmaf(acc0[r], acc0[r], fmaf(acc1[r], acc1[r], s));
+    s += __shfl_xor(s, 32, 64);
+    if (C == 0) res0 = s;
+    else res1 = s;
+  }
+  return hi ? res1 : res0;
+}
+
 // The argmin cell's outputs (gradient, GP variance, softmin variance) and every
-// output of the query; all lanes of the wave call it together.
-template <int MB, bool LANE = false>
+// output of the query; all lanes of the wave call it together.  MF (wave-shared cells,
+// MB = 64): the GP variance's L^{-1} k on the matrix cores (mfma_vv).
+template <int MB, bool LANE = false, bool MF = false>
 __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1) {
   const bool active = (p1.flags & 2) != 0, outside = (p1.flags & 1) != 0;
   const long qi = p1.qi;
@@ -658,11 +695,16 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
     const bool farl = ll > A.far2;
     const float k0 = c2 * (bref - ll);
     const float tx = 2.f * c2 * lx, ty = 2.f * c2 * ly, tz = 2.f * c2 * lz;
+    static_assert(!MF || (MB == 64 && !LANE), "the matrix-core GP variance needs m <= 64");
+    float v[MB];
+    if constexpr (MF) {
+#pragma unroll
+      for (int i = 0; i < MB; ++i) v[i] = 0.f;
+    }
     if (mine) {
       // samples per load group: 8 through scalar registers, 2 when each lane loads
       // its own cell into vector registers
       constexpr int CHP = LANE ? 2 : CH;
-      float v[MB];
       float S = 0.f, T1 = 0.f, X0 = 0.f, X1 = 0.f, X2 = 0.f;
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
@@ -703,7 +745,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
           }
         }
       }
-      vv = forward_subst<MB, LANE ? 16 : 32>(Lc, m, v);
+      if constexpr (!MF) vv = forward_subst<MB, LANE ? 16 : 32>(Lc, m, v);
       const float Tb = 1.f + T1 / S;
       var = (Tb * Tb * X0 - 2.f * Tb * X1 + X2) / (S * S);
       w0 = a0;
@@ -716,6 +758,10 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
         gv2 = g.z;
       }
       todo = false;
+    }
+    if constexpr (MF) {
+      const float vm = mfma_vv(A.Linv + 4096L * c, v);
+      if (mine) vv = vm;
     }
   }
 
@@ -943,6 +989,7 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   A.plo = reinterpret_cast<const float4*>(m->plo32);
   A.sv = m->sv32;
   A.L = m->L32;
+  A.Linv = m->Linv32;
   A.centre = reinterpret_cast<const float4*>(m->centre32);
   A.box = m->box32;
   for (int d = 0; d < 3; ++d) {

@@ -35,13 +35,13 @@ __global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, lo
   if (active) rec2[pos] = r;
 }
 
-template <int MB, int NT, bool LANE>
+template <int MB, int NT, bool LANE, bool MF = false>
 __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   Pass1 r{};
   r.bc = -1;
   if (sq < A.Q) r = rec2[sq];
-  query_finish<MB, LANE>(A, r);
+  query_finish<MB, LANE, MF>(A, r);
 }
 
 template <int NT, bool LANE>
@@ -59,6 +59,13 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* 
   hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum, cursor);
   hipLaunchKernelGGL(query_regroup_kernel, dim3((unsigned)((A.Q + 255) / 256)), dim3(256), 0, s, rec,
                      A.Q, m->n_cells, cursor, rec2);
+  if constexpr (!LANE) {
+    if (m->tuning.query_mfma && m->Linv32 && m->max_m <= 64) {
+      if (!m->linv_ok) launch_linv(m, s);
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
+      return;
+    }
+  }
   if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
   else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
 }

@@ -53,7 +53,7 @@ class Tuning(ctypes.Structure):
                 ("fused", ctypes.c_int), ("fit_min_bucket", ctypes.c_int),
                 ("query_split", ctypes.c_int), ("query_lanes", ctypes.c_int),
                 ("backward_lanes", ctypes.c_int),
-                ("query_pairs", ctypes.c_int)]
+                ("query_pairs", ctypes.c_int), ("query_mfma", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -28,8 +28,9 @@ import torch
 from .ksdf import FP64
 
 KNOBS = dict(query_sub=(1, 2, 4), query_block=(64, 256), fused=(0, 1), fit_min_bucket=(16, 32, 64),
-             query_split=(0, 1), query_lanes=(0, 1), backward_lanes=(0, 1), query_pairs=(0, 1))
-QUERY_KNOBS = ("query_sub", "query_block", "query_split", "query_lanes", "query_pairs")
+             query_split=(0, 1), query_lanes=(0, 1), backward_lanes=(0, 1), query_pairs=(0, 1), query_mfma=(0, 1))
+QUERY_KNOBS = ("query_sub", "query_block", "query_split", "query_lanes", "query_pairs",
+               "query_mfma")
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned.json")
 
 
@@ -103,6 +104,9 @@ def _valid(t: dict, fp64: bool) -> bool:
     if t.get("query_pairs", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or
                                          t.get("fused", 0) == 1):
         return False   # pairs apply to the two-kernel FP32 query
+    if t.get("query_mfma", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or
+                                        t.get("query_lanes", 0) == 1 or t.get("fused", 0) == 1):
+        return False   # the matrix-core pass 2 needs wave-shared cells in the two-kernel query
     return True
 
 
@@ -130,7 +134,7 @@ def tune(model, points: torch.Tensor, queries: torch.Tensor, sign=None, reps: in
     fastest.  Returns {"tuning", "ms", "table"}."""
     out = model._out(len(queries), queries.device)
     keys = ["query_sub", "query_block", "fused", "fit_min_bucket", "query_split", "query_lanes",
-            "query_pairs"]
+            "query_pairs", "query_mfma"]
     best, ms, table = _search(model, keys, lambda: model.fit_query(points, queries, sign, out=out),
                               reps, log)
     _store(cache_path, signature(model, len(queries)), best, ms)

@@ -198,13 +198,59 @@ def test_query_pairs_matches_wave_walk_and_oracle(tuning):
     model.close()
 
 
+@pytest.mark.parametrize("block", [64, 256])
+def test_query_mfma_gp_variance(block):
+    """The matrix-core GP variance (query_mfma) changes only var_f, within the parity
+    tolerance of the forward substitution it replaces."""
+    _say(f"query_mfma block {block}")
+    wl = scenes.small_room_workload(n_queries=12000, cfg_id=46)
+    model, cells = _model(wl)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    model.set_tuning(fused=0, query_split=1, query_block=block, query_mfma=0)
+    model.fit(P)
+    base = _clone(model.query(q, sg, grad_var=True))
+    model.set_tuning(query_mfma=1)
+    b = model.query(q, sg, grad_var=True)
+    again = model.query(q, sg, grad_var=True)
+    torch.cuda.synchronize()
+    _equal(b, again, keys=("mean", "grad", "var", "var_f", "grad_var", "argmin", "status"))
+    _equal(b, base, keys=("mean", "grad", "var", "grad_var", "argmin", "status"))
+    d = (b["var_f"] - base["var_f"]).abs().max().item()
+    print(f"query_mfma: max |var_f difference| {d:.3g}", flush=True)
+    assert d <= 1e-4
+    oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
+                      np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+                     sign=wl.sign, all_candidates=True)
+    assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
+                  label=f"query_mfma {block}")
+    # a fit with the knob on, and the fused launch, keep the dense L^{-1} current
+    for fused in (0, 1):
+        model.set_tuning(fused=fused, query_split=1 - fused, query_mfma=0)
+        model.fit(P * 1.001)               # a different factor, left stale
+        model.set_tuning(query_mfma=1)
+        if fused:
+            model.fit_query(P, q, sg)
+        else:
+            model.fit(P)
+        model.set_tuning(fused=0, query_split=1, query_mfma=1)
+        c = model.query(q, sg, grad_var=True)
+        torch.cuda.synchronize()
+        _equal(c, b, keys=("mean", "grad", "var", "var_f", "grad_var", "argmin", "status"))
+    model.close()
+
+
 def test_tuning_rejects_invalid_values():
     _say("tuning validation")
     wl = scenes.sphere_workload(n_queries=16)
     model, _ = _model(wl, precision="fp64")
     for bad in (dict(query_sub=3), dict(query_block=128), dict(fused=2), dict(fit_min_bucket=8),
                 dict(query_split=2), dict(query_lanes=2), dict(backward_lanes=-1),
-                dict(query_pairs=3)):
+                dict(query_pairs=3), dict(query_mfma=2)):
         with pytest.raises(ksdf.KsdfError):
             model.set_tuning(**bad)
     model.close()

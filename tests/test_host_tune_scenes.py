@@ -9,7 +9,7 @@ from paper_2603_29227_amd import scenes, tune
 
 def test_tuner_candidate_rules():
     base = dict(query_sub=2, query_block=64, fused=0, fit_min_bucket=16, query_split=1,
-                query_lanes=0, query_pairs=0)
+                query_lanes=0, query_pairs=0, query_mfma=0)
     assert tune._valid(base, fp64=False)
     assert not tune._valid({**base, "query_split": 0, "query_lanes": 1}, fp64=False)
     assert not tune._valid({**base, "fused": 1}, fp64=False)          # split + fused
@@ -18,9 +18,14 @@ def test_tuner_candidate_rules():
     assert not tune._valid({**base, "query_pairs": 1}, fp64=True)
     assert not tune._valid({**base, "query_split": 0, "fit_min_bucket": 32}, fp64=True)
     assert tune._valid({**base, "query_split": 0}, fp64=True)
+    assert tune._valid({**base, "query_mfma": 1}, fp64=False)
+    assert not tune._valid({**base, "query_mfma": 1, "query_split": 0}, fp64=False)
+    assert not tune._valid({**base, "query_mfma": 1, "query_lanes": 1}, fp64=False)
+    assert not tune._valid({**base, "query_mfma": 1}, fp64=True)
     # every knob the C struct accepts is searched
     assert set(tune.KNOBS) == {"query_sub", "query_block", "fused", "fit_min_bucket",
-                               "query_split", "query_lanes", "backward_lanes", "query_pairs"}
+                               "query_split", "query_lanes", "backward_lanes", "query_pairs",
+                               "query_mfma"}
 
 
 def test_tuner_cache_round_trip(tmp_path):
