@@ -229,8 +229,8 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
     hipLaunchKernelGGL(fit64_kernel, dim3((unsigned)std::min(budget, 2048)), dim3(FIT_THREADS), 0, s,
                        A);
   }
-  timer_mark(m, KSDF_TIMER_FIT, 1, s);
   if (m->precision != KSDF_FP64) launch_linv(m, s);
+  timer_mark(m, KSDF_TIMER_FIT, 1, s);
   hipLaunchKernelGGL(refit_reset_kernel, dim3(gb), dim3(256), 0, s, sel, n_sel, dirty, qcount);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
@@ -280,8 +280,8 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
     A.emit32 = 1;
     const int grid = m->n_cells < 2048 ? m->n_cells : 2048;
     hipLaunchKernelGGL(fit64_kernel, dim3(grid), dim3(FIT_THREADS), 0, s, A);
-    timer_mark(m, KSDF_TIMER_FIT, 1, s);
     launch_linv(m, s);
+    timer_mark(m, KSDF_TIMER_FIT, 1, s);
   }
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;

@@ -119,8 +119,8 @@ int launch_fused_t(ksdf_model* m, FitArgs& F, FastArgs& A, FusedCtl& C, hipStrea
   if (grid < 1) grid = 1;
   timer_mark(m, KSDF_TIMER_FUSED, 0, s);
   hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(FT), smem, s, F, A, C);
-  timer_mark(m, KSDF_TIMER_FUSED, 1, s);
   launch_linv(m, s);
+  timer_mark(m, KSDF_TIMER_FUSED, 1, s);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }
