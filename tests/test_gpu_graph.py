@@ -37,10 +37,13 @@ def _clone(d):
     return {k: v.clone() for k, v in d.items()}
 
 
-def test_graph_fit_query_backward_replays_match_eager():
-    _say("graph: fit + query + backward, 3 replays with eager work between")
+@pytest.mark.parametrize("mfma", [0, 1])
+def test_graph_fit_query_backward_replays_match_eager(mfma):
+    _say(f"graph: fit + query + backward, 3 replays with eager work between, query_mfma={mfma}")
     wl = scenes.small_room_workload(n_queries=20000, cfg_id=41, uneven=True)
     model, _ = _model(wl, adjoint=True)
+    if mfma:   # the two-kernel query with the matrix-core pass 2 (its inverse formed by the fit)
+        model.set_tuning(fused=0, query_split=1, query_block=64, query_mfma=1)
     dev = torch.device("cuda")
     P = torch.from_numpy(wl.points).to(dev, torch.float32)
     q = torch.from_numpy(wl.queries).to(dev, torch.float32)
