@@ -161,8 +161,8 @@ void ksdf_model_destroy(ksdf_model* model);
  *   the workspace grows by about 24 bytes per (query, candidate).
  * query_mfma: the second kernel of the two-kernel query (wave-shared cells) forms
  *   |L^{-1} k*|^2 of the GP variance on the matrix cores from a dense per-cell L^{-1},
- *   instead of by forward substitution.  Applies to FP32 models with m <= 64 (else
- *   ignored).  Setting it allocates the dense factors (16 KiB per cell, held until the
+ *   instead of by forward substitution.  Applies to FP32 RBF models with m <= 64
+ *   (else ignored).  Setting it allocates the dense factors (16 KiB per cell, held until the
  *   model is destroyed; KSDF_ERR_OUT_OF_MEMORY if that fails, the model unchanged);
  *   while it is on, each fit and refit also forms them, and the first query after it
  *   is turned on forms them if they are stale.  var_f then differs from the other

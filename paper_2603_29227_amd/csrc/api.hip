@@ -415,8 +415,10 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
-  // the dense L^{-1} of the matrix-core pass 2, allocated when first asked for
-  if (t->query_mfma && !m->Linv32 && m->precision == KSDF_FP32 && m->max_m <= 64 && m->n_cells > 0) {
+  // the dense L^{-1} of the matrix-core pass 2 (two-kernel RBF query of an FP32 model),
+  // allocated when first asked for
+  if (t->query_mfma && !m->Linv32 && m->precision == KSDF_FP32 && m->kernel == KSDF_KERNEL_RBF &&
+      m->max_m <= 64 && m->n_cells > 0) {
     int r = check_device(m);
     if (r) return r;
     r = dalloc(m, &m->Linv32, 4096L * m->n_cells);   // on failure the model is unchanged

@@ -80,6 +80,13 @@ def test_matern_fit_query_and_limits():
     torch.cuda.synchronize()
     for k in a:
         assert torch.equal(a[k], b[k]), f"fit_query and fit + query differ in {k}"
+    # the matrix-core option of the RBF two-kernel query leaves a Matern model alone
+    model.set_tuning(fused=0, query_split=1, query_block=64, query_mfma=1)
+    model.fit(pts)
+    c = model.query(q, sg)
+    torch.cuda.synchronize()
+    for k in a:
+        assert torch.equal(a[k], c[k]), f"query_mfma changed the Matern {k}"
     # a model fitted without the adjoint flag has no backward
     with pytest.raises(ksdf.KsdfError):
         model.backward(q, sg, torch.ones_like(b["mean"]))
