@@ -125,6 +125,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the cached tuning, do not time")
     ap.add_argument("--tune-cache", default=None, help="write the autotuner's choice to this cache")
     ap.add_argument("--no-graph", action="store_true", help="skip the graph-replay leg")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the trajectory query and backward after the grid query on one "
+                         "stream instead of beside it on a second stream")
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a plain 1 GiB copy (scale for the HBM byte counters)")
     ap.add_argument("--cpu-queries", type=int, default=1 << 20)
@@ -203,20 +206,54 @@ def main():
     fused = t_grid["fused"] == 1
     cst = torch.zeros(cells.n, dtype=torch.uint8, device=dev)
     grads = {}
+    # The trajectory query and backward need only the fit: unless the fit and the grid
+    # query are one fused launch, they run on a second stream (default priority) beside
+    # the grid query, with their own workspace, and join before the step ends.
+    overlap = not fused and not args.serial
+    traj_stream = torch.cuda.Stream()
+    traj_ws = model.new_workspace(QT)
 
-    def step():
-        model.set_tuning(**t_grid)
-        model.fit_query(pts, q, sg, cell_status=cst, out=out)
+    def traj_part(ws=None):
         model.set_tuning(**t_traj)
-        model.query(tq, tsg, out=tout)
+        model.query(tq, tsg, out=tout, workspace=ws)
         cotangents()
         model.set_tuning(**t_bwd)
         grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
-                                                         argmin=tout["argmin"])
+                                                         argmin=tout["argmin"], workspace=ws)
+
+    def step(mark=None, serial=not overlap):
+        main = torch.cuda.current_stream()
+        model.set_tuning(**t_grid)
+        if serial:
+            model.fit_query(pts, q, sg, cell_status=cst, out=out)
+            if mark is not None:
+                mark.record(main)
+            traj_part()
+            return
+        model.fit(pts, cell_status=cst)
+        traj_stream.wait_stream(main)
+        with torch.cuda.stream(traj_stream):
+            traj_part(traj_ws)
+        model.set_tuning(**t_grid)
+        model.query(q, sg, out=out)
+        if mark is not None:
+            mark.record(main)
+        main.wait_stream(traj_stream)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if overlap:
+        # the two-stream step must give the serial step's results bit for bit
+        step(serial=True)
+        torch.cuda.synchronize()
+        ref = [t.clone() for t in (*out.values(), *tout.values(), grads["points"], grads["hyper"])]
+        step()
+        torch.cuda.synchronize()
+        got = (*out.values(), *tout.values(), grads["points"], grads["hyper"])
+        if not all(torch.equal(a, b) for a, b in zip(ref, got)):
+            raise RuntimeError("the two-stream step differs from the serial step")
+        del ref
     if args.copy_calib:
         copy_calibration(torch, dev)
 
@@ -230,34 +267,48 @@ def main():
     t_start = time.perf_counter()
     for _ in range(args.steps):
         ev[0].record(stream)
-        model.set_tuning(**t_grid)
-        model.fit_query(pts, q, sg, cell_status=cst, out=out)
-        ev[1].record(stream)
-        model.set_tuning(**t_traj)
-        model.query(tq, tsg, out=tout)
-        cotangents()
-        model.set_tuning(**t_bwd)
-        grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
-                                                         argmin=tout["argmin"])
+        step(mark=ev[1])
         ev[2].record(stream)
         ev[2].synchronize()
         step_ms.append(ev[0].elapsed_time(ev[2]))
         fwd_ms.append(ev[0].elapsed_time(ev[1]))
         for k in ["fused"] if fused else ["fit"]:
             kern[k] += model.timer_read(k)
-        qt = model.timer_read("query")   # grid (when not fused), then trajectory
+        # query launches in launch order: grid then trajectory, or the reverse when the
+        # trajectory part is issued first on its own stream (fused: trajectory only)
+        qt = model.timer_read("query")
+        bt = model.timer_read("backward")
         if not fused:
-            kern["query"].append(qt[0])
-        kern["query_traj"].append(qt[-1])
-        kern["backward"] += model.timer_read("backward")
+            kern["query"].append(qt[-1] if overlap else qt[0])
+        if not overlap:   # beside the grid query these spans include waiting for it
+            kern["query_traj"].append(qt[-1])
+            kern["backward"] += bt
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t_start) / args.steps * 1e3
+    # the trajectory query + backward alone, on one stream (beside the grid query its
+    # time is hidden in the step, and its kernels' spans include waiting): the
+    # trajectory part's time and its kernels' times
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    traj_list, qt, bt = [], [], []
+    for _ in range(args.steps):
+        e0.record(stream)
+        traj_part()
+        e1.record(stream)
+        e1.synchronize()
+        traj_list.append(e0.elapsed_time(e1))
+        qt += model.timer_read("query")
+        bt += model.timer_read("backward")
+    traj_ms = float(np.mean(traj_list))
+    if overlap:
+        kern["query_traj"], kern["backward"] = qt, bt
     model.set_timing(False)
     step_avg = float(np.mean(step_ms))
     kavg = {k: float(np.mean(v)) for k, v in kern.items() if v}
     n_fp64 = int(((cst.cpu().numpy() & ksdf.C_FP64) != 0).sum())
     st = out["status"].cpu().numpy()
-    log(f"step {step_avg:.3f} ms (wall {wall:.3f}), grid fit+query {np.mean(fwd_ms):.3f} ms, "
+    log(f"step {step_avg:.3f} ms (wall {wall:.3f}; trajectory part beside the grid query: "
+        f"{overlap}), grid fit+query {np.mean(fwd_ms):.3f} ms, trajectory part alone "
+        f"{traj_ms:.3f} ms, "
         f"kernels {kavg}, fp64 cells {n_fp64}")
 
     # graph-replayed step (same work, launches captured once)
@@ -387,9 +438,11 @@ def main():
                                f"{args.grid}^3 grid queries + backward of the softplus collision "
                                f"cost at 4096 x 64 trajectory points", "grid_queries": Q,
                    "trajectory_points": QT, "k_fuse": k_fuse, "ell": wl.ell,
-                   "noise_var": wl.noise_var, "tuning": tuned},
+                   "noise_var": wl.noise_var, "tuning": tuned,
+                   "streams": 2 if overlap else 1},
         "fwd_qps": round(Q / (np.mean(fwd_ms) * 1e-3), 1),
-        "bwd_qps": round(QT / ((step_avg - np.mean(fwd_ms)) * 1e-3), 1),
+        "bwd_qps": round(QT / (traj_ms * 1e-3), 1),
+        "trajectory_part_ms": round(traj_ms, 4),
         "kernel_ms": {k: round(v, 4) for k, v in kavg.items()},
         "graph_ms_per_step": graph,
         "fp64_cells": n_fp64, "no_valid_queries": int(((st & 1) != 0).sum()),
@@ -428,7 +481,7 @@ def main():
         plain_step(pe)
         torch.cuda.synchronize()
         pf, pb = pe[0].elapsed_time(pe[1]), pe[1].elapsed_time(pe[2])
-        ours_b = step_avg - float(np.mean(fwd_ms))
+        ours_b = traj_ms
         result["plain_fp64"] = {"fit_query_ms": round(pf, 3), "traj_query_backward_ms": round(pb, 3),
                                 "step_ms": round(pf + pb, 3),
                                 "value": round((Q + QT) / ((pf + pb) * 1e-3), 1),

@@ -331,16 +331,28 @@ class Model:
         self.points = points
         self.sample_var = sample_var
 
-    def _workspace(self, nbytes: int):
+    def _workspace(self, nbytes: int, given: Optional[torch.Tensor] = None):
+        if given is not None:
+            # caller-owned scratch, e.g. one per stream for calls that run concurrently
+            if given.dtype != torch.uint8 or not given.is_cuda or given.numel() < nbytes:
+                raise ValueError(f"workspace must be a uint8 CUDA tensor of at least {nbytes} bytes")
+            return given
         if nbytes == 0:
             return None
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self._ws
 
+    def new_workspace(self, Q: int) -> torch.Tensor:
+        """Scratch for query() and backward() of up to Q points.  Calls on several
+        streams at once each need their own (by default every call shares one)."""
+        nb = max(self._lib.ksdf_query_workspace_bytes(self._h, Q),
+                 self._lib.ksdf_backward_workspace_bytes(self._h, Q), 1)
+        return torch.empty(nb, dtype=torch.uint8, device=self.device)
+
     def query(self, points: torch.Tensor, sign: Optional[torch.Tensor] = None, var_f=True,
               argmin=True, status=True, grad_var=False, out: Optional[dict] = None,
-              stream=None) -> dict:
+              stream=None, workspace: Optional[torch.Tensor] = None) -> dict:
         """Per-query outputs: mean, grad [Q,3], var, and optionally var_f, argmin, status
         and grad_var [Q,3] (the variance of each gradient component, App. C)."""
         if points.dtype != self.dtype or not points.is_cuda or not points.is_contiguous() \
@@ -352,7 +364,7 @@ class Model:
         if out is None:
             out = self._out(Q, points.device, var_f, argmin, status, grad_var)
         nb = self._lib.ksdf_query_workspace_bytes(self._h, Q)
-        ws = self._workspace(nb)
+        ws = self._workspace(nb, workspace)
         _check(self._lib.ksdf_query(self._h, _ptr(points), Q, _ptr(sign), _ptr(out["mean"]),
                                     _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
                                     _ptr(out.get("grad_var")), _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
@@ -398,13 +410,13 @@ class Model:
         return out
 
     def backward(self, points, sign, d_mean, d_grad=None, d_var=None, d_var_f=None, argmin=None,
-                 stream=None):
+                 stream=None, workspace: Optional[torch.Tensor] = None):
         """VJP: (d_points [Q,3], d_hyper [2] float64 = dL/d(ell, noise_var))."""
         Q = len(points)
         d_points = torch.empty(Q, 3, dtype=self.dtype, device=points.device)
         d_hyper = torch.empty(2, dtype=torch.float64, device=points.device)
         nb = self._lib.ksdf_backward_workspace_bytes(self._h, Q)
-        ws = self._workspace(nb)
+        ws = self._workspace(nb, workspace)
         c = [None if t is None else t.contiguous() for t in (d_mean, d_grad, d_var, d_var_f)]
         for t in c:
             if t is not None and t.dtype != self.dtype:

@@ -92,6 +92,44 @@ def test_graph_fit_query_backward_replays_match_eager(mfma):
     model.close()
 
 
+def test_concurrent_calls_on_two_streams_match_serial():
+    _say("query + backward on a second stream beside a grid query, own workspaces, 3 rounds")
+    wl = scenes.small_room_workload(n_queries=30000, cfg_id=43, uneven=True)
+    model, _ = _model(wl, adjoint=True)
+    dev = torch.device("cuda")
+    P = torch.from_numpy(wl.points).to(dev, torch.float32)
+    q = torch.from_numpy(wl.queries).to(dev, torch.float32)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    q2 = (q[:6000] * 0.999).contiguous()
+    sg2 = sg[:6000].contiguous()
+    dm = torch.from_numpy(np.random.default_rng(9).normal(size=len(q2))).to(dev, torch.float32)
+    model.set_tuning(fused=0, query_split=1, query_block=64, query_mfma=1)
+    model.fit(P)
+    ref = _clone(model.query(q, sg))
+    ref2 = _clone(model.query(q2, sg2))
+    rdp, rdh = model.backward(q2, sg2, dm, argmin=ref2["argmin"])
+    torch.cuda.synchronize()
+    rdp, rdh = rdp.clone(), rdh.clone()
+    with pytest.raises(ValueError):
+        model.query(q2, sg2, workspace=torch.empty(1, dtype=torch.uint8, device=dev))
+    side = torch.cuda.Stream()
+    ws2 = model.new_workspace(len(q2))
+    out, out2 = model._out(len(q), dev), model._out(len(q2), dev)
+    for rep in range(3):
+        main = torch.cuda.current_stream()
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            model.query(q2, sg2, out=out2, workspace=ws2)
+            dp, dh = model.backward(q2, sg2, dm, argmin=out2["argmin"], workspace=ws2)
+        model.query(q, sg, out=out)
+        main.wait_stream(side)
+        torch.cuda.synchronize()
+        _equal(out, ref)
+        _equal(out2, ref2)
+        assert torch.equal(dp, rdp) and torch.equal(dh, rdh), f"round {rep}: backward differs"
+    model.close()
+
+
 def test_graph_fused_fit_query_replays_match_eager():
     _say("graph: fused fit_query, 3 replays")
     wl = scenes.small_room_workload(n_queries=30000, cfg_id=42, uneven=True)
