@@ -236,7 +236,10 @@ int ksdf_fit_cells(ksdf_model* model, const void* surface_pts, int dtype, long n
  * argmin [Q] int32 cell id or NULL; q_status [Q] uint8 or NULL.  A query with no valid
  * cell gets mean = +inf, grad = 0, var = +inf, var_f = 1, grad_var = +inf.
  * workspace: device scratch of at least ksdf_query_workspace_bytes(model, Q) bytes
- * (may be NULL when that is 0).  Asynchronous; allocates nothing.
+ * (may be NULL when that is 0).  Asynchronous; allocates nothing.  The query only
+ * reads the model (except that, with the query_mfma tuning, it first forms the dense
+ * inverses when a fit made them stale), so queries and backward calls on different
+ * streams may run at once if each has its own workspace and no fit runs meanwhile.
  * ------------------------------------------------------------------------- */
 size_t ksdf_query_workspace_bytes(const ksdf_model* model, long Q);
 int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
