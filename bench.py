@@ -248,6 +248,8 @@ def main():
         step(serial=True)
         torch.cuda.synchronize()
         ref = [t.clone() for t in (*out.values(), *tout.values(), grads["points"], grads["hyper"])]
+        for t in (*out.values(), *tout.values()):
+            t.fill_(-1)   # so that an output the two-stream step leaves unwritten shows
         step()
         torch.cuda.synchronize()
         got = (*out.values(), *tout.values(), grads["points"], grads["hyper"])
