@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 GPU leg")
     ap.add_argument("--no-matern", action="store_true", help="skip the Matern 3/2 leg")
     ap.add_argument("--no-bhm", action="store_true", help="skip the BHM sign leg")
+    ap.add_argument("--no-refit", action="store_true", help="skip the streaming-refit leg")
     ap.add_argument("--no-grad-var", action="store_true",
                     help="skip timing the gradient-variance output")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -355,6 +356,46 @@ def main():
     gv_ms = gv_ms or None
     log(f"grid query without / with grad_var: {gv_ms}")
 
+    # streaming refit (App. G) on the fitted room model: the grid queries' argmin cells
+    # counted into the query counters, a tenth of the cells marked dirty (c2 in 1..3),
+    # and the training queue's highest-priority 512 cells refitted (ranking, bucketed
+    # FP32 fit with the adjoint vectors, counter reset)
+    refit = None
+    if not args.no_refit:
+        model.set_tuning(**t_grid)
+        rng = np.random.default_rng(11)
+        n_dirty = max(cells.n // 10, 1)
+        pick = torch.from_numpy(rng.choice(cells.n, n_dirty, replace=False)).long().to(dev)
+        c2 = torch.from_numpy(rng.integers(1, 4, n_dirty).astype(np.float32)).to(dev)
+        qcount = torch.zeros(cells.n, dtype=torch.float32, device=dev)
+        budget = min(512, cells.n)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        model.count_queries(out["argmin"], qcount)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(3):
+            model.count_queries(out["argmin"], qcount)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        count_ms = e0.elapsed_time(e1) / 3
+        rms = []
+        for rep_ in range(4):
+            dirty = torch.zeros(cells.n, dtype=torch.float32, device=dev)
+            dirty[pick] = c2
+            torch.cuda.synchronize()
+            e0.record(stream)
+            sel, nsel = model.refit(pts, dirty, qcount, 0.5, budget)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if rep_ > 0:
+                rms.append(e0.elapsed_time(e1))
+        if int(nsel.item()) != min(budget, n_dirty):
+            raise RuntimeError("the refit selected an unexpected number of cells")
+        refit = {"dirty_cells": n_dirty, "budget": budget, "refit_ms": round(float(np.mean(rms)), 4),
+                 "cells_per_s": round(budget / (float(np.mean(rms)) * 1e-3), 1),
+                 "count_queries_ms": round(count_ms, 4), "counted_queries": Q}
+        log(f"streaming refit: {refit}")
+
     # the Matern 3/2 variant (Table I) on the same room and grid, its own FP32 model:
     # float-float fit as for the RBF, the plain one-thread-per-query kernel in FP32
     matern = None
@@ -453,6 +494,7 @@ def main():
         "grad_var_cost": gv_ms,
         "matern32": matern,
         "bhm_sign": bhm,
+        "streaming_refit": refit,
     }
 
     if not args.no_plain:

@@ -110,11 +110,21 @@ __global__ void __launch_bounds__(256) refit_reset_kernel(const int* sel, const 
   qcount[c] = 0.5f * qcount[c];
 }
 
+// One atomic per distinct cell of a wave (queries that arrive spatially ordered mostly
+// share their argmin cell within a wave); each adds the wave's count for that cell, a
+// whole number, so the float sums are exact in any order.
 __global__ void __launch_bounds__(256) count_queries_kernel(const int* argmin, long Q, float* qcount) {
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
-  if (q >= Q) return;
-  const int c = argmin[q];
-  if (c >= 0) atomicAdd(qcount + c, 1.f);
+  const int c = q < Q ? argmin[q] : -1;
+  const int lane = threadIdx.x & 63;
+  unsigned long long todo = __ballot(c >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int key = __shfl(c, leader, 64);
+    const unsigned long long same = __ballot(c == key) & todo;
+    if (lane == leader) atomicAdd(qcount + key, (float)__popcll(same));
+    todo &= ~same;
+  }
 }
 
 __global__ void __launch_bounds__(256) cap_kernel(float* qcount, int n, float cap) {
