@@ -142,3 +142,21 @@ def test_edge_cases_of_the_streaming_and_sign_calls():
                       torch.from_numpy(b["weights"]).cuda())
     assert s.numel() == 0
     model.close()
+
+
+@pytest.mark.parametrize("Q", [1, 63, 1000, 200_003])
+def test_count_queries_shuffled_argmins_with_invalid_entries(Q):
+    _say(f"query counters on shuffled argmins with -1 entries, Q={Q}")
+    wl, cells, dt, p0, _, _ = _setup()
+    model = _model(wl, cells, "fp32")
+    rng = np.random.default_rng(Q)
+    # a few hot cells (many equal keys in a wave), the rest spread, some invalid
+    am = np.where(rng.random(Q) < 0.5, rng.integers(0, 5, Q), rng.integers(0, cells.n, Q))
+    am[rng.random(Q) < 0.1] = -1
+    am = am.astype(np.int32)
+    qcount = torch.full((cells.n,), 3.0, dtype=torch.float32, device="cuda")
+    model.count_queries(torch.from_numpy(am).cuda(), qcount, cap=1e7)
+    torch.cuda.synchronize()
+    want = 3.0 + np.bincount(am[am >= 0], minlength=cells.n)
+    assert np.array_equal(qcount.cpu().numpy(), want.astype(np.float32))
+    model.close()
