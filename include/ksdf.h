@@ -48,14 +48,16 @@ typedef enum ksdf_status {
   KSDF_ERR_HIP = -4,              /* a HIP runtime call failed (message in ksdf_last_error) */
   KSDF_ERR_DEVICE = -5,           /* no usable gfx950 device, or the model lives on another device */
   KSDF_ERR_UNSUPPORTED = -6,      /* a feature this build does not provide (e.g. m > 128) */
-  KSDF_ERR_OUT_OF_MEMORY = -7
+  KSDF_ERR_OUT_OF_MEMORY = -7,    /* kept for compatibility: the library allocates no device memory */
+  KSDF_ERR_TIMEOUT = -8           /* a fused launch's bounded wait expired (see ksdf_model_check) */
 } ksdf_status;
 
 enum { KSDF_FP64 = 0, KSDF_FP32 = 1 };           /* model precision */
 enum { KSDF_DTYPE_F32 = 0, KSDF_DTYPE_F64 = 1 };  /* element type of surface points */
 
 /* per-query status bits (uint8) */
-enum { KSDF_Q_NO_VALID_CELL = 1, KSDF_Q_CLAMPED = 2, KSDF_Q_GRAD_ZERO = 4, KSDF_Q_OUTSIDE_INDEX = 8 };
+enum { KSDF_Q_NO_VALID_CELL = 1, KSDF_Q_CLAMPED = 2, KSDF_Q_GRAD_ZERO = 4, KSDF_Q_OUTSIDE_INDEX = 8,
+       KSDF_Q_FIT_TIMEOUT = 16 /* answered by a fused launch whose wait for the fits expired */ };
 /* per-cell status bits (uint8) */
 enum { KSDF_C_FP64 = 1, KSDF_C_FAILED = 2 };
 
@@ -94,9 +96,11 @@ typedef struct ksdf_hyper {
 /* flags: KSDF_FIT_ADJOINT makes every fit also prepare the per-cell adjoint vectors
  * that ksdf_query_backward needs (xi_l = A^{-1} (dA/dl) a and xi_s = A^{-1} a);
  * KSDF_FIT_ADJOINT_VARF additionally keeps dA/dl packed per cell, needed for var_f
- * cotangents.  They must be set at ksdf_model_create (which sizes the storage) and
- * may then be dropped per fit. */
-enum { KSDF_FIT_ADJOINT = 1, KSDF_FIT_ADJOINT_VARF = 2 };
+ * cotangents.  KSDF_FIT_DENSE_INV reserves a dense L^{-1} per cell (16 KiB) for the
+ * matrix-core form of the GP variance (the query_mfma tuning; FP32 RBF models with
+ * m <= 64, else ignored).  They must be set at ksdf_model_bytes / ksdf_model_create
+ * (which size the store) and the adjoint bits may then be dropped per fit. */
+enum { KSDF_FIT_ADJOINT = 1, KSDF_FIT_ADJOINT_VARF = 2, KSDF_FIT_DENSE_INV = 4 };
 
 /* ---------------------------------------------------------------------------
  * Cell builder (host, OpenMP).  The per-octant GP training buffers of Sec. IV-B.1:
@@ -122,21 +126,42 @@ void ksdf_cellset_destroy(ksdf_cellset* cs);
 
 /* ---------------------------------------------------------------------------
  * Model: the per-cell store (gathered samples, weights a = (K+Sigma)^{-1} 1, packed
- * Cholesky factors, flags) and the candidate index for the K-nearest-cell search.
+ * Cholesky factors, flags; Sec. IV-B.1 eq. log_gp_posterior_mean) and the candidate
+ * index for the K-nearest-cell search ("the K nearest GPs", Sec. IV-B.1).
  *
- * ksdf_model_create allocates the model's device memory on the current device,
- * uploads the cell structure and builds the candidate index (it synchronises the
- * device once).  offsets/samples/keys: host int32 CSR as produced by the builder;
- * origin/h: the builder's lattice; n_points: number of surface samples the fits will
- * receive.  query_lo/query_hi (host, may be NULL): a box the queries are expected in;
- * the index covers it (queries outside still get exact answers through a slower
- * brute-force candidate scan and carry KSDF_Q_OUTSIDE_INDEX).  The model keeps the
- * hyperparameters' k_fuse and precision; ell, noise_var and alpha may change per fit.
+ * The caller owns all of the model's device memory; the library allocates none.
+ * Creating a model takes four calls:
+ *   1. ksdf_model_bytes (host, no device work): the store's size in bytes for these
+ *      arguments (0 if they are invalid; ksdf_model_create then reports why).
+ *   2. ksdf_model_create: carves the store (device, at least that many bytes, 256-byte
+ *      aligned) into the model's arrays, uploads the cell structure and runs the
+ *      index's count pass on `stream`, then synchronises that stream once.
+ *   3. ksdf_model_index_bytes: the size of the candidate lists, known after step 2.
+ *   4. ksdf_model_attach_index: hands over a device buffer of at least that many
+ *      bytes (4-byte aligned) and fills the lists on `stream` (asynchronous; calls on
+ *      other streams must wait for it).  Fits may run before this; queries,
+ *      ksdf_fit_query and the backward return KSDF_ERR_INVALID_ARGUMENT until it is done.
+ * Both buffers must stay allocated, unmodified by the caller, until the model is
+ * destroyed and its last launch has finished.  KSDF_ERR_WORKSPACE when a buffer is
+ * missing or too small.
+ * offsets/samples/keys: host int32 CSR as produced by the builder; origin/h: the
+ * builder's lattice; n_points: number of surface samples the fits will receive.
+ * query_lo/query_hi (host, may be NULL): a box the queries are expected in; the index
+ * covers it (queries outside still get exact answers through a slower brute-force
+ * candidate scan and carry KSDF_Q_OUTSIDE_INDEX).  The model keeps the
+ * hyperparameters' k_fuse, precision, kernel and flags; ell, noise_var and alpha may
+ * change per fit.  ksdf_model_destroy frees the host handle only.
  * ------------------------------------------------------------------------- */
 typedef struct ksdf_model ksdf_model;
+size_t ksdf_model_bytes(int n_cells, const int* offsets, const int* samples, const int* keys,
+                        const double origin[3], double h, long n_points, const ksdf_hyper* hyper,
+                        const double query_lo[3], const double query_hi[3]);
 int ksdf_model_create(int n_cells, const int* offsets, const int* samples, const int* keys,
                       const double origin[3], double h, long n_points, const ksdf_hyper* hyper,
-                      const double query_lo[3], const double query_hi[3], ksdf_model** out);
+                      const double query_lo[3], const double query_hi[3], void* store,
+                      size_t store_bytes, void* stream, ksdf_model** out);
+size_t ksdf_model_index_bytes(const ksdf_model* model);
+int ksdf_model_attach_index(ksdf_model* model, void* list, size_t list_bytes, void* stream);
 void ksdf_model_destroy(ksdf_model* model);
 /* Launch-shape knobs (host struct), picked per workload by the autotuner.
  * query_sub: index boxes are split into query_sub^3 sub-boxes (1, 2 or 4) for the
@@ -162,10 +187,10 @@ void ksdf_model_destroy(ksdf_model* model);
  * query_mfma: the second kernel of the two-kernel query (wave-shared cells) forms
  *   |L^{-1} k*|^2 of the GP variance on the matrix cores from a dense per-cell L^{-1},
  *   instead of by forward substitution.  Applies to FP32 RBF models with m <= 64
- *   (else ignored).  Setting it allocates the dense factors (16 KiB per cell, held until the
- *   model is destroyed; KSDF_ERR_OUT_OF_MEMORY if that fails, the model unchanged);
- *   while it is on, each fit and refit also forms them, and the first query after it
- *   is turned on forms them if they are stale.  var_f then differs from the other
+ *   (else ignored); such a model needs KSDF_FIT_DENSE_INV at creation (else
+ *   KSDF_ERR_UNSUPPORTED, the tuning unchanged).  While it is on, each fit and refit
+ *   also forms the dense factors, and the first query after it is turned on forms
+ *   them if they are stale.  var_f then differs from the other
  *   launch shapes in the last bits (a different summation order); every other output
  *   is identical. */
 typedef struct ksdf_tuning {
@@ -205,7 +230,8 @@ int ksdf_model_get_tuning(const ksdf_model* model, ksdf_tuning* tuning);
 int ksdf_model_set_timing(ksdf_model* model, int on);
 int ksdf_model_timer_read(ksdf_model* model, int timer, float* ms, int max_n, int* n);
 
-/* Host-side facts about a model: n_cells, nnz, largest m, index entries, device bytes. */
+/* Host-side facts about a model: n_cells, nnz, largest m, index entries, device bytes
+ * (the store plus, once attached, the candidate lists). */
 int ksdf_model_info(const ksdf_model* model, int* n_cells, long* nnz, int* max_m,
                     long* index_entries, size_t* device_bytes);
 
@@ -269,12 +295,17 @@ int ksdf_refit_cells(ksdf_model* model, const void* surface_pts, int dtype, long
                      int* refit_cells, int* n_refit, uint8_t* cell_status, void* workspace,
                      size_t ws_bytes, void* stream);
 
-/* ksdf_count_queries — the query counters of App. G: qcount[argmin[q]] += 1 for every
- * query with a valid argmin cell (the GP whose prediction was used), then
- * qcount = min(qcount, cap) (App. G caps at 10000).  argmin: device int [Q] from
- * ksdf_query; qcount: device float [n_cells].  Asynchronous. */
+/* ksdf_count_queries — the query counters of App. G: for every query with an argmin
+ * cell c in [0, n_cells) (the GP whose prediction was used; other values, such as
+ * -1 for no valid cell, are skipped), qcount[c] = min(qcount[c] + count_c, cap) with
+ * count_c the number of such queries, added once per cell (one rounding: the result
+ * does not depend on the order of the queries).  App. G caps at 10000.  argmin:
+ * device int [Q] from ksdf_query; qcount: device float [n_cells]; workspace: device,
+ * at least ksdf_count_queries_workspace_bytes(model) bytes (4 per cell).
+ * Asynchronous. */
+size_t ksdf_count_queries_workspace_bytes(const ksdf_model* model);
 int ksdf_count_queries(const ksdf_model* model, const int* argmin, long Q, float* qcount,
-                       float cap, void* stream);
+                       float cap, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * SDF sign from local Bayesian-Hilbert-map weights (Sec. IV-A, eq. sign_prediction;
@@ -318,6 +349,14 @@ int ksdf_bhm_update_tau(const ksdf_bhm_layout* layout, const int* box_bhm, const
  * ksdf_fit_query_workspace_bytes(model, Q) bytes.  Asynchronous; allocates nothing.
  * ------------------------------------------------------------------------- */
 size_t ksdf_fit_query_workspace_bytes(const ksdf_model* model, long Q);
+/* A workgroup's wait for the fits is bounded (2^26 sleeps by default).  If it expires
+ * the launch still ends normally, the queries that workgroup answers carry
+ * KSDF_Q_FIT_TIMEOUT (their values may come from unfinished fits), and the model
+ * records it: ksdf_model_check (host; synchronises `stream`) returns KSDF_ERR_TIMEOUT
+ * once and clears the record, else KSDF_OK.  ksdf_model_set_wait_limit sets the bound
+ * in sleeps (0 restores the default; a test can set 1 to exercise the path). */
+int ksdf_model_check(ksdf_model* model, void* stream);
+int ksdf_model_set_wait_limit(ksdf_model* model, long sleeps);
 int ksdf_fit_query(ksdf_model* model, const void* surface_pts, int dtype, long n_points,
                    const void* sample_var, const ksdf_hyper* hyper, uint8_t* cell_status,
                    const void* points, long Q, const int8_t* sign, void* mean, void* grad,

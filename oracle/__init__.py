@@ -55,18 +55,22 @@ def lib():
         L.oracle_fit.restype = ctypes.c_int
         L.oracle_fit.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, ctypes.c_double, ctypes.c_double,
                                  _dp, _dp, _ip, ctypes.c_int]
+        L.oracle_query.restype = ctypes.c_long
         L.oracle_query.argtypes = ([_dp, _dp, ctypes.c_int, _ip, _ip, _dp, _dp, _dp] +
-                                   [ctypes.c_double] * 3 + [ctypes.c_int] * 3 +
+                                   [ctypes.c_double] * 3 + [ctypes.c_int, ctypes.c_double, ctypes.c_int] +
                                    [_dp, ctypes.c_long, _i8p, _dp, _dp, _dp, _dp, _ip, _ip, _dp, _dp,
-                                    _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int])
+                                    _dp, _dp, ctypes.c_int, _ip, _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ctypes.c_int])
+        L.oracle_cond2.argtypes = [_dp, _dp, ctypes.c_int, _ip, _ip, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int, _ip, ctypes.c_long, _dp, _dp, _dp]
         L.oracle_softmin.argtypes = [_dp, _dp, ctypes.c_int, ctypes.c_double, _dp, _dp]
         L.oracle_bhm.argtypes = [_dp, ctypes.c_double, _ip, ctypes.c_int, ctypes.c_double, _ip, _dp,
                                  _dp, ctypes.c_long, ctypes.c_double, _dp, _ip, _ip]
         L.oracle_vjp.restype = ctypes.c_double
         L.oracle_vjp.argtypes = ([_dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_double, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_long, _i8p,
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_double, _dp, ctypes.c_long, _i8p,
                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, _dp, _dp, _dp, _dp,
-                                  _dp, _dp, _dp, _ip, ctypes.c_int])
+                                  _dp, _dp, _dp, _ip, _ip, ctypes.c_int])
         _lib = L
     return _lib
 
@@ -201,53 +205,90 @@ def fit(points, cells: Cells, ell, noise, svar=None, kernel="rbf") -> Fit:
     return Fit(a, Lf, lofs, ok, nf)
 
 
+TIE_REL = 1e-6    # reading R6: relative width of the tie band at the K-th distance
+TIE_EXTRA = 8     # list width beyond K for the tie group
+
+
 def query(points, cells: Cells, f: Fit, queries, ell, noise, alpha=None, k_fuse=8,
-          cand_prec=64, d_mode=0, sign=None, svar=None, all_candidates=False,
+          tie_rel=TIE_REL, d_mode=0, sign=None, svar=None, all_candidates=False,
           kernel="rbf") -> dict:
-    """All outputs of the back-end at each query (see ``oracle_query``).  With
-    all_candidates, also every candidate cell's gradient, variances and ratio
-    (keys cgrad [Q,K,3], cgrad_var [Q,K,3], cvar, cvar_f, cratio [Q,K]).  grad_var [Q,3]
-    is the SDF gradient variance V[grad_k u] of App. C."""
+    """All outputs of the back-end at each query (see ``oracle_query``).
+
+    The primary outputs use the K nearest cells by exact distance (ties by id).  The
+    candidate list ``cand`` [Q, K + TIE_EXTRA] (-1 padded) holds those K cells, or,
+    where the K-th place is tied within ``tie_rel`` (reading R6), the strictly nearer
+    cells followed by the whole tie group; ``tie`` [Q,3] = (n_def, n_tie, n_pick)
+    (n_tie = 0 without a tie: any n_pick of the n_tie tied cells complete the set).
+    ``ucand`` holds each listed cell's u.  With all_candidates, also every listed
+    cell's gradient, variances and ratio (keys cgrad [Q,W,3], cgrad_var [Q,W,3], cvar,
+    cvar_f, cratio [Q,W]).  grad_var [Q,3] is the SDF gradient variance V[grad_k u] of
+    App. C; ratio and fratio are the argmin cell's cancellation ratios of the direction
+    w and of the scaled mean f'."""
     L = lib()
     pts = _f64(points)
     q = _f64(queries).reshape(-1, 3)
     nq = len(q)
+    cw = k_fuse + TIE_EXTRA
     alpha = 1.0 / (2 * ell * ell) if alpha is None else alpha
     sv = None if svar is None else _f64(svar)
     sg = None if sign is None else np.ascontiguousarray(sign, dtype=np.int8)
-    out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "ratio")}
+    out = {k: np.zeros(nq) for k in ("mean", "var", "var_f", "u_best", "u_second", "ratio", "fratio")}
     out["grad"] = np.zeros((nq, 3))
     out["grad_var"] = np.zeros((nq, 3))
     out["argmin"] = np.zeros(nq, np.int32)
     out["status"] = np.zeros(nq, np.int32)
-    out["cand"] = np.zeros((nq, k_fuse), np.int32)
-    out["ucand"] = np.zeros((nq, k_fuse))
+    out["cand"] = np.zeros((nq, cw), np.int32)
+    out["ucand"] = np.zeros((nq, cw))
+    out["tie"] = np.zeros((nq, 3), np.int32)
     if all_candidates:
-        out["cgrad"] = np.zeros((nq, k_fuse, 3))
-        out["cgrad_var"] = np.zeros((nq, k_fuse, 3))
+        out["cgrad"] = np.zeros((nq, cw, 3))
+        out["cgrad_var"] = np.zeros((nq, cw, 3))
         for k in ("cvar", "cvar_f", "cratio"):
-            out[k] = np.zeros((nq, k_fuse))
+            out[k] = np.zeros((nq, cw))
     g = out.get
     ctr = _f64(cells.centres)
-    L.oracle_query(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
-                   _p(cells.samples, _ip), _p(ctr, _dp), _p(f.a, _dp), _p(f.L, _dp), ell, noise,
-                   alpha, k_fuse, cand_prec, d_mode, _p(q, _dp), nq, _p(sg, _i8p),
-                   _p(out["mean"], _dp), _p(out["grad"], _dp), _p(out["var"], _dp),
-                   _p(out["var_f"], _dp), _p(out["argmin"], _ip), _p(out["status"], _ip),
-                   _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["ratio"], _dp),
-                   _p(out["cand"], _ip), _p(out["ucand"], _dp), _p(g("cgrad"), _dp),
-                   _p(g("cvar"), _dp), _p(g("cvar_f"), _dp), _p(g("cratio"), _dp),
-                   _p(out["grad_var"], _dp), _p(g("cgrad_var"), _dp), KERNELS[kernel])
+    over = L.oracle_query(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
+                          _p(cells.samples, _ip), _p(ctr, _dp), _p(f.a, _dp), _p(f.L, _dp), ell,
+                          noise, alpha, k_fuse, float(tie_rel), d_mode, _p(q, _dp), nq, _p(sg, _i8p),
+                          _p(out["mean"], _dp), _p(out["grad"], _dp), _p(out["var"], _dp),
+                          _p(out["var_f"], _dp), _p(out["argmin"], _ip), _p(out["status"], _ip),
+                          _p(out["u_best"], _dp), _p(out["u_second"], _dp), _p(out["ratio"], _dp),
+                          _p(out["fratio"], _dp), cw, _p(out["cand"], _ip), _p(out["ucand"], _dp),
+                          _p(out["tie"], _ip), _p(g("cgrad"), _dp), _p(g("cvar"), _dp),
+                          _p(g("cvar_f"), _dp), _p(g("cratio"), _dp), _p(out["grad_var"], _dp),
+                          _p(g("cgrad_var"), _dp), KERNELS[kernel])
+    out["list_overflow"] = int(over)
+    out["sign"] = np.ones(nq, np.int8) if sg is None else sg.copy()
     return out
 
 
-def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_prec=64, sign=None,
+def cond2(points, cells: Cells, ell, noise, svar=None, kernel="rbf", ids=None):
+    """Exact cond_2 of the cells' A = K + Sigma (eigenvalues by cyclic Jacobi), for
+    every cell or for the cell ids given; returns (cond, smallest eigenvalue,
+    largest eigenvalue), one entry per cell (or per id)."""
+    pts = _f64(points)
+    sv = None if svar is None else _f64(svar)
+    sel = None if ids is None else np.ascontiguousarray(ids, np.int32)
+    n = cells.n if sel is None else len(sel)
+    cond = np.zeros(n)
+    lo = np.zeros(n)
+    hi = np.zeros(n)
+    lib().oracle_cond2(_p(pts, _dp), _p(sv, _dp), cells.n, _p(cells.offsets, _ip),
+                       _p(cells.samples, _ip), float(ell), float(noise), KERNELS[kernel],
+                       _p(sel, _ip), n, _p(cond, _dp), _p(lo, _dp), _p(hi, _dp))
+    return cond, lo, hi
+
+
+def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, tie_rel=TIE_REL, sign=None,
         mode=0, margin=0.3, weight=1.0, d_mean=None, d_grad=None, d_var=None, d_var_f=None,
-        per_point=False, force_argmin=None, kernel="rbf"):
+        per_point=False, force_argmin=None, kernel="rbf", forced_used=False):
     """Dual-number VJP.  mode 0: given cotangents; mode 1: softplus collision cost.
     Returns (loss, d_points [Q,3], d_hyper [2] = d/d(l, sigma^2)), and with per_point
-    also each query's own contribution to d_hyper [Q,2].  force_argmin [Q] (optional):
-    differentiate at that candidate cell where it is valid (near-tie resolution)."""
+    also each query's own contribution to d_hyper [Q,2].  force_argmin [Q] (optional,
+    -1 = none): differentiate at that cell where it is one of the query's listed
+    candidates (a near-tie resolved the other way, which the caller has checked against
+    the tolerance); with forced_used, also return where it was used (1), refused (0)
+    or not given (-1)."""
     L = lib()
     pts = _f64(points)
     q = _f64(queries).reshape(-1, 3)
@@ -256,14 +297,16 @@ def vjp(points, cells: Cells, queries, ell, noise, alpha=None, k_fuse=8, cand_pr
     dh = np.zeros(2)
     pp = np.zeros((len(q), 2)) if per_point else None
     fa = None if force_argmin is None else np.ascontiguousarray(force_argmin, dtype=np.int32)
+    fu = np.full(len(q), -1, np.int32)
     cot = [None if c is None else _f64(c) for c in (d_mean, d_grad, d_var, d_var_f)]
     ctr = _f64(cells.centres)
     loss = L.oracle_vjp(_p(pts, _dp), cells.n, _p(cells.offsets, _ip), _p(cells.samples, _ip),
                         _p(ctr, _dp), ell, noise, -1.0 if alpha is None else alpha, k_fuse,
-                        cand_prec, _p(q, _dp), len(q), _p(sg, _i8p), mode, margin, weight,
+                        float(tie_rel), _p(q, _dp), len(q), _p(sg, _i8p), mode, margin, weight,
                         *[_p(c, _dp) for c in cot], _p(dp, _dp), _p(dh, _dp), _p(pp, _dp),
-                        _p(fa, _ip), KERNELS[kernel])
-    return (loss, dp, dh, pp) if per_point else (loss, dp, dh)
+                        _p(fa, _ip), _p(fu, _ip), KERNELS[kernel])
+    res = (loss, dp, dh, pp) if per_point else (loss, dp, dh)
+    return res + (fu,) if forced_used else res
 
 
 def run(points, cells: Cells, queries, ell, noise, **kw):

@@ -217,8 +217,9 @@ T sample_var(const Inputs& in, int s, const T& noise) {
 }
 
 // Returns false when a pivot is not positive (cell not SPD).
+// A = K + Sigma of cell c, row-major m x m.
 template <class T>
-bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L) {
+std::vector<T> assemble_cell(const Inputs& in, int c, const T& ell, const T& noise) {
   const int b = in.offsets[c], m = in.offsets[c + 1] - b;
   std::vector<T> A((size_t)m * m);
   for (int i = 0; i < m; ++i)
@@ -230,6 +231,13 @@ bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L)
       A[(size_t)i * m + j] = i == j ? T(1.0) : kernel_r2(in.kernel, T(r2), ell);
       if (i == j) A[(size_t)i * m + j] = A[(size_t)i * m + j] + sample_var(in, in.samples[b + i], noise);
     }
+  return A;
+}
+
+template <class T>
+bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L) {
+  const int m = in.offsets[c + 1] - in.offsets[c];
+  std::vector<T> A = assemble_cell(in, c, ell, noise);
   for (int i = 0; i < m * m; ++i) L[i] = T(0.0);
   for (int j = 0; j < m; ++j) {
     T s = A[(size_t)j * m + j];
@@ -262,36 +270,54 @@ bool fit_cell(const Inputs& in, int c, const T& ell, const T& noise, T* a, T* L)
 struct QueryOpts {
   double ell_v, alpha_v;
   int k_fuse;
-  int cand_prec;        // 64: candidate distances in double; 32: in float (fmaf order)
+  double tie_rel;       // relative width of the tie band at the K-th distance (R6)
   int d_mode;           // 0: d = nearest sample (default); 1: d = first sample; 2: d = 0
   bool alpha_tied;      // alpha = 1/(2 l^2) follows l
 };
 
-// K nearest occupied cell centres, ties by lower id (Sec. IV-B.1, "K nearest GPs").
-std::vector<int> candidates(const Inputs& in, const double* q, const QueryOpts& o) {
+// The K nearest occupied cell centres by exact (double) distance, ties by lower id
+// (Sec. IV-B.1, "K nearest GPs").  Reading R6: when the K-th place is tied, i.e.
+// more cells than the free places lie within tie_rel of the K-th distance, any
+// choice of those tied cells is an acceptable candidate set.  `list` then holds the
+// strictly nearer cells followed by the whole tie group (n_def + n_tie cells, of
+// which n_pick tied cells join the set); otherwise it is the K nearest.  `kset` is
+// always the K nearest with ties broken by id.
+struct CandSet {
+  std::vector<int> kset, list;
+  int n_def = 0, n_tie = 0, n_pick = 0;
+};
+
+CandSet candidates(const Inputs& in, const double* q, const QueryOpts& o) {
+  CandSet cs;
   std::vector<std::pair<double, int>> d(in.n_cells);
   for (int c = 0; c < in.n_cells; ++c) {
     const double* ce = in.centres + 3 * (long)c;
-    double r2;
-    if (o.cand_prec == 32) {
-      float dx = (float)q[0] - (float)ce[0];
-      float dy = (float)q[1] - (float)ce[1];
-      float dz = (float)q[2] - (float)ce[2];
-      float t = dx * dx;
-      t = std::fmaf(dy, dy, t);
-      t = std::fmaf(dz, dz, t);
-      r2 = (double)t;
-    } else {
-      double dx = q[0] - ce[0], dy = q[1] - ce[1], dz = q[2] - ce[2];
-      r2 = dx * dx + dy * dy + dz * dz;
-    }
-    d[c] = {r2, c};
+    double dx = q[0] - ce[0], dy = q[1] - ce[1], dz = q[2] - ce[2];
+    d[c] = {dx * dx + dy * dy + dz * dz, c};
   }
-  int k = std::min(o.k_fuse, in.n_cells);
-  std::partial_sort(d.begin(), d.begin() + k, d.end());
-  std::vector<int> out(k);
-  for (int i = 0; i < k; ++i) out[i] = d[i].second;
-  return out;
+  const int k = std::min(o.k_fuse, in.n_cells);
+  if (k == 0) return cs;
+  std::nth_element(d.begin(), d.begin() + (k - 1), d.end());
+  const double dk2 = d[k - 1].first;
+  const double hi2 = dk2 * (1.0 + o.tie_rel) * (1.0 + o.tie_rel);
+  const double lo2 = dk2 * (1.0 - o.tie_rel) * (1.0 - o.tie_rel);
+  std::vector<std::pair<double, int>> near;
+  for (const auto& e : d)
+    if (e.first <= hi2) near.push_back(e);
+  std::sort(near.begin(), near.end());
+  for (int i = 0; i < k; ++i) cs.kset.push_back(near[i].second);
+  int n_def = 0, n_tie = 0;
+  for (const auto& e : near) (e.first < lo2 ? n_def : n_tie) += 1;
+  if (n_tie > k - n_def) {
+    for (const auto& e : near) cs.list.push_back(e.second);
+    cs.n_def = n_def;
+    cs.n_tie = n_tie;
+    cs.n_pick = k - n_def;
+  } else {
+    cs.list = cs.kset;
+    cs.n_def = k;
+  }
+  return cs;
 }
 
 // Per-candidate UDF (eq. log_gp_posterior_mean mean with App. D scaling, Table I transform).
@@ -342,6 +368,7 @@ struct CellOut {
   T var, var_f;
   T grad_var[3];         // V[grad_k u] of App. C
   double ratio;          // cancellation ratio sum|a_i| e_i |x*-x_i| / |w|
+  double fratio;         // cancellation ratio of the scaled mean: sum|a_i e_i| / |sum a_i e_i|
   bool grad_zero;
 };
 
@@ -369,12 +396,15 @@ CellOut<T> cell_outputs(const Inputs& in, int c, const T* q, const T* a, const T
   const T cm = matern_rate(ell);
   const T dref = matern ? sqrt(d2) : T(0.0);
   T w[3] = {T(0.0), T(0.0), T(0.0)};
-  double absum = 0;
+  double absum = 0, fabs_sum = 0, fsum = 0;
   for (int i = 0; i < m; ++i) {
     T e = matern ? exp(-cm * (sqrt(z2[i]) - dref)) : exp(-(z2[i] - d2) / (T(2.0) * ell * ell));
     for (int d = 0; d < 3; ++d) w[d] = w[d] + a[b + i] * e * diff[3 * i + d];
     absum += std::fabs(val(a[b + i]) * val(e)) * std::sqrt(val(z2[i]));
+    fabs_sum += std::fabs(val(a[b + i]) * val(e));
+    fsum += val(a[b + i]) * val(e);
   }
+  r.fratio = fsum != 0 ? fabs_sum / std::fabs(fsum) : std::numeric_limits<double>::infinity();
   T wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
   r.grad_zero = !(val(wn) > 0);
   for (int d = 0; d < 3; ++d) r.grad[d] = r.grad_zero ? T(0.0) : w[d] / wn;
@@ -451,15 +481,20 @@ template <class T>
 struct PointOut {
   T mean, grad[3], var, var_f, grad_var[3];
   int argmin;
-  double u_best, u_second, ratio;
+  double u_best, u_second, ratio, fratio;
   int status;
-  std::vector<int> cand;
-  std::vector<double> ucand;
-  std::vector<CellOut<T>> cout;   // per-candidate outputs (when requested)
+  CandSet cs;                     // the candidate set and its R6 tie group
+  std::vector<double> ucand;      // u of every cell of cs.list
+  std::vector<CellOut<T>> cout;   // per-cell outputs of cs.list (when requested)
+  int forced = -1;                // 1: the forced cell was used; 0: it was not in cs.list or invalid
 };
 
 enum { ST_NO_VALID = 1, ST_CLAMPED = 2, ST_GRAD_ZERO = 4 };
 
+// Outputs at one query.  The fused u is the minimum over the K nearest cells (ties by
+// id, also among equal u).  A forced cell (a near-tie of the candidate set or of the
+// min-fusion resolved the other way, which the caller has checked against the
+// tolerance) replaces the minimum when it is one of cs.list with a finite u.
 template <class T>
 PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, const T* L,
                         const T& ell, const T& noise, const T& alpha, const QueryOpts& o,
@@ -467,27 +502,39 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
   double qv[3] = {val(q[0]), val(q[1]), val(q[2])};
   PointOut<T> r;
   r.status = 0;
-  r.cand = candidates(in, qv, o);
-  std::vector<std::tuple<double, int, T, bool>> us;
-  for (int c : r.cand) {
+  r.cs = candidates(in, qv, o);
+  std::vector<T> ul(r.cs.list.size());
+  std::vector<bool> clamp(r.cs.list.size(), false);
+  for (size_t i = 0; i < r.cs.list.size(); ++i) {
     bool cl = false;
-    T u = cell_udf(in, c, q, a, ell, o, &cl);
-    us.push_back(std::make_tuple(val(u), c, u, cl));
-    r.ucand.push_back(val(u));
+    ul[i] = cell_udf(in, r.cs.list[i], q, a, ell, o, &cl);
+    clamp[i] = cl;
+    r.ucand.push_back(val(ul[i]));
   }
   if (all_candidates)
-    for (int c : r.cand) {
+    for (int c : r.cs.list) {
       CellOut<T> co = cell_outputs(in, c, q, a, L, ell, noise, alpha, o);
       for (int d = 0; d < 3; ++d) co.grad[d] = T((double)sign) * co.grad[d];
       r.cout.push_back(co);
     }
-  std::sort(us.begin(), us.end(), [](const auto& x, const auto& y) {
-    return std::make_pair(std::get<0>(x), std::get<1>(x)) < std::make_pair(std::get<0>(y), std::get<1>(y));
+  // the K nearest, ordered by (u, id)
+  std::vector<std::pair<double, int>> us;   // (u, position in cs.list)
+  for (size_t i = 0; i < r.cs.list.size(); ++i)
+    if (std::find(r.cs.kset.begin(), r.cs.kset.end(), r.cs.list[i]) != r.cs.kset.end())
+      us.push_back({r.ucand[i], (int)i});
+  std::sort(us.begin(), us.end(), [&](const auto& x, const auto& y) {
+    return std::make_pair(x.first, r.cs.list[x.second]) < std::make_pair(y.first, r.cs.list[y.second]);
   });
   const double inf = std::numeric_limits<double>::infinity();
-  r.argmin = -1; r.u_best = inf; r.u_second = inf; r.ratio = inf;
-  if (us.size() > 1) r.u_second = std::get<0>(us[1]);
-  if (us.empty() || !(std::get<0>(us[0]) < inf)) {
+  r.argmin = -1; r.u_best = inf; r.u_second = inf; r.ratio = inf; r.fratio = inf;
+  if (us.size() > 1) r.u_second = us[1].first;
+  int pick = us.empty() ? -1 : us[0].second;
+  if (forced >= 0) {
+    r.forced = 0;
+    for (size_t i = 0; i < r.cs.list.size(); ++i)
+      if (r.cs.list[i] == forced && r.ucand[i] < inf) { pick = (int)i; r.forced = 1; }
+  }
+  if (pick < 0 || !(r.ucand[pick] < inf)) {
     r.status = ST_NO_VALID;
     r.mean = T(inf);
     for (int d = 0; d < 3; ++d) r.grad[d] = T(0.0);
@@ -495,23 +542,57 @@ PointOut<T> query_point(const Inputs& in, const T* q, int sign, const T* a, cons
     for (int d = 0; d < 3; ++d) r.grad_var[d] = T(inf);
     return r;
   }
-  // a forced cell (a near-tie of the min-fusion resolved the other way, which the
-  // parity contract accepts) replaces the minimum when it is a valid candidate
-  size_t pick = 0;
-  if (forced >= 0)
-    for (size_t k = 0; k < us.size(); ++k)
-      if (std::get<1>(us[k]) == forced && std::get<0>(us[k]) < inf) pick = k;
-  r.argmin = std::get<1>(us[pick]);
-  r.u_best = std::get<0>(us[pick]);
-  if (std::get<3>(us[pick])) r.status |= ST_CLAMPED;
+  r.argmin = r.cs.list[pick];
+  r.u_best = r.ucand[pick];
+  if (clamp[pick]) r.status |= ST_CLAMPED;
   // d = s * u; grad d = s * grad u; V[d] = V[u] (deterministic sign).
-  r.mean = T((double)sign) * std::get<2>(us[pick]);
+  r.mean = T((double)sign) * ul[pick];
   CellOut<T> co = cell_outputs(in, r.argmin, q, a, L, ell, noise, alpha, o);
   for (int d = 0; d < 3; ++d) r.grad[d] = T((double)sign) * co.grad[d];
-  r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio;
+  r.var = co.var; r.var_f = co.var_f; r.ratio = co.ratio; r.fratio = co.fratio;
   for (int d = 0; d < 3; ++d) r.grad_var[d] = co.grad_var[d];
   if (co.grad_zero) r.status |= ST_GRAD_ZERO;
   return r;
+}
+
+// Eigenvalues of a symmetric m x m matrix (row-major) by the cyclic Jacobi method:
+// sweeps of plane rotations, each zeroing one off-diagonal pair, until the
+// off-diagonal mass is negligible against the whole (Golub and Van Loan, Matrix
+// Computations, Sec. 8.5).  Accurate to about machine precision times the norm.
+std::vector<double> sym_eigenvalues(std::vector<double> A, int m) {
+  auto at = [&](int i, int j) -> double& { return A[(size_t)i * m + j]; };
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0, all = 0;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        all += at(i, j) * at(i, j);
+        if (i != j) off += at(i, j) * at(i, j);
+      }
+    if (off <= 1e-32 * all) break;
+    for (int p = 0; p < m - 1; ++p)
+      for (int q = p + 1; q < m; ++q) {
+        const double apq = at(p, q);
+        if (apq == 0) continue;
+        // the rotation angle that zeroes (p, q): tan of it is the smaller root of
+        // t^2 + 2 tau t - 1 = 0 with tau = (a_qq - a_pp) / (2 a_pq)
+        const double tau = (at(q, q) - at(p, p)) / (2 * apq);
+        const double t = (tau >= 0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+        const double cs = 1 / std::sqrt(1 + t * t), sn = t * cs;
+        for (int k = 0; k < m; ++k) {        // A <- A J
+          const double kp = at(k, p), kq = at(k, q);
+          at(k, p) = cs * kp - sn * kq;
+          at(k, q) = sn * kp + cs * kq;
+        }
+        for (int k = 0; k < m; ++k) {        // A <- J^T A
+          const double pk = at(p, k), qk = at(q, k);
+          at(p, k) = cs * pk - sn * qk;
+          at(q, k) = sn * pk + cs * qk;
+        }
+      }
+  }
+  std::vector<double> ev(m);
+  for (int i = 0; i < m; ++i) ev[i] = at(i, i);
+  return ev;
 }
 
 Inputs make_inputs(const double* pts, const double* svar, int n_cells, const int* offsets,
@@ -638,22 +719,27 @@ int oracle_fit(const double* pts, const double* svar, int n_cells, const int* of
 }
 
 // Query every point.  Outputs per query: mean, grad[3], var, var_f, argmin, status,
-// the best and second-best u, the cancellation ratio of the argmin cell, the K
-// candidate ids and their u values, and (when cgrad is given) every candidate
-// cell's gradient, variances and ratio, for near-tie acceptance.
-void oracle_query(const double* pts, const double* svar, int n_cells, const int* offsets,
+// the best and second-best u among the K nearest, the cancellation ratios of the
+// argmin cell's direction and mean, and the candidate list (the K nearest, or with a
+// tie at the K-th place the nearer cells and the whole tie group; width cw, -1
+// padded) with each cell's u; tie[3] = (n_def, n_tie, n_pick) of the list (n_tie =
+// 0: no tie); and (when cgrad is given) every listed cell's gradient, variances and
+// ratio, for near-tie acceptance.  Returns the number of queries whose list did not
+// fit in cw.
+long oracle_query(const double* pts, const double* svar, int n_cells, const int* offsets,
                   const int* samples, const double* centres, const double* a_in,
                   const double* L_in, double ell, double noise, double alpha, int k_fuse,
-                  int cand_prec, int d_mode, const double* q, long nq, const int8_t* sign,
+                  double tie_rel, int d_mode, const double* q, long nq, const int8_t* sign,
                   double* mean, double* grad, double* var, double* var_f, int* argmin,
-                  int* status, double* u_best, double* u_second, double* ratio, int* cand,
-                  double* ucand, double* cgrad, double* cvar, double* cvar_f, double* cratio,
-                  double* grad_var, double* cgrad_var, int kernel) {
+                  int* status, double* u_best, double* u_second, double* ratio, double* fratio,
+                  int cw, int* cand, double* ucand, int* tie, double* cgrad, double* cvar,
+                  double* cvar_f, double* cratio, double* grad_var, double* cgrad_var, int kernel) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, centres, lofs, kernel);
-  QueryOpts o{ell, alpha, k_fuse, cand_prec, d_mode, false};
+  QueryOpts o{ell, alpha, k_fuse, tie_rel, d_mode, false};
   const double inf = std::numeric_limits<double>::infinity();
-#pragma omp parallel for schedule(dynamic, 64)
+  long overflow = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : overflow)
   for (long p = 0; p < nq; ++p) {
     PointOut<double> r = query_point<double>(in, q + 3 * p, sign ? sign[p] : 1, a_in, L_in,
                                              ell, noise, alpha, o, cgrad != nullptr);
@@ -665,10 +751,15 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
     if (u_best) u_best[p] = r.u_best;
     if (u_second) u_second[p] = r.u_second;
     if (ratio) ratio[p] = r.ratio;
-    for (int i = 0; i < k_fuse; ++i) {
-      bool have = i < (int)r.cand.size();
-      long j = (long)k_fuse * p + i;
-      if (cand) cand[j] = have ? r.cand[i] : -1;
+    if (fratio) fratio[p] = r.fratio;
+    if (tie) {
+      tie[3 * p] = r.cs.n_def; tie[3 * p + 1] = r.cs.n_tie; tie[3 * p + 2] = r.cs.n_pick;
+    }
+    if ((int)r.cs.list.size() > cw) ++overflow;
+    for (int i = 0; i < cw; ++i) {
+      bool have = i < (int)r.cs.list.size();
+      long j = (long)cw * p + i;
+      if (cand) cand[j] = have ? r.cs.list[i] : -1;
       if (ucand) ucand[j] = have ? r.ucand[i] : inf;
       if (cgrad) {
         for (int d = 0; d < 3; ++d) cgrad[3 * j + d] = have ? r.cout[i].grad[d] : 0.0;
@@ -680,6 +771,30 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
       }
     }
   }
+  return overflow;
+}
+
+// Exact 2-norm condition number of every cell's A = K + Sigma (the matrix the fit
+// factors): the ratio of its extreme eigenvalues from cyclic Jacobi rotations; +inf
+// where the smallest eigenvalue is not positive.
+// ids [n_ids] selects the cells (null: every cell, n_ids ignored); outputs follow ids.
+void oracle_cond2(const double* pts, const double* svar, int n_cells, const int* offsets,
+                  const int* samples, double ell, double noise, int kernel, const int* ids,
+                  long n_ids, double* cond, double* eig_min, double* eig_max) {
+  std::vector<long> lofs;
+  Inputs in = make_inputs(pts, svar, n_cells, offsets, samples, nullptr, lofs, kernel);
+  const long n = ids ? n_ids : n_cells;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (long j = 0; j < n; ++j) {
+    const int c = ids ? ids[j] : (int)j;
+    const int m = offsets[c + 1] - offsets[c];
+    std::vector<double> ev = sym_eigenvalues(assemble_cell<double>(in, c, ell, noise), m);
+    const double lo = *std::min_element(ev.begin(), ev.end());
+    const double hi = *std::max_element(ev.begin(), ev.end());
+    cond[j] = lo > 0 ? hi / lo : std::numeric_limits<double>::infinity();
+    if (eig_min) eig_min[j] = lo;
+    if (eig_max) eig_max[j] = hi;
+  }
 }
 
 // Vector-Jacobian product by forward-mode dual numbers.
@@ -687,17 +802,20 @@ void oracle_query(const double* pts, const double* svar, int n_cells, const int*
 //   mode 1: L = sum_q softplus(margin - mean + weight*sqrt(var))   (cotangent args unused)
 // d_points [nq,3] = dL/dq; d_hyper[2] = dL/d(l, sigma^2) through the fit as well
 // (the whole fit is redone in dual arithmetic); alpha = 1/(2 l^2) follows l
-// unless alpha_fixed > 0.  Returns L.
+// unless alpha_fixed > 0.  force_argmin [nq] (or null; -1 = none) differentiates at
+// that cell where it is one of the query's listed candidates (see query_point);
+// forced_used [nq] (or null) receives 1 where it was used, 0 where it was not, -1
+// where none was given.  Returns L.
 double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int* samples,
                   const double* centres, double ell, double noise, double alpha_fixed,
-                  int k_fuse, int cand_prec, const double* q, long nq, const int8_t* sign,
+                  int k_fuse, double tie_rel, const double* q, long nq, const int8_t* sign,
                   int mode, double margin, double weight, const double* d_mean,
                   const double* d_grad, const double* d_var, const double* d_var_f,
                   double* d_points, double* d_hyper, double* d_hyper_pp,
-                  const int* force_argmin, int kernel) {
+                  const int* force_argmin, int* forced_used, int kernel) {
   std::vector<long> lofs;
   Inputs in = make_inputs(pts, nullptr, n_cells, offsets, samples, centres, lofs, kernel);
-  QueryOpts o{ell, 0, k_fuse, cand_prec, 0, alpha_fixed <= 0};
+  QueryOpts o{ell, 0, k_fuse, tie_rel, 0, alpha_fixed <= 0};
   auto loss_of = [&](long p, auto mean, auto* g, auto var, auto var_f) {
     using T = decltype(mean);
     if (mode == 1) return softplus(T(margin) - mean + T(weight) * sqrt(var));
@@ -744,6 +862,7 @@ double oracle_vjp(const double* pts, int n_cells, const int* offsets, const int*
     for (int d = 0; d < 3; ++d) { qd[d] = D3(q[3 * p + d]); qd[d].d[d] = 1.0; }
     PointOut<D3> r = query_point<D3>(in, qd, sign ? sign[p] : 1, a3.data(), L3.data(), ell3,
                                      noise3, alpha3, o, false, force_argmin ? force_argmin[p] : -1);
+    if (forced_used) forced_used[p] = r.forced;
     if (r.status & ST_NO_VALID) {
       for (int d = 0; d < 3; ++d) d_points[3 * p + d] = 0;
       continue;

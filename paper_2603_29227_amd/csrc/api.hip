@@ -27,7 +27,7 @@ int check_hyper(const ksdf_hyper* hp) {
   }
   if (!(hp->ell > 0) || hp->noise_var < 0 || hp->k_fuse < 1 || hp->k_fuse > KSDF_MAX_K ||
       (hp->precision != KSDF_FP64 && hp->precision != KSDF_FP32) ||
-      !(hp->cond_fp64_threshold > 0) || (hp->flags & ~(KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) ||
+      !(hp->cond_fp64_threshold > 0) || (hp->flags & ~(KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF | KSDF_FIT_DENSE_INV)) ||
       (hp->kernel != KSDF_KERNEL_RBF && hp->kernel != KSDF_KERNEL_MATERN32)) {
     set_error("hyperparameter out of range (ell > 0, noise_var >= 0, 1 <= k_fuse <= 16, "
               "precision KSDF_FP64|KSDF_FP32, cond threshold > 0, kernel KSDF_KERNEL_*)");
@@ -45,58 +45,67 @@ int check_device(const ksdf_model* m) {
   return KSDF_OK;
 }
 
-template <class T>
-int dalloc(ksdf_model* m, T** p, size_t n) {
-  n = std::max<size_t>(n, 1);
-  if (hipMalloc(reinterpret_cast<void**>(p), n * sizeof(T)) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("device allocation failed");
-    return KSDF_ERR_OUT_OF_MEMORY;
+// Lays the model's device arrays out in one caller buffer, 256-byte aligned; with a
+// null base it only adds up the bytes.  model_layout below is the single place that
+// decides the layout, used both to size the store and to carve it.
+struct Carver {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  void take(T** p, size_t n) {
+    off = (off + 255) & ~size_t(255);
+    *p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(n, 1) * sizeof(T);
   }
-  m->device_bytes += n * sizeof(T);
-  return KSDF_OK;
+};
+
+void model_layout(ksdf_model* m, Carver& cv) {
+  const long n = m->n_cells, nnz = m->nnz, lsize = m->h_loff[m->n_cells];
+  cv.take(&m->offsets, n + 1);
+  cv.take(&m->samples, nnz);
+  cv.take(&m->loff, n + 1);
+  cv.take(&m->centre32, 4 * n);
+  cv.take(&m->centre64, 3 * n);
+  cv.take(&m->box32, 8 * n);
+  cv.take(&m->cstatus, n);
+  cv.take(&m->ps64, 4 * nnz);
+  cv.take(&m->sv64, nnz);
+  cv.take(&m->L64, lsize);
+  cv.take(&m->bucket_cells, n);
+  cv.take(&m->fused_order, n);
+  cv.take(&m->flags, 1);
+  if (m->adjoint_alloc) {
+    // the FP64 refit of an FP32 model writes its xi in FP32 too
+    if (m->precision == KSDF_FP32) cv.take(&m->xi32, 4 * (nnz + KSDF_PAD_SAMPLES));
+    else cv.take(&m->xi64, 2 * nnz);
+  }
+  if (m->adjoint_varf_alloc) {
+    if (m->precision == KSDF_FP32) cv.take(&m->D32, lsize + KSDF_PAD_FACTOR);
+    else cv.take(&m->D64, lsize);
+  }
+  if (m->precision == KSDF_FP32) {
+    // padded so the wave-uniform chunked loads of the last cell stay in bounds
+    cv.take(&m->ps32, 4 * (nnz + KSDF_PAD_SAMPLES));
+    cv.take(&m->plo32, 4 * (nnz + KSDF_PAD_SAMPLES));
+    cv.take(&m->sv32, nnz + KSDF_PAD_SAMPLES);
+    cv.take(&m->L32, lsize + KSDF_PAD_FACTOR);
+    cv.take(&m->cond32, n);
+    cv.take(&m->fb_list, n);
+    cv.take(&m->fb_count, 1);
+    if (m->dense_inv) cv.take(&m->Linv32, 4096 * n);
+  }
+  const long nb = m->index.n_boxes;
+  cv.take(&m->index.box_off, nb + 1);
+  cv.take(&m->index.box_rank, nb);
+  cv.take(&m->index.bound, nb);
+  cv.take(&m->index.counts, nb);
 }
 
-void free_model(ksdf_model* m) {
-  if (!m) return;
-  void* ptrs[] = {m->offsets, m->samples, m->loff, m->centre32, m->centre64, m->ps32, m->plo32, m->sv32,
-                  m->L32, m->Linv32, m->box32, m->cond32, m->fb_list, m->fb_count, m->ps64, m->sv64,
-                  m->L64, m->cstatus, m->bucket_cells, m->fused_order, m->xi32, m->xi64, m->D32, m->D64, m->index.box_off, m->index.box_list, m->index.box_rank};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  for (auto& phase : m->tev)
-    for (auto& pair : phase)
-      for (hipEvent_t e : pair)
-        if (e) (void)hipEventDestroy(e);
-  delete m;
-}
-
-}  // namespace
-
-void set_error(const std::string& msg) { g_last_error = msg; }
-
-}  // namespace ksdf
-
-using namespace ksdf;
-
-#define TRY(x)                 \
-  do {                         \
-    int _r = (x);              \
-    if (_r != KSDF_OK) {       \
-      free_model(m);           \
-      return _r;               \
-    }                          \
-  } while (0)
-
-extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* samples,
-                                 const int* keys, const double origin[3], double h,
-                                 long n_points, const ksdf_hyper* hyper, const double query_lo[3],
-                                 const double query_hi[3], ksdf_model** out) {
-  if (!out) {
-    set_error("out is null");
-    return KSDF_ERR_INVALID_ARGUMENT;
-  }
-  *out = nullptr;
+// Host part of model creation, shared by ksdf_model_bytes and ksdf_model_create:
+// argument checks, sizes, host copies of the structure and the index lattice.
+int model_host_setup(ksdf_model* m, int n_cells, const int* offsets, const int* samples,
+                     const int* keys, const double origin[3], double h, long n_points,
+                     const ksdf_hyper* hyper, const double query_lo[3], const double query_hi[3]) {
   int r = check_hyper(hyper);
   if (r) return r;
   if (n_cells < 0 || !offsets || (n_cells > 0 && (!samples || !keys)) || !finite3(origin) ||
@@ -131,15 +140,6 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
       set_error("a cell references a sample index outside [0, n_points)");
       return KSDF_ERR_INVALID_ARGUMENT;
     }
-  int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
-    (void)hipGetLastError();
-    set_error("no HIP device");
-    return KSDF_ERR_DEVICE;
-  }
-  auto* m = new ksdf_model;
-  (void)hipGetDevice(&m->device);
-  (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
   m->precision = hyper->precision;
   m->kernel = hyper->kernel;
   m->k_fuse = hyper->k_fuse;
@@ -157,59 +157,95 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
     m->h_loff[c + 1] = m->h_loff[c] + mc * (mc + 1) / 2;
   }
   m->h_centre.resize(3L * n_cells);
-  std::vector<float> c32(4L * n_cells, 0.f);
   for (int c = 0; c < n_cells; ++c)
-    for (int d = 0; d < 3; ++d) {
-      const double v = origin[d] + ((double)keys[3 * c + d] + 0.5) * h;
-      m->h_centre[3 * c + d] = v;
-      c32[4 * c + d] = (float)v;
-    }
-  const long lsize = m->h_loff[n_cells];
-  TRY(dalloc(m, &m->offsets, n_cells + 1));
-  TRY(dalloc(m, &m->samples, nnz));
-  TRY(dalloc(m, &m->loff, n_cells + 1));
-  TRY(dalloc(m, &m->centre32, 4L * n_cells));
-  TRY(dalloc(m, &m->centre64, 3L * n_cells));
-  TRY(dalloc(m, &m->box32, 8L * n_cells));
-  TRY(dalloc(m, &m->cstatus, n_cells));
-  TRY(dalloc(m, &m->ps64, 4L * nnz));
-  TRY(dalloc(m, &m->sv64, nnz));
-  TRY(dalloc(m, &m->L64, lsize));
+    for (int d = 0; d < 3; ++d) m->h_centre[3 * c + d] = origin[d] + ((double)keys[3 * c + d] + 0.5) * h;
   m->adjoint_alloc = (hyper->flags & (KSDF_FIT_ADJOINT | KSDF_FIT_ADJOINT_VARF)) != 0;
   m->adjoint_varf_alloc = (hyper->flags & KSDF_FIT_ADJOINT_VARF) != 0;
-  if (m->adjoint_alloc) {
-    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->xi32, 4L * (nnz + KSDF_PAD_SAMPLES)));
-    else TRY(dalloc(m, &m->xi64, 2L * nnz));
-    // the FP64 refit of an FP32 model writes its xi in FP32 too
+  // the dense inverses serve the matrix-core pass 2 of FP32 RBF models with m <= 64
+  m->dense_inv = (hyper->flags & KSDF_FIT_DENSE_INV) && m->precision == KSDF_FP32 &&
+                 m->kernel == KSDF_KERNEL_RBF && max_m <= 64 && n_cells > 0;
+  return index_lattice(m, query_lo, query_hi);
+}
+
+void destroy_model(ksdf_model* m) {
+  if (!m) return;
+  for (auto& phase : m->tev)
+    for (auto& pair : phase)
+      for (hipEvent_t e : pair)
+        if (e) (void)hipEventDestroy(e);
+  delete m;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace ksdf
+
+using namespace ksdf;
+
+extern "C" size_t ksdf_model_bytes(int n_cells, const int* offsets, const int* samples,
+                                   const int* keys, const double origin[3], double h,
+                                   long n_points, const ksdf_hyper* hyper,
+                                   const double query_lo[3], const double query_hi[3]) {
+  ksdf_model m;
+  if (model_host_setup(&m, n_cells, offsets, samples, keys, origin, h, n_points, hyper, query_lo,
+                       query_hi) != KSDF_OK)
+    return 0;
+  Carver cv;
+  model_layout(&m, cv);
+  return cv.off;
+}
+
+extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* samples,
+                                 const int* keys, const double origin[3], double h,
+                                 long n_points, const ksdf_hyper* hyper, const double query_lo[3],
+                                 const double query_hi[3], void* store, size_t store_bytes,
+                                 void* stream, ksdf_model** out) {
+  if (!out) {
+    set_error("out is null");
+    return KSDF_ERR_INVALID_ARGUMENT;
   }
-  if (m->adjoint_varf_alloc) {
-    if (m->precision == KSDF_FP32) TRY(dalloc(m, &m->D32, lsize + KSDF_PAD_FACTOR));
-    else TRY(dalloc(m, &m->D64, lsize));
+  *out = nullptr;
+  auto* m = new ksdf_model;
+  int r = model_host_setup(m, n_cells, offsets, samples, keys, origin, h, n_points, hyper, query_lo,
+                           query_hi);
+  if (r) {
+    destroy_model(m);
+    return r;
   }
-  if (m->precision == KSDF_FP32) {
-    // padded so the wave-uniform chunked loads of the last cell stay in bounds
-    TRY(dalloc(m, &m->ps32, 4L * (nnz + KSDF_PAD_SAMPLES)));
-    TRY(dalloc(m, &m->plo32, 4L * (nnz + KSDF_PAD_SAMPLES)));
-    TRY(dalloc(m, &m->sv32, nnz + KSDF_PAD_SAMPLES));
-    TRY(dalloc(m, &m->L32, lsize + KSDF_PAD_FACTOR));
-    KSDF_HIP_TRY(hipMemset(m->ps32, 0, 4L * (nnz + KSDF_PAD_SAMPLES) * sizeof(float)));
-    KSDF_HIP_TRY(hipMemset(m->sv32, 0, (nnz + KSDF_PAD_SAMPLES) * sizeof(float)));
-    KSDF_HIP_TRY(hipMemset(m->L32, 0, (lsize + KSDF_PAD_FACTOR) * sizeof(float)));
-    TRY(dalloc(m, &m->cond32, n_cells));
-    TRY(dalloc(m, &m->fb_list, n_cells));
-    TRY(dalloc(m, &m->fb_count, 1));
+  Carver size;
+  model_layout(m, size);
+  if (!store || store_bytes < size.off) {
+    destroy_model(m);
+    set_error("ksdf_model_create: the store is smaller than ksdf_model_bytes");
+    return KSDF_ERR_WORKSPACE;
   }
-  auto up = [&](void* dst, const void* src, size_t bytes) -> int {
-    if (bytes == 0) return KSDF_OK;
-    KSDF_HIP_TRY(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
-    return KSDF_OK;
-  };
-  TRY(up(m->offsets, offsets, (n_cells + 1) * sizeof(int)));
-  TRY(up(m->samples, samples, nnz * sizeof(int)));
-  TRY(up(m->loff, m->h_loff.data(), (n_cells + 1) * sizeof(long)));
-  TRY(up(m->centre32, c32.data(), c32.size() * sizeof(float)));
-  TRY(up(m->centre64, m->h_centre.data(), m->h_centre.size() * sizeof(double)));
-  {
+  if (reinterpret_cast<uintptr_t>(store) % 256 != 0) {
+    destroy_model(m);
+    set_error("ksdf_model_create: the store must be 256-byte aligned");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    destroy_model(m);
+    set_error("no HIP device");
+    return KSDF_ERR_DEVICE;
+  }
+  (void)hipGetDevice(&m->device);
+  (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+  Carver cv;
+  cv.base = static_cast<char*>(store);
+  model_layout(m, cv);
+  m->store_bytes = size.off;
+  m->device_bytes = size.off;
+  hipStream_t s = (hipStream_t)stream;
+  r = [&]() -> int {
+    const long nnz = m->nnz, lsize = m->h_loff[n_cells];
+    std::vector<float> c32(4L * n_cells, 0.f);
+    for (int c = 0; c < n_cells; ++c)
+      for (int d = 0; d < 3; ++d) c32[4 * c + d] = (float)m->h_centre[3 * c + d];
     // cells grouped by m bucket for the FP32 fit kernels
     const int edges[4] = {16, 32, 64, 128};
     std::vector<int> order;
@@ -223,24 +259,97 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
       }
       m->bucket_start[bk + 1] = (int)order.size();
     }
-    TRY(dalloc(m, &m->bucket_cells, n_cells));
-    TRY(up(m->bucket_cells, order.data(), order.size() * sizeof(int)));
     // fused-launch fit order: largest m first (longest tasks start earliest)
     std::vector<int> byM(order.rbegin(), order.rend());
     std::stable_sort(byM.begin(), byM.end(), [&](int x, int y) {
       return offsets[x + 1] - offsets[x] > offsets[y + 1] - offsets[y];
     });
-    TRY(dalloc(m, &m->fused_order, n_cells));
-    TRY(up(m->fused_order, byM.data(), byM.size() * sizeof(int)));
+    auto up = [&](void* dst, const void* src, size_t bytes) -> int {
+      if (bytes == 0) return KSDF_OK;
+      KSDF_HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+      return KSDF_OK;
+    };
+    int e;
+    if ((e = up(m->offsets, offsets, (n_cells + 1) * sizeof(int)))) return e;
+    if ((e = up(m->samples, samples, nnz * sizeof(int)))) return e;
+    if ((e = up(m->loff, m->h_loff.data(), (n_cells + 1) * sizeof(long)))) return e;
+    if ((e = up(m->centre32, c32.data(), c32.size() * sizeof(float)))) return e;
+    if ((e = up(m->centre64, m->h_centre.data(), m->h_centre.size() * sizeof(double)))) return e;
+    if ((e = up(m->bucket_cells, order.data(), order.size() * sizeof(int)))) return e;
+    if ((e = up(m->fused_order, byM.data(), byM.size() * sizeof(int)))) return e;
+    KSDF_HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(int), s));
+    if (m->precision == KSDF_FP32) {
+      // the padding past the last cell is read by chunked loads: keep it zero
+      KSDF_HIP_TRY(hipMemsetAsync(m->ps32, 0, 4L * (nnz + KSDF_PAD_SAMPLES) * sizeof(float), s));
+      KSDF_HIP_TRY(hipMemsetAsync(m->sv32, 0, (nnz + KSDF_PAD_SAMPLES) * sizeof(float), s));
+      KSDF_HIP_TRY(hipMemsetAsync(m->L32, 0, (lsize + KSDF_PAD_FACTOR) * sizeof(float), s));
+    }
+    // the index's count pass synchronises the stream, after which the host vectors
+    // above may go
+    return index_count(m, s);
+  }();
+  if (r) {
+    destroy_model(m);
+    return r;
   }
-  TRY(build_candidate_index(m, query_lo, query_hi));
   *out = m;
   return KSDF_OK;
 }
 
+extern "C" size_t ksdf_model_index_bytes(const ksdf_model* m) {
+  return m ? std::max<long>(m->index.entries, 1) * sizeof(int) : 0;
+}
+
+extern "C" int ksdf_model_attach_index(ksdf_model* m, void* list, size_t bytes, void* stream) {
+  if (!m || !list || bytes < ksdf_model_index_bytes(m)) {
+    set_error("ksdf_model_attach_index: list buffer missing or smaller than ksdf_model_index_bytes");
+    return KSDF_ERR_WORKSPACE;
+  }
+  if (reinterpret_cast<uintptr_t>(list) % 4 != 0) {
+    set_error("ksdf_model_attach_index: the list buffer must be 4-byte aligned");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  m->index.box_list = static_cast<int*>(list);
+  r = index_fill(m, (hipStream_t)stream);
+  if (r) return r;
+  m->device_bytes = m->store_bytes + ksdf_model_index_bytes(m);
+  m->index_ready = true;
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_model_check(ksdf_model* m, void* stream) {
+  if (!m) {
+    set_error("ksdf_model_check: model is null");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  hipStream_t s = (hipStream_t)stream;
+  int flags = 0;
+  KSDF_HIP_TRY(hipMemcpyAsync(&flags, m->flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  KSDF_HIP_TRY(hipStreamSynchronize(s));
+  if (flags & 1) {
+    KSDF_HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(int), s));
+    set_error("a fused fit+query launch stopped waiting for the fits; its queries marked "
+              "KSDF_Q_FIT_TIMEOUT may have read unfinished cells");
+    return KSDF_ERR_TIMEOUT;
+  }
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_model_set_wait_limit(ksdf_model* m, long sleeps) {
+  if (!m || sleeps < 0) {
+    set_error("ksdf_model_set_wait_limit: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  m->wait_limit = sleeps == 0 ? (1L << 26) : sleeps;
+  return KSDF_OK;
+}
+
 extern "C" void ksdf_model_destroy(ksdf_model* model) {
-  if (model) (void)hipDeviceSynchronize();
-  free_model(model);
+  destroy_model(model);
 }
 
 extern "C" int ksdf_model_info(const ksdf_model* m, int* n_cells, long* nnz, int* max_m,
@@ -353,15 +462,23 @@ extern "C" int ksdf_refit_cells(ksdf_model* m, const void* surface_pts, int dtyp
                       n_refit, cell_status, workspace, (hipStream_t)stream);
 }
 
+extern "C" size_t ksdf_count_queries_workspace_bytes(const ksdf_model* m) {
+  return m ? count_queries_workspace_bytes(m) : 0;
+}
+
 extern "C" int ksdf_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount,
-                                  float cap, void* stream) {
+                                  float cap, void* workspace, size_t ws_bytes, void* stream) {
   if (!m || Q < 0 || (Q > 0 && !argmin) || !qcount || !(cap >= 0)) {
     set_error("ksdf_count_queries: invalid argument");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
+  if (!workspace || ws_bytes < count_queries_workspace_bytes(m)) {
+    set_error("ksdf_count_queries: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
   int r = check_device(m);
   if (r) return r;
-  return launch_count_queries(m, argmin, Q, qcount, cap, (hipStream_t)stream);
+  return launch_count_queries(m, argmin, Q, qcount, cap, workspace, (hipStream_t)stream);
 }
 
 extern "C" size_t ksdf_fit_query_workspace_bytes(const ksdf_model* m, long Q) {
@@ -378,6 +495,10 @@ extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype,
   int r = prepare_fit(m, surface_pts, dtype, n_points, sample_var, hyper);
   if (r) return r;
   if ((r = check_query_args(m, points, Q, mean, grad, var))) return r;
+  if (!m->index_ready) {
+    set_error("ksdf_fit_query: the model's index is not attached");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
   const size_t need = ksdf_fit_query_workspace_bytes(m, Q);
   if (ws_bytes < need || (need > 0 && !workspace)) {
     set_error("ksdf_fit_query: workspace too small");
@@ -415,15 +536,12 @@ extern "C" int ksdf_model_set_tuning(ksdf_model* m, const ksdf_tuning* t) {
     set_error("ksdf_model_set_tuning: invalid tuning");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
-  // the dense L^{-1} of the matrix-core pass 2 (two-kernel RBF query of an FP32 model),
-  // allocated when first asked for
-  if (t->query_mfma && !m->Linv32 && m->precision == KSDF_FP32 && m->kernel == KSDF_KERNEL_RBF &&
+  // the matrix-core pass 2 (two-kernel RBF query of an FP32 model with m <= 64) reads
+  // the dense inverses, which the store holds only when created with KSDF_FIT_DENSE_INV
+  if (t->query_mfma && !m->dense_inv && m->precision == KSDF_FP32 && m->kernel == KSDF_KERNEL_RBF &&
       m->max_m <= 64 && m->n_cells > 0) {
-    int r = check_device(m);
-    if (r) return r;
-    r = dalloc(m, &m->Linv32, 4096L * m->n_cells);   // on failure the model is unchanged
-    if (r) return r;
-    m->linv_ok = false;
+    set_error("ksdf_model_set_tuning: query_mfma needs a model created with KSDF_FIT_DENSE_INV");
+    return KSDF_ERR_UNSUPPORTED;
   }
   m->tuning = *t;
   if (m->tuning.query_block == 0) m->tuning.query_block = 256;
@@ -477,8 +595,8 @@ extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const
                           void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                           uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
   if (int r0 = check_query_args(m, points, Q, mean, grad, var)) return r0;
-  if (!m->fitted) {
-    set_error("ksdf_query: the model has not been fitted");
+  if (!m->fitted || !m->index_ready) {
+    set_error("ksdf_query: the model has not been fitted or its index is not attached");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   const size_t need = query_workspace_bytes(m, Q);
@@ -505,8 +623,8 @@ extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long
     set_error("ksdf_query_backward: invalid argument");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
-  if (!m->fitted) {
-    set_error("ksdf_query_backward: the model has not been fitted");
+  if (!m->fitted || !m->index_ready) {
+    set_error("ksdf_query_backward: the model has not been fitted or its index is not attached");
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   const size_t need = backward_workspace_bytes(m, Q);
@@ -530,6 +648,7 @@ extern "C" const char* ksdf_status_string(int status) {
     case KSDF_ERR_DEVICE: return "no usable device / wrong device";
     case KSDF_ERR_UNSUPPORTED: return "unsupported";
     case KSDF_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case KSDF_ERR_TIMEOUT: return "a bounded wait expired";
     default: return "unknown status";
   }
 }

@@ -110,26 +110,38 @@ __global__ void __launch_bounds__(256) refit_reset_kernel(const int* sel, const 
   qcount[c] = 0.5f * qcount[c];
 }
 
-// One atomic per distinct cell of a wave (queries that arrive spatially ordered mostly
-// share their argmin cell within a wave); each adds the wave's count for that cell, a
-// whole number, so the float sums are exact in any order.
-__global__ void __launch_bounds__(256) count_queries_kernel(const int* argmin, long Q, float* qcount) {
+// Query counters of App. G in two steps, so that the result does not depend on the
+// order of the atomics: an integer histogram of the argmin cells (one atomic per
+// distinct cell of a wave; queries that arrive spatially ordered mostly share their
+// argmin cell within a wave), then one addition per cell, c0 = min(c0 + count, cap),
+// rounded once.  (Halving on refit leaves c0 fractional, so float atomics adding
+// counts to it directly would round differently in different orders.)  Argmins
+// outside [0, n_cells) are not counted.
+__global__ void __launch_bounds__(256) zero_kernel(unsigned* h, int n) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c < n) h[c] = 0u;
+}
+
+__global__ void __launch_bounds__(256) count_queries_kernel(const int* argmin, long Q, int n_cells,
+                                                            unsigned* hist) {
   const long q = (long)blockIdx.x * 256 + threadIdx.x;
-  const int c = q < Q ? argmin[q] : -1;
+  int c = q < Q ? argmin[q] : -1;
+  if (c >= n_cells) c = -1;
   const int lane = threadIdx.x & 63;
   unsigned long long todo = __ballot(c >= 0);
   while (todo) {
     const int leader = __ffsll((long long)todo) - 1;
     const int key = __shfl(c, leader, 64);
     const unsigned long long same = __ballot(c == key) & todo;
-    if (lane == leader) atomicAdd(qcount + key, (float)__popcll(same));
+    if (lane == leader) atomicAdd(hist + key, (unsigned)__popcll(same));
     todo &= ~same;
   }
 }
 
-__global__ void __launch_bounds__(256) cap_kernel(float* qcount, int n, float cap) {
+__global__ void __launch_bounds__(256) count_apply_kernel(const unsigned* hist, float* qcount, int n,
+                                                          float cap) {
   const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c < n) qcount[c] = fminf(qcount[c], cap);
+  if (c < n) qcount[c] = fminf(qcount[c] + (float)hist[c], cap);
 }
 
 // Dense L^{-1} of each cell (64 x 64, column-major, zero beyond m) from the packed
@@ -246,14 +258,21 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
   return KSDF_OK;
 }
 
+size_t count_queries_workspace_bytes(const ksdf_model* m) {
+  return (size_t)std::max(m->n_cells, 1) * sizeof(unsigned);
+}
+
 int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount, float cap,
-                         hipStream_t s) {
+                         void* ws, hipStream_t s) {
+  const int n = m->n_cells;
+  if (n == 0) return KSDF_OK;
+  unsigned* hist = static_cast<unsigned*>(ws);
+  const unsigned gc = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(zero_kernel, dim3(gc), dim3(256), 0, s, hist, n);
   if (Q > 0)
     hipLaunchKernelGGL(count_queries_kernel, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s,
-                       argmin, Q, qcount);
-  if (m->n_cells > 0)
-    hipLaunchKernelGGL(cap_kernel, dim3((unsigned)((m->n_cells + 255) / 256)), dim3(256), 0, s,
-                       qcount, m->n_cells, cap);
+                       argmin, Q, n, hist);
+  hipLaunchKernelGGL(count_apply_kernel, dim3(gc), dim3(256), 0, s, hist, qcount, n, cap);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

@@ -8,8 +8,10 @@
 // Every fit task is dequeued before any query task, so a workgroup that holds a query
 // task waits (acquire) only for fit tasks that other running workgroups already hold:
 // the wait always ends.  No query reads cell data before every fit has released its
-// writes, so no cache can hold a stale copy of them.  The spin is bounded; on expiry
-// the launch records an error flag instead of waiting further.
+// writes, so no cache can hold a stale copy of them.  The spin is bounded (a per-model
+// limit, settable for tests); on expiry the workgroup stops waiting, every query it
+// then answers carries KSDF_Q_FIT_TIMEOUT, and the model's flag in its store records
+// the expiry for ksdf_model_check.
 #include "fit_dev.h"
 #include "query_dev.h"
 
@@ -22,10 +24,11 @@ constexpr int WAVES = FT / 64;
 struct FusedCtl {
   int* next;          // task counter
   int* done;          // fit tasks completed
-  int* timeout;       // set when a wait expired
+  int* timeout;       // the model's flag (store-resident): set when a wait expired
   const int* order;   // cells in fit order (m descending)
   int n_fit;
   long n_qtasks;
+  long spin_limit;    // sleeps before a wait gives up
 };
 
 // Fit tasks and query tiles run in two consecutive loops (a workgroup's first query
@@ -73,28 +76,36 @@ __global__ void __launch_bounds__(FT) fused_kernel(FitArgs F, FastArgs Q, FusedC
   }
   if (t >= n_total) return;
   // every fit task has been taken: wait until they have all been released
+  __shared__ int expired_sh;
   if (threadIdx.x == 0) {
     long spins = 0;
+    int expired = 0;
     while (__hip_atomic_load(C.done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < C.n_fit) {
-      __builtin_amdgcn_s_sleep(8);
-      if (++spins > (1L << 26)) {
-        atomicExch(C.timeout, 1);
+      if (spins >= C.spin_limit) {
+        expired = 1;
+        atomicOr(C.timeout, 1);
         break;
       }
+      __builtin_amdgcn_s_sleep(8);
+      ++spins;
     }
+    expired_sh = expired;
   }
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const bool expired = expired_sh != 0;
   const int wave = threadIdx.x / 64;
   do {
     const long sq = ((t - C.n_fit) * WAVES + wave) * 64 + (threadIdx.x & 63);
-    query_tile<KM, MB>(Q, sq);
+    Pass1 p1 = query_pass1<KM>(Q, sq);
+    if (expired) p1.flags |= PASS1_FIT_TIMEOUT;   // the cells it read may be unreleased
+    query_finish<MB>(Q, p1);
     t = grab();
   } while (t < n_total);
 }
 
 __global__ void fused_reset_kernel(int* ctl) {
-  if (threadIdx.x < 3) ctl[threadIdx.x] = 0;
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0;
 }
 
 template <int KM, int MB, int MF>
@@ -149,7 +160,8 @@ int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void
   FusedCtl C{};
   C.next = ctl;
   C.done = ctl + 1;
-  C.timeout = ctl + 2;
+  C.timeout = m->flags;
+  C.spin_limit = m->wait_limit;
   C.order = m->fused_order;
   C.n_fit = m->n_cells;
   C.n_qtasks = (Q + FT - 1) / FT;

@@ -10,7 +10,9 @@
 //
 // One wave per box: lanes stride over the cells keeping a private sorted top-K of
 // farthest distances, K rounds of a wave-wide min merge give D_K, and a ballot
-// prefix writes the list in id order.  Built once per model (structure only).
+// prefix writes the list in id order.  Built once per model (structure only), in
+// two passes: the count pass fixes each box's list length (and so the list's size,
+// which the caller then provides), the fill pass writes the lists.
 #include <algorithm>
 #include <cmath>
 #include <utility>
@@ -141,7 +143,7 @@ __global__ void __launch_bounds__(IDX_THREADS) index_fill_kernel(IndexArgs A) {
 
 }  // namespace
 
-int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi) {
+int index_lattice(ksdf_model* m, const double* qlo, const double* qhi) {
   CandidateIndex& X = m->index;
   // lattice: occupied keys padded by two boxes, grown to cover the query box
   long klo[3] = {0, 0, 0}, khi[3] = {0, 0, 0};
@@ -162,8 +164,8 @@ int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi) {
     }
   long n_boxes = 1;
   for (int d = 0; d < 3; ++d) {
-    X.lo[d] = (int)klo[d];
-    X.dims[d] = (int)(khi[d] - klo[d] + 1);
+    X.lo[d] = m->n_cells ? (int)klo[d] : 0;
+    X.dims[d] = m->n_cells ? (int)(khi[d] - klo[d] + 1) : 0;
     n_boxes *= X.dims[d];
   }
   if (m->n_cells == 0 || n_boxes > (64L << 20)) {
@@ -174,6 +176,12 @@ int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi) {
     n_boxes = 0;
   }
   X.n_boxes = n_boxes;
+  return KSDF_OK;
+}
+
+namespace {
+IndexArgs index_args(const ksdf_model* m) {
+  const CandidateIndex& X = m->index;
   IndexArgs A{};
   A.centre = m->centre64;
   A.n_cells = m->n_cells;
@@ -184,64 +192,70 @@ int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi) {
     A.dims[d] = X.dims[d];
   }
   A.h = m->h;
-  A.n_boxes = n_boxes;
+  A.n_boxes = X.n_boxes;
+  A.bound = X.bound;
+  A.counts = X.counts;
+  A.off = X.box_off;
+  A.list = X.box_list;
+  return A;
+}
+}  // namespace
+
+int index_count(ksdf_model* m, hipStream_t s) {
+  CandidateIndex& X = m->index;
+  const long n_boxes = X.n_boxes;
+  X.entries = 0;
+  X.max_list = 0;
+  if (n_boxes == 0) return KSDF_OK;
+  IndexArgs A = index_args(m);
+  const unsigned grid = (unsigned)((n_boxes + BOXES_PER_BLOCK - 1) / BOXES_PER_BLOCK);
+  hipLaunchKernelGGL(index_count_kernel, dim3(grid), dim3(IDX_THREADS), 0, s, A);
+  KSDF_HIP_TRY(hipGetLastError());
+  std::vector<int> cnt(n_boxes);
+  KSDF_HIP_TRY(hipMemcpyAsync(cnt.data(), X.counts, n_boxes * sizeof(int), hipMemcpyDeviceToHost, s));
+  KSDF_HIP_TRY(hipStreamSynchronize(s));
   std::vector<int> off(n_boxes + 1, 0);
-  if (n_boxes > 0) {
-    double* bound = nullptr;
-    int* counts = nullptr;
-    KSDF_HIP_TRY(hipMalloc(&bound, n_boxes * sizeof(double)));
-    KSDF_HIP_TRY(hipMalloc(&counts, n_boxes * sizeof(int)));
-    A.bound = bound;
-    A.counts = counts;
-    const unsigned grid = (unsigned)((n_boxes + BOXES_PER_BLOCK - 1) / BOXES_PER_BLOCK);
-    hipLaunchKernelGGL(index_count_kernel, dim3(grid), dim3(IDX_THREADS), 0, 0, A);
-    KSDF_HIP_TRY(hipGetLastError());
-    std::vector<int> cnt(n_boxes);
-    KSDF_HIP_TRY(hipMemcpy(cnt.data(), counts, n_boxes * sizeof(int), hipMemcpyDeviceToHost));
-    long total = 0;
-    int mx = 0;
-    for (long b = 0; b < n_boxes; ++b) {
-      off[b] = (int)total;
-      total += cnt[b];
-      mx = std::max(mx, cnt[b]);
-    }
-    off[n_boxes] = (int)total;
-    if (total > INT32_MAX) {
-      (void)hipFree(bound);
-      (void)hipFree(counts);
-      set_error("candidate index too large");
-      return KSDF_ERR_UNSUPPORTED;
-    }
-    X.entries = total;
-    X.max_list = mx;
-    KSDF_HIP_TRY(hipMalloc(&X.box_off, (n_boxes + 1) * sizeof(int)));
-    KSDF_HIP_TRY(hipMalloc(&X.box_list, std::max<long>(total, 1) * sizeof(int)));
-    KSDF_HIP_TRY(hipMemcpy(X.box_off, off.data(), (n_boxes + 1) * sizeof(int), hipMemcpyHostToDevice));
-    A.off = X.box_off;
-    A.list = X.box_list;
-    hipLaunchKernelGGL(index_fill_kernel, dim3(grid), dim3(IDX_THREADS), 0, 0, A);
-    KSDF_HIP_TRY(hipGetLastError());
-    KSDF_HIP_TRY(hipDeviceSynchronize());
-    (void)hipFree(bound);
-    (void)hipFree(counts);
-    // Z-order rank of every box: query bucketing orders its bins by it, so that the
-    // queries of one wave stay spatially compact also where they are sparse
-    std::vector<std::pair<uint64_t, int>> z(n_boxes);
-    for (long b = 0; b < n_boxes; ++b) {
-      const long bx = b % X.dims[0], by = (b / X.dims[0]) % X.dims[1], bz = b / ((long)X.dims[0] * X.dims[1]);
-      uint64_t code = 0;
-      for (int bit = 0; bit < 21; ++bit)
-        code |= (((uint64_t)(bx >> bit) & 1) << (3 * bit)) | (((uint64_t)(by >> bit) & 1) << (3 * bit + 1)) |
-                (((uint64_t)(bz >> bit) & 1) << (3 * bit + 2));
-      z[b] = {code, (int)b};
-    }
-    std::sort(z.begin(), z.end());
-    std::vector<int> rank(n_boxes);
-    for (long r = 0; r < n_boxes; ++r) rank[z[r].second] = (int)r;
-    KSDF_HIP_TRY(hipMalloc(&X.box_rank, n_boxes * sizeof(int)));
-    KSDF_HIP_TRY(hipMemcpy(X.box_rank, rank.data(), n_boxes * sizeof(int), hipMemcpyHostToDevice));
-    m->device_bytes += (2 * n_boxes + 1 + std::max<long>(total, 1)) * sizeof(int);
+  long total = 0;
+  int mx = 0;
+  for (long b = 0; b < n_boxes; ++b) {
+    off[b] = (int)total;
+    total += cnt[b];
+    mx = std::max(mx, cnt[b]);
   }
+  if (total > INT32_MAX) {
+    set_error("candidate index too large");
+    return KSDF_ERR_UNSUPPORTED;
+  }
+  off[n_boxes] = (int)total;
+  X.entries = total;
+  X.max_list = mx;
+  // Z-order rank of every box: query bucketing orders its bins by it, so that the
+  // queries of one wave stay spatially compact also where they are sparse
+  std::vector<std::pair<uint64_t, int>> z(n_boxes);
+  for (long b = 0; b < n_boxes; ++b) {
+    const long bx = b % X.dims[0], by = (b / X.dims[0]) % X.dims[1], bz = b / ((long)X.dims[0] * X.dims[1]);
+    uint64_t code = 0;
+    for (int bit = 0; bit < 21; ++bit)
+      code |= (((uint64_t)(bx >> bit) & 1) << (3 * bit)) | (((uint64_t)(by >> bit) & 1) << (3 * bit + 1)) |
+              (((uint64_t)(bz >> bit) & 1) << (3 * bit + 2));
+    z[b] = {code, (int)b};
+  }
+  std::sort(z.begin(), z.end());
+  std::vector<int> rank(n_boxes);
+  for (long r = 0; r < n_boxes; ++r) rank[z[r].second] = (int)r;
+  KSDF_HIP_TRY(hipMemcpyAsync(X.box_off, off.data(), (n_boxes + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  KSDF_HIP_TRY(hipMemcpyAsync(X.box_rank, rank.data(), n_boxes * sizeof(int), hipMemcpyHostToDevice, s));
+  // the host vectors go out of scope on return
+  KSDF_HIP_TRY(hipStreamSynchronize(s));
+  return KSDF_OK;
+}
+
+int index_fill(ksdf_model* m, hipStream_t s) {
+  if (m->index.n_boxes == 0) return KSDF_OK;
+  IndexArgs A = index_args(m);
+  const unsigned grid = (unsigned)((m->index.n_boxes + BOXES_PER_BLOCK - 1) / BOXES_PER_BLOCK);
+  hipLaunchKernelGGL(index_fill_kernel, dim3(grid), dim3(IDX_THREADS), 0, s, A);
+  KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }
 

@@ -39,12 +39,15 @@ struct CandidateIndex {
   int* box_off = nullptr;      // [n_boxes+1]
   int* box_list = nullptr;     // [entries] cell ids, ascending within a box
   int* box_rank = nullptr;     // [n_boxes] position of each box in Z (Morton) order
+  double* bound = nullptr;     // [n_boxes] squared inclusion bound (count pass)
+  int* counts = nullptr;       // [n_boxes] list lengths (count pass)
   int max_list = 0;
 };
 
 }  // namespace ksdf
 
-// The model: per-cell store and candidate index (device memory owned by the model).
+// The model: per-cell store and candidate index, views into caller-owned device
+// memory (the store buffer and the index list buffer).
 struct ksdf_model {
   int device = 0;
   int n_cu = 0;  // compute units of the device
@@ -108,6 +111,11 @@ struct ksdf_model {
 
   ksdf::CandidateIndex index;
   ksdf_tuning tuning{0, 256, 1, 16, 1, 0, 0, 0, 0};
+  bool dense_inv = false;       // the store holds Linv32 (KSDF_FIT_DENSE_INV)
+  int* flags = nullptr;         // [1] (store) bit 0: a fused launch's wait for the fits expired
+  long wait_limit = 1L << 26;   // sleeps before the fused launch's wait gives up
+  bool index_ready = false;     // the candidate lists are attached and filled
+  size_t store_bytes = 0;
   // kernel timing: one event pair per phase, recorded when timing is on
   bool timing = false;
   hipEvent_t tev[KSDF_TIMER_COUNT][KSDF_TIMER_SLOTS][2] = {};
@@ -133,7 +141,12 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
 // computed after each fit while query_mfma is on, else marked stale (and then
 // computed by the first query that needs it)
 void launch_linv(const ksdf_model* m, hipStream_t s);
-int build_candidate_index(ksdf_model* m, const double* qlo, const double* qhi);
+// candidate index: lattice from the cell centres and the query box (host), the
+// count pass (fixes entries; synchronises the stream) and the fill pass (needs
+// index.box_list)
+int index_lattice(ksdf_model* m, const double* qlo, const double* qhi);
+int index_count(ksdf_model* m, hipStream_t s);
+int index_fill(ksdf_model* m, hipStream_t s);
 // sign from BHM weights
 size_t bhm_tau_workspace_bytes(long K);
 int launch_bhm_sign(const ksdf_bhm_layout* L, const int* box_bhm, const double* weights,
@@ -147,8 +160,9 @@ size_t refit_workspace_bytes(const ksdf_model* m, int budget);
 int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, float* dirty,
                  float* qcount, double eta, int budget, int* sel, int* n_sel, uint8_t* user_status,
                  void* ws, hipStream_t s);
+size_t count_queries_workspace_bytes(const ksdf_model* m);
 int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount, float cap,
-                         hipStream_t s);
+                         void* ws, hipStream_t s);
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
                  void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
                  size_t ws_bytes, hipStream_t s);

@@ -60,8 +60,10 @@ struct Pass1 {
   float qx, qy, qz, best;
   int qi, bc;
   float bref;
-  int flags;   // bit 0: query outside the candidate index; bit 1: active lane
+  int flags;   // bit 0: query outside the candidate index; bit 1: active lane;
+               // bit 2 (PASS1_FIT_TIMEOUT): read cells whose fit may be unreleased
 };
+constexpr int PASS1_FIT_TIMEOUT = 4;
 
 // two-kernel query launches (query_split{64,256}_{wave,lane}.hip)
 void launch_query_split_64_wave(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
@@ -768,6 +770,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   if (!active) return;
   const float sgn = A.sign ? (float)A.sign[qi] : 1.f;
   uint8_t st = outside ? KSDF_Q_OUTSIDE_INDEX : 0;
+  if (p1.flags & PASS1_FIT_TIMEOUT) st |= KSDF_Q_FIT_TIMEOUT;
   if (bc < 0) {
     if (A.grad_var) {
       A.grad_var[3 * qi] = INFINITY;

@@ -25,17 +25,19 @@ LIB_PATH = os.path.join(_HERE, "libksdf.so")
 
 FP64, FP32 = 0, 1
 DTYPE_F32, DTYPE_F64 = 0, 1
-Q_NO_VALID_CELL, Q_CLAMPED, Q_GRAD_ZERO, Q_OUTSIDE_INDEX = 1, 2, 4, 8
+Q_NO_VALID_CELL, Q_CLAMPED, Q_GRAD_ZERO, Q_OUTSIDE_INDEX, Q_FIT_TIMEOUT = 1, 2, 4, 8, 16
 C_FP64, C_FAILED = 1, 2
-FIT_ADJOINT, FIT_ADJOINT_VARF = 1, 2
+FIT_ADJOINT, FIT_ADJOINT_VARF, FIT_DENSE_INV = 1, 2, 4
 
 EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_cellset_destroy",
-           "ksdf_model_create", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
+           "ksdf_model_bytes", "ksdf_model_create", "ksdf_model_index_bytes",
+           "ksdf_model_attach_index", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
            "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
            "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
-           "ksdf_count_queries", "ksdf_bhm_sign", "ksdf_bhm_tau_workspace_bytes",
+           "ksdf_count_queries_workspace_bytes", "ksdf_count_queries", "ksdf_model_check",
+           "ksdf_model_set_wait_limit", "ksdf_bhm_sign", "ksdf_bhm_tau_workspace_bytes",
            "ksdf_bhm_update_tau", "ksdf_status_string",
            "ksdf_last_error"]
 
@@ -130,7 +132,13 @@ def lib():
         L.ksdf_cellset_copy.argtypes = [_vp, _vp, _vp, _vp]
         L.ksdf_cellset_destroy.argtypes = [_vp]
         L.ksdf_cellset_destroy.restype = None
-        L.ksdf_model_create.argtypes = [i, _vp, _vp, _vp, pd, d, l, H, pd, pd, ctypes.POINTER(_vp)]
+        L.ksdf_model_bytes.argtypes = [i, _vp, _vp, _vp, pd, d, l, H, pd, pd]
+        L.ksdf_model_bytes.restype = sz
+        L.ksdf_model_create.argtypes = [i, _vp, _vp, _vp, pd, d, l, H, pd, pd, _vp, sz, _vp,
+                                        ctypes.POINTER(_vp)]
+        L.ksdf_model_index_bytes.argtypes = [_vp]
+        L.ksdf_model_index_bytes.restype = sz
+        L.ksdf_model_attach_index.argtypes = [_vp, _vp, sz, _vp]
         L.ksdf_model_destroy.argtypes = [_vp]
         L.ksdf_model_destroy.restype = None
         L.ksdf_model_info.argtypes = [_vp, pi, pl, pi, pl, psz]
@@ -151,7 +159,11 @@ def lib():
         L.ksdf_refit_workspace_bytes.restype = sz
         L.ksdf_refit_cells.argtypes = [_vp, _vp, i, l, _vp, _vp, _vp, ctypes.c_double, i, _vp, _vp,
                                        _vp, _vp, sz, _vp]
-        L.ksdf_count_queries.argtypes = [_vp, _vp, l, _vp, ctypes.c_float, _vp]
+        L.ksdf_count_queries_workspace_bytes.argtypes = [_vp]
+        L.ksdf_count_queries_workspace_bytes.restype = sz
+        L.ksdf_count_queries.argtypes = [_vp, _vp, l, _vp, ctypes.c_float, _vp, sz, _vp]
+        L.ksdf_model_check.argtypes = [_vp, _vp]
+        L.ksdf_model_set_wait_limit.argtypes = [_vp, l]
         L.ksdf_bhm_sign.argtypes = [ctypes.POINTER(BhmLayout), _vp, _vp, _vp, i, l, d, _vp, _vp, _vp]
         L.ksdf_bhm_tau_workspace_bytes.argtypes = [l]
         L.ksdf_bhm_tau_workspace_bytes.restype = sz
@@ -233,40 +245,52 @@ def _stream(stream):
 
 
 class Model:
-    """A fitted set of local GPs (device memory owned by the library)."""
+    """A fitted set of local GPs.  Its device memory (the per-cell store and the
+    candidate lists) is two torch tensors this object owns; the library only holds
+    views into them."""
 
     def __init__(self, cells: CellSet, n_points: int, origin, h: float, ell: float = 0.2,
                  noise_var: float = 1e-4, k_fuse: int = 8, precision: str = "fp32",
                  alpha: Optional[float] = None, cond_threshold: float = 1e6, query_box=None,
-                 adjoint: bool = False, adjoint_var_f: bool = False, kernel: str = "rbf"):
+                 adjoint: bool = False, adjoint_var_f: bool = False, kernel: str = "rbf",
+                 dense_inverse: bool = False, stream=None):
         if not torch.cuda.is_available():
             raise KsdfError("no GPU: libksdf needs a gfx950 device")
         self._lib = lib()
+        self._h = ctypes.c_void_p()
         self.cells = cells
         self.n_points = int(n_points)
         self.origin = tuple(float(v) for v in origin)
         self.h = float(h)
         self.precision = FP64 if precision == "fp64" else FP32
         self.dtype = torch.float64 if self.precision == FP64 else torch.float32
-        flags = (FIT_ADJOINT if adjoint or adjoint_var_f else 0) | (FIT_ADJOINT_VARF if adjoint_var_f else 0)
+        flags = ((FIT_ADJOINT if adjoint or adjoint_var_f else 0) |
+                 (FIT_ADJOINT_VARF if adjoint_var_f else 0) | (FIT_DENSE_INV if dense_inverse else 0))
         if kernel not in KERNELS:
             raise ValueError(f"kernel must be one of {sorted(KERNELS)}")
         self.kernel = kernel
+        self.dense_inverse = bool(dense_inverse)
         self.hyper = Hyper(float(ell), float(noise_var), -1.0 if alpha is None else float(alpha),
                            int(k_fuse), self.precision, float(cond_threshold), flags,
                            KERNELS[kernel])
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self._h = ctypes.c_void_p()
         qlo = qhi = None
         if query_box is not None:
             qlo, qhi = _d3(query_box[0]), _d3(query_box[1])
         off = np.ascontiguousarray(cells.offsets, np.int32)
         smp = np.ascontiguousarray(cells.samples, np.int32)
         keys = np.ascontiguousarray(cells.keys, np.int32)
-        _check(self._lib.ksdf_model_create(cells.n, off.ctypes.data, smp.ctypes.data,
-                                           keys.ctypes.data, _d3(origin), self.h, self.n_points,
-                                           ctypes.byref(self.hyper), qlo, qhi,
+        args = (cells.n, off.ctypes.data, smp.ctypes.data, keys.ctypes.data, _d3(origin), self.h,
+                self.n_points, ctypes.byref(self.hyper), qlo, qhi)
+        nb = self._lib.ksdf_model_bytes(*args)
+        # the store and the candidate lists are caller-owned device memory
+        self._store = torch.empty(max(nb, 1), dtype=torch.uint8, device=self.device)
+        _check(self._lib.ksdf_model_create(*args, _ptr(self._store), nb, _stream(stream),
                                            ctypes.byref(self._h)), "ksdf_model_create")
+        ib = self._lib.ksdf_model_index_bytes(self._h)
+        self._index = torch.empty(ib, dtype=torch.uint8, device=self.device)
+        _check(self._lib.ksdf_model_attach_index(self._h, _ptr(self._index), ib, _stream(stream)),
+               "ksdf_model_attach_index")
         self._ws = None
         self.points = None
         self.sample_var = None
@@ -450,17 +474,35 @@ class Model:
         return cells, n
 
     def count_queries(self, argmin: torch.Tensor, qcount: torch.Tensor, cap: float = 10000.0,
-                      stream=None):
-        """App. G query counters: qcount[argmin] += 1 (valid argmins), capped at cap."""
+                      stream=None, workspace: Optional[torch.Tensor] = None):
+        """App. G query counters: qcount[c] = min(qcount[c] + #(argmin == c), cap) for
+        the valid argmin cells, one rounding per cell."""
         if argmin.dtype != torch.int32 or qcount.dtype != torch.float32:
             raise ValueError("argmin must be int32 and qcount float32")
+        if not qcount.is_cuda or qcount.numel() != self.n_cells:
+            raise ValueError("qcount must be a float32 CUDA tensor of n_cells")
+        nb = self._lib.ksdf_count_queries_workspace_bytes(self._h)
+        ws = self._workspace(nb, workspace)
         _check(self._lib.ksdf_count_queries(self._h, _ptr(argmin), argmin.numel(), _ptr(qcount),
-                                            float(cap), _stream(stream)), "ksdf_count_queries")
+                                            float(cap), _ptr(ws), nb, _stream(stream)),
+               "ksdf_count_queries")
+
+    def check(self, stream=None):
+        """Raise if a fused fit+query launch stopped waiting for the fits since the last
+        check (its queries carry Q_FIT_TIMEOUT); synchronises the stream."""
+        _check(self._lib.ksdf_model_check(self._h, _stream(stream)), "ksdf_model_check")
+
+    def set_wait_limit(self, sleeps: int):
+        """Bound of the fused launch's wait for the fits, in sleeps (0: the default)."""
+        _check(self._lib.ksdf_model_set_wait_limit(self._h, int(sleeps)), "ksdf_model_set_wait_limit")
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
+            # launches may still read the store: let them finish before it is released
+            torch.cuda.synchronize(self.device)
             self._lib.ksdf_model_destroy(self._h)
             self._h = ctypes.c_void_p()
+            self._store = self._index = self._ws = None
 
     def __del__(self):
         try:

@@ -75,6 +75,8 @@ def apply(model, n_queries: int, kind: str = "fit_query", cache_path: str = DEFA
     """Set the cached tuning for this call on the model; None if there is none."""
     t = cached(model, n_queries, kind, cache_path)
     if t is not None:
+        if not model.dense_inverse:
+            t = {**t, "query_mfma": 0}   # the model has no room for the dense inverses
         model.set_tuning(**t)
     return t
 
@@ -93,7 +95,7 @@ def _median_ms(fn, reps: int) -> float:
     return float(np.median(times))
 
 
-def _valid(t: dict, fp64: bool) -> bool:
+def _valid(t: dict, fp64: bool, dense_inverse: bool = True) -> bool:
     if fp64 and (t.get("fused", 0) == 1 or t.get("fit_min_bucket", 16) != 16 or
                  t.get("query_split", 0) == 1 or t.get("query_lanes", 0) == 1):
         return False   # FP64 models fit per cell and query on the plain path
@@ -104,9 +106,10 @@ def _valid(t: dict, fp64: bool) -> bool:
     if t.get("query_pairs", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or
                                          t.get("fused", 0) == 1):
         return False   # pairs apply to the two-kernel FP32 query
-    if t.get("query_mfma", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or
+    if t.get("query_mfma", 0) == 1 and (t.get("query_split", 0) == 0 or fp64 or not dense_inverse or
                                         t.get("query_lanes", 0) == 1 or t.get("fused", 0) == 1):
         return False   # the matrix-core pass 2 needs wave-shared cells in the two-kernel query
+                       # and a model created with room for the dense inverses
     return True
 
 
@@ -115,7 +118,7 @@ def _search(model, keys, run, reps, log):
     base = model.tuning()
     for combo in itertools.product(*(KNOBS[k] for k in keys)):
         t = {**base, **dict(zip(keys, combo))}
-        if not _valid(t, model.precision == FP64):
+        if not _valid(t, model.precision == FP64, model.dense_inverse):
             continue
         model.set_tuning(**t)
         ms = _median_ms(run, reps)

@@ -1,5 +1,6 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports every
 symbol ksdf.h declares, and its host cell builder agrees with the oracle's."""
+import ctypes
 import os
 import re
 
@@ -61,3 +62,37 @@ def test_status_strings():
     L = ksdf.lib()
     assert L.ksdf_status_string(0) == b"ok"
     assert b"workspace" in L.ksdf_status_string(-3)
+
+
+def _bytes(cells, wl, flags=0, precision=ksdf.FP32, qbox=None, k_fuse=8):
+    L = ksdf.lib()
+    hp = ksdf.Hyper(wl.ell, wl.noise_var, -1.0, k_fuse, precision, 1e6, flags, 0)
+    off = np.ascontiguousarray(cells.offsets, np.int32)
+    smp = np.ascontiguousarray(cells.samples, np.int32)
+    keys = np.ascontiguousarray(cells.keys, np.int32)
+    lo = hi = None
+    if qbox is not None:
+        lo, hi = ksdf._d3(qbox[0]), ksdf._d3(qbox[1])
+    return L.ksdf_model_bytes(cells.n, off.ctypes.data, smp.ctypes.data, keys.ctypes.data,
+                              ksdf._d3(wl.origin), wl.h, len(wl.points), ctypes.byref(hp), lo, hi)
+
+
+def test_model_bytes_is_a_host_query_that_grows_with_the_options():
+    """ksdf_model_bytes sizes the caller-owned store on the host (no device needed):
+    the adjoint storage, the var_f storage, the dense inverses (16 KiB per cell) and a
+    larger query box each add bytes; invalid arguments give 0."""
+    wl = scenes.small_room_workload(n_queries=8)
+    c = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min)
+    base = _bytes(c, wl)
+    assert base > 0
+    adj = _bytes(c, wl, ksdf.FIT_ADJOINT)
+    varf = _bytes(c, wl, ksdf.FIT_ADJOINT | ksdf.FIT_ADJOINT_VARF)
+    dinv = _bytes(c, wl, ksdf.FIT_DENSE_INV)
+    assert base < adj < varf
+    assert dinv - base >= 4096 * 4 * c.n
+    assert _bytes(c, wl, ksdf.FIT_DENSE_INV, precision=ksdf.FP64) == _bytes(c, wl, precision=ksdf.FP64)
+    assert _bytes(c, wl, qbox=((-5, -5, -5), (15, 15, 15))) > base
+    assert _bytes(c, wl, k_fuse=99) == 0
+    bad = ksdf.CellSet(c.offsets.copy(), c.samples.copy(), c.keys.copy())
+    bad.samples[0] = len(wl.points) + 1
+    assert _bytes(bad, wl) == 0

@@ -1,19 +1,15 @@
 """GPU backward (adjoint) against the oracle's dual-number VJP, through the C ABI.
 
-Tolerances: FP64 path within 1e-8 (relative per point, and for d_hyper); FP32 path
-d_points within 1e-3 relative (norm-wise per point) and d_hyper within 1e-3
-relative, or, where the per-query terms of that sum cancel, within 1e-4 of
-sum_q |term_q| (tests/parity.py hyper_within; the oracle gives the terms)
-(with a var_f cotangent 3e-3 per point and 5e-3 for d_hyper: beta = A^{-1} k
-comes from FP32 triangular solves with cond(A) up to 1e6, and the noise derivative
-carries |beta|^2).  Excluded and counted: points whose argmin cell differs between GPU and
-oracle (a near-tie of the min-fusion, where the derivative is that of another
-cell), points on a clamp, and in FP32 points whose gradient cancellation ratio
-sum|a_i| e_i |x-x_i| / |w| exceeds 1e3 (the same conditioning rule as the forward
-gradient; with a gradient cotangent, whose second derivatives cancel further, the
-rule is 3e2).  FP32 d_hyper is checked for mean / var / var_f cotangents: with a
-gradient cotangent it is dominated by the few near-ridge points whose direction
-derivative is ill-conditioned, and is reported rather than asserted.
+Every point is compared (tests/parity.py check_vjp): the GPU's argmin cell must be
+acceptable under readings R6 and R7, and where it differs from the oracle's own
+choice the oracle differentiates at the GPU's cell.  FP64 models: d_points within
+1e-8 relative per point and d_hyper within 1e-8.  FP32 models: d_points within
+max(1e-3, 2 cond_2(A_c) 2^-24) relative per point (norm-wise, floor 1e-3 of the
+median norm), the bound growing with the exact condition number of the argmin cell
+c because the weights and adjoint vectors come from solves with an FP32 factor;
+d_hyper within 1e-3 relative, or, where the per-query terms of that sum cancel,
+within 1e-4 of sum_q |term_q| (the oracle gives the terms), for every cotangent
+kind (mean, var, var_f and the gradient's kernel-Hessian terms).
 """
 import numpy as np
 import pytest
@@ -21,7 +17,7 @@ import torch
 
 import oracle
 from paper_2603_29227_amd import ksdf, scenes
-from tests.parity import hyper_within
+from tests.parity import check_vjp
 
 pytestmark = pytest.mark.gpu
 
@@ -63,37 +59,10 @@ def _gpu_vjp(model, q, sign, cot, dt):
     return dp.cpu().numpy().astype(np.float64), dh.cpu().numpy(), out["argmin"].cpu().numpy()
 
 
-def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, tol_p, tol_h, mode=0, max_ratio=np.inf,
-             check_hyper=True, kernel="rbf"):
-    oc = _ocells(wl, cells)
-    cp = 64 if prec == "fp64" else 32
-    kw = {} if mode == 1 else cot
-    # differentiate at the GPU's argmin cells: near-ties of the min-fusion may resolve
-    # either way, and d_hyper sums every point
-    _, odp, odh, opp = oracle.vjp(wl.points, oc, q, wl.ell, wl.noise_var, cand_prec=cp,
-                                  sign=sign, mode=mode, per_point=True, force_argmin=am,
-                                  kernel=kernel, **kw)
-    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel=kernel)
-    o = oracle.query(wl.points, oc, f, q, wl.ell, wl.noise_var, cand_prec=cp, sign=sign,
-                     kernel=kernel)
-    ok = (am == o["argmin"]) & (o["status"] & 3 == 0) & (o["u_best"] > 1e-3) & (o["ratio"] <= max_ratio)
-    assert ok.mean() > 0.8, ok.mean()
-    print(f"compared {ok.sum()} of {len(ok)} points", flush=True)
-    nr = np.linalg.norm(odp, axis=1)
-    scale = np.maximum(nr, 1e-3 * np.median(nr[ok]))
-    err = np.linalg.norm(dp - odp, axis=1) / scale
-    bad = np.where(ok & (err > tol_p))[0]
-    assert len(bad) == 0, f"{len(bad)} points over tolerance, worst {err[ok].max():.3g} at {bad[:5]}"
-    # d_hyper sums every query, the excluded ones included (at the GPU's cells):
-    # compare as a whole, with the allowance for cancelling per-query terms
-    # (tests/parity.py hyper_within)
-    rel = np.abs(dh - odh) / np.maximum(np.abs(odh), 1e-12)
-    hok, herr, hallow = hyper_within(dh, odh, np.abs(opp).sum(0), rel=tol_h, per_term=tol_h / 10)
-    print(f"d_hyper {dh} oracle {odh} sum|term| {np.abs(opp).sum(0)} err {herr} allowed {hallow}",
-          flush=True)
-    if check_hyper:
-        assert np.all(hok), f"d_hyper {dh} vs oracle {odh}: error {herr} over {hallow}"
-    return err[ok].max(), rel
+def _compare(dp, dh, am, wl, cells, q, sign, cot, prec, mode=0, kernel="rbf"):
+    rep = check_vjp(dp, dh, am, wl, _ocells(wl, cells), q, sign, prec, mode=mode, cot=cot,
+                    kernel=kernel, label=f"{prec} {kernel} mode {mode}")
+    return rep["err_max"], rep["d_hyper_err"]
 
 
 def test_fp64_backward_matches_oracle_vjp():
@@ -102,7 +71,7 @@ def test_fp64_backward_matches_oracle_vjp():
     model, cells, dt = _setup(wl, "fp64", var_f=True)
     cot = _cotangents(len(wl.queries), 0)
     dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
-    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp64", 1e-8, 1e-8)
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp64")
     print("fp64 max point err", e, "d_hyper rel", rel, flush=True)
 
 
@@ -113,10 +82,7 @@ def test_fp32_backward_matches_oracle_vjp(var_f):
     model, cells, dt = _setup(wl, "fp32", var_f=var_f)
     cot = _cotangents(len(wl.queries), 1, grad=False, var_f=var_f)
     dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
-    # a var_f cotangent brings beta = A^{-1} k, an FP32 triangular-solve pair whose error
-    # grows with cond(A) (up to 1e6 here): its per-point bound is 3e-3
-    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32",
-                      3e-3 if var_f else 1e-3, 5e-3 if var_f else 1e-3, max_ratio=1e3)
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32")
     print("fp32 max point err", e, "d_hyper rel", rel, flush=True)
 
 
@@ -126,9 +92,8 @@ def test_fp32_backward_with_gradient_cotangent():
     model, cells, dt = _setup(wl, "fp32", var_f=True)
     cot = _cotangents(len(wl.queries), 3, grad=True, var_f=True)
     dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
-    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32", 1e-3, 1e-3,
-                      max_ratio=3e2, check_hyper=False)
-    print("fp32 grad-cotangent max point err", e, "d_hyper rel (reported)", rel, flush=True)
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32")
+    print("fp32 grad-cotangent max point err", e, "d_hyper err", rel, flush=True)
 
 
 def test_matern_fp64_backward_matches_oracle_vjp():
@@ -137,8 +102,7 @@ def test_matern_fp64_backward_matches_oracle_vjp():
     model, cells, dt = _setup(wl, "fp64", var_f=True, kernel="matern32")
     cot = _cotangents(len(wl.queries), 5)
     dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
-    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp64", 1e-8, 1e-8,
-                      kernel="matern32")
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp64", kernel="matern32")
     print("matern fp64 max point err", e, "d_hyper rel", rel, flush=True)
 
 
@@ -149,9 +113,7 @@ def test_matern_fp32_backward_matches_oracle_vjp(var_f):
     model, cells, dt = _setup(wl, "fp32", var_f=var_f, kernel="matern32")
     cot = _cotangents(len(wl.queries), 6, grad=True, var_f=var_f)
     dp, dh, am = _gpu_vjp(model, wl.queries, wl.sign, cot, dt)
-    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32",
-                      3e-3 if var_f else 1e-3, 5e-3 if var_f else 1e-3, max_ratio=1e3,
-                      kernel="matern32")
+    e, rel = _compare(dp, dh, am, wl, cells, wl.queries, wl.sign, cot, "fp32", kernel="matern32")
     print("matern fp32 max point err", e, "d_hyper rel", rel, flush=True)
 
 
@@ -171,7 +133,7 @@ def test_fp32_collision_cost_gradient_via_autograd():
     torch.cuda.synchronize()
     am = model.query(q.detach(), sg)["argmin"].cpu().numpy()
     e, rel = _compare(gq.cpu().numpy().astype(np.float64), gth.cpu().numpy(), am, wl, cells,
-                      wl.queries, wl.sign, None, "fp32", 1e-3, 1e-3, mode=1, max_ratio=1e3)
+                      wl.queries, wl.sign, None, "fp32", mode=1)
     print("cost grad max point err", e, "theta rel", rel, flush=True)
 
 

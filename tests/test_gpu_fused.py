@@ -67,3 +67,45 @@ def test_fused_with_no_queries_still_fits():
     out2 = ref.query(torch.from_numpy(wl.queries).cuda())
     torch.cuda.synchronize()
     assert torch.equal(out["mean"], out2["mean"])
+
+
+def test_fused_wait_expiry_is_reported():
+    """The fused launch's bounded wait for the fits, forced from the host with a limit
+    of one sleep: every kernel still ends normally; queries answered by workgroups
+    that stopped waiting carry Q_FIT_TIMEOUT, ksdf_model_check reports the expiry once
+    (KSDF_ERR_TIMEOUT) and then clears it; the other queries equal the separate
+    launches bit for bit.  With the default bound nothing is flagged."""
+    print("[gpu-case] fused launch, forced wait expiry", flush=True)
+    wl = scenes.small_room_workload(n_queries=200_000, uneven=True, cfg_id=44)
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    ref = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var)
+    ref.fit(pts)
+    want = ref.query(q, sg)
+    m = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var)
+    m.set_tuning(fused=1, query_split=0)
+    m.set_wait_limit(1)
+    got = m.fit_query(pts, q, sg)
+    torch.cuda.synchronize()
+    flagged = (got["status"] & ksdf.Q_FIT_TIMEOUT) != 0
+    n_flag = int(flagged.sum())
+    print(f"forced expiry: {n_flag} of {len(q)} queries flagged", flush=True)
+    assert n_flag > 0
+    with pytest.raises(ksdf.KsdfError, match="timeout|wait"):
+        m.check()
+    m.check()   # reported once
+    keep = ~flagged
+    for k in ("mean", "grad", "var", "var_f", "argmin"):
+        assert torch.equal(got[k][keep], want[k][keep]), k
+    assert torch.equal(got["status"][keep], want["status"][keep])
+    m.set_wait_limit(0)
+    got = m.fit_query(pts, q, sg)
+    torch.cuda.synchronize()
+    m.check()
+    for k in want:
+        assert torch.equal(got[k], want[k]), k
+    m.close()
+    ref.close()

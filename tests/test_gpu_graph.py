@@ -25,7 +25,7 @@ def _model(wl, precision="fp32", adjoint=False):
     cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
                              wl.m_cap_grid, wl.key_lo)
     return ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
-                      precision=precision, adjoint=adjoint), cells
+                      precision=precision, adjoint=adjoint, dense_inverse=True), cells
 
 
 def _equal(a: dict, b: dict, keys=("mean", "grad", "var", "var_f", "argmin", "status")):
@@ -193,7 +193,7 @@ def test_tuning_preserves_outputs(tuning):
     oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
                       np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
-    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var,
                      sign=wl.sign, all_candidates=True)
     assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
                   label=str(tuning))
@@ -232,7 +232,7 @@ def test_query_pairs_matches_wave_walk_and_oracle(tuning):
     oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
                       np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
-    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var,
                      sign=wl.sign, all_candidates=True)
     assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
                   label=f"pairs {tuning}")
@@ -265,7 +265,7 @@ def test_query_mfma_gp_variance(block):
     oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
                       np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
-    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, cand_prec=32,
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var,
                      sign=wl.sign, all_candidates=True)
     assert_parity({k: v.cpu().numpy() for k, v in b.items()}, o, wl.ell, "fp32", wl.sign,
                   label=f"query_mfma {block}")

@@ -41,7 +41,7 @@ def _run(wl, precision):
     oc = _ocells(wl, cells)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel="matern32")
     o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, kernel="matern32",
-                     cand_prec=64 if precision == "fp64" else 32, sign=wl.sign, all_candidates=True)
+                     sign=wl.sign, all_candidates=True)
     return model, cells, g, o, st.cpu().numpy()[:cells.n]
 
 

@@ -42,8 +42,7 @@ def oracle_run(wl, cells, queries, sign, precision, k_fuse=8, svar=None):
                       np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, svar=svar)
     return oracle.query(wl.points, oc, f, queries, wl.ell, wl.noise_var, k_fuse=k_fuse,
-                        cand_prec=64 if precision == "fp64" else 32, sign=sign, svar=svar,
-                        all_candidates=True)
+                        sign=sign, svar=svar, all_candidates=True)
 
 
 def test_sphere_fp64_plain_path_matches_oracle():
@@ -181,3 +180,38 @@ def test_far_queries_over_sloped_patches_fp32():
     torch.cuda.synchronize()
     res2 = {k: v.cpu().numpy() for k, v in out.items()}
     assert_parity(res2, ora, wl.ell, "fp32", wl.sign, label="sloped far, pairs")
+
+
+def test_fp64_fallback_decision_matches_exact_condition_number():
+    """The FP64 refit rule (Cholesky in FP64 only where cond_2(A) > 1e6) against the
+    oracle's exact cond_2.  Cells in the strong-correlation limit of App. E (64 samples
+    within 1e-5 m of one point) have cond_2 = (64 + s2) / s2, so per-sample variances
+    place them on both sides of the threshold: s2 = 2e-4, 1e-4, 8e-5 (cond 3.2e5 to
+    8e5) stay FP32, s2 = 5e-5, 4e-5, 2e-5 (1.28e6 to 3.2e6) go to FP64.  The natural
+    cell of a noisy patch (cond about 3.6e5) stays FP32.  Queries around the clusters then
+    match the oracle."""
+    _say("FP64 fallback decision at cond 1e6 (strong-correlation cells)")
+    rng = np.random.default_rng(11)
+    s2s = [2e-4, 1e-4, 8e-5, 5e-5, 4e-5, 2e-5]
+    pts, sv = [], []
+    for i, s2 in enumerate(s2s):
+        pts.append(np.array([0.5 + 2.0 * i, 0.5, 0.5]) + rng.uniform(-1e-5, 1e-5, (64, 3)))
+        sv.append(np.full(64, s2))
+    xy = rng.uniform(0, 1, (400, 2))
+    pts.append(np.column_stack([xy[:, 0] + 0.0, xy[:, 1] + 3.0, 0.5 + rng.normal(0, 0.005, 400)]))
+    sv.append(np.full(400, 1e-4))
+    P = np.concatenate(pts).astype(np.float32)
+    S = np.concatenate(sv).astype(np.float32)
+    q = np.concatenate([c[:1] + rng.normal(0, 0.2, (64, 3)) for c in pts]).astype(np.float32)
+    wl = scenes.Workload(97, "cond_cells", P, (0.0, 0.0, 0.0), 1.0, 0.5, 64, 1, q,
+                         np.ones(len(q), np.int8))
+    model, cells, g = gpu_run(wl, svar=S)
+    oc = oracle.Cells(cells.offsets, cells.samples, cells.keys, (cells.keys + 0.5) * 1.0)
+    cond, _, _ = oracle.cond2(P, oc, wl.ell, wl.noise_var, svar=S.astype(np.float64))
+    fp64 = (g["cell_status"] & ksdf.C_FP64) != 0
+    print("cells", cells.n, "m", cells.m.tolist(), "cond", np.round(cond).tolist(), "fp64", fp64.tolist(),
+          flush=True)
+    assert (cond > 1e6).sum() == 3 and (cond < 1e6).sum() == cells.n - 3
+    np.testing.assert_array_equal(fp64, cond > 1e6)
+    o = oracle_run(wl, cells, q, wl.sign, "fp32", svar=S.astype(np.float64))
+    assert_parity(g, o, wl.ell, "fp32", label="strong-correlation cells")

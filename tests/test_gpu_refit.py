@@ -146,17 +146,28 @@ def test_edge_cases_of_the_streaming_and_sign_calls():
 
 @pytest.mark.parametrize("Q", [1, 63, 1000, 200_003])
 def test_count_queries_shuffled_argmins_with_invalid_entries(Q):
-    _say(f"query counters on shuffled argmins with -1 entries, Q={Q}")
+    """Counters left fractional by refits (halved) and argmins that are -1 or past the
+    last cell: each valid cell's count is added once, c0 + count rounded once in
+    float32, whatever the order of the queries; invalid argmins are skipped."""
+    _say(f"query counters on shuffled argmins with invalid entries, Q={Q}")
     wl, cells, dt, p0, _, _ = _setup()
     model = _model(wl, cells, "fp32")
     rng = np.random.default_rng(Q)
     # a few hot cells (many equal keys in a wave), the rest spread, some invalid
     am = np.where(rng.random(Q) < 0.5, rng.integers(0, 5, Q), rng.integers(0, cells.n, Q))
     am[rng.random(Q) < 0.1] = -1
+    am[rng.random(Q) < 0.05] = cells.n + rng.integers(0, 1 << 20, 1)[0]
     am = am.astype(np.int32)
-    qcount = torch.full((cells.n,), 3.0, dtype=torch.float32, device="cuda")
+    # fractional counters: 3 halved up to 20 times, plus fine fractions
+    c0 = (3.0 * 0.5 ** rng.integers(0, 21, cells.n) + rng.integers(0, 2, cells.n) * 2.0 ** -20)
+    c0 = c0.astype(np.float32)
+    qcount = torch.from_numpy(c0.copy()).cuda()
     model.count_queries(torch.from_numpy(am).cuda(), qcount, cap=1e7)
     torch.cuda.synchronize()
-    want = 3.0 + np.bincount(am[am >= 0], minlength=cells.n)
-    assert np.array_equal(qcount.cpu().numpy(), want.astype(np.float32))
+    valid = am[(am >= 0) & (am < cells.n)]
+    want = np.minimum(c0 + np.bincount(valid, minlength=cells.n).astype(np.float32), np.float32(1e7))
+    assert want.dtype == np.float32
+    assert np.array_equal(qcount.cpu().numpy(), want)
+    with pytest.raises(ValueError):
+        model.count_queries(torch.from_numpy(am).cuda(), qcount[:-1])
     model.close()

@@ -334,8 +334,11 @@ def test_min_fusion_takes_the_smallest_candidate():
                  [(-0.2, 0, 0), (0.2, 0, 0), (0, 0.2, 0)])
     Q = rng.normal(size=(100, 3)) * 0.6
     _, o = oracle.run(X, cs, Q, ELL, NOISE, k_fuse=3)
-    np.testing.assert_array_equal(np.sort(o["cand"], 1), np.tile([0, 1, 2], (100, 1)))
-    uc = o["ucand"]
+    # only three cells: every list holds exactly them (then -1 padding)
+    np.testing.assert_array_equal(np.sort(o["cand"][:, :3], 1), np.tile([0, 1, 2], (100, 1)))
+    assert np.all(o["cand"][:, 3:] == -1)
+    o = {**o, "cand": o["cand"][:, :3]}
+    uc = o["ucand"][:, :3]
     np.testing.assert_allclose(o["mean"], uc.min(1), rtol=0)
     for p in range(100):
         tied = o["cand"][p][uc[p] == uc[p].min()]
@@ -371,7 +374,8 @@ def test_candidates_are_nearest_centres_by_brute_force():
     for p in range(0, 500, 7):
         d = ((cells.centres - wl.queries[p]) ** 2).sum(1)
         order = sorted(range(cells.n), key=lambda c: (d[c], c))[:8]
-        assert list(o["cand"][p]) == order
+        assert o["tie"][p][1] == 0   # no tie at the 8th place among these queries
+        assert list(o["cand"][p][:8]) == order and np.all(o["cand"][p][8:] == -1)
 
 
 def test_non_spd_cell_is_excluded():

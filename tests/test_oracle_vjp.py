@@ -127,3 +127,11 @@ def test_forced_argmin_matches_free_choice_and_switches_cell():
                      per_point=True, force_argmin=forced)
     changed = np.where(np.any(alt[1] != base[1], axis=1))[0]
     assert set(changed) <= set(second) and len(changed) > 0
+    # a cell outside the query's candidate list is refused (and reported)
+    far = np.full(len(wl.queries), -1, np.int32)
+    for p in range(10):
+        far[p] = next(c for c in range(oc.n) if c not in o["cand"][p])
+    res = oracle.vjp(wl.points, oc, wl.queries, wl.ell, wl.noise_var, sign=wl.sign, mode=1,
+                     per_point=True, force_argmin=far, forced_used=True)
+    assert np.array_equal(res[1], base[1])
+    assert np.all(res[4][:10] == 0) and np.all(res[4][10:] == -1)
