@@ -273,6 +273,21 @@ int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t
                uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * ksdf_query_noalloc — ksdf_query for callers that cannot allocate device memory
+ * (code under graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, outputs and launches as ksdf_query, without the workspace: the
+ * scratch lives in a fixed device array of KSDF_NOALLOC_SCRATCH_BYTES that each device
+ * holds until the process ends (its address is looked up on the first call on a
+ * device).  Queries whose ksdf_query_workspace_bytes exceeds that size return
+ * KSDF_ERR_WORKSPACE (use ksdf_query with a workspace).  Calls that overlap on one
+ * device share the array and race: issue them on one stream, or serialise them.
+ * ------------------------------------------------------------------------- */
+#define KSDF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int ksdf_query_noalloc(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
+                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
+                       uint8_t* q_status, void* stream);
+
+/* ---------------------------------------------------------------------------
  * ksdf_refit_cells — streaming update of the fitted cells (Sec. IV-C, App. G "GP
  * training queue").  dirty [n_cells] (device float, the count c2 of buffer updates
  * since a cell's last training) and qcount [n_cells] (device float, the query count

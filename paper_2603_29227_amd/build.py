@@ -12,7 +12,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["api.hip", "fit.hip", "index.hip", "query.hip", "query_fast.hip", "query_split64_wave.hip",
            "query_split64_lane.hip", "query_split256_wave.hip", "query_split256_lane.hip",
-           "query_pairs.hip", "fused.hip", "backward.hip", "bhm.hip"]
+           "query_pairs.hip", "fused.hip", "backward.hip", "bhm.hip", "noalloc.hip"]
 HOST_SOURCES = ["cells_host.cpp"]
 
 # Packed FP32 VALU forms are disabled for all device code.

@@ -32,7 +32,8 @@ FIT_ADJOINT, FIT_ADJOINT_VARF, FIT_DENSE_INV = 1, 2, 4
 EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_cellset_destroy",
            "ksdf_model_bytes", "ksdf_model_create", "ksdf_model_index_bytes",
            "ksdf_model_attach_index", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
-           "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_backward_workspace_bytes",
+           "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_query_noalloc",
+           "ksdf_backward_workspace_bytes",
            "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
            "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
@@ -147,6 +148,7 @@ def lib():
         L.ksdf_query_workspace_bytes.restype = sz
         L.ksdf_query.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
                                  _vp]
+        L.ksdf_query_noalloc.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.ksdf_backward_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
