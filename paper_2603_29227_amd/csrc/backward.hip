@@ -22,6 +22,7 @@
 // differentiated through when tied.  k* is recomputed, never stored.
 #include <cmath>
 
+#include "ff.h"
 #include "ksdf_internal.h"
 
 namespace ksdf {
@@ -53,6 +54,7 @@ struct BwdArgs {
   const double* centre64;
   const float* box;        // [n,8] sample AABB (cell-local)
   T ell, two_l2, alpha;
+  float c2_ff[2];          // log2(e) / (2 l^2) as a float pair (FP32 models)
   double ell_d, alpha_d;   // the same in FP64
   int alpha_tied;
   int uniform_noise;
@@ -469,165 +471,193 @@ __global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
   A.part[2 * q + 1] = th[1];
 }
 
-// VJP without a var_f cotangent for an FP32 model (the terms of query_vjp<T, false>),
-// for a wave-uniform cell: every lane of the wave runs it, so the per-cell data are
-// read by scalar loads, BCH samples per load group, outside divergent control flow; a
-// lane keeps the result only when c is its own argmin cell.  The arithmetic is FP64 on
-// the store's float-float values (samples, weights, adjoint vectors): the sums
-// f' = sum a_i e_i and sum e_i xi_i cancel strongly in ill-conditioned cells, which
-// FP32 would turn into errors of 1e-3 in the hyperparameter gradient, while FP64
-// issues at the rate of unpacked FP32 on this hardware.
-constexpr int BCH = 2;
-constexpr double LOG2E_D = 1.4426950408889634;
+// Compensated FP32 sum (TwoSum, Knuth): the running sum and the sum of its rounding
+// errors, so that m terms carry about one rounding of the result instead of m.
+struct CAcc {
+  float s = 0.f, c = 0.f;
+  __device__ __forceinline__ void add(float x) {
+#pragma clang fp contract(off)
+    const float t = s + x;
+    const float bb = t - s;
+    c += (s - (t - bb)) + (x - bb);
+    s = t;
+  }
+  __device__ __forceinline__ float val() const { return s + c; }
+};
 
-// exp(x) for x <= 0 from the hardware 2^r on the fraction r in [0, 1) of x log2(e):
-// relative error about 1e-7 (the FP32 rounding of r and the instruction's ulp)
-// instead of the library's FP64 exp, which costs several times more.
-__device__ __forceinline__ double exp_neg(double x) {
-  const double t = x * LOG2E_D;
-  const double n = floor(t);
-  if (n < -1000.0) return 0.0;
-  return ldexp((double)__builtin_amdgcn_exp2f((float)(t - n)), (int)n);
-}
+// VJP of one query on its argmin cell for an FP32 model, in FP32.  Each term carries
+// about one float rounding (cell-local differences from the float-float store, the
+// kernel value from the hardware 2^x), and the sums whose terms cancel -- f' = sum
+// a_i e_i, w', Z, the kernel-Hessian and z^2-weighted vectors and the fit's adjoint
+// sums sum e_i xi_i -- are accumulated with compensation, so that their error is a
+// few roundings of the terms rather than of the sum; the softmin sums (positive
+// terms) are plain.  The per-query hyperparameter terms leave in FP64 for the
+// fixed-order reduction.  UNI: the cell is wave-uniform (scalar loads).
+constexpr int BCH = 2;
 
 template <bool UNI>
-__device__ __forceinline__ void vjp_ff64(const BwdArgs<float>& A, double x0, double x1, double x2,
-                                         double s, double gm, const double gg[3], double gv, int c,
-                                         double out_dx[3], double out_th[2]) {
+__device__ __forceinline__ void vjp_f32(const BwdArgs<float>& A, float x0, float x1, float x2,
+                                        float s, float gm, const float gg[3], float gv, int c,
+                                        float out_dx[3], double out_th[2]) {
   const float4* __restrict__ P4 = reinterpret_cast<const float4*>(A.ps);
   const float4* __restrict__ PL = reinterpret_cast<const float4*>(A.plo);
   const float4* __restrict__ X4 = reinterpret_cast<const float4*>(A.xi);
   const float* __restrict__ SV = A.sv;
   const int b = UNI ? __builtin_amdgcn_readfirstlane(A.offsets[c]) : A.offsets[c];
   const int m = (UNI ? __builtin_amdgcn_readfirstlane(A.offsets[c + 1]) : A.offsets[c + 1]) - b;
-  const double lt = A.ell_d, two_l2 = 2.0 * lt * lt, inv2l2 = 1.0 / two_l2, al = A.alpha_d;
-  const double l0 = x0 - A.centre64[3L * c], l1 = x1 - A.centre64[3L * c + 1],
-               l2 = x2 - A.centre64[3L * c + 2];
-  // sample i in FP64: coordinates and weight from the float-float pair
-  auto load = [&](int i, double& px, double& py, double& pz, double& pa) {
+  const float lt = A.ell, two_l2 = A.two_l2, al = A.alpha;
+  const float ca = 1.4426950408889634f * al;
+  // the query in the cell's frame, exact as a float pair (the store's coordinates are
+  // relative to the float centre)
+  const ff lx = ff_two_sum(x0, -(float)A.centre64[3L * c]);
+  const ff ly = ff_two_sum(x1, -(float)A.centre64[3L * c + 1]);
+  const ff lz = ff_two_sum(x2, -(float)A.centre64[3L * c + 2]);
+  // the differences to sample i (float), and |x - x_i|^2 as a float-float pair from
+  // the exact differences, so that the kernel exponent keeps its precision where it
+  // is large (far samples of big cells)
+  auto diff = [&](int i, float di[3], ff& z2) {
     const float4 h = P4[b + i], lo = PL[b + i];
-    px = (double)h.x + (double)lo.x;
-    py = (double)h.y + (double)lo.y;
-    pz = (double)h.z + (double)lo.z;
-    pa = (double)h.w + (double)lo.w;
+    const ff dx = ff_add(lx, ff{-h.x, -lo.x});
+    const ff dy = ff_add(ly, ff{-h.y, -lo.y});
+    const ff dz = ff_add(lz, ff{-h.z, -lo.z});
+    di[0] = dx.hi;
+    di[1] = dy.hi;
+    di[2] = dz.hi;
+    z2 = ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
   };
-  double d2 = INFINITY;
+  // e = exp(-(z2 - d2) / (2 l^2)) = 2^-t with t = (z2 - d2) log2(e) / (2 l^2) formed
+  // in float-float: the hardware 2^x on the fraction of t.hi, the low part by its
+  // first-order term
+  const ff c2f{A.c2_ff[0], A.c2_ff[1]};
+  auto kval = [&](ff z2, ff d2f) {
+    const ff t = ff_mul(ff_add(z2, ff_neg(d2f)), c2f);
+    const float n = floorf(t.hi);
+    const float e = __builtin_amdgcn_exp2f(n - t.hi) * (1.f - 0.6931471805599453f * t.lo);
+    return ldexpf(e, -(int)n);
+  };
+  auto weight = [&](int i) {
+    const float4 h = P4[b + i], lo = PL[b + i];
+    return h.w + lo.w;
+  };
+  ff d2f{INFINITY, 0.f};
   for (int i0 = 0; i0 < m; i0 += BCH) {
 #pragma unroll
     for (int j = 0; j < BCH; ++j) {
-      double px, py, pz, pa;
-      load(i0 + j, px, py, pz, pa);   // the store is padded
-      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
-      const double z2 = dx * dx + dy * dy + dz * dz;
-      if (i0 + j < m) d2 = fmin(d2, z2);
+      float di[3];
+      ff z2;
+      diff(i0 + j, di, z2);   // the store is padded
+      if (i0 + j < m && (z2.hi < d2f.hi || (z2.hi == d2f.hi && z2.lo < d2f.lo))) d2f = z2;
     }
   }
-  const double zmin = sqrt(d2);
+  const float d2 = d2f.hi + d2f.lo;
+  const float zmin = sqrtf(d2);
   // pass A: f', w', Z, softmin moments
-  double f = 0, w[3] = {0, 0, 0}, Za = 0, S = 0, M1 = 0, M2 = 0;
+  CAcc f, w[3], Za;
+  float S = 0.f, M1 = 0.f, M2 = 0.f;
   for (int i0 = 0; i0 < m; i0 += BCH) {
 #pragma unroll
     for (int j = 0; j < BCH; ++j) {
       const bool ok = i0 + j < m;
-      double px, py, pz, pa;
-      load(i0 + j, px, py, pz, pa);
-      const double dx = l0 - px, dy = l1 - py, dz = l2 - pz;
-      const double z2 = dx * dx + dy * dy + dz * dz;
-      const double e = ok ? exp_neg(-(z2 - d2) * inv2l2) : 0.0;
-      const double ae = pa * e;
-      f += ae;
-      w[0] += ae * dx;
-      w[1] += ae * dy;
-      w[2] += ae * dz;
-      Za += ae * z2;
-      const double t = sqrt(z2) - zmin;
-      const double sm = ok ? exp_neg(-al * t) : 0.0;
+      float di[3];
+      ff z2f;
+      diff(i0 + j, di, z2f);
+      const float z2 = z2f.hi + z2f.lo;
+      const float e = ok ? kval(z2f, d2f) : 0.f;
+      const float ae = weight(i0 + j) * e;
+      f.add(ae);
+      w[0].add(ae * di[0]);
+      w[1].add(ae * di[1]);
+      w[2].add(ae * di[2]);
+      Za.add(ae * z2);
+      const float t = sqrtf(z2) - zmin;
+      const float sm = ok ? __builtin_amdgcn_exp2f(-ca * t) : 0.f;
       S += sm;
       M1 += sm * t;
       M2 += sm * t * t;
     }
   }
-  const double u2 = f > 0.0 ? d2 - two_l2 * log(f) : -1.0;
-  const bool mean_live = u2 > 0.0;
-  const double u = mean_live ? sqrt(u2) : 0.0;
-  const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-  double y[3] = {0, 0, 0};
-  if (wn > 0.0) {
-    const double gw = (gg[0] * w[0] + gg[1] * w[1] + gg[2] * w[2]) / wn;
-    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * w[d] / wn) / wn;
+  const float fv = f.val();
+  const float wv[3] = {w[0].val(), w[1].val(), w[2].val()};
+  const float u2 = fv > 0.f ? d2 - two_l2 * logf(fv) : -1.f;
+  const bool mean_live = u2 > 0.f;
+  const float u = mean_live ? sqrtf(u2) : 0.f;
+  const float wn = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+  float y[3] = {0.f, 0.f, 0.f};
+  if (wn > 0.f) {
+    const float gw = (gg[0] * wv[0] + gg[1] * wv[1] + gg[2] * wv[2]) / wn;
+    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * wv[d] / wn) / wn;
   }
-  const double iS = 1.0 / S;
-  const double m1 = M1 * iS;
-  const double h = zmin + m1;
-  const double Vz = M2 * iS - m1 * m1;
+  const float iS = 1.f / S;
+  const float m1 = M1 * iS;
+  const float h = zmin + m1;
+  const float Vz = M2 * iS - m1 * m1;
   // pass B: every per-sample sum at once.  d var / d z_j = 2 alpha (-sigma_j^2 c_j
   // (c_j + s_j) + s_j V + c_j P) needs V and P of the same pass, so the point
   // derivative keeps its three parts apart (Q1, Q2, Q3) and combines them after.
-  double V = 0, Pp = 0, dVa = 0, C2 = 0;
-  double Q1[3] = {0, 0, 0}, Q2[3] = {0, 0, 0}, Q3[3] = {0, 0, 0}, Hy[3] = {0, 0, 0},
-         Wz[3] = {0, 0, 0};
-  double El = 0, Es = 0, Eld[3] = {0, 0, 0}, Esd[3] = {0, 0, 0};
+  float V = 0.f, Pp = 0.f, dVa = 0.f, C2 = 0.f;
+  float Q1[3] = {0.f, 0.f, 0.f}, Q2[3] = {0.f, 0.f, 0.f}, Q3[3] = {0.f, 0.f, 0.f};
+  CAcc Hy[3], Wz[3], El, Es, Eld[3], Esd[3];
   for (int i0 = 0; i0 < m; i0 += BCH) {
 #pragma unroll
     for (int j = 0; j < BCH; ++j) {
       const bool ok = i0 + j < m;
-      double px, py, pz, pa;
-      load(i0 + j, px, py, pz, pa);
+      float di[3];
+      ff z2f;
+      diff(i0 + j, di, z2f);
       const float4 xq = X4[b + i0 + j];
-      const double svj = ok ? (double)SV[b + i0 + j] : 0.0;
-      const double x0j = ok ? (double)xq.x + (double)xq.z : 0.0;
-      const double x1j = ok ? (double)xq.y + (double)xq.w : 0.0;
-      const double di[3] = {l0 - px, l1 - py, l2 - pz};
-      const double z2 = di[0] * di[0] + di[1] * di[1] + di[2] * di[2];
-      const double z = sqrt(z2);
-      const double e = ok ? exp_neg(-(z2 - d2) * inv2l2) : 0.0;
-      const double ae = pa * e;
-      const double si = ok ? exp_neg(-al * (z - zmin)) * iS : 0.0;
-      const double Bi = al * (h - z) + 1.0;
-      const double ci = si * Bi;
+      const float svj = ok ? SV[b + i0 + j] : 0.f;
+      const float x0j = ok ? xq.x + xq.z : 0.f;
+      const float x1j = ok ? xq.y + xq.w : 0.f;
+      const float z2 = z2f.hi + z2f.lo;
+      const float z = sqrtf(z2);
+      const float e = ok ? kval(z2f, d2f) : 0.f;
+      const float ae = weight(i0 + j) * e;
+      const float si = ok ? __builtin_amdgcn_exp2f(-ca * (z - zmin)) * iS : 0.f;
+      const float Bi = al * (h - z) + 1.f;
+      const float ci = si * Bi;
       V += svj * ci * ci;
       Pp += svj * ci * si;
       C2 += ci * ci;
-      dVa += 2.0 * svj * ci * (si * (h - z) * (Bi + 1.0) - al * si * Vz);
-      const double rz = z > 0.0 ? 1.0 / z : 0.0;
-      const double q1 = -svj * ci * (ci + si) * rz, q2 = si * rz, q3 = ci * rz;
-      const double dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
+      dVa += 2.f * svj * ci * (si * (h - z) * (Bi + 1.f) - al * si * Vz);
+      const float rz = z > 0.f ? 1.f / z : 0.f;
+      const float q1 = -svj * ci * (ci + si) * rz, q2 = si * rz, q3 = ci * rz;
+      const float dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         Q1[d] += q1 * di[d];
         Q2[d] += q2 * di[d];
         Q3[d] += q3 * di[d];
-        Hy[d] += ae * dy * di[d];
-        Wz[d] += ae * z2 * di[d];
-        Eld[d] += e * x0j * di[d];
-        Esd[d] += e * x1j * di[d];
+        Hy[d].add(ae * dy * di[d]);
+        Wz[d].add(ae * z2 * di[d]);
+        Eld[d].add(e * x0j * di[d]);
+        Esd[d].add(e * x1j * di[d]);
       }
-      El += e * x0j;
-      Es += e * x1j;
+      El.add(e * x0j);
+      Es.add(e * x1j);
     }
   }
-  const double l3 = lt * lt * lt;
+  const float l3 = lt * lt * lt;
   for (int d = 0; d < 3; ++d) {
-    const double dxv = 2.0 * al * (Q1[d] + V * Q2[d] + Pp * Q3[d]);
-    double r = s * (f * y[d] - Hy[d] / (lt * lt)) + gv * dxv;
-    if (mean_live) r += s * gm * w[d] / (f * u);
+    const float dxv = 2.f * al * (Q1[d] + V * Q2[d] + Pp * Q3[d]);
+    float r = s * (fv * y[d] - Hy[d].val() / (lt * lt)) + gv * dxv;
+    if (mean_live) r += s * gm * wv[d] / (fv * u);
     out_dx[d] = r;
   }
-  double aXl = s * (y[0] * Eld[0] + y[1] * Eld[1] + y[2] * Eld[2]);
-  double aXs = s * (y[0] * Esd[0] + y[1] * Esd[1] + y[2] * Esd[2]);
+  float aXl = s * (y[0] * Eld[0].val() + y[1] * Eld[1].val() + y[2] * Eld[2].val());
+  float aXs = s * (y[0] * Esd[0].val() + y[1] * Esd[1].val() + y[2] * Esd[2].val());
   if (mean_live) {
-    const double cm = -s * gm * lt * lt / (u * f);
-    aXl += cm * El;
-    aXs += cm * Es;
+    const float cm = -s * gm * lt * lt / (u * fv);
+    aXl += cm * El.val();
+    aXs += cm * Es.val();
   }
-  double dl = 0, ds = 0;
-  if (mean_live) dl += s * gm * (u2 - Za / f) / (lt * u);
-  dl += s * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]) / l3;
-  if (A.alpha_tied) dl += gv * dVa * (-2.0 * al / lt);
+  float dl = 0.f, ds = 0.f;
+  if (mean_live) dl += s * gm * (u2 - Za.val() / fv) / (lt * u);
+  dl += s * (y[0] * Wz[0].val() + y[1] * Wz[1].val() + y[2] * Wz[2].val()) / l3;
+  if (A.alpha_tied) dl += gv * dVa * (-2.f * al / lt);
   dl -= aXl;
   if (A.uniform_noise) ds += gv * C2 - aXs;
-  out_th[0] = dl;
-  out_th[1] = ds;
+  out_th[0] = (double)dl;
+  out_th[1] = (double)ds;
 }
 
 // FP32: lanes take queries in argmin-cell order (perm), and each wave walks the
@@ -645,20 +675,21 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
   double th[2] = {0.0, 0.0};
   bool todo = bc >= 0;
   // per-lane inputs (the no-var_f path reads them once for all its cells)
-  const double x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
-  const double sgn = A.sign ? (double)A.sign[q] : 1.0;
-  const double gm = A.d_mean ? (double)A.d_mean[q] : 0.0;
-  double gg[3] = {0.0, 0.0, 0.0};
+  const float x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
+  const float sgn = A.sign ? (float)A.sign[q] : 1.f;
+  const float gm = A.d_mean ? A.d_mean[q] : 0.f;
+  float gg[3] = {0.f, 0.f, 0.f};
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
-  const double gv = A.d_var ? (double)A.d_var[q] : 0.0;
+  const float gv = A.d_var ? A.d_var[q] : 0.f;
   if constexpr (LANE && !VARF) {
     // per lane (sparse queries): every lane its own argmin cell, in one round
     if (__ballot(todo)) {
-      double tdx[3], tth[2];
-      vjp_ff64<false>(A, x0, x1, x2, sgn, gm, gg, gv, todo ? bc : 0, tdx, tth);
+      float tdx[3];
+      double tth[2];
+      vjp_f32<false>(A, x0, x1, x2, sgn, gm, gg, gv, todo ? bc : 0, tdx, tth);
       if (todo) {
-        for (int d = 0; d < 3; ++d) dx[d] = (float)tdx[d];
+        for (int d = 0; d < 3; ++d) dx[d] = tdx[d];
         th[0] = tth[0];
         th[1] = tth[1];
         todo = false;
@@ -679,10 +710,11 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
         todo = false;
       }
     } else {
-      double tdx[3], tth[2];
-      vjp_ff64<true>(A, x0, x1, x2, sgn, gm, gg, gv, c, tdx, tth);
+      float tdx[3];
+      double tth[2];
+      vjp_f32<true>(A, x0, x1, x2, sgn, gm, gg, gv, c, tdx, tth);
       if (todo && bc == c) {
-        for (int d = 0; d < 3; ++d) dx[d] = (float)tdx[d];
+        for (int d = 0; d < 3; ++d) dx[d] = tdx[d];
         th[0] = tth[0];
         th[1] = tth[1];
         todo = false;
@@ -884,6 +916,11 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.centre64 = m->centre64; A.box = m->box32;
     A.ell = (float)m->ell; A.two_l2 = (float)two_l2; A.alpha = (float)m->alpha;
     A.ell_d = m->ell; A.alpha_d = m->alpha; A.plo = m->plo32;
+    {
+      const double c2 = 1.4426950408889634 / two_l2;
+      A.c2_ff[0] = (float)c2;
+      A.c2_ff[1] = (float)(c2 - (double)A.c2_ff[0]);
+    }
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
     if (Q > 0 && m->kernel == KSDF_KERNEL_MATERN32) {

@@ -123,9 +123,13 @@ constexpr Tab make_tab() {
 }
 }  // namespace exp_tab_detail
 
+// The table in constant memory: a constexpr local indexed at run time would be copied
+// into every lane's private memory.
+static __constant__ const exp_tab_detail::Tab kExpTab = exp_tab_detail::make_tab();
+
 __host__ __device__ __forceinline__ ff ff_exp_neg_tab(ff t) {
 #pragma clang fp contract(off)
-  constexpr exp_tab_detail::Tab TAB = exp_tab_detail::make_tab();
+  const exp_tab_detail::Tab& TAB = kExpTab;
   constexpr float C1 = 0.0108184814453125f;
   constexpr float C2 = 1.1943250683543738e-05f;
   constexpr float C3 = 2.531013593154441e-13f;
@@ -150,6 +154,57 @@ __host__ __device__ __forceinline__ ff ff_exp_neg_tab(ff t) {
   p = ff_mul(p, ff{TAB.hi[j], TAB.lo[j]});
   const int e = -(ki >> 6);
   return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
+}
+
+// exp(-t), t >= 0, in float-float to a few parts in 1e14, cheaper than ff_exp_neg_tab:
+// the same reduction (t = k ln2/64 + r, |r| <= ln2/128), then exp(-r) = 1 - r + r^2/2
+// - r^3/6 + r^4/24 with 1 - r_hi exact as a float pair, r_hi^2/2 exact by TwoProduct,
+// and -r_lo + r_hi r_lo - r^3/6 + r^4/24 (below 3e-8) in FP32, whose rounding (below
+// 2e-15) and the dropped r^5/120 (below 4e-14) are the series' errors; then the table
+// factor.
+__host__ __device__ __forceinline__ ff ff_exp_neg_fast(ff t) {
+#pragma clang fp contract(off)
+  const exp_tab_detail::Tab& TAB = kExpTab;
+  constexpr float C1 = 0.0108184814453125f;
+  constexpr float C2 = 1.1943250683543738e-05f;
+  constexpr float C3 = 2.531013593154441e-13f;
+  constexpr float INV = 92.33248261689366f;    // 64 / ln 2
+  if (!(t.hi < 103.0f)) return {0.f, 0.f};
+  const float k = rintf(t.hi * INV);
+  ff r = ff_two_sum(t.hi - k * C1, t.lo);
+  r = ff_add(r, ff_neg(ff_two_prod(k, C2)));
+  r = ff_add(r, ff{-k * C3, 0.f});
+  const float rh = r.hi;
+  // -r_lo + r_hi r_lo (the cross term of r^2 / 2) - r^3/6 + r^4/24
+  const float rest = __builtin_fmaf(rh * rh * rh, __builtin_fmaf(rh, 1.f / 24, -1.f / 6),
+                                    __builtin_fmaf(rh, r.lo, -r.lo));
+  ff p = ff_two_sum(1.f, -rh);
+  p = ff_add(p, ff_two_prod(rh, 0.5f * rh));
+  p = ff_add(p, ff{rest, 0.f});
+  const int ki = (int)k;
+  const int j = ki & 63;
+  p = ff_mul(p, ff{TAB.hi[j], TAB.lo[j]});
+  const int e = -(ki >> 6);
+  return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
+}
+
+// Natural log of a float-float f > 0 to about 1e-13 absolute: the FP32 log y0 of the
+// leading part corrected by ln g ~ g - 1 with g = f exp(-y0) = 1 + O(1e-7) (the
+// dropped (g - 1)^2 / 2 is below 1e-14).  With w = exp(-|y0|) from the float-float
+// exponential, g - 1 = f w - 1 for y0 >= 0 and (f - w) / w for y0 < 0.
+__host__ __device__ __forceinline__ ff ff_log(ff f) {
+#pragma clang fp contract(off)
+  const float y0 = logf(f.hi);
+  const ff w = ff_exp_neg_fast(ff{fabsf(y0), 0.f});
+  float d;
+  if (y0 >= 0.f) {
+    const ff g1 = ff_add(ff_mul(f, w), ff{-1.f, 0.f});
+    d = g1.hi + g1.lo;
+  } else {
+    const ff num = ff_add(f, ff_neg(w));
+    d = (num.hi + num.lo) / w.hi;
+  }
+  return ff_two_sum(y0, d);
 }
 
 // Square root of a float-float a >= 0: the float root s of the leading part, then one

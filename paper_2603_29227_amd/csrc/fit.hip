@@ -1,19 +1,22 @@
 // Per-cell log-GP fit (Sec. IV-B.1, eq. log_gp_posterior_mean; RBF of Table I).
 //
-// One workgroup per cell (256 threads, 4 waves of 64).  The workgroup gathers the
-// cell's samples into cell-local coordinates, assembles A = K + Sigma, factors it
-// A = L L^T in place (right-looking, packed lower triangle), solves a = A^{-1} 1
-// with wave-0 triangular solves whose dot products reduce by cross-lane shuffles,
-// and writes the per-cell store: (p_i, a_i), sigma_i^2, the packed factor with the
-// reciprocal diagonal, the sample bounding box and A+ = sum of positive a_i.
+// Cells with m <= 64 are fitted by one wave each (fit_wave.h: rows in registers, four
+// cells per workgroup, no workgroup barriers); larger cells by one workgroup each
+// (256 threads, 4 waves of 64), which gathers the cell's samples into cell-local
+// coordinates, assembles A = K + Sigma, factors it A = L L^T in place (right-looking,
+// packed lower triangle), solves a = A^{-1} 1 with wave-0 triangular solves whose dot
+// products reduce by cross-lane shuffles.  Both write the per-cell store: (p_i, a_i),
+// sigma_i^2, the packed factor with the reciprocal diagonal, the sample bounding box
+// and A+ = sum of positive a_i.
 //
-// FP32 cells keep A in LDS (float-float entries plus the FP32 factor, 99 KB at
-// m = 128) and estimate cond_2(A) by power and inverse iteration; a cell above the
-// threshold or with a non-positive pivot is queued for the FP64 kernel, which
+// The workgroup fit keeps A in LDS (float-float entries plus the FP32 factor, 99 KB
+// at m = 128).  Both estimate cond_2(A) by power and inverse iteration; a cell above
+// the threshold or with a non-positive pivot is queued for the FP64 kernel, which
 // factors in global memory (the plain FP64 path uses that kernel for every cell).
 #include <algorithm>
 
 #include "fit_dev.h"
+#include "fit_wave.h"
 
 namespace ksdf {
 namespace {
@@ -31,6 +34,36 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
   if (threadIdx.x == 0 && need64) {
     const int slot = atomicAdd(A.fb_count, 1);
     A.fb_list[slot] = c;
+  }
+}
+
+// One wave per cell for m <= MB <= 64 (fit_wave.h), four cells per workgroup; n: the
+// list's length when count is null
+template <int MB>
+__global__ void __launch_bounds__(FIT_THREADS) fit32w_kernel(FitArgs A, const int* list,
+                                                             const int* count, int n) {
+  __shared__ WaveFitLds<MB> lds[FIT_THREADS / 64];
+  const int w = threadIdx.x / 64;
+  const int t = blockIdx.x * (FIT_THREADS / 64) + w;
+  if (t >= (count ? *count : n)) return;
+  const int c = list[t];
+  const bool need64 = fit32_wave<MB>(A, c, lds[w]);
+  if ((threadIdx.x & 63) == 0 && need64) {
+    const int slot = atomicAdd(A.fb_count, 1);
+    A.fb_list[slot] = c;
+  }
+}
+
+// launch a bucket: the one-wave fit up to m = 64, the workgroup fit above
+template <int MB>
+void launch_bucket(const FitArgs& A, const int* list, const int* count, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if constexpr (MB <= 64) {
+    const int per = FIT_THREADS / 64;
+    hipLaunchKernelGGL(fit32w_kernel<MB>, dim3((unsigned)((n + per - 1) / per)), dim3(FIT_THREADS), 0, s,
+                       A, list, count, n);
+  } else {
+    hipLaunchKernelGGL(fit32_kernel<MB>, dim3((unsigned)n), dim3(FIT_THREADS), 0, s, A, list, count);
   }
 }
 
@@ -233,18 +266,10 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
     const int n16 = minb < 32 ? bs[1] - bs[0] : 0;
     const int n32 = minb < 64 ? bs[2] - lo32 : 0;
     const int n64 = bs[3] - lo64, n128 = bs[4] - bs[3];
-    if (n16 > 0)
-      hipLaunchKernelGGL(fit32_kernel<16>, dim3(std::min(n16, budget)), dim3(FIT_THREADS), 0, s, A,
-                         blist, bcount);
-    if (n32 > 0)
-      hipLaunchKernelGGL(fit32_kernel<32>, dim3(std::min(n32, budget)), dim3(FIT_THREADS), 0, s, A,
-                         blist + budget, bcount + 1);
-    if (n64 > 0)
-      hipLaunchKernelGGL(fit32_kernel<64>, dim3(std::min(n64, budget)), dim3(FIT_THREADS), 0, s, A,
-                         blist + 2L * budget, bcount + 2);
-    if (n128 > 0)
-      hipLaunchKernelGGL(fit32_kernel<128>, dim3(std::min(n128, budget)), dim3(FIT_THREADS), 0, s, A,
-                         blist + 3L * budget, bcount + 3);
+    launch_bucket<16>(A, blist, bcount, std::min(n16, budget), s);
+    launch_bucket<32>(A, blist + budget, bcount + 1, std::min(n32, budget), s);
+    launch_bucket<64>(A, blist + 2L * budget, bcount + 2, std::min(n64, budget), s);
+    launch_bucket<128>(A, blist + 3L * budget, bcount + 3, std::min(n128, budget), s);
     A.list = m->fb_list;
     A.list_count = m->fb_count;
     A.emit32 = 1;
@@ -296,14 +321,10 @@ int launch_fit(ksdf_model* m, const void* pts, int dtype, const void* svar, uint
     const int minb = m->tuning.fit_min_bucket;
     const int lo32 = minb >= 32 ? bs[0] : bs[1];
     const int lo64 = minb >= 64 ? bs[0] : bs[2];
-    if (minb < 32 && bs[1] > bs[0])
-      hipLaunchKernelGGL(fit32_kernel<16>, dim3(bs[1] - bs[0]), dim3(FIT_THREADS), 0, s, A, lists + bs[0], nullptr);
-    if (minb < 64 && bs[2] > lo32)
-      hipLaunchKernelGGL(fit32_kernel<32>, dim3(bs[2] - lo32), dim3(FIT_THREADS), 0, s, A, lists + lo32, nullptr);
-    if (bs[3] > lo64)
-      hipLaunchKernelGGL(fit32_kernel<64>, dim3(bs[3] - lo64), dim3(FIT_THREADS), 0, s, A, lists + lo64, nullptr);
-    if (bs[4] > bs[3])
-      hipLaunchKernelGGL(fit32_kernel<128>, dim3(bs[4] - bs[3]), dim3(FIT_THREADS), 0, s, A, lists + bs[3], nullptr);
+    if (minb < 32) launch_bucket<16>(A, lists + bs[0], nullptr, bs[1] - bs[0], s);
+    if (minb < 64) launch_bucket<32>(A, lists + lo32, nullptr, bs[2] - lo32, s);
+    launch_bucket<64>(A, lists + lo64, nullptr, bs[3] - lo64, s);
+    launch_bucket<128>(A, lists + bs[3], nullptr, bs[4] - bs[3], s);
     A.list = m->fb_list;
     A.list_count = m->fb_count;
     A.emit32 = 1;

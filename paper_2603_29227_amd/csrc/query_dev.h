@@ -48,9 +48,8 @@ struct FastArgs {
   float alpha_l2e;   // alpha * log2(e)
   float alpha;
   float inv2l2_ff[2];
-  float far2;
-  double two_l2_d;   // 2 l^2 and 1 / (2 l^2) in FP64 (re-evaluation of uncertain cells)
-  double inv2l2_d;        // |x - centre|^2 beyond which pass 2 takes the far-field exponent
+  float far2;         // |x - centre|^2 beyond which pass 2 takes the far-field exponent
+  float two_l2_ff[2];   // 2 l^2 as a float pair (re-evaluation of uncertain cells)
 };
 
 // What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
@@ -128,36 +127,39 @@ __device__ __forceinline__ long box_key(const FastArgs& A, float qx, float qy, f
 }
 
 // ---------------------------------------------------------------------------
-// FP64 re-evaluation of one cell's u^2 for one lane (rare path)
+// Float-float re-evaluation of one cell's u^2 for one lane (rare path)
 // ---------------------------------------------------------------------------
-// Coordinates and weights come from the float-float store (hi + lo is exact in
-// double), the scaling reference is the nearest sample, exp and log are the double
-// ones.  The FP64 units run at the rate of unpacked FP32 here, and a double exp costs
-// a fraction of a float-float one.
-__device__ float cell_u2_f64(const FastArgs& A, int c, float qx, float qy, float qz) {
+// Coordinates and weights come from the float-float store (hi + lo), the differences
+// to the query are exact float-float sums, the scaling reference is the nearest
+// sample (its float-float z^2), and the kernel values and the log come from
+// ff_exp_neg_fast / ff_log (about 2e-12 relative), so that f' carries an error of a
+// few parts in 1e12 of sum |a_i e_i| instead of the FP32 pass's 1e-7.
+__device__ float cell_u2_ff(const FastArgs& A, int c, float qx, float qy, float qz) {
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const float4 ctr = A.centre[c];
-  const double lx = (double)qx - (double)ctr.x, ly = (double)qy - (double)ctr.y,
-               lz = (double)qz - (double)ctr.z;
-  double d2 = INFINITY;
+  const ff lx = ff_two_sum(qx, -ctr.x), ly = ff_two_sum(qy, -ctr.y), lz = ff_two_sum(qz, -ctr.z);
+  auto z2_of = [&](int i) {
+    const float4 p = A.ps[b + i], pl = A.plo[b + i];
+    const ff dx = ff_add(lx, ff{-p.x, -pl.x});
+    const ff dy = ff_add(ly, ff{-p.y, -pl.y});
+    const ff dz = ff_add(lz, ff{-p.z, -pl.z});
+    return ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
+  };
+  ff d2{INFINITY, 0.f};
+  for (int i = 0; i < m; ++i) {
+    const ff z2 = z2_of(i);
+    if (z2.hi < d2.hi || (z2.hi == d2.hi && z2.lo < d2.lo)) d2 = z2;
+  }
+  const ff inv{A.inv2l2_ff[0], A.inv2l2_ff[1]};
+  ff f{0.f, 0.f};
   for (int i = 0; i < m; ++i) {
     const float4 p = A.ps[b + i], pl = A.plo[b + i];
-    const double dx = lx - ((double)p.x + (double)pl.x);
-    const double dy = ly - ((double)p.y + (double)pl.y);
-    const double dz = lz - ((double)p.z + (double)pl.z);
-    d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
+    const ff t = ff_mul(ff_add(z2_of(i), ff_neg(d2)), inv);
+    f = ff_add(f, ff_mul(ff{p.w, pl.w}, ff_exp_neg_fast(t)));
   }
-  double f = 0.0;
-  for (int i = 0; i < m; ++i) {
-    const float4 p = A.ps[b + i], pl = A.plo[b + i];
-    const double dx = lx - ((double)p.x + (double)pl.x);
-    const double dy = ly - ((double)p.y + (double)pl.y);
-    const double dz = lz - ((double)p.z + (double)pl.z);
-    const double z2 = dx * dx + dy * dy + dz * dz;
-    f += ((double)p.w + (double)pl.w) * exp(-(z2 - d2) * A.inv2l2_d);
-  }
-  if (!(f > 0.0)) return INFINITY;
-  return (float)(d2 - A.two_l2_d * log(f));
+  if (!(f.hi > 0.f)) return INFINITY;
+  const ff u2 = ff_add(d2, ff_neg(ff_mul(ff{A.two_l2_ff[0], A.two_l2_ff[1]}, ff_log(f))));
+  return u2.hi + u2.lo;
 }
 
 // lower bound of the squared distance from local point (x,y,z) to the cell's
@@ -173,7 +175,7 @@ __device__ __forceinline__ float aabb_d2(const float* bx, float x, float y, floa
 // 2 l^2 * 1e-5 on u^2 near u = 0 where the square root amplifies errors.  The
 // per-cell error bound del (a worst-case sum of per-term rounding errors) was
 // measured against FP64 on 52k room queries: the actual error never exceeded 0.31
-// of it (median 0.02).  A cell is re-evaluated in FP64 when 0.35 * del could
+// of it (median 0.02).  A cell is re-evaluated in float-float when 0.35 * del could
 // reach half the target, i.e. del > BUDGET_SCALE * target.
 constexpr float BUDGET_SCALE = 0.5f / 0.35f;
 __device__ __forceinline__ float u2_budget(float u2, float two_l2) {
@@ -365,7 +367,7 @@ __device__ __forceinline__ void cell_u2_wave(const FastArgs& A, int b, int m, fl
 
 // Min-fusion of the candidates' u^2 (ties to the lower id); where the error bounds of
 // the best and of a rival overlap by more than the budget, the overlapping cells are
-// re-evaluated in FP64.  Returns the argmin cell (-1: none valid); best = its u^2.
+// re-evaluated in float-float.  Returns the argmin cell (-1: none valid); best = its u^2.
 template <int KM>
 __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float qx, float qy,
                                            float qz, const int (&cid)[KM], int n, float (&cu2)[KM],
@@ -391,7 +393,7 @@ __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float
 #pragma unroll
         for (int r = 0; r < KM; ++r)
           if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
-            cu2[r] = cell_u2_f64(A, cid[r], qx, qy, qz);
+            cu2[r] = cell_u2_ff(A, cid[r], qx, qy, qz);
           }
         bu = INFINITY;
         bc = -1;
@@ -542,7 +544,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     }
   }
 
-  // ---- resolve the minimum; re-evaluate uncertain cells in FP64
+  // ---- resolve the minimum; re-evaluate uncertain cells in float-float
   const int bc = resolve_min<KM>(A, active, qx, qy, qz, cid, n, cu2, cdl, best);
   // the argmin cell's scaling reference from pass 1 (box bound, or its nearest sample
   // where the box bound would have underflowed the terms)
@@ -1015,8 +1017,8 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   const double inv = 1.0 / two_l2;
   A.inv2l2_ff[0] = (float)inv;
   A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);
-  A.two_l2_d = two_l2;
-  A.inv2l2_d = inv;
+  A.two_l2_ff[0] = (float)two_l2;
+  A.two_l2_ff[1] = (float)(two_l2 - (double)(float)two_l2);
   return A;
 }
 

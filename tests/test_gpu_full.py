@@ -91,10 +91,11 @@ def test_room_batch_uneven_full_size():
     model.set_tuning(fused=0)
     sep = model.fit_query(pts, q, sg)
     torch.cuda.synchronize()
-    for k in fused:
-        assert torch.equal(fused[k], sep[k]), f"fused and separate launches differ in {k}"
+    # the fused launch fits with whole workgroups, the separate launches with one wave per
+    # cell up to m = 64: both are held to the oracle on the same sample
     idx = _sample(sep, 12000, 4000, 21)
     _check_sample(wl, cells, sep, idx, "room batch")
+    _check_sample(wl, cells, fused, idx, "room batch, fused")
     model.close()
 
 

@@ -1,6 +1,9 @@
-"""The persistent fused fit+query launch against separate fit and query launches
-(bit-identical: the same per-cell arithmetic in a different schedule) and
-against the oracle, on cells with uneven m."""
+"""The persistent fused fit+query launch against separate fit and query launches and
+against the oracle, on cells with uneven m.  The fused launch fits every cell with a
+whole workgroup while the separate launches fit cells of up to 64 samples with one
+wave each (rows in registers), so the two agree within the parity tolerances, not
+bit for bit: both are held to the oracle, with the same FP64-refit decisions and
+argmin cells except at near ties."""
 import numpy as np
 import pytest
 import torch
@@ -48,10 +51,10 @@ def test_fused_launch_matches_separate_launches_and_oracle(case):
         wl = scenes.small_room_workload(n_queries=3000, cfg_id=42)
     cells, sep, fus, st_a, st_b = _run_both(wl)
     np.testing.assert_array_equal(st_a, st_b)
-    for k in sep:
-        np.testing.assert_array_equal(sep[k], fus[k], err_msg=k)
     o = oracle_run(wl, cells, wl.queries, wl.sign, "fp32")
     assert_parity(fus, o, wl.ell, "fp32", label=f"fused {case}")
+    assert_parity(sep, o, wl.ell, "fp32", label=f"separate {case}")
+    assert np.mean(sep["argmin"] == fus["argmin"]) > 0.99
 
 
 def test_fused_with_no_queries_still_fits():
@@ -59,22 +62,26 @@ def test_fused_with_no_queries_still_fits():
     wl = scenes.small_room_workload(n_queries=64, cfg_id=43)
     cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min)
     m = ksdf.Model(cells, len(wl.points), wl.origin, wl.h)
+    m.set_tuning(fused=1)
     pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
     m.fit_query(pts, torch.zeros(0, 3, dtype=torch.float32, device="cuda"))
-    out = m.query(torch.from_numpy(wl.queries).cuda())
+    out = m.query(q)
+    # the same fused fit, launched with queries: the cells' fits agree bit for bit
     ref = ksdf.Model(cells, len(wl.points), wl.origin, wl.h)
-    ref.fit(pts)
-    out2 = ref.query(torch.from_numpy(wl.queries).cuda())
+    ref.set_tuning(fused=1)
+    want = {k: v.clone() for k, v in ref.fit_query(pts, q).items()}
     torch.cuda.synchronize()
-    assert torch.equal(out["mean"], out2["mean"])
+    for k in ("mean", "grad", "var", "argmin", "status"):
+        assert torch.equal(out[k], want[k]), k
 
 
 def test_fused_wait_expiry_is_reported():
     """The fused launch's bounded wait for the fits, forced from the host with a limit
     of one sleep: every kernel still ends normally; queries answered by workgroups
     that stopped waiting carry Q_FIT_TIMEOUT, ksdf_model_check reports the expiry once
-    (KSDF_ERR_TIMEOUT) and then clears it; the other queries equal the separate
-    launches bit for bit.  With the default bound nothing is flagged."""
+    (KSDF_ERR_TIMEOUT) and then clears it; the other queries equal a fused launch
+    that waited, bit for bit.  With the default bound nothing is flagged."""
     print("[gpu-case] fused launch, forced wait expiry", flush=True)
     wl = scenes.small_room_workload(n_queries=200_000, uneven=True, cfg_id=44)
     cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
@@ -83,8 +90,9 @@ def test_fused_wait_expiry_is_reported():
     q = torch.from_numpy(wl.queries).cuda()
     sg = torch.from_numpy(wl.sign).cuda()
     ref = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var)
-    ref.fit(pts)
-    want = ref.query(q, sg)
+    ref.set_tuning(fused=1, query_split=0)
+    want = {k: v.clone() for k, v in ref.fit_query(pts, q, sg).items()}
+    ref.check()
     m = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var)
     m.set_tuning(fused=1, query_split=0)
     m.set_wait_limit(1)

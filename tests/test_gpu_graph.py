@@ -179,17 +179,24 @@ def test_tuning_preserves_outputs(tuning):
     P = torch.from_numpy(wl.points).to(dev, torch.float32)
     q = torch.from_numpy(wl.queries).to(dev, torch.float32)
     sg = torch.from_numpy(wl.sign).to(dev)
-    base = model.fit_query(P, q, sg)
+    # the fused launch fits every cell with a workgroup, the separate fit with one wave
+    # per cell up to m = 64: each tuning is compared with the default of its own fit
+    model.set_tuning(fused=1)
+    base_fused = _clone(model.fit_query(P, q, sg))
+    model.set_tuning(fused=0)
+    model.fit(P)
+    base_sep = _clone(model.query(q, sg))
     torch.cuda.synchronize()
-    base = _clone(base)
     model.set_tuning(**tuning)
     assert all(model.tuning()[k] == v for k, v in tuning.items())
     a = model.fit_query(P, q, sg)
+    torch.cuda.synchronize()
+    a = _clone(a)
     model.fit(P)
     b = model.query(q, sg)
     torch.cuda.synchronize()
-    _equal(a, base)
-    _equal(b, base)
+    _equal(a, base_fused if tuning["fused"] else base_sep)
+    _equal(b, base_sep)
     oc = oracle.Cells(cells.offsets, cells.samples, cells.keys,
                       np.asarray(wl.origin) + (cells.keys + 0.5) * wl.h)
     f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var)
@@ -279,9 +286,21 @@ def test_query_mfma_gp_variance(block):
         else:
             model.fit(P)
         model.set_tuning(fused=0, query_split=1, query_mfma=1)
-        c = model.query(q, sg, grad_var=True)
+        c = _clone(model.query(q, sg, grad_var=True))
+        if not fused:
+            torch.cuda.synchronize()
+            _equal(c, b, keys=("mean", "grad", "var", "var_f", "grad_var", "argmin", "status"))
+            continue
+        # the fused launch fits with its own workgroup kernel, so its factor differs
+        # from the separate fit's by rounding: compare with the forward substitution
+        # on the factor it left
+        model.set_tuning(query_mfma=0)
+        fs = model.query(q, sg, grad_var=True)
         torch.cuda.synchronize()
-        _equal(c, b, keys=("mean", "grad", "var", "var_f", "grad_var", "argmin", "status"))
+        _equal(c, fs, keys=("mean", "grad", "var", "grad_var", "argmin", "status"))
+        d = (c["var_f"] - fs["var_f"]).abs().max().item()
+        print(f"query_mfma after the fused fit: max |var_f difference| {d:.3g}", flush=True)
+        assert d <= 1e-4
     model.close()
 
 
