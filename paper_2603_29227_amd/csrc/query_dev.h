@@ -127,36 +127,57 @@ __device__ __forceinline__ long box_key(const FastArgs& A, float qx, float qy, f
 }
 
 // ---------------------------------------------------------------------------
-// Float-float re-evaluation of one cell's u^2 for one lane (rare path)
+// Float-float re-evaluation of one cell's u^2 (rare path), by the whole wave
 // ---------------------------------------------------------------------------
 // Coordinates and weights come from the float-float store (hi + lo), the differences
 // to the query are exact float-float sums, the scaling reference is the nearest
 // sample (its float-float z^2), and the kernel values and the log come from
 // ff_exp_neg_fast / ff_log (about 2e-12 relative), so that f' carries an error of a
-// few parts in 1e12 of sum |a_i e_i| instead of the FP32 pass's 1e-7.
-__device__ float cell_u2_ff(const FastArgs& A, int c, float qx, float qy, float qz) {
+// few parts in 1e12 of sum |a_i e_i| instead of the FP32 pass's 1e-7.  Every lane of
+// the wave calls it with the same cell and query; lane l takes samples l, l + 64, ...
+// and the nearest-sample minimum and the sum of f' are wave reductions (float-float
+// addition is commutative, so every lane ends with the same value).
+__device__ __forceinline__ float shfl_xor_f(float v, int o) { return __shfl_xor(v, o, 64); }
+
+__device__ float cell_u2_ff_wave(const FastArgs& A, int c, float qx, float qy, float qz) {
+  constexpr int SPL = (KSDF_MAX_M + 63) / 64;
+  const int lane = threadIdx.x & 63;
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const float4 ctr = A.centre[c];
   const ff lx = ff_two_sum(qx, -ctr.x), ly = ff_two_sum(qy, -ctr.y), lz = ff_two_sum(qz, -ctr.z);
-  auto z2_of = [&](int i) {
-    const float4 p = A.ps[b + i], pl = A.plo[b + i];
-    const ff dx = ff_add(lx, ff{-p.x, -pl.x});
-    const ff dy = ff_add(ly, ff{-p.y, -pl.y});
-    const ff dz = ff_add(lz, ff{-p.z, -pl.z});
-    return ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
-  };
+  ff z2[SPL];
   ff d2{INFINITY, 0.f};
-  for (int i = 0; i < m; ++i) {
-    const ff z2 = z2_of(i);
-    if (z2.hi < d2.hi || (z2.hi == d2.hi && z2.lo < d2.lo)) d2 = z2;
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int i = lane + 64 * k;
+    z2[k] = ff{INFINITY, 0.f};
+    if (i < m) {
+      const float4 p = A.ps[b + i], pl = A.plo[b + i];
+      const ff dx = ff_add(lx, ff{-p.x, -pl.x});
+      const ff dy = ff_add(ly, ff{-p.y, -pl.y});
+      const ff dz = ff_add(lz, ff{-p.z, -pl.z});
+      z2[k] = ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
+      if (z2[k].hi < d2.hi || (z2[k].hi == d2.hi && z2[k].lo < d2.lo)) d2 = z2[k];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const ff t{shfl_xor_f(d2.hi, o), shfl_xor_f(d2.lo, o)};
+    if (t.hi < d2.hi || (t.hi == d2.hi && t.lo < d2.lo)) d2 = t;
   }
   const ff inv{A.inv2l2_ff[0], A.inv2l2_ff[1]};
   ff f{0.f, 0.f};
-  for (int i = 0; i < m; ++i) {
-    const float4 p = A.ps[b + i], pl = A.plo[b + i];
-    const ff t = ff_mul(ff_add(z2_of(i), ff_neg(d2)), inv);
-    f = ff_add(f, ff_mul(ff{p.w, pl.w}, ff_exp_neg_fast(t)));
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int i = lane + 64 * k;
+    if (i < m) {
+      const float aw = A.ps[b + i].w, awl = A.plo[b + i].w;
+      const ff t = ff_mul(ff_add(z2[k], ff_neg(d2)), inv);
+      f = ff_add(f, ff_mul(ff{aw, awl}, ff_exp_neg_fast(t)));
+    }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) f = ff_add(f, ff{shfl_xor_f(f.hi, o), shfl_xor_f(f.lo, o)});
   if (!(f.hi > 0.f)) return INFINITY;
   const ff u2 = ff_add(d2, ff_neg(ff_mul(ff{A.two_l2_ff[0], A.two_l2_ff[1]}, ff_log(f))));
   return u2.hi + u2.lo;
@@ -372,41 +393,63 @@ template <int KM>
 __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float qx, float qy,
                                            float qz, const int (&cid)[KM], int n, float (&cu2)[KM],
                                            const float (&cdl)[KM], float& best) {
-  int bc = -1;
-  if (active) {
-    float bu = INFINITY, bd = 0.f;
+  auto argmin = [&](float& bu, float& bd) {
+    int c = -1;
+    bu = INFINITY;
+    bd = 0.f;
 #pragma unroll
     for (int r = 0; r < KM; ++r)
-      if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
+      if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < c))) {
         bu = cu2[r];
         bd = cdl[r];
-        bc = cid[r];
+        c = cid[r];
       }
-    if (bc >= 0) {
-      const float budget = u2_budget(bu, A.two_l2);
-      bool redo = false;
+    return c;
+  };
+  float bu = INFINITY, bd = 0.f;
+  int bc = active ? argmin(bu, bd) : -1;
+  const bool found = bc >= 0;
+  // the candidates to re-evaluate, one bit per slot
+  unsigned need = 0;
+  if (bc >= 0) {
+    const float budget = u2_budget(bu, A.two_l2);
+    bool redo = false;
+#pragma unroll
+    for (int r = 0; r < KM; ++r)
+      if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
+        redo = true;
+    if (redo) {
 #pragma unroll
       for (int r = 0; r < KM; ++r)
-        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
-          redo = true;
-      if (redo) {
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) {
-            cu2[r] = cell_u2_ff(A, cid[r], qx, qy, qz);
-          }
-        bu = INFINITY;
-        bc = -1;
-#pragma unroll
-        for (int r = 0; r < KM; ++r)
-          if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < bc))) {
-            bu = cu2[r];
-            bc = cid[r];
-          }
-      }
-      best = bu;
+        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) need |= 1u << r;
     }
   }
+  const bool redone = need != 0;
+  // the wave takes the flagged (query, cell) pairs one at a time, lowest lane first
+  while (true) {
+    const unsigned long long pend = __ballot(need != 0);
+    if (!pend) break;
+    const int src = __builtin_ctzll(pend);
+    const int myr = need ? __builtin_ctz(need) : 0;
+    int myc = 0;
+#pragma unroll
+    for (int r = 0; r < KM; ++r)
+      if (r == myr) myc = cid[r];
+    const int c = __builtin_amdgcn_readlane(myc, src);
+    const int rs = __builtin_amdgcn_readlane(myr, src);
+    const float sx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qx), src));
+    const float sy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qy), src));
+    const float sz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qz), src));
+    const float u2 = cell_u2_ff_wave(A, c, sx, sy, sz);
+    if ((int)(threadIdx.x & 63) == src) {
+#pragma unroll
+      for (int r = 0; r < KM; ++r)
+        if (r == rs) cu2[r] = u2;
+      need &= ~(1u << rs);
+    }
+  }
+  if (redone) bc = argmin(bu, bd);
+  if (found) best = bu;
   return bc;
 }
 
