@@ -188,6 +188,82 @@ __host__ __device__ __forceinline__ ff ff_exp_neg_fast(ff t) {
   return {ldexpf(p.hi, e), ldexpf(p.lo, e)};
 }
 
+// exp(-t) for float-float t >= 0, the reduction and series of ff_exp_neg_fast with
+// fewer operations: r = t - k ln2/64 from exact products (k C1, and TwoProduct for
+// k C2) and one TwoSum, the series' leading terms 1 - r_hi (exact by Fast2Sum, as
+// |r_hi| < 1/2) and r_hi^2/2 (exact by TwoProduct) added by Fast2Sum, the rest in
+// FP32.  Below about 1e-13 relative for t < 87; 0 from t >= 87 (exp(-87) is at the
+// bottom of the FP32 normal range).  Branch-free.
+__host__ __device__ __forceinline__ ff ff_exp_neg_lean(ff t) {
+#pragma clang fp contract(off)
+  const exp_tab_detail::Tab& TAB = kExpTab;
+  constexpr float C1 = 0.0108184814453125f;
+  constexpr float C2 = 1.1943250683543738e-05f;
+  constexpr float C3 = 2.531013593154441e-13f;
+  constexpr float INV = 92.33248261689366f;    // 64 / ln 2
+  const bool live = t.hi < 87.f;
+  const float th = live ? t.hi : 0.f, tl = live ? t.lo : 0.f;
+  const float k = rintf(th * INV);
+  const float r0 = th - k * C1;                 // exact: k C1 has at most 24 bits, Sterbenz
+  const ff p = ff_two_prod(k, C2);
+  const ff r1 = ff_two_sum(r0, -p.hi);
+  const ff r = ff_fast_two_sum(r1.hi, (__builtin_fmaf(-k, C3, tl - p.lo)) + r1.lo);
+  const float rh = r.hi;
+  const float rest = __builtin_fmaf(rh * rh * rh, __builtin_fmaf(rh, 1.f / 24, -1.f / 6),
+                                    __builtin_fmaf(rh, r.lo, -r.lo));
+  const ff a = ff_fast_two_sum(1.f, -rh);
+  const ff q = ff_two_prod(rh, 0.5f * rh);
+  const ff b = ff_fast_two_sum(a.hi, q.hi);
+  ff e = ff_fast_two_sum(b.hi, ((a.lo + q.lo) + b.lo) + rest);
+  const int ki = (int)k;
+  const int j = ki & 63;
+  e = ff_mul(e, ff{TAB.hi[j], TAB.lo[j]});
+  const int sh = -(ki >> 6);
+  return live ? ff{ldexpf(e.hi, sh), ldexpf(e.lo, sh)} : ff{0.f, 0.f};
+}
+
+// (xh + xl) - (yh + yl) for two float-float coordinates of the same frame: TwoSum of
+// the leading parts and one rounding of the low parts' difference (below 2^-47 of the
+// operands).
+__host__ __device__ __forceinline__ ff ff_sub_lean(float xh, float xl, float yh, float yl) {
+#pragma clang fp contract(off)
+  const ff s = ff_two_sum(xh, -yh);
+  return ff_fast_two_sum(s.hi, s.lo + (xl - yl));
+}
+
+// |v|^2 of a float-float 3-vector: the squares of the leading parts exact by
+// TwoProduct and added by TwoSum, the cross terms 2 hi lo and every error term summed
+// in FP32 (about 2^-46 relative; the dropped lo^2 are smaller still).
+__host__ __device__ __forceinline__ ff ff_norm2_lean(ff x, ff y, ff z) {
+#pragma clang fp contract(off)
+  const ff px = ff_two_prod(x.hi, x.hi), py = ff_two_prod(y.hi, y.hi), pz = ff_two_prod(z.hi, z.hi);
+  const ff s = ff_two_sum(px.hi, py.hi);
+  const ff t = ff_two_sum(s.hi, pz.hi);
+  float e = ((px.lo + py.lo) + (pz.lo + s.lo)) + t.lo;
+  e = __builtin_fmaf(2.f * x.hi, x.lo, e);
+  e = __builtin_fmaf(2.f * y.hi, y.lo, e);
+  e = __builtin_fmaf(2.f * z.hi, z.lo, e);
+  return ff_fast_two_sum(t.hi, e);
+}
+
+// One step of a compensated dot product (Ogita, Rump and Oishi's Dot2, with the
+// float-float operands' cross terms): s + c -= (ah + al)(xh + xl), the product's
+// rounding error (TwoProduct) and the sum's (TwoSum) collected in c, al xl dropped.
+// The result is as accurate as if computed in twice the working precision.
+__host__ __device__ __forceinline__ void dot2_sub(float& s, float& c, float ah, float al, float xh,
+                                                  float xl) {
+#pragma clang fp contract(off)
+  const float p = ah * xh;
+  const float pe = __builtin_fmaf(ah, xh, -p);
+  const float t = s - p;
+  const float bb = t - s;
+  const float se = (s - (t - bb)) + (-p - bb);
+  s = t;
+  c = c + (se - pe);
+  c = __builtin_fmaf(-ah, xl, c);
+  c = __builtin_fmaf(-al, xh, c);
+}
+
 // Natural log of a float-float f > 0 to about 1e-13 absolute: the FP32 log y0 of the
 // leading part corrected by ln g ~ g - 1 with g = f exp(-y0) = 1 + O(1e-7) (the
 // dropped (g - 1)^2 / 2 is below 1e-14).  With w = exp(-|y0|) from the float-float

@@ -39,15 +39,16 @@ __global__ void __launch_bounds__(FIT_THREADS) fit32_kernel(FitArgs A, const int
 
 // One wave per cell for m <= MB <= 64 (fit_wave.h), four cells per workgroup; n: the
 // list's length when count is null
-template <int MB>
-__global__ void __launch_bounds__(FIT_THREADS) fit32w_kernel(FitArgs A, const int* list,
+template <int MB, bool MATERN>
+__global__ void __launch_bounds__(FIT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+fit32w_kernel(FitArgs A, const int* list,
                                                              const int* count, int n) {
   __shared__ WaveFitLds<MB> lds[FIT_THREADS / 64];
   const int w = threadIdx.x / 64;
   const int t = blockIdx.x * (FIT_THREADS / 64) + w;
   if (t >= (count ? *count : n)) return;
   const int c = list[t];
-  const bool need64 = fit32_wave<MB>(A, c, lds[w]);
+  const bool need64 = fit32_wave<MB, MATERN>(A, c, lds[w]);
   if ((threadIdx.x & 63) == 0 && need64) {
     const int slot = atomicAdd(A.fb_count, 1);
     A.fb_list[slot] = c;
@@ -60,8 +61,11 @@ void launch_bucket(const FitArgs& A, const int* list, const int* count, int n, h
   if (n <= 0) return;
   if constexpr (MB <= 64) {
     const int per = FIT_THREADS / 64;
-    hipLaunchKernelGGL(fit32w_kernel<MB>, dim3((unsigned)((n + per - 1) / per)), dim3(FIT_THREADS), 0, s,
-                       A, list, count, n);
+    const dim3 grid((unsigned)((n + per - 1) / per));
+    if (A.kernel == KSDF_KERNEL_MATERN32)
+      hipLaunchKernelGGL((fit32w_kernel<MB, true>), grid, dim3(FIT_THREADS), 0, s, A, list, count, n);
+    else
+      hipLaunchKernelGGL((fit32w_kernel<MB, false>), grid, dim3(FIT_THREADS), 0, s, A, list, count, n);
   } else {
     hipLaunchKernelGGL(fit32_kernel<MB>, dim3((unsigned)n), dim3(FIT_THREADS), 0, s, A, list, count);
   }
