@@ -147,6 +147,9 @@ class Timer:
         return med(ms), ms
 
 
+COST_MARGIN, COST_KVAR = 0.3, 1.0   # c = sum softplus(0.3 - d + 1.0 sqrt(var))
+
+
 def softplus_cotangents(torch, out, d_mean, d_var):
     # cost c = sum softplus(0.3 - d + sqrt(var)): dc/dd = -sigmoid(t), dc/dvar = sigmoid(t) / (2 sqrt(var))
     sd = torch.sqrt(torch.clamp_min(out["var"], 1e-30))
@@ -166,9 +169,10 @@ def roofline_query(flop_q, tr_q, Q, kernel_ms, kernel, extra_flop=0.0, traffic=N
             "issue_frac": round(slots / (kernel_ms * 1e-3) / (PEAK_VALU_TSLOTS * 1e12), 4)}
 
 
-def roofline_backward(m_mean, QT, kernel_ms, var_f, fp64_arith=True):
-    """The backward kernel of an FP32 model computes in FP64 (from the float-float store):
-    scored against the FP64 vector peak."""
+def roofline_backward(m_mean, QT, kernel_ms, var_f, fp64_arith=False):
+    """The backward kernel of an FP32 model computes in FP32 (float-float differences and
+    kernel exponents, compensated sums): scored at the algorithmic flop count against the
+    FP32 vector peak."""
     flops = backward_flops(m_mean, var_f) * QT
     peak = PEAK_FP64_TFLOPS if fp64_arith else PEAK_FP32_TFLOPS
     ach = flops / (kernel_ms * 1e-3) / 1e12
@@ -282,12 +286,13 @@ def main():
     traj_ws = model.new_workspace(QT)
 
     def traj_part(ws=None):
+        # the softplus margin cost's gradient, its cotangents formed inside the backward
         model.set_tuning(**t_traj)
         model.query(tq, tsg, out=tout, workspace=ws)
-        cotangents()
         model.set_tuning(**t_bwd)
-        grads["points"], grads["hyper"] = model.backward(tq, tsg, d_mean, None, d_var, None,
-                                                         argmin=tout["argmin"], workspace=ws)
+        grads["points"], grads["hyper"] = model.cost_backward(
+            tq, tsg, tout["mean"], tout["var"], argmin=tout["argmin"], margin=COST_MARGIN,
+            kvar=COST_KVAR, workspace=ws)
 
     def step(mark=None, serial=not overlap):
         main = torch.cuda.current_stream()
@@ -544,6 +549,7 @@ def main():
         p64, q64, tq64 = pts.double(), q.double(), tq.double()
         pout = plain._out(Q, dev)
         ptout = plain._out(QT, dev, status=False)
+        softplus_cotangents(torch, tout, d_mean, d_var)   # the plain path takes them as inputs
         dm64, dv64 = d_mean.double(), d_var.double()
 
         def plain_grid():
@@ -706,9 +712,9 @@ def leg_terrain(args, torch, dev, ksdf, scenes, tune, timer):
     def traj():
         model.set_tuning(**{**tg, **tqt})
         model.query(tq, tsg, out=tout)
-        softplus_cotangents(torch, tout, d_mean, d_var)
         model.set_tuning(**{**tg, **tqt, **tbt})
-        return model.backward(tq, tsg, d_mean, None, d_var, None, argmin=tout["argmin"])
+        return model.cost_backward(tq, tsg, tout["mean"], tout["var"], argmin=tout["argmin"],
+                                   margin=COST_MARGIN, kvar=COST_KVAR)
 
     grid()
     traj()
@@ -753,6 +759,7 @@ def leg_terrain(args, torch, dev, ksdf, scenes, tune, timer):
         p64, q64, tq64 = pts.double(), q.double(), tq.double()
         pout = plain._out(Q, dev)
         ptout = plain._out(QT, dev, status=False)
+        softplus_cotangents(torch, tout, d_mean, d_var)   # the plain path takes them as inputs
         dm64, dv64 = d_mean.double(), d_var.double()
 
         def pgrid():

@@ -400,6 +400,24 @@ int ksdf_query_backward(const ksdf_model* model, const void* points, long Q, con
                         const void* d_var, const void* d_var_f, void* d_points, double* d_hyper,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * ksdf_cost_backward -- the gradient of a collision cost for trajectory optimisation
+ * (the use of SDF values and gradients motivated in Sec. I): the softplus margin cost
+ *   C = sum_q softplus(t_q),  t_q = margin - mean_q + kvar * sqrt(var_q),
+ * of the outputs mean [Q] and var [Q] (device, the model's precision) of a ksdf_query
+ * of the same points, with respect to the points and (ell, noise_var).  It is
+ * ksdf_query_backward with d_mean = -sigmoid(t) and d_var = kvar sigmoid(t) /
+ * (2 sqrt(var)) formed inside the kernel (var clamped below at 1e-30; stable sigmoid
+ * and softplus), so no separate cotangent pass runs.  argmin, d_points, d_hyper,
+ * the argmin rule and the workspace (ksdf_backward_workspace_bytes) are those of
+ * ksdf_query_backward.  cost (device [Q] of the model's precision, or NULL): the
+ * per-point softplus(t_q).  margin and kvar must be finite.
+ * ------------------------------------------------------------------------- */
+int ksdf_cost_backward(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
+                       const int* argmin, const void* mean, const void* var, double margin,
+                       double kvar, void* cost, void* d_points, double* d_hyper, void* workspace,
+                       size_t ws_bytes, void* stream);
+
 /* Static description of a status code; ksdf_last_error() gives the calling
  * thread's last detailed message (never NULL). */
 const char* ksdf_status_string(int status);

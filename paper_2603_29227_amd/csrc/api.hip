@@ -638,6 +638,32 @@ extern "C" int ksdf_query_backward(const ksdf_model* m, const void* points, long
                          d_hyper, workspace, ws_bytes, (hipStream_t)stream);
 }
 
+extern "C" int ksdf_cost_backward(const ksdf_model* m, const void* points, long Q,
+                                  const int8_t* sign, const int* argmin, const void* mean,
+                                  const void* var, double margin, double kvar, void* cost,
+                                  void* d_points, double* d_hyper, void* workspace,
+                                  size_t ws_bytes, void* stream) {
+  if (!m || Q < 0 || (Q > 0 && (!points || !d_points || !mean || !var)) || !d_hyper ||
+      !std::isfinite(margin) || !std::isfinite(kvar)) {
+    set_error("ksdf_cost_backward: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!m->fitted || !m->index_ready) {
+    set_error("ksdf_cost_backward: the model has not been fitted or its index is not attached");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = backward_workspace_bytes(m, Q);
+  if (ws_bytes < need || (need > 0 && !workspace)) {
+    set_error("ksdf_cost_backward: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  const CostArgs c{mean, var, margin, kvar, cost};
+  return launch_backward(m, points, Q, sign, argmin, nullptr, nullptr, nullptr, nullptr, d_points,
+                         d_hyper, workspace, ws_bytes, (hipStream_t)stream, &c);
+}
+
 extern "C" const char* ksdf_status_string(int status) {
   switch (status) {
     case KSDF_OK: return "ok";

@@ -24,6 +24,7 @@
 
 #include "ff.h"
 #include "ksdf_internal.h"
+#include "wave_ops.h"
 
 namespace ksdf {
 namespace {
@@ -58,7 +59,32 @@ struct BwdArgs {
   double ell_d, alpha_d;   // the same in FP64
   int alpha_tied;
   int uniform_noise;
+  // the softplus margin cost (ksdf_cost_backward): when c_mean is set, the mean and
+  // var cotangents are formed from the forward outputs instead of read
+  const T* c_mean;
+  const T* c_var;
+  T c_margin, c_kvar;
+  T* c_cost;               // per-query cost, or null
 };
+
+// Cotangents of mean and var for query q: the given ones, or those of the cost
+// softplus(t), t = margin - mean + kvar sqrt(var): d/dmean = -sigmoid(t) and
+// d/dvar = kvar sigmoid(t) / (2 sqrt(var)), with the stable forms of sigmoid and
+// softplus (max(t, 0) + log1p(e^-|t|)); var is clamped below at 1e-30.
+template <class T>
+__device__ __forceinline__ void mean_var_cotangents(const BwdArgs<T>& A, long q, T& gm, T& gv) {
+  gm = A.d_mean ? A.d_mean[q] : T(0);
+  gv = A.d_var ? A.d_var[q] : T(0);
+  if (A.c_mean) {
+    const T sd = sqrt(fmax(A.c_var[q], T(1e-30)));
+    const T t = A.c_margin - A.c_mean[q] + A.c_kvar * sd;
+    const T e = exp(-fabs(t));
+    const T sg = t >= T(0) ? T(1) / (T(1) + e) : e / (T(1) + e);
+    gm = -sg;
+    gv = A.c_kvar * sg / (T(2) * sd);
+    if (A.c_cost) A.c_cost[q] = fmax(t, T(0)) + log1p(e);
+  }
+}
 
 template <class T>
 __device__ __forceinline__ T aabb_d2(const float* bx, T x, T y, T z) {
@@ -79,11 +105,11 @@ __device__ __forceinline__ void query_vjp(const BwdArgs<T>& A, long q, int c, T*
   const T lt = A.ell;
   const T x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
   const T s = A.sign ? (T)A.sign[q] : T(1);
-  const T gm = A.d_mean ? A.d_mean[q] : T(0);
+  T gm, gv;
+  mean_var_cotangents(A, q, gm, gv);
   T gg[3] = {T(0), T(0), T(0)};
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
-  const T gv = A.d_var ? A.d_var[q] : T(0);
   const T gf = VARF && A.d_var_f ? A.d_var_f[q] : T(0);
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const T* p = A.ps + 4L * b;
@@ -243,6 +269,10 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
   if (c >= A.n_cells) c = -1;   // not a cell of this model: no contribution
   T dx[3] = {T(0), T(0), T(0)};
   double th[2] = {0.0, 0.0};
+  if (c < 0 && A.c_mean) {
+    T gm, gv;
+    mean_var_cotangents(A, q, gm, gv);   // the cost alone
+  }
   if (c >= 0) {
     if constexpr (VARF) {
       T v[KSDF_MAX_M];
@@ -277,11 +307,12 @@ __device__ void vjp_matern(const BwdArgs<T>& A, long q, int c, double* v, double
   const double mc = sqrt(3.0) / lt;
   const double x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
   const double s = A.sign ? (double)A.sign[q] : 1.0;
-  const double gm = A.d_mean ? (double)A.d_mean[q] : 0.0;
+  T gmt, gvt;
+  mean_var_cotangents(A, q, gmt, gvt);
+  const double gm = gmt, gv = gvt;
   double gg[3] = {0, 0, 0};
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
-  const double gv = A.d_var ? (double)A.d_var[q] : 0.0;
   const double gf = VARF && A.d_var_f ? (double)A.d_var_f[q] : 0.0;
   const int b = A.offsets[c], m = A.offsets[c + 1] - b;
   const T* Lc = A.L + A.loff[c];
@@ -458,6 +489,10 @@ __global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
   int c = A.argmin[q];
   if (c >= A.n_cells) c = -1;
   double dx[3] = {0, 0, 0}, th[2] = {0, 0};
+  if (c < 0 && A.c_mean) {
+    T gm, gv;
+    mean_var_cotangents(A, q, gm, gv);   // the cost alone
+  }
   if (c >= 0) {
     if constexpr (VARF) {
       double v[KSDF_MAX_M];
@@ -517,20 +552,20 @@ __device__ __forceinline__ void vjp_f32(const BwdArgs<float>& A, float x0, float
   // is large (far samples of big cells)
   auto diff = [&](int i, float di[3], ff& z2) {
     const float4 h = P4[b + i], lo = PL[b + i];
-    const ff dx = ff_add(lx, ff{-h.x, -lo.x});
-    const ff dy = ff_add(ly, ff{-h.y, -lo.y});
-    const ff dz = ff_add(lz, ff{-h.z, -lo.z});
+    const ff dx = ff_sub_lean(lx.hi, lx.lo, h.x, lo.x);
+    const ff dy = ff_sub_lean(ly.hi, ly.lo, h.y, lo.y);
+    const ff dz = ff_sub_lean(lz.hi, lz.lo, h.z, lo.z);
     di[0] = dx.hi;
     di[1] = dy.hi;
     di[2] = dz.hi;
-    z2 = ff_add(ff_add(ff_mul(dx, dx), ff_mul(dy, dy)), ff_mul(dz, dz));
+    z2 = ff_norm2_lean(dx, dy, dz);
   };
   // e = exp(-(z2 - d2) / (2 l^2)) = 2^-t with t = (z2 - d2) log2(e) / (2 l^2) formed
   // in float-float: the hardware 2^x on the fraction of t.hi, the low part by its
   // first-order term
   const ff c2f{A.c2_ff[0], A.c2_ff[1]};
   auto kval = [&](ff z2, ff d2f) {
-    const ff t = ff_mul(ff_add(z2, ff_neg(d2f)), c2f);
+    const ff t = ff_mul(ff_sub_lean(z2.hi, z2.lo, d2f.hi, d2f.lo), c2f);
     const float n = floorf(t.hi);
     const float e = __builtin_amdgcn_exp2f(n - t.hi) * (1.f - 0.6931471805599453f * t.lo);
     return ldexpf(e, -(int)n);
@@ -677,11 +712,11 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
   // per-lane inputs (the no-var_f path reads them once for all its cells)
   const float x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
   const float sgn = A.sign ? (float)A.sign[q] : 1.f;
-  const float gm = A.d_mean ? A.d_mean[q] : 0.f;
+  float gm = 0.f, gv = 0.f;
+  if (active) mean_var_cotangents(A, q, gm, gv);
   float gg[3] = {0.f, 0.f, 0.f};
   if (A.d_grad)
     for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
-  const float gv = A.d_var ? A.d_var[q] : 0.f;
   if constexpr (LANE && !VARF) {
     // per lane (sparse queries): every lane its own argmin cell, in one round
     if (__ballot(todo)) {
@@ -736,11 +771,11 @@ __global__ void fill_int_kernel(int* p, long n, int v) {
 __global__ void __launch_bounds__(ST) argmin_count_kernel(const int* argmin, long Q, int n_cells,
                                                           int* key, int* count) {
   const long q = (long)blockIdx.x * ST + threadIdx.x;
-  if (q >= Q) return;
-  int c = argmin[q];
+  const bool valid = q < Q;
+  int c = valid ? argmin[q] : n_cells;
   if (c < 0 || c >= n_cells) c = n_cells;
-  key[q] = c;
-  atomicAdd(count + c, 1);
+  if (valid) key[q] = c;
+  wave_count(count, c, valid);   // consecutive queries mostly share their cell
 }
 // exclusive scan of count[0..n) into start (one block; n is a cell count)
 __global__ void __launch_bounds__(1024) scan_counts_kernel(const int* count, int n, int* start) {
@@ -767,8 +802,9 @@ __global__ void __launch_bounds__(1024) scan_counts_kernel(const int* count, int
 __global__ void __launch_bounds__(ST) argmin_scatter_kernel(long Q, const int* key, int* cursor,
                                                             int* perm) {
   const long q = (long)blockIdx.x * ST + threadIdx.x;
-  if (q >= Q) return;
-  perm[atomicAdd(cursor + key[q], 1)] = (int)q;
+  const bool valid = q < Q;
+  const int pos = wave_slot(cursor, valid ? key[q] : 0, valid);
+  if (valid) perm[pos] = (int)q;
 }
 
 // Deterministic FP64 reduction of the per-query hyperparameter partials: RB blocks each
@@ -825,7 +861,7 @@ size_t backward_workspace_bytes(const ksdf_model* m, long Q) {
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                     const int* argmin, const void* d_mean, const void* d_grad, const void* d_var,
                     const void* d_var_f, void* d_points, double* d_hyper, void* ws,
-                    size_t ws_bytes, hipStream_t s) {
+                    size_t ws_bytes, hipStream_t s, const CostArgs* cost) {
   if (!m->adjoint) {
     set_error("backward: the model was not fitted with KSDF_FIT_ADJOINT");
     return KSDF_ERR_INVALID_ARGUMENT;
@@ -882,6 +918,13 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.d_var = static_cast<const double*>(d_var);
     A.d_var_f = static_cast<const double*>(d_var_f);
     A.d_points = static_cast<double*>(d_points);
+    if (cost) {
+      A.c_mean = static_cast<const double*>(cost->mean);
+      A.c_var = static_cast<const double*>(cost->var);
+      A.c_margin = cost->margin;
+      A.c_kvar = cost->kvar;
+      A.c_cost = static_cast<double*>(cost->cost);
+    }
     A.part = part;
     A.n_cells = m->n_cells;
     A.offsets = m->offsets; A.loff = m->loff;
@@ -908,6 +951,13 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     A.d_var = static_cast<const float*>(d_var);
     A.d_var_f = static_cast<const float*>(d_var_f);
     A.d_points = static_cast<float*>(d_points);
+    if (cost) {
+      A.c_mean = static_cast<const float*>(cost->mean);
+      A.c_var = static_cast<const float*>(cost->var);
+      A.c_margin = (float)cost->margin;
+      A.c_kvar = (float)cost->kvar;
+      A.c_cost = static_cast<float*>(cost->cost);
+    }
     A.part = part;
     A.n_cells = m->n_cells;
     A.offsets = m->offsets; A.loff = m->loff;

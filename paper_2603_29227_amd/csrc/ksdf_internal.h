@@ -171,10 +171,19 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
 size_t query_fast_workspace_bytes(const ksdf_model* m, long Q);
+// the softplus margin cost whose mean/var cotangents ksdf_cost_backward forms in the
+// backward kernel (device arrays of the model's precision)
+struct CostArgs {
+  const void* mean;
+  const void* var;
+  double margin, kvar;
+  void* cost;
+};
 int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                     const int* argmin, const void* d_mean, const void* d_grad, const void* d_var,
                     const void* d_var_f, void* d_points, double* d_hyper, void* ws,
-                    size_t ws_bytes, hipStream_t s);
+                    size_t ws_bytes, hipStream_t s,
+                    const CostArgs* cost = nullptr);
 size_t backward_workspace_bytes(const ksdf_model* m, long Q);
 size_t fused_workspace_bytes(const ksdf_model* m, long Q);
 int launch_fit_query_fused(ksdf_model* m, const void* pts, int dtype, const void* svar,

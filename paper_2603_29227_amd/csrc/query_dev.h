@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "ff.h"
+#include "wave_ops.h"
 #include "ksdf_internal.h"
 
 namespace ksdf {
@@ -863,37 +864,6 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
 template <int KM, int MB>
 __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
   query_finish<MB>(A, query_pass1<KM>(A, sq));
-}
-
-// Wave-aggregated counting-sort steps over small integer keys: the lanes that share
-// a key take one atomic between them (the lowest lane issues it).
-__device__ __forceinline__ void wave_count(int* count, int key, bool valid) {
-  unsigned long long pending = __ballot(valid);
-  const int lane = threadIdx.x & 63;
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int k = __builtin_amdgcn_readlane(key, leader);
-    const unsigned long long mask = __ballot(valid && key == k);
-    if (lane == leader) atomicAdd(count + k, (int)__popcll(mask));
-    pending &= ~mask;
-  }
-}
-// position of each valid lane in its key's range (cursor: running start per key)
-__device__ __forceinline__ int wave_slot(int* cursor, int key, bool valid) {
-  unsigned long long pending = __ballot(valid);
-  const int lane = threadIdx.x & 63;
-  int pos = -1;
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int k = __builtin_amdgcn_readlane(key, leader);
-    const unsigned long long mask = __ballot(valid && key == k);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(cursor + k, (int)__popcll(mask));
-    base = __builtin_amdgcn_readlane(base, leader);
-    if (valid && key == k) pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
-    pending &= ~mask;
-  }
-  return pos;
 }
 
 // ---------------------------------------------------------------------------

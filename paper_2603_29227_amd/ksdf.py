@@ -34,7 +34,8 @@ EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_c
            "ksdf_model_attach_index", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_query_noalloc",
            "ksdf_backward_workspace_bytes",
-           "ksdf_query_backward", "ksdf_fit_query_workspace_bytes", "ksdf_fit_query",
+           "ksdf_query_backward", "ksdf_cost_backward", "ksdf_fit_query_workspace_bytes",
+           "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
            "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
            "ksdf_count_queries_workspace_bytes", "ksdf_count_queries", "ksdf_model_check",
@@ -153,6 +154,8 @@ def lib():
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                           _vp, sz, _vp]
+        L.ksdf_cost_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, ctypes.c_double,
+                                         ctypes.c_double, _vp, _vp, _vp, _vp, sz, _vp]
         L.ksdf_fit_query_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_fit_query_workspace_bytes.restype = sz
         L.ksdf_fit_query.argtypes = [_vp, _vp, i, l, _vp, H, _vp, _vp, l, _vp, _vp, _vp, _vp, _vp,
@@ -452,6 +455,28 @@ class Model:
         _check(self._lib.ksdf_query_backward(self._h, _ptr(points), Q, _ptr(sign), _ptr(argmin),
                                              *[_ptr(t) for t in c], _ptr(d_points), _ptr(d_hyper),
                                              _ptr(ws), nb, _stream(stream)), "ksdf_query_backward")
+        return d_points, d_hyper
+
+    def cost_backward(self, points, sign, mean, var, argmin=None, margin: float = 0.3,
+                      kvar: float = 1.0, cost: Optional[torch.Tensor] = None, stream=None,
+                      workspace: Optional[torch.Tensor] = None):
+        """Gradient of the softplus margin cost sum softplus(margin - mean + kvar sqrt(var))
+        of a query's outputs: (d_points [Q,3], d_hyper [2] float64); the per-point cost
+        goes to `cost` ([Q], model dtype) when given."""
+        Q = len(points)
+        d_points = torch.empty(Q, 3, dtype=self.dtype, device=points.device)
+        d_hyper = torch.empty(2, dtype=torch.float64, device=points.device)
+        nb = self._lib.ksdf_backward_workspace_bytes(self._h, Q)
+        ws = self._workspace(nb, workspace)
+        for t in (mean, var, cost):
+            if t is not None and (t.dtype != self.dtype or t.numel() != Q or not t.is_contiguous()):
+                raise ValueError("mean, var and cost must be contiguous [Q] tensors of the model dtype")
+        if argmin is not None and (argmin.dtype != torch.int32 or argmin.numel() != Q):
+            raise ValueError("argmin must be int32 [Q]")
+        _check(self._lib.ksdf_cost_backward(self._h, _ptr(points), Q, _ptr(sign), _ptr(argmin),
+                                            _ptr(mean), _ptr(var), float(margin), float(kvar),
+                                            _ptr(cost), _ptr(d_points), _ptr(d_hyper), _ptr(ws), nb,
+                                            _stream(stream)), "ksdf_cost_backward")
         return d_points, d_hyper
 
     def refit(self, points: torch.Tensor, dirty: torch.Tensor, qcount: torch.Tensor, eta: float,
