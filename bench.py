@@ -446,19 +446,22 @@ def main():
         log(f"streaming refit: {refit}")
 
     # the Matern 3/2 variant (Table I) on the same room and grid, its own FP32 model:
-    # float-float fit as for the RBF, the plain one-thread-per-query kernel in FP32
+    # float-float fit as for the RBF, and the RBF's wave-shared two-kernel query with the
+    # Matern cell value, launch shapes of the grid's tuning (no matrix-core variance:
+    # the dense inverses are an RBF option)
     matern = None
     if not args.no_matern:
         mat = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell,
                          noise_var=wl.noise_var, precision="fp32", query_box=ROOM_BOX,
                          kernel="matern32")
+        mat.set_tuning(**{**t_grid, "fused": 0, "query_mfma": 0, "query_pairs": 0})
         mout = mat._out(Q, dev)
         mat.fit(pts)
         mat.query(q, sg, out=mout)
         torch.cuda.synchronize()
         mat.set_timing(True)
         mf, mq = [], []
-        for _ in range(3):
+        for _ in range(5):
             mat.fit(pts)
             mat.query(q, sg, out=mout)
             torch.cuda.synchronize()

@@ -354,14 +354,6 @@ int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* 
     timer_mark(m, KSDF_TIMER_QUERY, 0, s);
     hipLaunchKernelGGL(query_plain_kernel<double>, dim3(grid), dim3(QT), 0, s, A);
     timer_mark(m, KSDF_TIMER_QUERY, 1, s);
-  } else if (m->kernel != KSDF_KERNEL_RBF) {
-    QueryArgs<float> A = make_args<float>(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
-    A.ps = m->ps32;
-    A.sv = m->sv32;
-    A.L = m->L32;
-    timer_mark(m, KSDF_TIMER_QUERY, 0, s);
-    hipLaunchKernelGGL(query_plain_kernel<float>, dim3(grid), dim3(QT), 0, s, A);
-    timer_mark(m, KSDF_TIMER_QUERY, 1, s);
   } else {
     return launch_query_fast(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, ws,
                              ws_bytes, s);

@@ -51,6 +51,14 @@ struct FastArgs {
   float inv2l2_ff[2];
   float far2;         // |x - centre|^2 beyond which pass 2 takes the far-field exponent
   float two_l2_ff[2];   // 2 l^2 as a float pair (re-evaluation of uncertain cells)
+  // Matern 3/2 models (Table I): k(r) = (1 + c r) e^{-c r}, c = sqrt(3) / l.  Then the
+  // per-cell value of pass 1 and the record's `best` are u itself (App. D inverts
+  // (1 + c u) e^{-c u} ~ f through the exponential: u = d - ln f' / c), not u^2.
+  int matern;
+  float mc;            // c
+  float mc_l2e;        // c log2(e)
+  float mc_ff[2];      // c and 1 / c as float pairs (re-evaluation)
+  float inv_mc_ff[2];
 };
 
 // What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
@@ -184,6 +192,54 @@ __device__ float cell_u2_ff_wave(const FastArgs& A, int c, float qx, float qy, f
   return u2.hi + u2.lo;
 }
 
+// The Matern 3/2 counterpart: u = d - ln f' / c with f' = sum a_i (1 + c z_i)
+// e^{-c (z_i - d)} and d the nearest sample's distance, every step in float-float
+// (square roots by one Newton step on the exact residual).
+__device__ float cell_u_matern_ff_wave(const FastArgs& A, int c, float qx, float qy, float qz) {
+  constexpr int SPL = (KSDF_MAX_M + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int b = A.offsets[c], m = A.offsets[c + 1] - b;
+  const float4 ctr = A.centre[c];
+  const ff lx = ff_two_sum(qx, -ctr.x), ly = ff_two_sum(qy, -ctr.y), lz = ff_two_sum(qz, -ctr.z);
+  ff z2[SPL];
+  ff d2{INFINITY, 0.f};
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int i = lane + 64 * k;
+    z2[k] = ff{INFINITY, 0.f};
+    if (i < m) {
+      const float4 p = A.ps[b + i], pl = A.plo[b + i];
+      z2[k] = ff_norm2_lean(ff_sub_lean(lx.hi, lx.lo, p.x, pl.x), ff_sub_lean(ly.hi, ly.lo, p.y, pl.y),
+                            ff_sub_lean(lz.hi, lz.lo, p.z, pl.z));
+      if (z2[k].hi < d2.hi || (z2[k].hi == d2.hi && z2[k].lo < d2.lo)) d2 = z2[k];
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const ff t{shfl_xor_f(d2.hi, o), shfl_xor_f(d2.lo, o)};
+    if (t.hi < d2.hi || (t.hi == d2.hi && t.lo < d2.lo)) d2 = t;
+  }
+  const ff cc{A.mc_ff[0], A.mc_ff[1]};
+  const ff d = ff_sqrt(d2);
+  ff f{0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    const int i = lane + 64 * k;
+    if (i < m) {
+      const float aw = A.ps[b + i].w, awl = A.plo[b + i].w;
+      const ff z = ff_sqrt(z2[k]);
+      const ff t = ff_mul(ff_add(z, ff_neg(d)), cc);
+      const ff g = ff_add(ff{1.f, 0.f}, ff_mul(z, cc));
+      f = ff_add(f, ff_mul(ff{aw, awl}, ff_mul(g, ff_exp_neg_lean(t))));
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) f = ff_add(f, ff{shfl_xor_f(f.hi, o), shfl_xor_f(f.lo, o)});
+  if (!(f.hi > 0.f)) return INFINITY;
+  const ff u = ff_add(d, ff_neg(ff_mul(ff_log(f), ff{A.inv_mc_ff[0], A.inv_mc_ff[1]})));
+  return u.hi + u.lo;
+}
+
 // lower bound of the squared distance from local point (x,y,z) to the cell's
 // sample bounding box
 __device__ __forceinline__ float aabb_d2(const float* bx, float x, float y, float z) {
@@ -203,6 +259,10 @@ constexpr float BUDGET_SCALE = 0.5f / 0.35f;
 __device__ __forceinline__ float u2_budget(float u2, float two_l2) {
   const float u = sqrtf(fmaxf(u2, 0.f));
   return BUDGET_SCALE * fmaxf(two_l2 * 1e-5f, 2.f * u * 1e-4f * fmaxf(u, 1.f));
+}
+// Matern: pass 1 carries u, so the target applies directly
+__device__ __forceinline__ float u_budget(float u) {
+  return BUDGET_SCALE * 1e-4f * fmaxf(fabsf(u), 1.f);
 }
 
 // Sample-chunk size of the wave-uniform loops: one group of scalar loads (8 float4 =
@@ -387,6 +447,125 @@ __device__ __forceinline__ void cell_u2_wave(const FastArgs& A, int b, int m, fl
   }
 }
 
+// Matern 3/2 pass-1 sums over one chunk: f = sum a g, R = sum |a| g, RZ = sum |a| g z
+// with g_i = (1 + c z_i) 2^(c log2(e) (dref - z_i)) and emax the largest exponential
+// factor; dref <= every z_i (the sample box's lower bound), so no factor exceeds 1.
+template <bool MASK>
+__device__ __forceinline__ void um_chunk(const float4 (&P)[CH], int i0, int m, float lx, float ly,
+                                         float lz, float mc, float mcl, float dref, float& f,
+                                         float& R, float& RZ, float& emax) {
+#pragma unroll
+  for (int j = 0; j < CH; ++j) {
+    const bool in = !MASK || i0 + j < m;
+    const float aw = P[j].w;
+    const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
+    const float z = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    const float ex = in ? __builtin_amdgcn_exp2f(mcl * (dref - z)) : 0.f;
+    const float g = fmaf(mc, z, 1.f) * ex;
+    const float ag = fabsf(aw) * g;
+    f = fmaf(aw, g, f);
+    R += ag;
+    RZ = fmaf(ag, z, RZ);
+    emax = fmaxf(emax, ex);
+  }
+}
+
+// u = dref - ln(f') / c of one Matern cell and its rounding-error bound: each term
+// carries at most eps (5 + 3 c z_i) relative error (the root, the exponent's argument
+// c (dref - z_i), the factor 1 + c z_i, the products) and the sum a few eps of
+// sum |terms|, so |d f'| <= eps (8 R + 4 c RZ) and |d u| <= |d f'| / (c f').
+// Wave-uniform like cell_u2_wave (same two-pass underflow rule).
+__device__ __forceinline__ void cell_u_matern_wave(const FastArgs& A, int b, int m, float lx,
+                                                   float ly, float lz, bool ev, float& d2ref,
+                                                   float& u, float& del) {
+  const float mc = A.mc, mcl = A.mc_l2e;
+  u = INFINITY;
+  del = 0.f;
+  if (!__ballot(ev)) return;
+  float f = 0.f, R = 0.f, RZ = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    const float dref = __builtin_amdgcn_sqrtf(d2ref);
+    float emax = 0.f;
+    f = 0.f;
+    R = 0.f;
+    RZ = 0.f;
+    for (int i0 = 0; i0 < m; i0 += CH) {
+      float4 P[CH];
+#pragma unroll
+      for (int j = 0; j < CH; ++j) P[j] = A.ps[b + i0 + j];   // the store is padded
+      if (i0 + CH <= m) um_chunk<false>(P, i0, m, lx, ly, lz, mc, mcl, dref, f, R, RZ, emax);
+      else um_chunk<true>(P, i0, m, lx, ly, lz, mc, mcl, dref, f, R, RZ, emax);
+    }
+    const bool low = ev && !(emax >= 0x1p-24f);
+    if (!__ballot(low)) break;
+    if (low) {
+      float d2 = INFINITY;
+      for (int i = 0; i < m; ++i) {
+        const float4 p = A.ps[b + i];
+        const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
+        d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      }
+      d2ref = d2;
+    }
+  }
+  if (ev && f > 0.f) {
+    u = __builtin_amdgcn_sqrtf(d2ref) - LN2 * __log2f(f) / mc;
+    del = EPS32 * (8.f * R + 4.f * mc * RZ) / (mc * f);
+  }
+}
+
+// The per-lane (vector-load) form of the same, for the sparse-query walk.
+__device__ __forceinline__ void cell_u_matern_lane(const FastArgs& A, int b, int m, float lx,
+                                                   float ly, float lz, float& d2ref, float& u,
+                                                   float& del) {
+  const float mc = A.mc, mcl = A.mc_l2e;
+  float f = 0.f, R = 0.f, RZ = 0.f;
+  u = INFINITY;
+  del = 0.f;
+  for (int pass = 0; pass < 2; ++pass) {
+    const float dref = __builtin_amdgcn_sqrtf(d2ref);
+    float emax = 0.f;
+    f = 0.f;
+    R = 0.f;
+    RZ = 0.f;
+    for (int i = 0; i < m; ++i) {
+      const float4 P = A.ps[b + i];
+      const float dx = lx - P.x, dy = ly - P.y, dz = lz - P.z;
+      const float z = __builtin_amdgcn_sqrtf(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+      const float ex = __builtin_amdgcn_exp2f(mcl * (dref - z));
+      const float g = fmaf(mc, z, 1.f) * ex;
+      const float ag = fabsf(P.w) * g;
+      f = fmaf(P.w, g, f);
+      R += ag;
+      RZ = fmaf(ag, z, RZ);
+      emax = fmaxf(emax, ex);
+    }
+    if (emax >= 0x1p-24f) break;
+    float d2 = INFINITY;
+    for (int i = 0; i < m; ++i) {
+      const float4 p = A.ps[b + i];
+      const float dx = lx - p.x, dy = ly - p.y, dz = lz - p.z;
+      d2 = fminf(d2, fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+    }
+    d2ref = d2;
+  }
+  if (f > 0.f) {
+    u = __builtin_amdgcn_sqrtf(d2ref) - LN2 * __log2f(f) / mc;
+    del = EPS32 * (8.f * R + 4.f * mc * RZ) / (mc * f);
+  }
+}
+
+// Lower bound of a cell's value from its sample box: RBF u^2 >= d^2 - 2 l^2 ln max(A+, 1)
+// (every scaled term is at most a_i); Matern u >= d - ln(max(A+, 1) (1 + c d)) / c
+// ((1 + c z) e^{-c (z - d)} decreases in z >= d, so each term is at most a_i (1 + c d)).
+__device__ __forceinline__ float cell_lower_bound(const FastArgs& A, float d2box, float apos) {
+  if (A.matern) {
+    const float d = __builtin_amdgcn_sqrtf(d2box);
+    return d - logf(fmaxf(apos, 1.f) * fmaf(A.mc, d, 1.f)) / A.mc;
+  }
+  return d2box - A.two_l2 * logf(fmaxf(apos, 1.f));
+}
+
 // Min-fusion of the candidates' u^2 (ties to the lower id); where the error bounds of
 // the best and of a rival overlap by more than the budget, the overlapping cells are
 // re-evaluated in float-float.  Returns the argmin cell (-1: none valid); best = its u^2.
@@ -413,7 +592,7 @@ __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float
   // the candidates to re-evaluate, one bit per slot
   unsigned need = 0;
   if (bc >= 0) {
-    const float budget = u2_budget(bu, A.two_l2);
+    const float budget = A.matern ? u_budget(bu) : u2_budget(bu, A.two_l2);
     bool redo = false;
 #pragma unroll
     for (int r = 0; r < KM; ++r)
@@ -441,7 +620,8 @@ __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float
     const float sx = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qx), src));
     const float sy = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qy), src));
     const float sz = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qz), src));
-    const float u2 = cell_u2_ff_wave(A, c, sx, sy, sz);
+    const float u2 = A.matern ? cell_u_matern_ff_wave(A, c, sx, sy, sz)
+                              : cell_u2_ff_wave(A, c, sx, sy, sz);
     if ((int)(threadIdx.x & 63) == src) {
 #pragma unroll
       for (int r = 0; r < KM; ++r)
@@ -504,11 +684,12 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     const float* bx = A.box + 8L * c;
     const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
     float d2ref = aabb_d2(bx, lx, ly, lz);
-    const float lb = d2ref - A.two_l2 * logf(fmaxf(bx[3], 1.f));
+    const float lb = cell_lower_bound(A, d2ref, bx[3]);
     const bool part = slot >= 0;
     const bool ev = part && !(lb > best + 2.f * best_del + 1e-6f);
     float u2 = INFINITY, del = 0.f;
-    cell_u2_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
+    if (A.matern) cell_u_matern_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
+    else cell_u2_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
     if (part) {
       if (!ev) u2 = INFINITY;   // pruned: provably not the minimum
 #pragma unroll
@@ -542,9 +723,11 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
         const float* bx = A.box + 8L * c;
         const float lx = qx - ctr.x, ly = qy - ctr.y, lz = qz - ctr.z;
         float d2ref = aabb_d2(bx, lx, ly, lz);
-        const float lb = d2ref - A.two_l2 * logf(fmaxf(bx[3], 1.f));
+        const float lb = cell_lower_bound(A, d2ref, bx[3]);
         float u2 = INFINITY, del = 0.f;
-        if (!(lb > best + 2.f * best_del + 1e-6f)) {
+        if (A.matern) {
+          if (!(lb > best + 2.f * best_del + 1e-6f)) cell_u_matern_lane(A, b, m, lx, ly, lz, d2ref, u2, del);
+        } else if (!(lb > best + 2.f * best_del + 1e-6f)) {
           float f = 0.f, R = 0.f, RZ = 0.f;
           for (int pass = 0; pass < 2; ++pass) {
             const float c2d = c2 * d2ref;
@@ -743,6 +926,11 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
     const bool farl = ll > A.far2;
     const float k0 = c2 * (bref - ll);
     const float tx = 2.f * c2 * lx, ty = 2.f * c2 * ly, tz = 2.f * c2 * lz;
+    // Matern: e_i = e^{-c (z_i - zref)}, far from the cell through zref - z_i =
+    // ((bref - |l|^2) + 2 l.p_i - |p_i|^2) / (zref + z_i), and k_i = (1 + c z_i) e_i e^{-c zref}
+    const bool mat = A.matern != 0;
+    const float ginvm = mat ? __builtin_amdgcn_exp2f(-A.mc_l2e * zref) : 0.f;
+    const float bm = bref - ll;
     static_assert(!MF || (MB == 64 && !LANE), "the matrix-core GP variance needs m <= 64");
     float v[MB];
     if constexpr (MF) {
@@ -772,16 +960,25 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
             const float dx = lx - P[j].x, dy = ly - P[j].y, dz = lz - P[j].z;
             const float z2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
             const float pp = fmaf(P[j].z, P[j].z, fmaf(P[j].y, P[j].y, P[j].x * P[j].x));
-            const float arg_far = fmaf(tx, P[j].x, fmaf(ty, P[j].y, fmaf(tz, P[j].z, fmaf(-c2, pp, k0))));
-            const float arg = farl ? arg_far : fmaf(z2, -c2, c2d);
-            const float e = in ? __builtin_amdgcn_exp2f(arg) : 0.f;   // see pass 1
+            const float z = __builtin_amdgcn_sqrtf(z2);
+            float e, kv;
+            if (mat) {
+              const float lp2 = fmaf(2.f * lx, P[j].x, fmaf(2.f * ly, P[j].y, fmaf(2.f * lz, P[j].z, bm - pp)));
+              const float dd = farl ? lp2 / (zref + z) : zref - z;
+              e = in ? __builtin_amdgcn_exp2f(A.mc_l2e * dd) : 0.f;
+              kv = fmaf(A.mc, z, 1.f) * e * ginvm;
+            } else {
+              const float arg_far = fmaf(tx, P[j].x, fmaf(ty, P[j].y, fmaf(tz, P[j].z, fmaf(-c2, pp, k0))));
+              const float arg = farl ? arg_far : fmaf(z2, -c2, c2d);
+              e = in ? __builtin_amdgcn_exp2f(arg) : 0.f;   // see pass 1
+              kv = e * ginv;                                 // k_i = exp(-z_i^2 / 2 l^2)
+            }
             const float ae = aw * e;
             a0 = fmaf(ae, dx, a0);
             a1 = fmaf(ae, dy, a1);
             a2 = fmaf(ae, dz, a2);
-            v[i0 + j] = in ? e * ginv : 0.f;                  // k_i = exp(-z_i^2 / 2 l^2)
+            v[i0 + j] = in ? kv : 0.f;
             // softmin with t_i = alpha (z_i - zref) >= 0
-            const float z = __builtin_amdgcn_sqrtf(z2);
             const float ti = A.alpha * (z - zref);
             const float sm = in ? __builtin_amdgcn_exp2f(-A.alpha_l2e * (z - zref)) : 0.f;
             const float q = sm * sm * SV[j];
@@ -835,7 +1032,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   }
   float u = 0.f;
   if (best < 0.f) st |= KSDF_Q_CLAMPED;
-  else u = sqrtf(best);
+  else u = A.matern ? best : sqrtf(best);   // Matern records carry u, RBF u^2
   const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
   float gx = 0.f, gy = 0.f, gz = 0.f;
   if (wn > 0.f) {
@@ -1032,6 +1229,14 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   A.inv2l2_ff[1] = (float)(inv - (double)(float)inv);
   A.two_l2_ff[0] = (float)two_l2;
   A.two_l2_ff[1] = (float)(two_l2 - (double)(float)two_l2);
+  A.matern = m->kernel == KSDF_KERNEL_MATERN32 ? 1 : 0;
+  const double mc = std::sqrt(3.0) / m->ell;
+  A.mc = (float)mc;
+  A.mc_l2e = (float)(mc * 1.4426950408889634);
+  A.mc_ff[0] = (float)mc;
+  A.mc_ff[1] = (float)(mc - (double)(float)mc);
+  A.inv_mc_ff[0] = (float)(1.0 / mc);
+  A.inv_mc_ff[1] = (float)(1.0 / mc - (double)(float)(1.0 / mc));
   return A;
 }
 

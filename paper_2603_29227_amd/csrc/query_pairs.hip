@@ -145,7 +145,8 @@ int km_of(const ksdf_model* m) { return m->k_fuse <= 8 ? 8 : 16; }
 
 bool query_pairs_usable(const ksdf_model* m, long Q) {
   const long nc = (long)m->n_cells + 1;
-  return Q * km_of(m) < (1L << 31) && (nc + SCAN_TILE - 1) / SCAN_TILE <= (long)SCAN_TILE;
+  return m->kernel == KSDF_KERNEL_RBF && Q * km_of(m) < (1L << 31) &&
+         (nc + SCAN_TILE - 1) / SCAN_TILE <= (long)SCAN_TILE;
 }
 
 size_t query_pairs_workspace_bytes(const ksdf_model* m, long Q) {

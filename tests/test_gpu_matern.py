@@ -91,3 +91,39 @@ def test_matern_fit_query_and_limits():
     with pytest.raises(ksdf.KsdfError):
         model.backward(q, sg, torch.ones_like(b["mean"]))
     model.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(query_split=0, query_block=64, query_sub=2),
+    dict(query_split=1, query_block=64, query_sub=2, query_lanes=0),
+    dict(query_split=1, query_block=256, query_sub=4, query_lanes=0),
+    dict(query_split=1, query_block=256, query_sub=1, query_lanes=1),
+])
+def test_matern_fp32_launch_shapes_match_each_other_and_oracle(tuning):
+    """The Matern cell value rides the RBF's wave-shared query (one kernel or two,
+    wave-shared or per-lane cells): every launch shape gives the same outputs, bit for
+    bit, and they pass parity with the oracle."""
+    _say(f"matern32 fp32 launch shape {tuning}")
+    wl = scenes.small_room_workload(n_queries=6000, cfg_id=47, uneven=True)
+    cells = _cells(wl)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var,
+                       kernel="matern32")
+    pts = torch.from_numpy(wl.points).cuda()
+    q = torch.from_numpy(wl.queries).cuda()
+    sg = torch.from_numpy(wl.sign).cuda()
+    model.fit(pts)
+    model.set_tuning(query_split=0, query_block=64, query_sub=2, query_lanes=0)
+    base = {k: v.clone() for k, v in model.query(q, sg, grad_var=True).items()}
+    model.set_tuning(**tuning)
+    got = model.query(q, sg, grad_var=True)
+    torch.cuda.synchronize()
+    for k in base:
+        assert torch.equal(base[k], got[k]), f"{k} differs under {tuning}"
+    oc = _ocells(wl, cells)
+    f = oracle.fit(wl.points, oc, wl.ell, wl.noise_var, kernel="matern32")
+    o = oracle.query(wl.points, oc, f, wl.queries, wl.ell, wl.noise_var, kernel="matern32",
+                     sign=wl.sign, all_candidates=True)
+    rep = assert_parity({k: v.cpu().numpy() for k, v in got.items()}, o, wl.ell, "fp32", wl.sign,
+                        label=f"matern {tuning}")
+    print(rep, flush=True)
+    model.close()
