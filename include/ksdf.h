@@ -292,8 +292,8 @@ int ksdf_query_noalloc(const ksdf_model* model, const void* points, long Q, cons
  * training queue").  dirty [n_cells] (device float, the count c2 of buffer updates
  * since a cell's last training) and qcount [n_cells] (device float, the query count
  * c0, see ksdf_count_queries) give each cell with c2 > 0 the priority
- * s = c2 (1 + eta c0), computed in FP64 as c2 * (1 + (eta * c0)) with each operation
- * rounded once; the min(budget, #dirty) cells of highest priority (ties to the lower
+ * s = c2 (1 + eta c0), computed in FP32 as c2 * (1 + (eta * c0)) with each operation
+ * rounded once (eta rounded to float first); the min(budget, #dirty) cells of highest priority (ties to the lower
  * id) are refitted from surface_pts (and sample_var, or the uniform noise_var) with
  * the model's current hyperparameters, exactly as ksdf_fit_cells fits them; then
  * c2 = 0 and c0 = c0 / 2 for those cells.  All other cells keep their fit.
@@ -390,7 +390,8 @@ int ksdf_fit_query(ksdf_model* model, const void* surface_pts, int dtype, long n
  * same points, or NULL to recompute it.  Clamped outputs contribute zero.  d_hyper for
  * noise_var is defined for the uniform variance (zero when the fit had per-sample
  * variances).  k* is recomputed, not stored.  The theta reduction is deterministic
- * (fixed order, FP64, no atomics).  The model's last fit must have had
+ * (fixed order, no atomics; FP64 for FP64 models, float-float for FP32 models).  The
+ * model's last fit must have had
  * KSDF_FIT_ADJOINT (and KSDF_FIT_ADJOINT_VARF when d_var_f is given).
  * workspace: at least ksdf_backward_workspace_bytes(model, Q) bytes.
  * ------------------------------------------------------------------------- */

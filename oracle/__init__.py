@@ -110,13 +110,16 @@ def bhm_update_tau(tau, hit_logodds, alpha):
 
 def refit_priority(dirty, qcount, eta, budget):
     """The GP training queue of App. G: the cells with c2 > 0 ordered by decreasing
-    s = c2 (1 + eta c0), ties to the lower id, the first `budget` of them.  The score
-    is formed in double as c2 * (1 + (eta * c0)), one rounding per operation (the
-    counters are float32)."""
-    c2 = np.asarray(dirty, np.float32).astype(np.float64)
-    c0 = np.asarray(qcount, np.float32).astype(np.float64)
+    s = c2 (1 + eta c0), ties to the lower id, the first `budget` of them.  The order is
+    a decision taken in the precision of the counters (float32): the score is formed
+    in float32 as c2 * (1 + (eta * c0)), one rounding per operation, eta rounded to
+    float32 first."""
+    c2 = np.asarray(dirty, np.float32)
+    c0 = np.asarray(qcount, np.float32)
+    e = np.float32(eta)
     ids = [i for i in range(len(c2)) if c2[i] > 0]
-    score = {i: c2[i] * (1.0 + eta * c0[i]) for i in ids}
+    score = {i: np.float32(c2[i] * np.float32(np.float32(1.0) + np.float32(e * c0[i])))
+             for i in ids}
     ids.sort(key=lambda i: (-score[i], i))
     return np.asarray(ids[:budget], np.int32)
 

@@ -246,19 +246,31 @@ __device__ __forceinline__ void query_vjp(const BwdArgs<T>& A, long q, int c, T*
     aXl += cm * El;
     aXs += cm * Es;
   }
-  double dl = 0, ds = 0;
-  if (mean_live) dl += (double)(s * gm * (u2 - Za / f) / (lt * u));
-  dl += (double)(s * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]) / l3);
-  if (A.alpha_tied) dl += (double)(gv * dVa * (-T(2) * A.alpha / lt));
-  if (varf_live) dl += (double)(gf * (-T(2) * bkz / l3 + bDb));
-  dl -= (double)aXl;
+  T dl = 0, ds = 0;
+  if (mean_live) dl += s * gm * (u2 - Za / f) / (lt * u);
+  dl += s * (y[0] * Wz[0] + y[1] * Wz[1] + y[2] * Wz[2]) / l3;
+  if (A.alpha_tied) dl += gv * dVa * (-T(2) * A.alpha / lt);
+  if (varf_live) dl += gf * (-T(2) * bkz / l3 + bDb);
+  dl -= aXl;
   if (A.uniform_noise) {
-    ds += (double)(gv * C2);
-    if (varf_live) ds += (double)(gf * bb);
-    ds -= (double)aXs;
+    ds += gv * C2;
+    if (varf_live) ds += gf * bb;
+    ds -= aXs;
   }
-  out_th[0] = dl;
-  out_th[1] = ds;
+  out_th[0] = (double)dl;
+  out_th[1] = (double)ds;
+}
+
+// the per-query hyperparameter terms: FP64 models keep doubles; FP32 models keep
+// float pairs (dl, ds), summed afterwards in float-float
+template <class T>
+__device__ __forceinline__ void store_theta(const BwdArgs<T>& A, long q, const double th[2]) {
+  if constexpr (sizeof(T) == 8) {
+    A.part[2 * q] = th[0];
+    A.part[2 * q + 1] = th[1];
+  } else {
+    reinterpret_cast<float2*>(A.part)[q] = make_float2((float)th[0], (float)th[1]);
+  }
 }
 
 template <class T, bool VARF>
@@ -282,8 +294,7 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
     }
   }
   for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = dx[d];
-  A.part[2 * q] = th[0];
-  A.part[2 * q + 1] = th[1];
+  store_theta(A, q, th);
 }
 
 // VJP of one query on its argmin cell for a Matern 3/2 model (Table I, App. D), in
@@ -502,8 +513,7 @@ __global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
     }
   }
   for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = (T)dx[d];
-  A.part[2 * q] = th[0];
-  A.part[2 * q + 1] = th[1];
+  store_theta(A, q, th);
 }
 
 // Compensated FP32 sum (TwoSum, Knuth): the running sum and the sum of its rounding
@@ -758,8 +768,7 @@ __global__ void __launch_bounds__(BT) bwd_wave_kernel(BwdArgs<float> A, const in
   }
   if (!active) return;
   for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = dx[d];
-  A.part[2 * q] = th[0];
-  A.part[2 * q + 1] = th[1];
+  store_theta(A, q, th);
 }
 
 // Counting sort of the queries by argmin cell (queries without a cell go last).
@@ -842,6 +851,53 @@ __global__ void __launch_bounds__(RT) theta_partial_kernel(const double* part, l
 }
 __global__ void __launch_bounds__(RT) theta_final_kernel(const double* red, double* out) {
   block_sum2(red[2 * threadIdx.x], red[2 * threadIdx.x + 1], out);
+}
+
+// The same fixed-order reduction for FP32 models, in float-float: the per-query float
+// pairs, RB block partials (hi, lo) x 2, then one block; the result leaves as the
+// double hi + lo.
+__device__ void block_sum2_ff(ff a, ff b, float4* out) {
+  __shared__ float r0h[RT], r0l[RT], r1h[RT], r1l[RT];
+  r0h[threadIdx.x] = a.hi;
+  r0l[threadIdx.x] = a.lo;
+  r1h[threadIdx.x] = b.hi;
+  r1l[threadIdx.x] = b.lo;
+  __syncthreads();
+  for (int o = RT / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const int t = threadIdx.x;
+      const ff x = ff_add(ff{r0h[t], r0l[t]}, ff{r0h[t + o], r0l[t + o]});
+      const ff y = ff_add(ff{r1h[t], r1l[t]}, ff{r1h[t + o], r1l[t + o]});
+      r0h[t] = x.hi;
+      r0l[t] = x.lo;
+      r1h[t] = y.hi;
+      r1l[t] = y.lo;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = make_float4(r0h[0], r0l[0], r1h[0], r1l[0]);
+}
+__global__ void __launch_bounds__(RT) theta_partial32_kernel(const float2* part, long Q, float4* red) {
+  const long per = (Q + RB - 1) / RB;
+  const long beg = (long)blockIdx.x * per;
+  const long end = beg + per < Q ? beg + per : Q;
+  ff a{0.f, 0.f}, b{0.f, 0.f};
+  for (long i = beg + threadIdx.x; i < end; i += RT) {
+    const float2 v = part[i];
+    a = ff_add(a, ff{v.x, 0.f});
+    b = ff_add(b, ff{v.y, 0.f});
+  }
+  block_sum2_ff(a, b, red + blockIdx.x);
+}
+__global__ void __launch_bounds__(RT) theta_final32_kernel(const float4* red, double* out) {
+  const float4 v = red[threadIdx.x];
+  __shared__ float4 r;
+  block_sum2_ff(ff{v.x, v.y}, ff{v.z, v.w}, &r);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[0] = (double)r.x + (double)r.y;
+    out[1] = (double)r.z + (double)r.w;
+  }
 }
 
 size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -984,8 +1040,15 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
     }
     timer_mark(m, KSDF_TIMER_BACKWARD, 1, s);
   }
-  hipLaunchKernelGGL(theta_partial_kernel, dim3(RB), dim3(RT), 0, s, part, Q, red);
-  hipLaunchKernelGGL(theta_final_kernel, dim3(1), dim3(RT), 0, s, red, d_hyper);
+  if (m->precision == KSDF_FP64) {
+    hipLaunchKernelGGL(theta_partial_kernel, dim3(RB), dim3(RT), 0, s, part, Q, red);
+    hipLaunchKernelGGL(theta_final_kernel, dim3(1), dim3(RT), 0, s, red, d_hyper);
+  } else {
+    hipLaunchKernelGGL(theta_partial32_kernel, dim3(RB), dim3(RT), 0, s,
+                       reinterpret_cast<const float2*>(part), Q, reinterpret_cast<float4*>(red));
+    hipLaunchKernelGGL(theta_final32_kernel, dim3(1), dim3(RT), 0, s,
+                       reinterpret_cast<const float4*>(red), d_hyper);
+  }
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
 }

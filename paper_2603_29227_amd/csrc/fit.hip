@@ -81,32 +81,32 @@ __global__ void __launch_bounds__(FIT_THREADS) fit64_kernel(FitArgs A) {
 
 // ---- streaming refit (Sec. IV-C, App. G) ----
 
-// Training-queue score of App. G, s = c2 (1 + eta c0), in FP64 with every rounding
+// Training-queue score of App. G, s = c2 (1 + eta c0), in FP32 with every rounding
 // explicit (no contraction), so that a host computation in the same order agrees.
-__device__ __forceinline__ double refit_score(const float* dirty, const float* qcount, double eta,
-                                              int c) {
-  return __dmul_rn((double)dirty[c], __dadd_rn(1.0, __dmul_rn(eta, (double)qcount[c])));
+__device__ __forceinline__ float refit_score(const float* dirty, const float* qcount, float eta,
+                                             int c) {
+  return __fmul_rn(dirty[c], __fadd_rn(1.f, __fmul_rn(eta, qcount[c])));
 }
 
 // Rank of every dirty cell (c2 > 0) by descending score, ties to the lower id, by
 // comparison with every other cell through LDS tiles; the first `budget` ranks name
 // the cells to refit.  n_dirty counts the dirty cells.
 __global__ void __launch_bounds__(256) refit_rank_kernel(const float* dirty, const float* qcount,
-                                                         double eta, int n, int budget, int* sel,
+                                                         float eta, int n, int budget, int* sel,
                                                          int* n_dirty) {
-  __shared__ double ts[256];
+  __shared__ float ts[256];
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool mine = i < n && dirty[i] > 0.f;
-  const double si = mine ? refit_score(dirty, qcount, eta, i) : -1.0;
+  const float si = mine ? refit_score(dirty, qcount, eta, i) : -1.f;
   int rank = 0;
   for (int base = 0; base < n; base += 256) {
     __syncthreads();
     const int j = base + threadIdx.x;
-    ts[threadIdx.x] = (j < n && dirty[j] > 0.f) ? refit_score(dirty, qcount, eta, j) : -1.0;
+    ts[threadIdx.x] = (j < n && dirty[j] > 0.f) ? refit_score(dirty, qcount, eta, j) : -1.f;
     __syncthreads();
     const int lim = min(256, n - base);
     for (int k = 0; k < lim; ++k) {
-      const double sj = ts[k];
+      const float sj = ts[k];
       rank += (sj > si || (sj == si && base + k < i)) ? 1 : 0;
     }
   }
@@ -248,7 +248,7 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
   const unsigned gc = (unsigned)((m->n_cells + 255) / 256);
   const unsigned gb = (unsigned)((budget + 255) / 256);
   hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, n_dirty, 0);
-  hipLaunchKernelGGL(refit_rank_kernel, dim3(gc), dim3(256), 0, s, dirty, qcount, eta, m->n_cells,
+  hipLaunchKernelGGL(refit_rank_kernel, dim3(gc), dim3(256), 0, s, dirty, qcount, (float)eta, m->n_cells,
                      budget, sel, n_dirty);
   hipLaunchKernelGGL(refit_count_kernel, dim3(1), dim3(64), 0, s, n_dirty, budget, n_sel, bcount);
   FitArgs A = make_fit_args(m, pts, dtype, svar, user_status);

@@ -99,7 +99,7 @@ __global__ void __launch_bounds__(FT) fused_kernel(FitArgs F, FastArgs Q, FusedC
     const long sq = ((t - C.n_fit) * WAVES + wave) * 64 + (threadIdx.x & 63);
     Pass1 p1 = query_pass1<KM>(Q, sq);
     if (expired) p1.flags |= PASS1_FIT_TIMEOUT;   // the cells it read may be unreleased
-    query_finish<MB>(Q, p1);
+    query_finish_t<MB, false, false, false>(Q, p1);   // the fused launch serves RBF models
     t = grab();
   } while (t < n_total);
 }

@@ -637,7 +637,7 @@ __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float
 // Candidates, per-candidate u^2 and the min-fusion for the 64 sorted queries sq ..
 // of a wave (lanes pass their own sq); every lane of the wave must call it together
 // (wave-uniform loops inside).
-template <int KM, bool LANE = false>
+template <int KM, bool LANE = false, bool MAT = false>
 __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
   const bool active = sq < A.Q;
   const long qi = active ? A.perm[sq] : 0;
@@ -688,7 +688,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
     const bool part = slot >= 0;
     const bool ev = part && !(lb > best + 2.f * best_del + 1e-6f);
     float u2 = INFINITY, del = 0.f;
-    if (A.matern) cell_u_matern_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
+    if constexpr (MAT) cell_u_matern_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
     else cell_u2_wave(A, b, m, lx, ly, lz, ev, d2ref, u2, del);
     if (part) {
       if (!ev) u2 = INFINITY;   // pruned: provably not the minimum
@@ -725,7 +725,7 @@ __device__ __forceinline__ Pass1 query_pass1(const FastArgs& A, long sq) {
         float d2ref = aabb_d2(bx, lx, ly, lz);
         const float lb = cell_lower_bound(A, d2ref, bx[3]);
         float u2 = INFINITY, del = 0.f;
-        if (A.matern) {
+        if constexpr (MAT) {
           if (!(lb > best + 2.f * best_del + 1e-6f)) cell_u_matern_lane(A, b, m, lx, ly, lz, d2ref, u2, del);
         } else if (!(lb > best + 2.f * best_del + 1e-6f)) {
           float f = 0.f, R = 0.f, RZ = 0.f;
@@ -883,8 +883,8 @@ __device__ __forceinline__ float mfma_vv(const float* __restrict__ Li, const flo
 // The argmin cell's outputs (gradient, GP variance, softmin variance) and every
 // output of the query; all lanes of the wave call it together.  MF (wave-shared cells,
 // MB = 64): the GP variance's L^{-1} k on the matrix cores (mfma_vv).
-template <int MB, bool LANE = false, bool MF = false>
-__device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1) {
+template <int MB, bool LANE, bool MF, bool MAT>
+__device__ __forceinline__ void query_finish_t(const FastArgs& A, const Pass1& p1) {
   const bool active = (p1.flags & 2) != 0, outside = (p1.flags & 1) != 0;
   const long qi = p1.qi;
   const float qx = p1.qx, qy = p1.qy, qz = p1.qz;
@@ -928,7 +928,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
     const float tx = 2.f * c2 * lx, ty = 2.f * c2 * ly, tz = 2.f * c2 * lz;
     // Matern: e_i = e^{-c (z_i - zref)}, far from the cell through zref - z_i =
     // ((bref - |l|^2) + 2 l.p_i - |p_i|^2) / (zref + z_i), and k_i = (1 + c z_i) e_i e^{-c zref}
-    const bool mat = A.matern != 0;
+    constexpr bool mat = MAT;
     const float ginvm = mat ? __builtin_amdgcn_exp2f(-A.mc_l2e * zref) : 0.f;
     const float bm = bref - ll;
     static_assert(!MF || (MB == 64 && !LANE), "the matrix-core GP variance needs m <= 64");
@@ -962,7 +962,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
             const float pp = fmaf(P[j].z, P[j].z, fmaf(P[j].y, P[j].y, P[j].x * P[j].x));
             const float z = __builtin_amdgcn_sqrtf(z2);
             float e, kv;
-            if (mat) {
+            if constexpr (mat) {
               const float lp2 = fmaf(2.f * lx, P[j].x, fmaf(2.f * ly, P[j].y, fmaf(2.f * lz, P[j].z, bm - pp)));
               const float dd = farl ? lp2 / (zref + z) : zref - z;
               e = in ? __builtin_amdgcn_exp2f(A.mc_l2e * dd) : 0.f;
@@ -1032,7 +1032,7 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   }
   float u = 0.f;
   if (best < 0.f) st |= KSDF_Q_CLAMPED;
-  else u = A.matern ? best : sqrtf(best);   // Matern records carry u, RBF u^2
+  else u = MAT ? best : sqrtf(best);   // Matern records carry u, RBF u^2
   const float wn = sqrtf(w0 * w0 + w1 * w1 + w2 * w2);
   float gx = 0.f, gy = 0.f, gz = 0.f;
   if (wn > 0.f) {
@@ -1057,10 +1057,10 @@ __device__ __forceinline__ void query_finish(const FastArgs& A, const Pass1& p1)
   if (A.qst) A.qst[qi] = st;
 }
 
-// The whole query for one wave of sorted queries.
-template <int KM, int MB>
+// The whole query for one wave of sorted queries (MAT: a Matern model).
+template <int KM, int MB, bool MAT = false>
 __device__ __forceinline__ void query_tile(const FastArgs& A, long sq) {
-  query_finish<MB>(A, query_pass1<KM>(A, sq));
+  query_finish_t<MB, false, false, MAT>(A, query_pass1<KM, false, MAT>(A, sq));
 }
 
 // ---------------------------------------------------------------------------

@@ -29,20 +29,26 @@
 namespace ksdf {
 namespace {
 
-template <int KM, int MB, int NT>
+template <int KM, int MB, int NT, bool MAT>
 __global__ void __launch_bounds__(NT) query_fast_kernel(FastArgs A) {
-  query_tile<KM, MB>(A, (long)blockIdx.x * NT + threadIdx.x);
+  query_tile<KM, MB, MAT>(A, (long)blockIdx.x * NT + threadIdx.x);
+}
+
+template <int NT, bool MAT>
+void launch_query_nt_k(const ksdf_model* m, const FastArgs& A, hipStream_t s) {
+  const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
+  const bool k8 = m->k_fuse <= 8;
+  const bool m64 = m->max_m <= 64;
+  if (k8 && m64) hipLaunchKernelGGL((query_fast_kernel<8, 64, NT, MAT>), dim3(g), dim3(NT), 0, s, A);
+  else if (k8) hipLaunchKernelGGL((query_fast_kernel<8, 128, NT, MAT>), dim3(g), dim3(NT), 0, s, A);
+  else if (m64) hipLaunchKernelGGL((query_fast_kernel<16, 64, NT, MAT>), dim3(g), dim3(NT), 0, s, A);
+  else hipLaunchKernelGGL((query_fast_kernel<16, 128, NT, MAT>), dim3(g), dim3(NT), 0, s, A);
 }
 
 template <int NT>
 void launch_query_nt(const ksdf_model* m, const FastArgs& A, hipStream_t s) {
-  const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
-  const bool k8 = m->k_fuse <= 8;
-  const bool m64 = m->max_m <= 64;
-  if (k8 && m64) hipLaunchKernelGGL((query_fast_kernel<8, 64, NT>), dim3(g), dim3(NT), 0, s, A);
-  else if (k8) hipLaunchKernelGGL((query_fast_kernel<8, 128, NT>), dim3(g), dim3(NT), 0, s, A);
-  else if (m64) hipLaunchKernelGGL((query_fast_kernel<16, 64, NT>), dim3(g), dim3(NT), 0, s, A);
-  else hipLaunchKernelGGL((query_fast_kernel<16, 128, NT>), dim3(g), dim3(NT), 0, s, A);
+  if (A.matern) launch_query_nt_k<NT, true>(m, A, s);
+  else launch_query_nt_k<NT, false>(m, A, s);
 }
 
 size_t bucketing_bytes(const ksdf_model* m, long Q) {

@@ -16,10 +16,10 @@
 namespace ksdf {
 namespace {
 
-template <int KM, int NT, bool LANE>
+template <int KM, int NT, bool LANE, bool MAT = false>
 __global__ void __launch_bounds__(NT) query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
-  const Pass1 r = query_pass1<KM, LANE>(A, sq);
+  const Pass1 r = query_pass1<KM, LANE, MAT>(A, sq);
   const bool active = (r.flags & 2) != 0;
   if (active) rec[sq] = r;
   wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
@@ -35,13 +35,13 @@ __global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, lo
   if (active) rec2[pos] = r;
 }
 
-template <int MB, int NT, bool LANE, bool MF = false>
+template <int MB, int NT, bool LANE, bool MF = false, bool MAT = false>
 __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   Pass1 r{};
   r.bc = -1;
   if (sq < A.Q) r = rec2[sq];
-  query_finish<MB, LANE, MF>(A, r);
+  query_finish_t<MB, LANE, MF, MAT>(A, r);
 }
 
 template <int NT, bool LANE>
@@ -52,6 +52,10 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* 
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
   if (pws) launch_pass1_pairs(m, A, rec, count, pws, s);
+  else if (A.matern && m->k_fuse <= 8)
+    hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE, true>), dim3(g), dim3(NT), 0, s, A, rec, count);
+  else if (A.matern)
+    hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE, true>), dim3(g), dim3(NT), 0, s, A, rec, count);
   else if (m->k_fuse <= 8) hipLaunchKernelGGL((query_p1_kernel<8, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
   else hipLaunchKernelGGL((query_p1_kernel<16, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec, count);
   hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum);
@@ -66,8 +70,15 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* 
       return;
     }
   }
-  if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
-  else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+  // the kernel function picks the pass-2 instantiation (Matern models carry u, not u^2)
+  if (A.matern) {
+    if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
+    else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
+  } else if (m->max_m <= 64) {
+    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+  } else {
+    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+  }
 }
 
 }  // namespace
