@@ -56,6 +56,8 @@ struct BwdArgs {
   const float* box;        // [n,8] sample AABB (cell-local)
   T ell, two_l2, alpha;
   float c2_ff[2];          // log2(e) / (2 l^2) as a float pair (FP32 models)
+  float mc_ff[2];          // Matern c = sqrt(3) / l and c log2(e) as float pairs
+  float mcl_ff[2];
   double ell_d, alpha_d;   // the same in FP64
   int alpha_tied;
   int uniform_noise;
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(BT) bwd_plain_kernel(BwdArgs<T> A) {
 }
 
 // VJP of one query on its argmin cell for a Matern 3/2 model (Table I, App. D), in
-// FP64 for either store (the FP32 store's float-float pairs are exact in double).
+// FP64 (FP64 models; vjp_matern_f32 below is the FP32 models' form).
 // With c = sqrt(3)/l, the nearest sample distance d, e_i = exp(-c (z_i - d)),
 // k'_i = (1 + c z_i) e_i, f' = sum a_i k'_i, w' = sum a_i e_i d_i (d_i = x - x_i):
 //   u = d - ln(f')/c           du/dx = c w'/f',  du/dl|_a = (u - c Z/f')/l, Z = sum a e z^2,
@@ -493,29 +495,6 @@ __device__ void vjp_matern(const BwdArgs<T>& A, long q, int c, double* v, double
   out_th[1] = ds;
 }
 
-template <class T, bool VARF>
-__global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
-  const long q = (long)blockIdx.x * BT + threadIdx.x;
-  if (q >= A.Q) return;
-  int c = A.argmin[q];
-  if (c >= A.n_cells) c = -1;
-  double dx[3] = {0, 0, 0}, th[2] = {0, 0};
-  if (c < 0 && A.c_mean) {
-    T gm, gv;
-    mean_var_cotangents(A, q, gm, gv);   // the cost alone
-  }
-  if (c >= 0) {
-    if constexpr (VARF) {
-      double v[KSDF_MAX_M];
-      vjp_matern<T, true>(A, q, c, v, dx, th);
-    } else {
-      vjp_matern<T, false>(A, q, c, nullptr, dx, th);
-    }
-  }
-  for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = (T)dx[d];
-  store_theta(A, q, th);
-}
-
 // Compensated FP32 sum (TwoSum, Knuth): the running sum and the sum of its rounding
 // errors, so that m terms carry about one rounding of the result instead of m.
 struct CAcc {
@@ -529,6 +508,243 @@ struct CAcc {
   }
   __device__ __forceinline__ float val() const { return s + c; }
 };
+
+// The Matern 3/2 VJP of one query for an FP32 model, in FP32: the same sums as
+// vjp_matern, with the differences to the samples exact as float pairs, z_i and
+// z_i - d as float pairs (the square root by one Newton step), the exponentials from
+// float-pair arguments (the hardware 2^x on the fraction, the low part to first
+// order), and the sums whose terms cancel accumulated with compensation.  With VARF
+// the triangular solves for A^{-1} k run in FP32 on the factor (as query_vjp).
+template <bool VARF>
+__device__ void vjp_matern_f32(const BwdArgs<float>& A, long q, int c, float* v, float out_dx[3],
+                               double out_th[2]) {
+  const float lt = A.ell, al = A.alpha;
+  const float mc = A.mc_ff[0];
+  const ff mclf{A.mcl_ff[0], A.mcl_ff[1]};
+  const float x0 = A.pts[3 * q], x1 = A.pts[3 * q + 1], x2 = A.pts[3 * q + 2];
+  const float s = A.sign ? (float)A.sign[q] : 1.f;
+  float gm, gv;
+  mean_var_cotangents(A, q, gm, gv);
+  float gg[3] = {0.f, 0.f, 0.f};
+  if (A.d_grad)
+    for (int d = 0; d < 3; ++d) gg[d] = A.d_grad[3 * q + d];
+  const float gf = VARF && A.d_var_f ? A.d_var_f[q] : 0.f;
+  const int b = A.offsets[c], m = A.offsets[c + 1] - b;
+  const float* Lc = A.L + A.loff[c];
+  const float4* P4 = reinterpret_cast<const float4*>(A.ps);
+  const float4* PL = reinterpret_cast<const float4*>(A.plo);
+  const float4* X4 = reinterpret_cast<const float4*>(A.xi);
+  const ff lx = ff_two_sum(x0, -(float)A.centre64[3L * c]);
+  const ff ly = ff_two_sum(x1, -(float)A.centre64[3L * c + 1]);
+  const ff lz = ff_two_sum(x2, -(float)A.centre64[3L * c + 2]);
+  auto load = [&](int i, float di[3], ff& z2, float& pa) {
+    const float4 h = P4[b + i], lo = PL[b + i];
+    const ff dx = ff_sub_lean(lx.hi, lx.lo, h.x, lo.x);
+    const ff dy = ff_sub_lean(ly.hi, ly.lo, h.y, lo.y);
+    const ff dz = ff_sub_lean(lz.hi, lz.lo, h.z, lo.z);
+    di[0] = dx.hi;
+    di[1] = dy.hi;
+    di[2] = dz.hi;
+    z2 = ff_norm2_lean(dx, dy, dz);
+    pa = h.w + lo.w;
+  };
+  // e^{-c t} for a float-pair t >= 0 as 2^{-c log2(e) t}
+  auto expc = [&](ff t) {
+    const ff u = ff_mul(t, mclf);
+    const float n = floorf(u.hi);
+    const float e = __builtin_amdgcn_exp2f(n - u.hi) * (1.f - 0.6931471805599453f * u.lo);
+    return ldexpf(e, -(int)n);
+  };
+  ff d2f{INFINITY, 0.f};
+  for (int i = 0; i < m; ++i) {
+    float di[3], pa;
+    ff z2;
+    load(i, di, z2, pa);
+    if (z2.hi < d2f.hi || (z2.hi == d2f.hi && z2.lo < d2f.lo)) d2f = z2;
+  }
+  const ff zminf = ff_sqrt(d2f);
+  const float zmin = zminf.hi + zminf.lo;
+  // pass A: f', sum a e, w', Z, softmin moments, k
+  CAcc f, fe, w[3], Za;
+  float S = 0.f, M1 = 0.f, M2 = 0.f;
+  for (int i = 0; i < m; ++i) {
+    float di[3], pa;
+    ff z2f;
+    load(i, di, z2f, pa);
+    const ff zf = ff_sqrt(z2f);
+    const float z = zf.hi + zf.lo, z2 = z2f.hi + z2f.lo;
+    const ff tf = ff_sub_lean(zf.hi, zf.lo, zminf.hi, zminf.lo);
+    const float e = expc(tf);
+    const float ae = pa * e;
+    f.add(ae * fmaf(mc, z, 1.f));
+    fe.add(ae);
+    w[0].add(ae * di[0]);
+    w[1].add(ae * di[1]);
+    w[2].add(ae * di[2]);
+    Za.add(ae * z2);
+    const float t = tf.hi + tf.lo;
+    const float sm = __builtin_amdgcn_exp2f(-1.4426950408889634f * al * t);
+    S += sm;
+    M1 += sm * t;
+    M2 += sm * t * t;
+    if constexpr (VARF) v[i] = fmaf(mc, z, 1.f) * expc(zf);
+  }
+  float vv = 0.f;
+  if constexpr (VARF) {
+    for (int i = 0; i < m; ++i) {
+      const float* row = Lc + (long)i * (i + 1) / 2;
+      float t = v[i];
+      for (int j = 0; j < i; ++j) t -= row[j] * v[j];
+      v[i] = t * row[i];
+      vv += v[i] * v[i];
+    }
+    for (int i = m - 1; i >= 0; --i) {
+      const float* row = Lc + (long)i * (i + 1) / 2;
+      v[i] *= row[i];
+      for (int j = 0; j < i; ++j) v[j] -= row[j] * v[i];
+    }
+  }
+  const float fv = f.val(), fev = fe.val();
+  const float wv[3] = {w[0].val(), w[1].val(), w[2].val()};
+  const float u = fv > 0.f ? zmin - logf(fv) / mc : -1.f;
+  const bool mean_live = u > 0.f;
+  const float wn = sqrtf(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+  float y[3] = {0.f, 0.f, 0.f};
+  if (wn > 0.f) {
+    const float gw = (gg[0] * wv[0] + gg[1] * wv[1] + gg[2] * wv[2]) / wn;
+    for (int d = 0; d < 3; ++d) y[d] = (gg[d] - gw * wv[d] / wn) / wn;
+  }
+  const bool varf_live = VARF && (1.f - vv) > 0.f;
+  const float iS = 1.f / S;
+  const float m1 = M1 * iS;
+  const float h = zmin + m1;
+  const float Vz = M2 * iS - m1 * m1;
+  float V = 0.f, Pp = 0.f, dVa = 0.f, C2 = 0.f;
+  for (int i = 0; i < m; ++i) {
+    float di[3], pa;
+    ff z2f;
+    load(i, di, z2f, pa);
+    const ff zf = ff_sqrt(z2f);
+    const ff tf = ff_sub_lean(zf.hi, zf.lo, zminf.hi, zminf.lo);
+    const float z = zf.hi + zf.lo, t = tf.hi + tf.lo;
+    const float si = __builtin_amdgcn_exp2f(-1.4426950408889634f * al * t) * iS;
+    const float Bi = al * (h - z) + 1.f;
+    const float ci = si * Bi;
+    const float svi = A.sv[b + i];
+    V += svi * ci * ci;
+    Pp += svi * ci * si;
+    C2 += ci * ci;
+    dVa += 2.f * svi * ci * (si * (h - z) * (Bi + 1.f) - al * si * Vz);
+  }
+  float dxv[3] = {0.f, 0.f, 0.f}, bk[3] = {0.f, 0.f, 0.f};
+  CAcc Hy[3], Wz[3], El, Es, Eld[3], Esd[3];
+  float bkz = 0.f, bb = 0.f;
+  for (int i = 0; i < m; ++i) {
+    float di[3], pa;
+    ff z2f;
+    load(i, di, z2f, pa);
+    const ff zf = ff_sqrt(z2f);
+    const ff tf = ff_sub_lean(zf.hi, zf.lo, zminf.hi, zminf.lo);
+    const float z = zf.hi + zf.lo, z2 = z2f.hi + z2f.lo, t = tf.hi + tf.lo;
+    const float e = expc(tf);
+    const float kp = fmaf(mc, z, 1.f) * e;
+    const float ae = pa * e;
+    const float si = __builtin_amdgcn_exp2f(-1.4426950408889634f * al * t) * iS;
+    const float ci = si * (al * (h - z) + 1.f);
+    const float svi = A.sv[b + i];
+    const float dvdz = 2.f * al * (-svi * ci * (ci + si) + si * V + ci * Pp);
+    const float dy = di[0] * y[0] + di[1] * y[1] + di[2] * y[2];
+    float kb = 0.f;
+    if constexpr (VARF) kb = v[i] * expc(zf);
+    const float4 xq = X4[b + i];
+    const float xl = xq.x + xq.z, xs = xq.y + xq.w;
+    const float rz = z > 0.f ? 1.f / z : 0.f;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      dxv[d] += dvdz * di[d] * rz;
+      Hy[d].add(ae * dy * di[d] * rz);
+      Wz[d].add(ae * z * di[d]);
+      if constexpr (VARF) bk[d] += kb * di[d];
+      Eld[d].add(e * xl * di[d]);
+      Esd[d].add(e * xs * di[d]);
+    }
+    if constexpr (VARF) {
+      bkz += kb * z2;
+      bb += v[i] * v[i];
+    }
+    El.add(kp * xl);
+    Es.add(kp * xs);
+  }
+  float bDb = 0.f;
+  if (VARF && A.D && gf != 0.f && varf_live) {
+    const float* Dc = A.D + A.loff[c];
+    for (int i = 1; i < m; ++i) {
+      const float* row = Dc + (long)i * (i + 1) / 2;
+      float t = 0.f;
+      for (int j = 0; j < i; ++j) t += row[j] * v[j];
+      bDb += 2.f * v[i] * t;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    float r = s * (fev * y[d] - mc * Hy[d].val()) + gv * dxv[d];
+    if (mean_live) r += s * gm * mc * wv[d] / fv;
+    if (varf_live) r += gf * 2.f * mc * mc * bk[d];
+    out_dx[d] = r;
+  }
+  float aXl = s * (y[0] * Eld[0].val() + y[1] * Eld[1].val() + y[2] * Eld[2].val());
+  float aXs = s * (y[0] * Esd[0].val() + y[1] * Esd[1].val() + y[2] * Esd[2].val());
+  if (mean_live) {
+    const float cm = -s * gm / (mc * fv);
+    aXl += cm * El.val();
+    aXs += cm * Es.val();
+  }
+  float dl = 0.f, ds = 0.f;
+  if (mean_live) dl += s * gm * (u - mc * Za.val() / fv) / lt;
+  dl += s * (mc / lt) * (y[0] * Wz[0].val() + y[1] * Wz[1].val() + y[2] * Wz[2].val());
+  if (A.alpha_tied) dl += gv * dVa * (-2.f * al / lt);
+  if (varf_live) dl += gf * (-2.f * mc * mc * bkz / lt + bDb);
+  dl -= aXl;
+  if (A.uniform_noise) {
+    ds += gv * C2;
+    if (varf_live) ds += gf * bb;
+    ds -= aXs;
+  }
+  out_th[0] = (double)dl;
+  out_th[1] = (double)ds;
+}
+
+template <class T, bool VARF>
+__global__ void __launch_bounds__(BT) bwd_matern_kernel(BwdArgs<T> A) {
+  const long q = (long)blockIdx.x * BT + threadIdx.x;
+  if (q >= A.Q) return;
+  int c = A.argmin[q];
+  if (c >= A.n_cells) c = -1;
+  double dx[3] = {0, 0, 0}, th[2] = {0, 0};
+  if (c < 0 && A.c_mean) {
+    T gm, gv;
+    mean_var_cotangents(A, q, gm, gv);   // the cost alone
+  }
+  if (c >= 0) {
+    if constexpr (sizeof(T) == 4) {
+      float fdx[3];
+      if constexpr (VARF) {
+        float v[KSDF_MAX_M];
+        vjp_matern_f32<true>(A, q, c, v, fdx, th);
+      } else {
+        vjp_matern_f32<false>(A, q, c, nullptr, fdx, th);
+      }
+      for (int d = 0; d < 3; ++d) dx[d] = fdx[d];
+    } else if constexpr (VARF) {
+      double v[KSDF_MAX_M];
+      vjp_matern<T, true>(A, q, c, v, dx, th);
+    } else {
+      vjp_matern<T, false>(A, q, c, nullptr, dx, th);
+    }
+  }
+  for (int d = 0; d < 3; ++d) A.d_points[3 * q + d] = (T)dx[d];
+  store_theta(A, q, th);
+}
+
 
 // VJP of one query on its argmin cell for an FP32 model, in FP32.  Each term carries
 // about one float rounding (cell-local differences from the float-float store, the
@@ -1026,6 +1242,11 @@ int launch_backward(const ksdf_model* m, const void* points, long Q, const int8_
       const double c2 = 1.4426950408889634 / two_l2;
       A.c2_ff[0] = (float)c2;
       A.c2_ff[1] = (float)(c2 - (double)A.c2_ff[0]);
+      const double mc = std::sqrt(3.0) / m->ell, mcl = mc * 1.4426950408889634;
+      A.mc_ff[0] = (float)mc;
+      A.mc_ff[1] = (float)(mc - (double)A.mc_ff[0]);
+      A.mcl_ff[0] = (float)mcl;
+      A.mcl_ff[1] = (float)(mcl - (double)A.mcl_ff[0]);
     }
     A.alpha_tied = m->alpha_tied; A.uniform_noise = !m->has_svar;
     timer_mark(m, KSDF_TIMER_BACKWARD, 0, s);
