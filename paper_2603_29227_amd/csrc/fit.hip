@@ -17,6 +17,7 @@
 
 #include "fit_dev.h"
 #include "fit_wave.h"
+#include "fit_quad.h"
 
 namespace ksdf {
 namespace {
@@ -55,7 +56,21 @@ fit32w_kernel(FitArgs A, const int* list,
   }
 }
 
-// launch a bucket: the one-wave fit up to m = 64, the workgroup fit above
+// One workgroup (four waves) per cell for 64 < m <= 128 (fit_quad.h)
+template <bool MATERN>
+__global__ void __launch_bounds__(FIT_THREADS) __attribute__((amdgpu_waves_per_eu(2)))
+fit32q_kernel(FitArgs A, const int* list, const int* count) {
+  __shared__ QuadFitLds lds;
+  if (count && (int)blockIdx.x >= *count) return;
+  const int c = list[blockIdx.x];
+  const bool need64 = fit32_quad<MATERN>(A, c, lds);
+  if (threadIdx.x == 0 && need64) {
+    const int slot = atomicAdd(A.fb_count, 1);
+    A.fb_list[slot] = c;
+  }
+}
+
+// launch a bucket: the one-wave fit up to m = 64, the four-wave fit above
 template <int MB>
 void launch_bucket(const FitArgs& A, const int* list, const int* count, int n, hipStream_t s) {
   if (n <= 0) return;
@@ -67,7 +82,10 @@ void launch_bucket(const FitArgs& A, const int* list, const int* count, int n, h
     else
       hipLaunchKernelGGL((fit32w_kernel<MB, false>), grid, dim3(FIT_THREADS), 0, s, A, list, count, n);
   } else {
-    hipLaunchKernelGGL(fit32_kernel<MB>, dim3((unsigned)n), dim3(FIT_THREADS), 0, s, A, list, count);
+    if (A.kernel == KSDF_KERNEL_MATERN32)
+      hipLaunchKernelGGL((fit32q_kernel<true>), dim3((unsigned)n), dim3(FIT_THREADS), 0, s, A, list, count);
+    else
+      hipLaunchKernelGGL((fit32q_kernel<false>), dim3((unsigned)n), dim3(FIT_THREADS), 0, s, A, list, count);
   }
 }
 
