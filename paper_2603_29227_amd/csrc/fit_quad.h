@@ -34,8 +34,7 @@ struct QuadFitLds {
   alignas(16) float vl[128];
   alignas(16) float wh[128];
   alignas(16) float wl[128];
-  alignas(16) float y[128];       // hand-offs of the triangular solves (two right-hand sides)
-  alignas(16) float y2[128];
+  alignas(16) float y[128];       // hand-offs of the triangular solves
   alignas(16) float col[64];      // the column of a register factorisation step
   float ps[2][128];               // partial sums of the second column block: [rhs][row]
   float pc[2][128];
@@ -152,90 +151,6 @@ struct QuadFit {
 
   __device__ __forceinline__ float solve(float b) { return backward(forward(b)); }
 
-  // two right-hand sides
-  __device__ __forceinline__ void solve2(float b0, float b1, float& x0, float& x1) {
-    float y0 = 0.f, y1 = 0.f;
-    if (w == 0) {
-      const float* row = S.L + pkq(lane, 0);
-      float r0 = b0, r1 = b1;
-#pragma unroll 4
-      for (int j = 0; j < 64; ++j) {
-        const float u0 = readlane(r0 * rd, j), u1 = readlane(r1 * rd, j);
-        if (lane == j) {
-          y0 = u0;
-          y1 = u1;
-        }
-        const float l = row[j];
-        r0 = fmaf(-l, u0, r0);
-        r1 = fmaf(-l, u1, r1);
-      }
-      S.y[lane] = y0;
-      S.y2[lane] = y1;
-    }
-    __syncthreads();
-    if (w == 1) {
-      const float* row = S.L + pkq(64 + lane, 0);
-      float r0 = b0, r1 = b1;
-#pragma unroll 8
-      for (int j = 0; j < 64; ++j) {
-        const float l = row[j];
-        r0 = fmaf(-l, S.y[j], r0);
-        r1 = fmaf(-l, S.y2[j], r1);
-      }
-#pragma unroll 4
-      for (int j = 0; j < m - 64; ++j) {
-        const float u0 = readlane(r0 * rd, j), u1 = readlane(r1 * rd, j);
-        if (lane == j) {
-          y0 = u0;
-          y1 = u1;
-        }
-        const float l = row[64 + j];
-        r0 = fmaf(-l, u0, r0);
-        r1 = fmaf(-l, u1, r1);
-      }
-    }
-    x0 = 0.f;
-    x1 = 0.f;
-    if (w == 1) {
-      float r0 = y0, r1 = y1;
-#pragma unroll 4
-      for (int i = m - 65; i >= 0; --i) {
-        const float u0 = readlane(r0 * rd, i), u1 = readlane(r1 * rd, i);
-        if (lane == i) {
-          x0 = u0;
-          x1 = u1;
-        }
-        const float l = S.L[pkq(64 + i, 64) + lane];
-        r0 = fmaf(-l, u0, r0);
-        r1 = fmaf(-l, u1, r1);
-      }
-      S.y[64 + lane] = x0;
-      S.y2[64 + lane] = x1;
-    }
-    __syncthreads();
-    if (w == 0) {
-      float r0 = y0, r1 = y1;
-#pragma unroll 8
-      for (int i = 0; i < 64; ++i) {
-        const float l = S.L[pkq(64 + i, 0) + lane];
-        r0 = fmaf(-l, S.y[64 + i], r0);
-        r1 = fmaf(-l, S.y2[64 + i], r1);
-      }
-#pragma unroll 4
-      for (int i = 63; i >= 0; --i) {
-        const float u0 = readlane(r0 * rd, i), u1 = readlane(r1 * rd, i);
-        if (lane == i) {
-          x0 = u0;
-          x1 = u1;
-        }
-        const float l = S.L[pkq(i, 0) + lane];
-        r0 = fmaf(-l, u0, r0);
-        r1 = fmaf(-l, u1, r1);
-      }
-    }
-    __syncthreads();
-  }
-
   // (A x)_R with the FP32 leading parts (x on waves 0 and 1)
   __device__ __forceinline__ float matvec(float x) {
     if (w < 2) S.vh[R] = x;
@@ -256,6 +171,9 @@ struct QuadFit {
 
   // Dot2 partial of -(A x) over this wave's columns for the float-float x in (vh, vl)
   __device__ __forceinline__ void partial(const float* vh, const float* vl, float& s, float& c) const {
+    // the low parts of A do not change between calls: without this the compiler keeps
+    // all 64 of them live across the refinement loop
+    asm volatile("" ::: "memory");
     s = 0.f;
     c = 0.f;
     static_for<0, 16>([&](auto G) {
@@ -267,7 +185,7 @@ struct QuadFit {
       dot2_sub(s, c, ah[4 * g + 2], alo(4 * g + 2), h.z, l.z);
       dot2_sub(s, c, ah[4 * g + 3], alo(4 * g + 3), h.w, l.w);
       // keep the scheduler from hoisting every group's loads at once (registers)
-      if constexpr (g % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_sched_barrier(0);
     });
   }
 
@@ -278,7 +196,7 @@ struct QuadFit {
     return ff_fast_two_sum(h.hi, ((rhs.lo + c) + (S.pc[k][R] + a.lo)) + h.lo);
   }
 
-  // rhs - (A x)_R in float-float for one or two right-hand sides (x on waves 0 and 1)
+  // rhs - (A x)_R in float-float (x on waves 0 and 1)
   __device__ __forceinline__ ff residual(ff rhs, ff x) {
     if (w < 2) {
       S.vh[R] = x.hi;
@@ -294,28 +212,6 @@ struct QuadFit {
     __syncthreads();
     return w < 2 ? combine(rhs, s, c, 0) : ff{0.f, 0.f};
   }
-  __device__ __forceinline__ void residual2(ff rhs0, ff x0, ff rhs1, ff x1, ff& r0, ff& r1) {
-    if (w < 2) {
-      S.vh[R] = x0.hi;
-      S.vl[R] = x0.lo;
-      S.wh[R] = x1.hi;
-      S.wl[R] = x1.lo;
-    }
-    __syncthreads();
-    float s0, c0, s1, c1;
-    partial(S.vh, S.vl, s0, c0);
-    partial(S.wh, S.wl, s1, c1);
-    if (w >= 2) {
-      S.ps[0][R] = s0;
-      S.pc[0][R] = c0;
-      S.ps[1][R] = s1;
-      S.pc[1][R] = c1;
-    }
-    __syncthreads();
-    r0 = w < 2 ? combine(rhs0, s0, c0, 0) : ff{0.f, 0.f};
-    r1 = w < 2 ? combine(rhs1, s1, c1, 1) : ff{0.f, 0.f};
-  }
-
   __device__ __forceinline__ ff refined_solve(ff rhs, float tol) {
     const bool mine = w < 2 && R < m;
     ff x{solve(mine ? rhs.hi : 0.f), 0.f};
@@ -330,36 +226,6 @@ struct QuadFit {
       if (stop) break;
     }
     return x;
-  }
-
-  __device__ __forceinline__ void refined_solve2(ff rhs0, ff rhs1, float tol, ff& x0, ff& x1) {
-    const bool mine = w < 2 && R < m;
-    {
-      float z0, z1;
-      solve2(mine ? rhs0.hi : 0.f, mine ? rhs1.hi : 0.f, z0, z1);
-      x0 = ff{z0, 0.f};
-      x1 = ff{z1, 0.f};
-    }
-    float prev0 = INFINITY, prev1 = INFINITY;
-    bool run0 = true, run1 = true;
-    for (int it = 0; it < REFINE_MAX && (run0 || run1); ++it) {
-      ff r0, r1;
-      residual2(rhs0, x0, rhs1, x1, r0, r1);
-      float d0, d1;
-      solve2(mine ? r0.hi + r0.lo : 0.f, mine ? r1.hi + r1.lo : 0.f, d0, d1);
-      if (run0) {
-        x0 = ff_add(x0, ff{d0, 0.f});
-        const float dn = rows_max(fabsf(d0)), xn = rows_max(fabsf(x0.hi));
-        run0 = dn > tol * xn && dn < 0.5f * prev0;
-        prev0 = dn;
-      }
-      if (run1) {
-        x1 = ff_add(x1, ff{d1, 0.f});
-        const float dn = rows_max(fabsf(d1)), xn = rows_max(fabsf(x1.hi));
-        run1 = dn > tol * xn && dn < 0.5f * prev1;
-        prev1 = dn;
-      }
-    }
   }
 
   // squared distance of samples R and C, float-float
@@ -479,7 +345,7 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
     Q.ah[k] = v.hi;
     if (C <= R) S.Alo[pkq(R, 0) + C] = v.lo;   // the lower triangle, each entry once
     Lr[k] = v.hi;
-    if constexpr (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_sched_barrier(0);   // one entry's temporaries at a time
   });
   // L11 (wave 0)
   if (w == 0) {
@@ -527,7 +393,9 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
         const float xa = S.L[pkq(64 + 32 * I + lo, 2 * t + hi)];
         const float xb = S.L[pkq(64 + 32 * J + lo, 2 * t + hi)];
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xa, xb, acc, 0, 0, 0);
+        if constexpr (t % 4 == 3) __builtin_amdgcn_sched_barrier(0);
       });
+      __builtin_amdgcn_sched_barrier(0);
       static_for<0, 16>([&](auto Rg) {
         constexpr int r = Rg;
         const int row = 32 * I + 8 * (r / 4) + 4 * hi + r % 4, colj = 32 * J + lo;
@@ -609,7 +477,7 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
             Drow[C] = MATERN ? A.mc2_ff[0] * r2.hi * expf(-A.mc_ff[0] * sqrtf(r2.hi)) * A.inv_l_ff[0]
                              : Q.ah[k] * r2.hi * il3f;
         }
-        if constexpr (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
       });
       if (Drow && w < 2) Drow[R] = 0.f;
       if (w >= 2) {
@@ -621,8 +489,10 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
       if (w < 2) g = ff_mul(ff_neg(Q.combine(ff{0.f, 0.f}, gs, gc, 0)), il);
       __syncthreads();
       ff xil, xis{0.f, 0.f};
-      if (!A.svar) Q.refined_solve2(row ? g : ff{0.f, 0.f}, a, REFINE_TOL_ADJOINT, xil, xis);
-      else xil = Q.refined_solve(row ? g : ff{0.f, 0.f}, REFINE_TOL_ADJOINT);
+      // one right-hand side at a time: the two-RHS sweep needs more registers than the
+      // four-wave layout leaves
+      xil = Q.refined_solve(row ? g : ff{0.f, 0.f}, REFINE_TOL_ADJOINT);
+      if (!A.svar) xis = Q.refined_solve(a, REFINE_TOL_ADJOINT);
       if (row) {
         float4 xv;
         xv.x = xil.hi;
