@@ -8,7 +8,7 @@
 //   * wave 0 factors A11 = L11 L11^T in registers (right-looking by columns, as the
 //     one-wave fit) and publishes L11 in the packed factor in LDS;
 //   * wave 1 forms L21 = A21 L11^-T row by row in registers (a triangular solve per
-//     lane against L11's broadcast columns);
+//     lane against L11's broadcast rows);
 //   * wave 3 forms the trailing update S = L21 L21^T on the matrix cores (three 32 x 32
 //     tiles of v_mfma_f32_32x32x2f32 over k = 64, the lower triangle only), then
 //     factors A22 - S = L22 L22^T in registers.
@@ -39,9 +39,11 @@ struct QuadFitLds {
   float ps[2][128];               // partial sums of the second column block: [rhs][row]
   float pc[2][128];
   float red[2];                   // cross-wave reductions
+  float red3[2][3];
   int flag;                       // 0 once a pivot failed
   alignas(16) float L[QF_NP + 64];   // packed factor rows, reciprocal diagonal (+ reach)
-  float Alo[QF_NP];               // low parts of A, packed lower triangle (A is symmetric)
+  float Alo[QF_NP + 256];         // low parts of A, packed lower triangle (A is symmetric),
+                                  // then one dummy slot per thread
 };
 
 __device__ __forceinline__ int pkq(int i, int k) { return i * (i + 1) / 2 + k; }
@@ -53,14 +55,15 @@ struct QuadFit {
   float ah[64];           // row R of A, columns 64 cb + k (leading parts); identity past m
   float rd;               // 1 / L_RR for the lanes of waves 0 and 1
 
-  // the low part of A[R][64 cb + k] from the packed lower triangle in LDS (row R, or
-  // the symmetric entry's row): blocks below the diagonal read their own row, the
+  // the low part of A[R][64 cb + k] from the packed lower triangle in LDS: entry
+  // (max(R, C), min(R, C)), so the block below the diagonal reads its own rows and the
   // block above reads by column (consecutive lanes, consecutive entries)
-  __device__ __forceinline__ float alo(int k) const {
+  // (Rv: the row, passed through an empty asm so that the 64 addresses are formed at
+  // each use instead of being kept live across the refinement loop)
+  __device__ __forceinline__ float alo(int k, int Rv) const {
     const int C = 64 * cb + k;
-    if (w == 1) return S.Alo[pkq(R, 0) + C];
-    if (w == 2) return S.Alo[pkq(C, 0) + R];
-    return S.Alo[C <= R ? pkq(R, 0) + C : pkq(C, 0) + R];
+    const int hi = max(C, Rv), lo = min(C, Rv);   // one branch-free form for every block
+    return S.Alo[pkq(hi, 0) + lo];
   }
 
   __device__ __forceinline__ QuadFit(QuadFitLds& s, int m_)
@@ -76,6 +79,33 @@ struct QuadFit {
     }
     __syncthreads();
     return S.red[0] + S.red[1];
+  }
+  // three sums / two maxima with one pair of barriers
+  __device__ __forceinline__ float3 rows_sum3(float a, float b, float c) {
+    __syncthreads();
+    if (w < 2) {
+      const float ta = wave_sum(a), tb = wave_sum(b), tc = wave_sum(c);
+      if (lane == 0) {
+        S.red3[w][0] = ta;
+        S.red3[w][1] = tb;
+        S.red3[w][2] = tc;
+      }
+    }
+    __syncthreads();
+    return make_float3(S.red3[0][0] + S.red3[1][0], S.red3[0][1] + S.red3[1][1],
+                       S.red3[0][2] + S.red3[1][2]);
+  }
+  __device__ __forceinline__ float2 rows_max2(float a, float b) {
+    __syncthreads();
+    if (w < 2) {
+      const float ta = wave_max(a), tb = wave_max(b);
+      if (lane == 0) {
+        S.red3[w][0] = ta;
+        S.red3[w][1] = tb;
+      }
+    }
+    __syncthreads();
+    return make_float2(fmaxf(S.red3[0][0], S.red3[1][0]), fmaxf(S.red3[0][1], S.red3[1][1]));
   }
   __device__ __forceinline__ float rows_max(float v) {
     __syncthreads();
@@ -171,19 +201,18 @@ struct QuadFit {
 
   // Dot2 partial of -(A x) over this wave's columns for the float-float x in (vh, vl)
   __device__ __forceinline__ void partial(const float* vh, const float* vl, float& s, float& c) const {
-    // the low parts of A do not change between calls: without this the compiler keeps
-    // all 64 of them live across the refinement loop
-    asm volatile("" ::: "memory");
+    int Rv = R;
+    asm volatile("" : "+v"(Rv));
     s = 0.f;
     c = 0.f;
     static_for<0, 16>([&](auto G) {
       constexpr int g = G;
       const float4 h = reinterpret_cast<const float4*>(vh + 64 * cb)[g];
       const float4 l = reinterpret_cast<const float4*>(vl + 64 * cb)[g];
-      dot2_sub(s, c, ah[4 * g], alo(4 * g), h.x, l.x);
-      dot2_sub(s, c, ah[4 * g + 1], alo(4 * g + 1), h.y, l.y);
-      dot2_sub(s, c, ah[4 * g + 2], alo(4 * g + 2), h.z, l.z);
-      dot2_sub(s, c, ah[4 * g + 3], alo(4 * g + 3), h.w, l.w);
+      dot2_sub(s, c, ah[4 * g], alo(4 * g, Rv), h.x, l.x);
+      dot2_sub(s, c, ah[4 * g + 1], alo(4 * g + 1, Rv), h.y, l.y);
+      dot2_sub(s, c, ah[4 * g + 2], alo(4 * g + 2, Rv), h.z, l.z);
+      dot2_sub(s, c, ah[4 * g + 3], alo(4 * g + 3, Rv), h.w, l.w);
       // keep the scheduler from hoisting every group's loads at once (registers)
       __builtin_amdgcn_sched_barrier(0);
     });
@@ -220,7 +249,8 @@ struct QuadFit {
       const ff r = residual(rhs, x);
       const float d = solve(mine ? r.hi + r.lo : 0.f);
       x = ff_add(x, ff{d, 0.f});
-      const float dn = rows_max(fabsf(d)), xn = rows_max(fabsf(x.hi));
+      const float2 mx = rows_max2(fabsf(d), fabsf(x.hi));
+      const float dn = mx.x, xn = mx.y;
       const bool stop = !(dn > tol * xn) || !(dn < 0.5f * prev);
       prev = dn;
       if (stop) break;
@@ -343,7 +373,9 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
       if (mine) v = kv;
     }
     Q.ah[k] = v.hi;
-    if (C <= R) S.Alo[pkq(R, 0) + C] = v.lo;   // the lower triangle, each entry once
+    // the lower triangle, each entry once (entries above it go to a per-lane dummy slot,
+    // which keeps the store unconditional)
+    S.Alo[C <= R ? pkq(R, 0) + C : QF_NP + threadIdx.x] = v.lo;
     Lr[k] = v.hi;
     __builtin_amdgcn_sched_barrier(0);   // one entry's temporaries at a time
   });
@@ -363,14 +395,19 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
   }
   __syncthreads();
   bool ok = S.flag != 0;
-  // L21 = A21 L11^-T (wave 1): each lane solves its row against L11's columns
+  // L21 = A21 L11^-T (wave 1): each lane solves its row against L11, left-looking:
+  // x_j = (a_j - sum_{k<j} x_k L11[j][k]) / L11[j][j] with row j of L11 read by
+  // broadcast loads (contiguous, so pairs merge) and four partial sums per row
   if (ok && w == 1) {
     static_for<0, 64>([&](auto J) {
       constexpr int j = J;
-      const float x = Lr[j] * S.L[pkq(j, j)];
-      Lr[j] = x;
-      static_for<j + 1, 64>([&](auto K) { Lr[K] = fmaf(-x, S.L[pkq(K, j)], Lr[K]); });
-      __builtin_amdgcn_sched_barrier(0);
+      const float* Lj = S.L + pkq(j, 0);
+      float t[4] = {Lr[j], 0.f, 0.f, 0.f};
+      static_for<0, j>([&](auto K) {
+        constexpr int k = K;
+        t[k % 4] = fmaf(-Lr[k], Lj[k], t[k % 4]);
+      });
+      Lr[j] = ((t[0] + t[1]) + (t[2] + t[3])) * Lj[j];   // Lj[j]: the reciprocal diagonal
     });
     static_for<0, 64>([&](auto K) { S.L[pkq(64 + lane, K)] = Lr[K]; });
   }
@@ -428,20 +465,20 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
     const bool row = w < 2 && mine;
     float x = row ? 1.f : 0.f, lmax = 0.f;
     for (int it = 0; it < 4; ++it) {
-      const float nx = Q.rows_sum(x * x);
       const float y = Q.matvec(x);
-      const float xy = Q.rows_sum(x * y), yy = sqrtf(Q.rows_sum(y * y));
-      lmax = xy / nx;
-      x = y / yy;
+      const float3 r3 = Q.rows_sum3(x * x, x * y, y * y);
+      lmax = r3.y / r3.x;
+      x = y / sqrtf(r3.z);
     }
+    // inverse iteration: |x| = sqrt(m) at the start, 1 after each normalisation
     x = row ? ((R & 1) ? -1.f : 1.f) : 0.f;
-    float inv_lmin = 0.f;
+    float nx = sqrtf((float)m), inv_lmin = 0.f;
     for (int it = 0; it < 4; ++it) {
-      const float nx = sqrtf(Q.rows_sum(x * x));
       const float y = Q.solve(x);
       const float ny = sqrtf(Q.rows_sum(y * y));
       inv_lmin = ny / nx;
       x = y / ny;
+      nx = 1.f;
     }
     cond = lmax * inv_lmin;
   }
@@ -470,7 +507,7 @@ __device__ __forceinline__ bool fit32_quad(const FitArgs& A, int c, QuadFitLds& 
           const ff r2 = Q.dist2(xh, xl, C);
           ff dk;
           if constexpr (MATERN) dk = ff_mul(ff_mul(ff_exp_neg_lean(ff_mul(ff_sqrt(r2), mc)), r2), mc2);
-          else dk = ff_mul(ff{Q.ah[k], Q.alo(k)}, r2);
+          else dk = ff_mul(ff{Q.ah[k], Q.alo(k, R)}, r2);
           if (C == R) dk = ff{0.f, 0.f};
           dot2_sub(gs, gc, dk.hi, dk.lo, S.vh[C], S.vl[C]);
           if (Drow && C < R)
