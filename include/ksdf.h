@@ -144,8 +144,10 @@ void ksdf_cellset_destroy(ksdf_cellset* cs);
  * Both buffers must stay allocated, unmodified by the caller, until the model is
  * destroyed and its last launch has finished.  KSDF_ERR_WORKSPACE when a buffer is
  * missing or too small.
- * offsets/samples/keys: host int32 CSR as produced by the builder; origin/h: the
- * builder's lattice; n_points: number of surface samples the fits will receive.
+ * offsets/samples/keys: host int32 CSR as produced by the builder (keys unique and in
+ * lexicographic order, else KSDF_ERR_INVALID_ARGUMENT); origin/h: the builder's lattice
+ * (cell c's centre is origin + (key_c + 1/2) h); n_points: number of surface samples
+ * the fits will receive.
  * query_lo/query_hi (host, may be NULL): a box the queries are expected in; the index
  * covers it (queries outside still get exact answers through a slower brute-force
  * candidate scan and carry KSDF_Q_OUTSIDE_INDEX).  The model keeps the

@@ -97,6 +97,7 @@ void model_layout(ksdf_model* m, Carver& cv) {
   const long nb = m->index.n_boxes;
   cv.take(&m->index.box_off, nb + 1);
   cv.take(&m->index.box_rank, nb);
+  cv.take(&m->index.kmap, nb);
   cv.take(&m->index.bound, nb);
   cv.take(&m->index.counts, nb);
 }
@@ -134,6 +135,15 @@ int model_host_setup(ksdf_model* m, int n_cells, const int* offsets, const int* 
     }
     max_m = std::max(max_m, mc);
   }
+  // the candidate index visits keys in order and must meet cell ids ascending
+  for (int c = 1; c < n_cells; ++c) {
+    const int* a = keys + 3L * (c - 1);
+    const int* b = keys + 3L * c;
+    if (!std::lexicographical_compare(a, a + 3, b, b + 3)) {
+      set_error("cell keys must be unique and in lexicographic order (as the cell builder writes them)");
+      return KSDF_ERR_INVALID_ARGUMENT;
+    }
+  }
   const long nnz = offsets[n_cells];
   for (long i = 0; i < nnz; ++i)
     if (samples[i] < 0 || samples[i] >= n_points) {
@@ -156,6 +166,7 @@ int model_host_setup(ksdf_model* m, int n_cells, const int* offsets, const int* 
     const long mc = offsets[c + 1] - offsets[c];
     m->h_loff[c + 1] = m->h_loff[c] + mc * (mc + 1) / 2;
   }
+  m->h_keys.assign(keys, keys + 3L * n_cells);
   m->h_centre.resize(3L * n_cells);
   for (int c = 0; c < n_cells; ++c)
     for (int d = 0; d < 3; ++d) m->h_centre[3 * c + d] = origin[d] + ((double)keys[3 * c + d] + 0.5) * h;

@@ -39,7 +39,8 @@ struct CandidateIndex {
   int* box_off = nullptr;      // [n_boxes+1]
   int* box_list = nullptr;     // [entries] cell ids, ascending within a box
   int* box_rank = nullptr;     // [n_boxes] position of each box in Z (Morton) order
-  double* bound = nullptr;     // [n_boxes] squared inclusion bound (count pass)
+  int* kmap = nullptr;         // [n_boxes] cell id at each lattice key, -1 where none
+  long* bound = nullptr;       // [n_boxes] inclusion bound on near distances, (h/2)^2 units
   int* counts = nullptr;       // [n_boxes] list lengths (count pass)
   int max_list = 0;
 };
@@ -70,6 +71,7 @@ struct ksdf_model {
   std::vector<int> h_offsets;   // host copy of the CSR offsets
   std::vector<long> h_loff;     // host copy of packed-factor offsets
   std::vector<double> h_centre; // host copy of the cell centres [n,3]
+  std::vector<int> h_keys;      // host copy of the cell keys [n,3]
 
   // structure (device)
   int* offsets = nullptr;       // [n+1]

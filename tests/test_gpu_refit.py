@@ -171,3 +171,79 @@ def test_count_queries_shuffled_argmins_with_invalid_entries(Q):
     with pytest.raises(ValueError):
         model.count_queries(torch.from_numpy(am).cuda(), qcount[:-1])
     model.close()
+
+
+def test_streaming_refit_step_in_a_captured_graph_matches_eager():
+    """A streaming step (Sec. IV-C, App. G) captured once and replayed on new scans: the
+    new samples arrive in the static point buffer and their cells' buffer counters c2
+    grow; the step counts the previous queries' argmin cells (c0), refits the budget's
+    highest-priority dirty cells and queries again.  A twin model runs the same steps
+    eagerly; after every replay the selection, counters and query outputs agree bit for
+    bit, with eager queries of the captured model between the replays."""
+    _say("graph: count + refit + query, 4 replays on new scans vs an eager twin")
+    wl, cells, dt, p0, _, _ = _setup()
+    dev = torch.device("cuda")
+    owner = np.repeat(np.arange(cells.n), np.diff(cells.offsets))
+    P = torch.from_numpy(p0).to(dev)
+    q = torch.from_numpy(wl.queries).to(dev)
+    sg = torch.from_numpy(wl.sign).to(dev)
+    budget, eta = 24, 0.5
+    models, state = [], []
+    for _ in range(2):
+        m = _model(wl, cells, "fp32")
+        m.fit(P)
+        out = m._out(len(q), dev)
+        m.query(q, sg, out=out)
+        state.append(dict(out=out, dirty=torch.zeros(cells.n, dtype=torch.float32, device=dev),
+                          qcount=torch.zeros(cells.n, dtype=torch.float32, device=dev)))
+        models.append(m)
+    inc = torch.zeros(cells.n, dtype=torch.float32, device=dev)
+
+    def step(m, s):
+        s["dirty"].add_(inc)
+        m.count_queries(s["out"]["argmin"], s["qcount"])
+        sel, n = m.refit(P, s["dirty"], s["qcount"], eta, budget)
+        m.query(q, sg, out=s["out"])
+        return sel, n
+
+    gm, gs = models[0], state[0]
+    em, es = models[1], state[1]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step(gm, gs)   # warm-up on zero increments: sizes the workspace
+    torch.cuda.current_stream().wait_stream(side)
+    step(em, es)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gsel, gn = step(gm, gs)
+    rng = np.random.default_rng(11)
+    cur = p0.copy()
+    total = 0
+    for rep in range(4):
+        # a new scan: about 2% of the samples move, each cell counting its new samples
+        moved = rng.choice(len(cur), size=len(cur) // 50, replace=False)
+        cur[moved] += rng.normal(0, 0.003, (len(moved), 3)).astype(cur.dtype)
+        hit = np.zeros(len(cur), bool)
+        hit[moved] = True
+        counts = np.bincount(owner[hit[cells.samples]], minlength=cells.n).astype(np.float32)
+        P.copy_(torch.from_numpy(cur))
+        inc.copy_(torch.from_numpy(counts))
+        g.replay()
+        torch.cuda.synchronize()
+        # an eager query of the captured model between replays
+        gm.query(q[:500].contiguous(), sg[:500].contiguous())
+        esel, en = step(em, es)
+        torch.cuda.synchronize()
+        n = int(gn.item())
+        assert n == int(en.item()) and 0 < n <= budget
+        total += n
+        assert torch.equal(gsel[:n], esel[:n]), f"replay {rep}: refit selection differs"
+        assert torch.equal(gs["dirty"], es["dirty"]) and torch.equal(gs["qcount"], es["qcount"])
+        for k in gs["out"]:
+            assert torch.equal(gs["out"][k], es["out"][k]), f"replay {rep}: {k} differs"
+    # cells stay dirty across steps: the queue carries over while the budget is short
+    assert float(gs["dirty"].gt(0).sum()) > 0 and total == 4 * budget
+    for m in models:
+        m.close()
