@@ -318,14 +318,80 @@ __device__ __forceinline__ float forward_subst(const float* __restrict__ Lc, int
   return vv;
 }
 
+__device__ __forceinline__ float readlane_f(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Top-KM of (distance, id) over the list of index box b0, for a wave whose active lanes
+// all lie in that box (every lane of the wave calls it; `ref` is an active lane).  Lane
+// j loads entry j of each 64-entry chunk of the list; the chunk is sorted across the
+// wave (bitonic) by its distance to the query of lane ref, so that every lane meets
+// its nearest cells early and later entries rarely enter; the entries then reach all
+// lanes by readlane.  They do not arrive in id order, so equal distances are ordered
+// by id explicitly, which gives the same top-KM as the scan in id order.
+template <int KM>
+__device__ __forceinline__ void candidates_shared_box(const FastArgs& A, bool active, float qx,
+                                                      float qy, float qz, int b0, int ref,
+                                                      float (&cd)[KM], int (&cid)[KM], int& len) {
+  const int lane = threadIdx.x & 63;
+  const int beg = uniform(A.box_off[b0]), end = uniform(A.box_off[b0 + 1]);
+  len = end - beg;
+  const float rx = readlane_f(qx, ref), ry = readlane_f(qy, ref), rz = readlane_f(qz, ref);
+  for (int t0 = beg; t0 < end; t0 += 64) {
+    const int t = t0 + lane;
+    const bool have = t < end;
+    const int id = have ? A.box_list[t] : 0;
+    const float4 ce = A.centre[id];
+    float key = have ? cand_d2(rx, ry, rz, ce) : INFINITY;
+    int src = lane;
+#pragma unroll
+    for (int size = 2; size <= 64; size <<= 1) {
+#pragma unroll
+      for (int j = size >> 1; j > 0; j >>= 1) {
+        const float ok = __shfl_xor(key, j, 64);
+        const int os = __shfl_xor(src, j, 64);
+        // ascending blocks keep the smaller pair in the lower lane, descending the larger
+        const bool keep_min = ((lane & j) == 0) == ((lane & size) == 0);
+        const bool other_less = ok < key || (ok == key && os < src);
+        if (other_less == keep_min) {
+          key = ok;
+          src = os;
+        }
+      }
+    }
+    const int cnt = min(64, end - t0);
+    for (int e = 0; e < cnt; ++e) {
+      const int s = __builtin_amdgcn_readlane(src, e);
+      int xi = __builtin_amdgcn_readlane(id, s);
+      const float4 c = make_float4(readlane_f(ce.x, s), readlane_f(ce.y, s), readlane_f(ce.z, s), 0.f);
+      float x = cand_d2(qx, qy, qz, c);
+      if (active && (x < cd[KM - 1] || (x == cd[KM - 1] && xi < cid[KM - 1]))) {
+#pragma unroll
+        for (int r = 0; r < KM; ++r) {
+          if (x < cd[r] || (x == cd[r] && xi < cid[r])) {
+            const float tx = cd[r];
+            const int ti = cid[r];
+            cd[r] = x;
+            cid[r] = xi;
+            x = tx;
+            xi = ti;
+          }
+        }
+      }
+    }
+  }
+}
+
 // K nearest occupied cell centres of the candidate-index box list of (qx,qy,qz), ties
 // by id (Sec. IV-B.1): the first n entries of cid, nearest first.  outside: the point
-// lies outside the index lattice (then every cell is scanned).
+// lies outside the index lattice (then every cell is scanned).  Every lane of the wave
+// calls it together.
 template <int KM>
 __device__ __forceinline__ void query_candidates(const FastArgs& A, bool active, float qx, float qy,
                                                  float qz, int (&cid)[KM], int& n, bool& outside) {
-  // sorted top-KM of (distance, id); ids arrive ascending, so a later equal distance
-  // never moves ahead of an earlier one; the first k entries are the K nearest
+  // sorted top-KM of (distance, id), compared as pairs: an entry displaced by an
+  // insertion moves down past equal distances only in id order; the first k entries
+  // are the K nearest
   float cd[KM];
 #pragma unroll
   for (int r = 0; r < KM; ++r) {
@@ -336,6 +402,17 @@ __device__ __forceinline__ void query_candidates(const FastArgs& A, bool active,
   const long bkey = box_key(A, qx, qy, qz, &subkey);
   outside = bkey < 0;
   n = 0;
+  const unsigned long long act = __ballot(active);
+  if (act) {
+    const int ref = __builtin_ctzll(act);
+    const int b0 = __builtin_amdgcn_readlane((int)bkey, ref);
+    if (b0 >= 0 && !__ballot(active && bkey != b0)) {
+      int len;
+      candidates_shared_box<KM>(A, active, qx, qy, qz, b0, ref, cd, cid, len);
+      n = active ? min(A.k, len) : 0;
+      return;
+    }
+  }
   if (active) {
     int beg = 0, end = A.n_cells;
     if (!outside) {
@@ -354,12 +431,13 @@ __device__ __forceinline__ void query_candidates(const FastArgs& A, bool active,
       for (int u = 0; u < 4; ++u) ce[u] = A.centre[cc[u]];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        float x = (t0 + u < end) ? cand_d2(qx, qy, qz, ce[u]) : INFINITY;
-        if (x < cd[KM - 1]) {
-          int xi = cc[u];
+        const bool in = t0 + u < end;
+        float x = in ? cand_d2(qx, qy, qz, ce[u]) : INFINITY;
+        int xi = in ? cc[u] : 0x7fffffff;
+        if (x < cd[KM - 1] || (x == cd[KM - 1] && xi < cid[KM - 1])) {
 #pragma unroll
           for (int r = 0; r < KM; ++r) {
-            if (x < cd[r]) {
+            if (x < cd[r] || (x == cd[r] && xi < cid[r])) {
               const float tx = cd[r];
               const int ti = cid[r];
               cd[r] = x;

@@ -17,7 +17,8 @@ namespace ksdf {
 namespace {
 
 template <int KM, int NT, bool LANE, bool MAT = false>
-__global__ void __launch_bounds__(NT) query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(KM == 8 ? 5 : 1)))
+query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   const Pass1 r = query_pass1<KM, LANE, MAT>(A, sq);
   const bool active = (r.flags & 2) != 0;

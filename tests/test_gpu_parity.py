@@ -215,3 +215,48 @@ def test_fp64_fallback_decision_matches_exact_condition_number():
     np.testing.assert_array_equal(fp64, cond > 1e6)
     o = oracle_run(wl, cells, q, wl.sign, "fp32", svar=S.astype(np.float64))
     assert_parity(g, o, wl.ell, "fp32", label="strong-correlation cells")
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(query_split=1, query_block=64, query_sub=2, query_lanes=0),
+    dict(query_split=1, query_block=256, query_sub=1, query_lanes=1),
+    dict(query_split=0, query_block=64, query_sub=4),
+])
+def test_tied_candidates_give_the_same_answer_in_any_query_order(tuning):
+    """Queries on the lattice of cell faces and centres sit exactly midway between cell
+    centres in x and y, so FP32 candidate distances tie.  The K nearest cells are kept in (distance,
+    id) order whichever path a wave takes (the wave-shared scan of one index box, or each
+    lane's own scan) and whatever the wave's other queries are: shuffling the queries,
+    which regroups them into other waves, changes no output bit.  The outputs also pass
+    parity with the oracle (ties at the K-th place accepted as R6 reads them)."""
+    _say(f"tied candidate distances, shuffled query order, {tuning}")
+    wl = scenes.small_room_workload(n_queries=16, cfg_id=48)
+    # x and y on the half-lattice of cell faces and centres (tie groups of up to four
+    # mirrored cells), z generic
+    half = wl.h / 2
+    rng = np.random.default_rng(48)
+    pts = [np.array([wl.origin[0] + half * i, wl.origin[1] + half * j, rng.uniform(0.05, 2.95)])
+           for i in range(1, 80) for j in range(1, 64) for _ in range(2)]
+    q = np.asarray(pts, dtype=np.float32)
+    q = q[np.all((q > 0.05) & (q < np.array([9.95, 7.95, 2.95])), axis=1)]
+    assert len(q) > 5000
+    sign = np.ones(len(q), dtype=np.int8)
+    cells = ksdf.build_cells(wl.points, wl.origin, wl.h, wl.margin, wl.m_max, wl.m_min,
+                             wl.m_cap_grid, wl.key_lo)
+    model = ksdf.Model(cells, len(wl.points), wl.origin, wl.h, ell=wl.ell, noise_var=wl.noise_var)
+    model.set_tuning(**tuning)
+    model.fit(torch.from_numpy(wl.points).cuda())
+    perm = np.random.default_rng(3).permutation(len(q))
+    a = model.query(torch.from_numpy(q).cuda(), torch.from_numpy(sign).cuda())
+    a = {k: v.clone() for k, v in a.items()}
+    b = model.query(torch.from_numpy(np.ascontiguousarray(q[perm])).cuda(),
+                    torch.from_numpy(sign[perm]).cuda())
+    torch.cuda.synchronize()
+    pt = torch.from_numpy(perm).cuda()
+    for k in a:
+        assert torch.equal(a[k][pt], b[k]), f"{k} depends on the query order"
+    o = oracle_run(wl, cells, q, sign, "fp32")
+    rep = assert_parity({k: v.cpu().numpy() for k, v in a.items()}, o, wl.ell, "fp32", sign,
+                        label=f"tied candidates {tuning}")
+    print(rep, flush=True)
+    model.close()
