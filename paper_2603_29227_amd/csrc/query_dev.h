@@ -644,45 +644,57 @@ __device__ __forceinline__ float cell_lower_bound(const FastArgs& A, float d2box
   return d2box - A.two_l2 * logf(fmaxf(apos, 1.f));
 }
 
-// Min-fusion of the candidates' u^2 (ties to the lower id); where the error bounds of
-// the best and of a rival overlap by more than the budget, the overlapping cells are
-// re-evaluated in float-float.  Returns the argmin cell (-1: none valid); best = its u^2.
+// Min-fusion of the candidates' u^2 (ties to the lower id), with float-float
+// re-evaluation where FP32 could be off by more than the error budget: the best
+// cell's own error may take half of it, and the misordering of the best and a rival
+// whose error band overlaps it (at most the sum of their errors) the other half.
+// While a condition fails, the cell with the larger error of the failing pair is
+// re-evaluated (its error then counts as zero) and the conditions are checked again,
+// so near-tied cells of small error are not redone.  Returns the argmin cell (-1:
+// none valid); best = its u^2.
 template <int KM>
 __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float qx, float qy,
                                            float qz, const int (&cid)[KM], int n, float (&cu2)[KM],
-                                           const float (&cdl)[KM], float& best) {
-  auto argmin = [&](float& bu, float& bd) {
+                                           float (&cdl)[KM], float& best) {
+  auto argmin = [&](float& bu, float& bd, int& bs) {
     int c = -1;
     bu = INFINITY;
     bd = 0.f;
+    bs = 0;
 #pragma unroll
     for (int r = 0; r < KM; ++r)
       if (r < n && (cu2[r] < bu || (cu2[r] == bu && cu2[r] < INFINITY && cid[r] < c))) {
         bu = cu2[r];
         bd = cdl[r];
         c = cid[r];
+        bs = r;
       }
     return c;
   };
-  float bu = INFINITY, bd = 0.f;
-  int bc = active ? argmin(bu, bd) : -1;
-  const bool found = bc >= 0;
-  // the candidates to re-evaluate, one bit per slot
-  unsigned need = 0;
-  if (bc >= 0) {
+  // the slot to re-evaluate next (a one-bit mask), or 0 when the budget holds
+  auto next = [&](int bc, float bu, float bd, int bs) -> unsigned {
+    if (bc < 0) return 0u;
     const float budget = A.matern ? u_budget(bu) : u2_budget(bu, A.two_l2);
-    bool redo = false;
+    if (bd > budget) return 1u << bs;
+    int pick = -1;
+    float worst = 0.f;
 #pragma unroll
     for (int r = 0; r < KM; ++r)
-      if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd && cdl[r] + bd > budget)
-        redo = true;
-    if (redo) {
-#pragma unroll
-      for (int r = 0; r < KM; ++r)
-        if (r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd) need |= 1u << r;
-    }
-  }
-  const bool redone = need != 0;
+      if (r != bs && r < n && cu2[r] < INFINITY && cu2[r] - cdl[r] <= bu + bd &&
+          cdl[r] + bd > budget) {
+        const float e = fmaxf(cdl[r], bd);
+        if (e > worst) {
+          worst = e;
+          pick = cdl[r] >= bd ? r : bs;
+        }
+      }
+    return pick >= 0 ? 1u << pick : 0u;
+  };
+  float bu = INFINITY, bd = 0.f;
+  int bs = 0;
+  int bc = active ? argmin(bu, bd, bs) : -1;
+  const bool found = bc >= 0;
+  unsigned need = active ? next(bc, bu, bd, bs) : 0u;
   // the wave takes the flagged (query, cell) pairs one at a time, lowest lane first
   while (true) {
     const unsigned long long pend = __ballot(need != 0);
@@ -703,11 +715,14 @@ __device__ __forceinline__ int resolve_min(const FastArgs& A, bool active, float
     if ((int)(threadIdx.x & 63) == src) {
 #pragma unroll
       for (int r = 0; r < KM; ++r)
-        if (r == rs) cu2[r] = u2;
-      need &= ~(1u << rs);
+        if (r == rs) {
+          cu2[r] = u2;
+          cdl[r] = 0.f;
+        }
+      bc = argmin(bu, bd, bs);
+      need = next(bc, bu, bd, bs);
     }
   }
-  if (redone) bc = argmin(bu, bd);
   if (found) best = bu;
   return bc;
 }
