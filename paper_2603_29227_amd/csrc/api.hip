@@ -109,6 +109,10 @@ int model_host_setup(ksdf_model* m, int n_cells, const int* offsets, const int* 
                      const ksdf_hyper* hyper, const double query_lo[3], const double query_hi[3]) {
   int r = check_hyper(hyper);
   if (r) return r;
+  if (n_cells >= (1 << 28) - 1) {
+    set_error("ksdf_model_create: more than 2^28 - 2 cells");
+    return KSDF_ERR_UNSUPPORTED;
+  }
   if (n_cells < 0 || !offsets || (n_cells > 0 && (!samples || !keys)) || !finite3(origin) ||
       !(h > 0) || n_points < 0 || ((query_lo == nullptr) != (query_hi == nullptr))) {
     set_error("ksdf_model_create: invalid argument");

@@ -63,7 +63,7 @@ struct FastArgs {
 
 // What the min-fusion leaves for the argmin cell's outputs: the query, its argmin
 // cell (-1: none valid), the minimum u^2 and the scaling reference used for that
-// cell.  32 bytes, the record the split query passes between its two kernels.
+// cell (P1Rec below is its stored form).
 struct Pass1 {
   float qx, qy, qz, best;
   int qi, bc;
@@ -73,19 +73,43 @@ struct Pass1 {
 };
 constexpr int PASS1_FIT_TIMEOUT = 4;
 
+// The 16-byte form of a Pass1 that the split query stores between its kernels: the
+// query index, the argmin cell + 1 with the flags in the top four bits, the minimum
+// and the scaling reference.  The second kernel reads the query point again from the
+// caller's points (the same FP32 values the first kernel used).
+struct alignas(16) P1Rec {
+  int qi;
+  unsigned cf;
+  float best;
+  float bref;
+};
+constexpr int P1REC_CELL_BITS = 28;   // n_cells + 1 < 2^28 (checked at model creation)
+
+__device__ __forceinline__ P1Rec pack_p1(const Pass1& r) {
+  P1Rec o;
+  o.qi = r.qi;
+  o.cf = (unsigned)(r.bc + 1) | ((unsigned)r.flags << P1REC_CELL_BITS);
+  o.best = r.best;
+  o.bref = r.bref;
+  return o;
+}
+__device__ __forceinline__ int p1rec_cell(const P1Rec& o) {
+  return (int)(o.cf & ((1u << P1REC_CELL_BITS) - 1u)) - 1;
+}
+
 // two-kernel query launches (query_split{64,256}_{wave,lane}.hip)
-void launch_query_split_64_wave(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+void launch_query_split_64_wave(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2,
                                int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
-void launch_query_split_64_lane(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+void launch_query_split_64_lane(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2,
                                int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
-void launch_query_split_256_wave(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+void launch_query_split_256_wave(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2,
                                int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
-void launch_query_split_256_lane(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2,
+void launch_query_split_256_lane(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2,
                                int* count, int* cursor, int* tsum, void* pws, hipStream_t s);
 // pair form of pass 1 (query_pairs.hip): usable for Q queries, its workspace, launch
 bool query_pairs_usable(const ksdf_model* m, long Q);
 size_t query_pairs_workspace_bytes(const ksdf_model* m, long Q);
-void launch_pass1_pairs(const ksdf_model* m, const FastArgs& A, Pass1* rec, int* count, void* ws,
+void launch_pass1_pairs(const ksdf_model* m, const FastArgs& A, P1Rec* rec, int* count, void* ws,
                         hipStream_t s);
 
 namespace {

@@ -64,7 +64,7 @@ size_t query_fast_workspace_bytes(const ksdf_model* m, long Q) {
   const long nc = (long)m->n_cells + 1;
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
   const bool pairs = m->tuning.query_split && m->tuning.query_pairs && query_pairs_usable(m, Q);
-  return bucketing_bytes(m, Q) + 2 * align256(Q * sizeof(Pass1)) + 2 * align256(nc * sizeof(int)) +
+  return bucketing_bytes(m, Q) + 2 * align256(Q * sizeof(P1Rec)) + 2 * align256(nc * sizeof(int)) +
          align256(tiles * sizeof(int)) + (pairs ? query_pairs_workspace_bytes(m, Q) : 0);
 }
 
@@ -80,10 +80,10 @@ int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int
   if (m->tuning.query_split) {
     char* w = static_cast<char*>(ws) + bucketing_bytes(m, Q);
     const long nc = (long)m->n_cells + 1;
-    Pass1* rec = reinterpret_cast<Pass1*>(w);
-    w += align256(Q * sizeof(Pass1));
-    Pass1* rec2 = reinterpret_cast<Pass1*>(w);
-    w += align256(Q * sizeof(Pass1));
+    P1Rec* rec = reinterpret_cast<P1Rec*>(w);
+    w += align256(Q * sizeof(P1Rec));
+    P1Rec* rec2 = reinterpret_cast<P1Rec*>(w);
+    w += align256(Q * sizeof(P1Rec));
     int* count = reinterpret_cast<int*>(w);
     w += align256(nc * sizeof(int));
     int* cursor = reinterpret_cast<int*>(w);

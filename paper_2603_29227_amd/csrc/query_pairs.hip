@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(PT) pair_eval_kernel(FastArgs A, const int* pa
 
 template <int KM>
 __global__ void __launch_bounds__(PT) pair_fuse_kernel(FastArgs A, const int* cand, const float4* res,
-                                                        Pass1* rec, int* count) {
+                                                        P1Rec* rec, int* count) {
   const long sq = (long)blockIdx.x * PT + threadIdx.x;
   const bool active = sq < A.Q;
   const long qi = active ? A.perm[sq] : 0;
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(PT) pair_fuse_kernel(FastArgs A, const int* ca
   o.bc = bc;
   o.bref = bref;
   o.flags = (outside ? 1 : 0) | (active ? 2 : 0);
-  if (active) rec[sq] = o;
+  if (active) rec[sq] = pack_p1(o);
   wave_count(count, bc < 0 ? A.n_cells : bc, active);
 }
 
@@ -157,7 +157,7 @@ size_t query_pairs_workspace_bytes(const ksdf_model* m, long Q) {
          2 * align256(nc * sizeof(int)) + align256(tiles * sizeof(int));
 }
 
-void launch_pass1_pairs(const ksdf_model* m, const FastArgs& A, Pass1* rec, int* count, void* ws,
+void launch_pass1_pairs(const ksdf_model* m, const FastArgs& A, P1Rec* rec, int* count, void* ws,
                         hipStream_t s) {
   const int KM = km_of(m);
   const long np = A.Q * KM;

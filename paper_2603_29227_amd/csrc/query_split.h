@@ -1,7 +1,7 @@
 // Two-kernel form of the FP32 query (a launch choice with the same outputs as the
 // one-kernel form of query_fast.hip).
 //
-// Pass 1 (candidates, min-fusion) writes one record per query in wave order and
+// Pass 1 (candidates, min-fusion) writes one 16-byte record per query in wave order and
 // counts the queries of each argmin cell; the records are regrouped by argmin cell;
 // pass 2 then meets one or two argmin cells per wave instead of the two to three of
 // a spatial bucket, so the per-cell work (gradient, GP variance by forward
@@ -18,35 +18,46 @@ namespace {
 
 template <int KM, int NT, bool LANE, bool MAT = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(KM == 8 ? 5 : 1)))
-query_p1_kernel(FastArgs A, Pass1* rec, int* count) {
+query_p1_kernel(FastArgs A, P1Rec* rec, int* count) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   const Pass1 r = query_pass1<KM, LANE, MAT>(A, sq);
   const bool active = (r.flags & 2) != 0;
-  if (active) rec[sq] = r;
+  if (active) rec[sq] = pack_p1(r);
   wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
 }
 
-__global__ void __launch_bounds__(256) query_regroup_kernel(const Pass1* rec, long Q, int n_cells,
-                                                            int* cursor, Pass1* rec2) {
+__global__ void __launch_bounds__(256) query_regroup_kernel(const P1Rec* rec, long Q, int n_cells,
+                                                            int* cursor, P1Rec* rec2) {
   const long sq = (long)blockIdx.x * 256 + threadIdx.x;
   const bool active = sq < Q;
-  Pass1 r{};
+  P1Rec r{};
   if (active) r = rec[sq];
-  const int pos = wave_slot(cursor, r.bc < 0 ? n_cells : r.bc, active);
+  const int bc = p1rec_cell(r);
+  const int pos = wave_slot(cursor, bc < 0 ? n_cells : bc, active);
   if (active) rec2[pos] = r;
 }
 
 template <int MB, int NT, bool LANE, bool MF = false, bool MAT = false>
-__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const Pass1* rec2) {
+__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const P1Rec* rec2) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
   Pass1 r{};
   r.bc = -1;
-  if (sq < A.Q) r = rec2[sq];
+  if (sq < A.Q) {
+    const P1Rec o = rec2[sq];
+    r.qi = o.qi;
+    r.bc = p1rec_cell(o);
+    r.flags = (int)(o.cf >> P1REC_CELL_BITS);
+    r.best = o.best;
+    r.bref = o.bref;
+    r.qx = A.pts[3L * o.qi];
+    r.qy = A.pts[3L * o.qi + 1];
+    r.qz = A.pts[3L * o.qi + 2];
+  }
   query_finish_t<MB, LANE, MF, MAT>(A, r);
 }
 
 template <int NT, bool LANE>
-void launch_split_nt(const ksdf_model* m, const FastArgs& A, Pass1* rec, Pass1* rec2, int* count,
+void launch_split_nt(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2, int* count,
                      int* cursor, int* tsum, void* pws, hipStream_t s) {
   const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
   const long nc = (long)m->n_cells + 1;
