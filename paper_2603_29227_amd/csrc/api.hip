@@ -72,6 +72,7 @@ void model_layout(ksdf_model* m, Carver& cv) {
   cv.take(&m->sv64, nnz);
   cv.take(&m->L64, lsize);
   cv.take(&m->bucket_cells, n);
+  cv.take(&m->bucket_rank, n);
   cv.take(&m->fused_order, n);
   cv.take(&m->flags, 1);
   if (m->adjoint_alloc) {
@@ -291,6 +292,9 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
     if ((e = up(m->centre32, c32.data(), c32.size() * sizeof(float)))) return e;
     if ((e = up(m->centre64, m->h_centre.data(), m->h_centre.size() * sizeof(double)))) return e;
     if ((e = up(m->bucket_cells, order.data(), order.size() * sizeof(int)))) return e;
+    std::vector<int> rank(order.size());
+    for (size_t i = 0; i < order.size(); ++i) rank[order[i]] = (int)i;
+    if ((e = up(m->bucket_rank, rank.data(), rank.size() * sizeof(int)))) return e;
     if ((e = up(m->fused_order, byM.data(), byM.size() * sizeof(int)))) return e;
     KSDF_HIP_TRY(hipMemsetAsync(m->flags, 0, sizeof(int), s));
     if (m->precision == KSDF_FP32) {

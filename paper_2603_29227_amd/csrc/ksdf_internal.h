@@ -108,6 +108,7 @@ struct ksdf_model {
   float* D32 = nullptr;         // packed dA/dl (FP32 models)
   double* D64 = nullptr;        // packed dA/dl (FP64 models)
   int* bucket_cells = nullptr;  // [n] cell ids grouped by m bucket (<=16, <=32, <=64, <=128)
+  int* bucket_rank = nullptr;   // [n] position of each cell in bucket_cells
   int* fused_order = nullptr;   // [n] cell ids by m descending (fused launch fit order)
   int bucket_start[5] = {0, 0, 0, 0, 0};
 

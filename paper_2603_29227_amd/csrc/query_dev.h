@@ -24,6 +24,10 @@ struct FastArgs {
   int* argmin;
   uint8_t* qst;
   const int* perm;
+  // models with cells of more than 64 samples: the split query groups its records by
+  // this rank (cells of up to 64 samples first) so that its second kernel runs in two
+  // launches sized for 64 and 128 samples; null otherwise (records grouped by cell id)
+  const int* p2rank;
   int n_cells;
   int k;
   const int* __restrict__ offsets;
@@ -1322,6 +1326,7 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   A.sv = m->sv32;
   A.L = m->L32;
   A.Linv = m->Linv32;
+  A.p2rank = m->max_m > 64 ? m->bucket_rank : nullptr;
   A.centre = reinterpret_cast<const float4*>(m->centre32);
   A.box = m->box32;
   for (int d = 0; d < 3; ++d) {

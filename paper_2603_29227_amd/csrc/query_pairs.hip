@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(PT) pair_fuse_kernel(FastArgs A, const int* ca
   o.bref = bref;
   o.flags = (outside ? 1 : 0) | (active ? 2 : 0);
   if (active) rec[sq] = pack_p1(o);
-  wave_count(count, bc < 0 ? A.n_cells : bc, active);
+  wave_count(count, bc < 0 ? A.n_cells : (A.p2rank ? A.p2rank[bc] : bc), active);
 }
 
 int km_of(const ksdf_model* m) { return m->k_fuse <= 8 ? 8 : 16; }

@@ -23,26 +23,40 @@ query_p1_kernel(FastArgs A, P1Rec* rec, int* count) {
   const Pass1 r = query_pass1<KM, LANE, MAT>(A, sq);
   const bool active = (r.flags & 2) != 0;
   if (active) rec[sq] = pack_p1(r);
-  wave_count(count, r.bc < 0 ? A.n_cells : r.bc, active);
+  wave_count(count, r.bc < 0 ? A.n_cells : (A.p2rank ? A.p2rank[r.bc] : r.bc), active);
 }
 
 __global__ void __launch_bounds__(256) query_regroup_kernel(const P1Rec* rec, long Q, int n_cells,
-                                                            int* cursor, P1Rec* rec2) {
+                                                            const int* p2rank, int* cursor,
+                                                            P1Rec* rec2) {
   const long sq = (long)blockIdx.x * 256 + threadIdx.x;
   const bool active = sq < Q;
   P1Rec r{};
   if (active) r = rec[sq];
   const int bc = p1rec_cell(r);
-  const int pos = wave_slot(cursor, bc < 0 ? n_cells : bc, active);
+  const int pos = wave_slot(cursor, bc < 0 ? n_cells : (p2rank ? p2rank[bc] : bc), active);
   if (active) rec2[pos] = r;
 }
 
+// split_bin >= 0: the records are grouped by A.p2rank and the launch takes those of
+// the cells of rank < split_bin (side 0) or the rest (side 1); their boundary is the
+// first record of bin split_bin (its cursor, advanced by the regroup, less its count)
 template <int MB, int NT, bool LANE, bool MF = false, bool MAT = false>
-__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const P1Rec* rec2) {
+__global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const P1Rec* rec2,
+                                                      const int* cursor, const int* count,
+                                                      int split_bin, int side) {
   const long sq = (long)blockIdx.x * NT + threadIdx.x;
+  long lo = 0, hi = A.Q;
+  if (split_bin >= 0) {
+    const long S = (long)cursor[split_bin] - count[split_bin];
+    if (side == 0) hi = S;
+    else lo = S;
+    const long w0 = sq - (threadIdx.x & 63);
+    if (w0 + 64 <= lo || w0 >= hi) return;   // the whole wave is on the other side
+  }
   Pass1 r{};
   r.bc = -1;
-  if (sq < A.Q) {
+  if (sq >= lo && sq < hi) {
     const P1Rec o = rec2[sq];
     r.qi = o.qi;
     r.bc = p1rec_cell(o);
@@ -74,22 +88,39 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* 
   hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(SCAN_T), 0, s, tsum, (int)tiles);
   hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(SCAN_T), 0, s, count, nc, tsum, cursor);
   hipLaunchKernelGGL(query_regroup_kernel, dim3((unsigned)((A.Q + 255) / 256)), dim3(256), 0, s, rec,
-                     A.Q, m->n_cells, cursor, rec2);
+                     A.Q, m->n_cells, A.p2rank, cursor, rec2);
   if constexpr (!LANE) {
     if (m->tuning.query_mfma && m->Linv32 && m->max_m <= 64) {
       if (!m->linv_ok) launch_linv(m, s);
-      hipLaunchKernelGGL((query_p2_kernel<64, NT, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+                         cursor, count, -1, 0);
       return;
     }
   }
-  // the kernel function picks the pass-2 instantiation (Matern models carry u, not u^2)
+  // the kernel function picks the pass-2 instantiation (Matern models carry u, not u^2);
+  // with cells of more than 64 samples, the records of the cells of up to 64 run in the
+  // launch sized for 64 (fewer registers, more waves per SIMD) and the rest in the one
+  // sized for 128
+  if (m->max_m <= 64) {
+    if (A.matern)
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+                         cursor, count, -1, 0);
+    else
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor,
+                         count, -1, 0);
+    return;
+  }
+  const int split = m->bucket_start[3];   // ranks of the cells of up to 64 samples
   if (A.matern) {
-    if (m->max_m <= 64) hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
-    else hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2);
-  } else if (m->max_m <= 64) {
-    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+                       cursor, count, split, 0);
+    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+                       cursor, count, split, 1);
   } else {
-    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2);
+    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor, count,
+                       split, 0);
+    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor,
+                       count, split, 1);
   }
 }
 
