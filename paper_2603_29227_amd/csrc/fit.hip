@@ -106,32 +106,55 @@ __device__ __forceinline__ float refit_score(const float* dirty, const float* qc
   return __fmul_rn(dirty[c], __fadd_rn(1.f, __fmul_rn(eta, qcount[c])));
 }
 
-// Rank of every dirty cell (c2 > 0) by descending score, ties to the lower id, by
-// comparison with every other cell through LDS tiles; the first `budget` ranks name
-// the cells to refit.  n_dirty counts the dirty cells.
-__global__ void __launch_bounds__(256) refit_rank_kernel(const float* dirty, const float* qcount,
-                                                         float eta, int n, int budget, int* sel,
-                                                         int* n_dirty) {
-  __shared__ float ts[256];
+// The dirty cells (c2 > 0) and their scores, appended in any order (wave-aggregated
+// slots); n_dirty counts them.  The ranking below does not depend on the order.
+__global__ void __launch_bounds__(256) refit_compact_kernel(const float* dirty, const float* qcount,
+                                                            float eta, int n, int* dlist,
+                                                            float* dscore, int* n_dirty) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   const bool mine = i < n && dirty[i] > 0.f;
-  const float si = mine ? refit_score(dirty, qcount, eta, i) : -1.f;
+  const unsigned long long live = __ballot(mine);
+  if (!live) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)live) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(n_dirty, __popcll(live));
+  base = __shfl(base, leader, 64);
+  if (mine) {
+    const int slot = base + __popcll(live & ((1ull << lane) - 1ull));
+    dlist[slot] = i;
+    dscore[slot] = refit_score(dirty, qcount, eta, i);
+  }
+}
+
+// Rank of every dirty cell by descending score, ties to the lower id, by comparison
+// with the other dirty cells through LDS tiles (work grows with the square of the
+// dirty count, not of the cell count); the first `budget` ranks name the cells to
+// refit.  Launched with one thread per cell: blocks past the dirty count exit.
+__global__ void __launch_bounds__(256) refit_rank_kernel(const int* dlist, const float* dscore,
+                                                         const int* n_dirty, int budget, int* sel) {
+  __shared__ float ts[256];
+  __shared__ int tid_[256];
+  const int d = *n_dirty;
+  if ((int)blockIdx.x * 256 >= d) return;   // uniform over the block
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const bool mine = t < d;
+  const float si = mine ? dscore[t] : 0.f;
+  const int ci = mine ? dlist[t] : 0;
   int rank = 0;
-  for (int base = 0; base < n; base += 256) {
+  for (int base = 0; base < d; base += 256) {
     __syncthreads();
     const int j = base + threadIdx.x;
-    ts[threadIdx.x] = (j < n && dirty[j] > 0.f) ? refit_score(dirty, qcount, eta, j) : -1.f;
+    ts[threadIdx.x] = j < d ? dscore[j] : 0.f;
+    tid_[threadIdx.x] = j < d ? dlist[j] : 0;
     __syncthreads();
-    const int lim = min(256, n - base);
+    const int lim = min(256, d - base);
     for (int k = 0; k < lim; ++k) {
       const float sj = ts[k];
-      rank += (sj > si || (sj == si && base + k < i)) ? 1 : 0;
+      rank += (sj > si || (sj == si && tid_[k] < ci)) ? 1 : 0;
     }
   }
-  if (mine) {
-    if (rank < budget) sel[rank] = i;
-    atomicAdd(n_dirty, 1);
-  }
+  if (mine && rank < budget) sel[rank] = ci;
 }
 
 // n_sel = min(budget, n_dirty); clears the per-bucket counts
@@ -248,7 +271,8 @@ void launch_linv(const ksdf_model* m, hipStream_t s) {
 
 size_t refit_workspace_bytes(const ksdf_model* m, int budget) {
   const long b = std::min(budget, m->n_cells);
-  return 4 * b * sizeof(int) + 8 * sizeof(int);
+  // bucket lists, bucket counts + n_dirty, then the dirty cells' ids and scores
+  return 4 * b * sizeof(int) + 8 * sizeof(int) + 2 * (long)m->n_cells * sizeof(int);
 }
 
 int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, float* dirty,
@@ -263,11 +287,14 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
   int* blist = static_cast<int*>(ws);
   int* bcount = blist + 4L * budget;
   int* n_dirty = bcount + 4;
+  int* dlist = bcount + 8;
+  float* dscore = reinterpret_cast<float*>(dlist + m->n_cells);
   const unsigned gc = (unsigned)((m->n_cells + 255) / 256);
   const unsigned gb = (unsigned)((budget + 255) / 256);
   hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, s, n_dirty, 0);
-  hipLaunchKernelGGL(refit_rank_kernel, dim3(gc), dim3(256), 0, s, dirty, qcount, (float)eta, m->n_cells,
-                     budget, sel, n_dirty);
+  hipLaunchKernelGGL(refit_compact_kernel, dim3(gc), dim3(256), 0, s, dirty, qcount, (float)eta,
+                     m->n_cells, dlist, dscore, n_dirty);
+  hipLaunchKernelGGL(refit_rank_kernel, dim3(gc), dim3(256), 0, s, dlist, dscore, n_dirty, budget, sel);
   hipLaunchKernelGGL(refit_count_kernel, dim3(1), dim3(64), 0, s, n_dirty, budget, n_sel, bcount);
   FitArgs A = make_fit_args(m, pts, dtype, svar, user_status);
   timer_mark(m, KSDF_TIMER_FIT, 0, s);

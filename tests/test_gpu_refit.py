@@ -98,6 +98,13 @@ def test_refit_selection_and_counters_match_oracle():
         q2[want] *= 0.5
         assert np.array_equal(dirty.cpu().numpy(), d2)
         assert np.array_equal(qcount.cpu().numpy(), q2)
+    # no dirty cell: nothing is ranked or refitted, the counters stay as they are
+    dirty = torch.zeros(cells.n, dtype=torch.float32, device="cuda")
+    qcount = torch.full((cells.n,), 3.0, dtype=torch.float32, device="cuda")
+    sel, n = model.refit(P0, dirty, qcount, 0.5, 8)
+    torch.cuda.synchronize()
+    assert int(n.item()) == 0
+    assert bool((qcount == 3.0).all())
     model.close()
 
 
