@@ -275,6 +275,28 @@ int ksdf_query(const ksdf_model* model, const void* points, long Q, const int8_t
                uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * ksdf_query_bucket, ksdf_query_bucketed — ksdf_query in two calls, so that its first
+ * step can run while the cells are still being fitted (Sec. IV-B: the K nearest GPs
+ * of a point depend on the cell lattice only, not on the fit).
+ * ksdf_query_bucket sorts the Q points by candidate-index box and sub-box into
+ * `workspace` (the counting sort that opens every FP32 query); it reads the points and
+ * the model's candidate index, not the fitted cells, and may therefore run on another
+ * stream beside ksdf_fit_cells.  ksdf_query_bucketed then runs the rest of ksdf_query
+ * on that workspace, with the same arguments, outputs and errors as ksdf_query, and
+ * gives its results bit for bit.  Between the two calls the caller keeps the points,
+ * the workspace contents and the model's tuning unchanged, and orders the calls (one
+ * stream, or an event).  Workspace: at least ksdf_query_workspace_bytes(model, Q)
+ * bytes for both.  For FP64 models (which do not bucket) ksdf_query_bucket does
+ * nothing and ksdf_query_bucketed is ksdf_query.  Asynchronous; allocates nothing.
+ * ------------------------------------------------------------------------- */
+int ksdf_query_bucket(const ksdf_model* model, const void* points, long Q, void* workspace,
+                      size_t ws_bytes, void* stream);
+int ksdf_query_bucketed(const ksdf_model* model, const void* points, long Q, const int8_t* sign,
+                        void* mean, void* grad, void* var, void* var_f, void* grad_var,
+                        int* argmin, uint8_t* q_status, void* workspace, size_t ws_bytes,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * ksdf_query_noalloc — ksdf_query for callers that cannot allocate device memory
  * (code under graph capture, tight serving loops, harnesses that forbid allocation).
  * Same arguments, outputs and launches as ksdf_query, without the workspace: the
@@ -361,9 +383,13 @@ int ksdf_bhm_update_tau(const ksdf_bhm_layout* layout, const int* box_bhm, const
  * drain a task queue holding every cell fit (largest m first, FP64 refit in place
  * where the condition estimate asks for it) and then the query tiles, which start
  * once all fits have released their results.  Intended for cells with uneven m,
- * where separate per-bucket launches leave the device idle between kernels.  FP64
- * models run the plain fit and query back to back.  workspace: at least
- * ksdf_fit_query_workspace_bytes(model, Q) bytes.  Asynchronous; allocates nothing.
+ * where separate per-bucket launches leave the device idle between kernels.  With the
+ * tuning fused = 0 (or a Matern model) it runs the separate fit launches, with the
+ * query's bucketing (see ksdf_query_bucket) on a second stream that the model owns
+ * (default priority, forked from `stream` and joined back within the call, so the
+ * call stays capturable in a graph).  FP64 models run the plain fit and query back
+ * to back.  workspace: at least ksdf_fit_query_workspace_bytes(model, Q) bytes.
+ * Asynchronous; allocates nothing.
  * ------------------------------------------------------------------------- */
 size_t ksdf_fit_query_workspace_bytes(const ksdf_model* model, long Q);
 /* A workgroup's wait for the fits is bounded (2^26 sleeps by default).  If it expires

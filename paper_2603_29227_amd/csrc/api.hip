@@ -189,7 +189,25 @@ void destroy_model(ksdf_model* m) {
     for (auto& pair : phase)
       for (hipEvent_t e : pair)
         if (e) (void)hipEventDestroy(e);
+  if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+  if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+  if (m->aux) (void)hipStreamDestroy(m->aux);
   delete m;
+}
+
+// The model's second stream and its fork/join events; on any failure the model runs
+// every step on the caller's stream.
+void make_aux_stream(ksdf_model* m) {
+  if (hipStreamCreateWithFlags(&m->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+    if (m->aux) (void)hipStreamDestroy(m->aux);
+    m->aux = nullptr;
+    m->ev_fork = m->ev_join = nullptr;
+  }
 }
 
 }  // namespace
@@ -251,6 +269,7 @@ extern "C" int ksdf_model_create(int n_cells, const int* offsets, const int* sam
   }
   (void)hipGetDevice(&m->device);
   (void)hipDeviceGetAttribute(&m->n_cu, hipDeviceAttributeMultiprocessorCount, m->device);
+  make_aux_stream(m);
   Carver cv;
   cv.base = static_cast<char*>(store);
   model_layout(m, cv);
@@ -532,11 +551,32 @@ extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype,
                         ws_bytes, s);
   }
   if (!m->tuning.fused || m->kernel != KSDF_KERNEL_RBF) {
+    if (!m->aux || Q == 0) {
+      r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
+      if (r) return r;
+      m->fitted = true;
+      return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status,
+                          workspace, ws_bytes, s);
+    }
+    // The query's bucketing reads only the queries and the candidate index: it runs on
+    // the model's second stream beside the fit (which is latency-bound and leaves room
+    // on the chip), forked after the caller's earlier work and joined before the query
+    // kernels.  Both events are recorded on every path, so a graph capture of the call
+    // always joins the second stream back.
+    KSDF_HIP_TRY(hipEventRecord(m->ev_fork, s));
+    KSDF_HIP_TRY(hipStreamWaitEvent(m->aux, m->ev_fork, 0));
+    const int rb = launch_query_bucketing(m, points, Q, workspace, m->aux);
+    KSDF_HIP_TRY(hipEventRecord(m->ev_join, m->aux));
     r = launch_fit(m, surface_pts, dtype, sample_var, cell_status, s);
+    KSDF_HIP_TRY(hipStreamWaitEvent(s, m->ev_join, 0));
+    if (rb) return rb;
     if (r) return r;
     m->fitted = true;
-    return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
-                        ws_bytes, s);
+    m->prebucketed = true;
+    r = launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
+                     ws_bytes, s);
+    m->prebucketed = false;
+    return r;
   }
   r = launch_fit_query_fused(m, surface_pts, dtype, sample_var, cell_status, points, Q, sign,
                              mean, grad, var, var_f, grad_var, argmin, q_status, workspace, ws_bytes, s);
@@ -627,6 +667,42 @@ extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const
   if (r) return r;
   return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
                       ws_bytes, (hipStream_t)stream);
+}
+
+extern "C" int ksdf_query_bucket(const ksdf_model* m, const void* points, long Q, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+  if (!m || Q < 0 || (Q > 0 && !points)) {
+    set_error("ksdf_query_bucket: invalid argument");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  if (!m->index_ready) {
+    set_error("ksdf_query_bucket: the model's index is not attached");
+    return KSDF_ERR_INVALID_ARGUMENT;
+  }
+  const size_t need = query_workspace_bytes(m, Q);
+  if (ws_bytes < need || (need > 0 && !workspace)) {
+    set_error("ksdf_query_bucket: workspace too small");
+    return KSDF_ERR_WORKSPACE;
+  }
+  int r = check_device(m);
+  if (r) return r;
+  if (m->precision != KSDF_FP32 || Q == 0) return KSDF_OK;
+  r = launch_query_bucketing(m, points, Q, workspace, (hipStream_t)stream);
+  if (r) return r;
+  KSDF_HIP_TRY(hipGetLastError());
+  return KSDF_OK;
+}
+
+extern "C" int ksdf_query_bucketed(const ksdf_model* m, const void* points, long Q,
+                                   const int8_t* sign, void* mean, void* grad, void* var,
+                                   void* var_f, void* grad_var, int* argmin, uint8_t* q_status,
+                                   void* workspace, size_t ws_bytes, void* stream) {
+  if (!m) return KSDF_ERR_INVALID_ARGUMENT;
+  m->prebucketed = m->precision == KSDF_FP32;
+  const int r = ksdf_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status,
+                           workspace, ws_bytes, stream);
+  m->prebucketed = false;
+  return r;
 }
 
 extern "C" size_t ksdf_backward_workspace_bytes(const ksdf_model* m, long Q) {

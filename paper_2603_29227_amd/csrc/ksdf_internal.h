@@ -124,6 +124,11 @@ struct ksdf_model {
   hipEvent_t tev[KSDF_TIMER_COUNT][KSDF_TIMER_SLOTS][2] = {};
   mutable int tcount[KSDF_TIMER_COUNT] = {};   // launches since the last read
   size_t device_bytes = 0;
+  // second stream (default priority) for the query bucketing beside the fit in
+  // ksdf_fit_query, with its fork and join events; null when it could not be made
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  mutable bool prebucketed = false;   // the query's bucketing already sits in the workspace
 };
 
 namespace ksdf {
@@ -170,6 +175,9 @@ int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* 
                  void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
                  size_t ws_bytes, hipStream_t s);
 size_t query_workspace_bytes(const ksdf_model* m, long Q);
+// The query's bucketing alone (the first step of launch_query_fast), for running it
+// beside the fit; launch_query_fast then skips it while m->prebucketed is set.
+int launch_query_bucketing(const ksdf_model* m, const void* points, long Q, void* ws, hipStream_t s);
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);

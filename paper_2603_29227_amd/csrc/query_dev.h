@@ -1362,6 +1362,11 @@ inline FastArgs make_fast_args(const ksdf_model* m, const void* points, long Q, 
   return A;
 }
 
+// The permutation written by launch_bucketing (the workspace's second array).
+inline int* bucketed_perm(void* ws, long Q) {
+  return reinterpret_cast<int*>(static_cast<char*>(ws) + align256(Q * sizeof(int)));
+}
+
 // Counting sort of the queries by (index box, sub-box); sets A.perm.
 inline int launch_bucketing(const ksdf_model* m, FastArgs& A, void* ws, hipStream_t s) {
   const long Q = A.Q;

@@ -68,14 +68,25 @@ size_t query_fast_workspace_bytes(const ksdf_model* m, long Q) {
          align256(tiles * sizeof(int)) + (pairs ? query_pairs_workspace_bytes(m, Q) : 0);
 }
 
+int launch_query_bucketing(const ksdf_model* m, const void* points, long Q, void* ws, hipStream_t s) {
+  if (Q == 0) return KSDF_OK;
+  FastArgs A = make_fast_args(m, points, Q, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr);
+  return launch_bucketing(m, A, ws, s);
+}
+
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
                       uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
   (void)ws_bytes;   // checked by the caller against query_workspace_bytes
   if (Q == 0) return KSDF_OK;
   FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
-  int r = launch_bucketing(m, A, ws, s);
-  if (r != KSDF_OK) return r;
+  if (m->prebucketed) {
+    A.perm = bucketed_perm(ws, Q);
+  } else {
+    int r = launch_bucketing(m, A, ws, s);
+    if (r != KSDF_OK) return r;
+  }
   timer_mark(m, KSDF_TIMER_QUERY, 0, s);
   if (m->tuning.query_split) {
     char* w = static_cast<char*>(ws) + bucketing_bytes(m, Q);

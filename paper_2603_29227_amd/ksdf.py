@@ -34,7 +34,7 @@ EXPORTS = ["ksdf_build_cells", "ksdf_cellset_info", "ksdf_cellset_copy", "ksdf_c
            "ksdf_model_attach_index", "ksdf_model_destroy", "ksdf_model_info", "ksdf_fit_cells",
            "ksdf_query_workspace_bytes", "ksdf_query", "ksdf_query_noalloc",
            "ksdf_backward_workspace_bytes",
-           "ksdf_query_backward", "ksdf_cost_backward", "ksdf_fit_query_workspace_bytes",
+           "ksdf_query_bucket", "ksdf_query_bucketed", "ksdf_query_backward", "ksdf_cost_backward", "ksdf_fit_query_workspace_bytes",
            "ksdf_fit_query",
            "ksdf_model_set_tuning", "ksdf_model_get_tuning", "ksdf_model_set_timing",
            "ksdf_model_timer_read", "ksdf_refit_workspace_bytes", "ksdf_refit_cells",
@@ -150,6 +150,9 @@ def lib():
         L.ksdf_query.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, sz,
                                  _vp]
         L.ksdf_query_noalloc.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.ksdf_query_bucket.argtypes = [_vp, _vp, l, _vp, sz, _vp]
+        L.ksdf_query_bucketed.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                          sz, _vp]
         L.ksdf_backward_workspace_bytes.argtypes = [_vp, l]
         L.ksdf_backward_workspace_bytes.restype = sz
         L.ksdf_query_backward.argtypes = [_vp, _vp, l, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -379,11 +382,26 @@ class Model:
                  self._lib.ksdf_backward_workspace_bytes(self._h, Q), 1)
         return torch.empty(nb, dtype=torch.uint8, device=self.device)
 
+    def bucket(self, points: torch.Tensor, stream=None,
+               workspace: Optional[torch.Tensor] = None):
+        """The first step of query() alone (ksdf_query_bucket): sorts the points into the
+        workspace; it does not read the fit, so it may run beside fit() on another
+        stream.  query(..., bucketed=True) with the same points and workspace finishes."""
+        if points.dtype != self.dtype or not points.is_cuda or not points.is_contiguous() \
+                or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError(f"points must be a contiguous [Q,3] CUDA {self.dtype} tensor")
+        Q = len(points)
+        nb = self._lib.ksdf_query_workspace_bytes(self._h, Q)
+        ws = self._workspace(nb, workspace)
+        _check(self._lib.ksdf_query_bucket(self._h, _ptr(points), Q, _ptr(ws), nb, _stream(stream)),
+               "ksdf_query_bucket")
+
     def query(self, points: torch.Tensor, sign: Optional[torch.Tensor] = None, var_f=True,
               argmin=True, status=True, grad_var=False, out: Optional[dict] = None,
-              stream=None, workspace: Optional[torch.Tensor] = None) -> dict:
+              stream=None, workspace: Optional[torch.Tensor] = None, bucketed=False) -> dict:
         """Per-query outputs: mean, grad [Q,3], var, and optionally var_f, argmin, status
-        and grad_var [Q,3] (the variance of each gradient component, App. C)."""
+        and grad_var [Q,3] (the variance of each gradient component, App. C).  bucketed:
+        the workspace already holds bucket()'s sort of these points."""
         if points.dtype != self.dtype or not points.is_cuda or not points.is_contiguous() \
                 or points.dim() != 2 or points.shape[1] != 3:
             raise ValueError(f"points must be a contiguous [Q,3] CUDA {self.dtype} tensor")
@@ -394,10 +412,11 @@ class Model:
             out = self._out(Q, points.device, var_f, argmin, status, grad_var)
         nb = self._lib.ksdf_query_workspace_bytes(self._h, Q)
         ws = self._workspace(nb, workspace)
-        _check(self._lib.ksdf_query(self._h, _ptr(points), Q, _ptr(sign), _ptr(out["mean"]),
-                                    _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
-                                    _ptr(out.get("grad_var")), _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
-                                    _stream(stream)), "ksdf_query")
+        fn = self._lib.ksdf_query_bucketed if bucketed else self._lib.ksdf_query
+        _check(fn(self._h, _ptr(points), Q, _ptr(sign), _ptr(out["mean"]),
+                  _ptr(out["grad"]), _ptr(out["var"]), _ptr(out.get("var_f")),
+                  _ptr(out.get("grad_var")), _ptr(out.get("argmin")), _ptr(out.get("status")), _ptr(ws), nb,
+                  _stream(stream)), "ksdf_query_bucketed" if bucketed else "ksdf_query")
         return out
 
     def _out(self, Q, device, var_f=True, argmin=True, status=True, grad_var=False):

@@ -130,10 +130,14 @@ def test_concurrent_calls_on_two_streams_match_serial():
     model.close()
 
 
-def test_graph_fused_fit_query_replays_match_eager():
-    _say("graph: fused fit_query, 3 replays")
+@pytest.mark.parametrize("fused", [1, 0])
+def test_graph_fit_query_call_replays_match_eager(fused):
+    """fused=1: the persistent launch; fused=0: the fit with the query's bucketing on the
+    model's second stream beside it (forked and joined inside the captured call)."""
+    _say(f"graph: fit_query (fused={fused}), 3 replays")
     wl = scenes.small_room_workload(n_queries=30000, cfg_id=42, uneven=True)
     model, _ = _model(wl)
+    model.set_tuning(fused=fused, query_split=1 - fused)
     dev = torch.device("cuda")
     P = torch.from_numpy(wl.points).to(dev, torch.float32)
     q = torch.from_numpy(wl.queries).to(dev, torch.float32)
