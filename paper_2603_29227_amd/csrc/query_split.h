@@ -16,10 +16,22 @@
 namespace ksdf {
 namespace {
 
+// Workgroups go to the chip's 8 XCDs (each with its own L2) in turn: workgroup i runs
+// on XCD i mod 8.  Both passes read the cells of neighbouring workgroups (a spatial
+// bucket, or one argmin cell's run of records), so each XCD is given one contiguous
+// range of the logical workgroups instead: a cell's samples and inverse then fill one
+// L2, not eight.  The map is a bijection of [0, n); the results do not depend on it.
+constexpr int N_XCD = 8;
+__device__ __forceinline__ long xcd_block(long n) {
+  const long i = blockIdx.x, q = n / N_XCD, r = n % N_XCD;
+  const long x = i % N_XCD, k = i / N_XCD;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 template <int KM, int NT, bool LANE, bool MAT = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(KM == 8 ? 5 : 1)))
 query_p1_kernel(FastArgs A, P1Rec* rec, int* count) {
-  const long sq = (long)blockIdx.x * NT + threadIdx.x;
+  const long sq = xcd_block(gridDim.x) * NT + threadIdx.x;
   const Pass1 r = query_pass1<KM, LANE, MAT>(A, sq);
   const bool active = (r.flags & 2) != 0;
   if (active) rec[sq] = pack_p1(r);
@@ -45,7 +57,7 @@ template <int MB, int NT, bool LANE, bool MF = false, bool MAT = false>
 __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const P1Rec* rec2,
                                                       const int* cursor, const int* count,
                                                       int split_bin, int side) {
-  const long sq = (long)blockIdx.x * NT + threadIdx.x;
+  const long sq = xcd_block(gridDim.x) * NT + threadIdx.x;
   long lo = 0, hi = A.Q;
   if (split_bin >= 0) {
     const long S = (long)cursor[split_bin] - count[split_bin];
