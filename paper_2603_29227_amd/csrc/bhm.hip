@@ -80,13 +80,52 @@ __device__ double bhm_logodds64(const BhmArgs& A, const double* pts, long q, con
 // factors from the FP32 exp, the inner sums over the last axis plain and the outer sum
 // with TwoSum compensation.  The error is a few float roundings of sum |terms|; where
 // |l - tau| is below that, the sign is the FP32 decision.
-__device__ float bhm_logodds32(const BhmArgs& A, const float* pts, long q, const long key[3],
-                               const double* w) {
+// The FP32 log-odds with the hinge count as a compile-time constant NH: every loop
+// unrolls and the per-axis factors stay in registers.  The same operations in the same
+// order as bhm_logodds32_any below.
+template <int NH>
+__device__ __forceinline__ float bhm_logodds32_t(const BhmArgs& A, const float* pts, long q,
+                                                 const long key[3], const double* w) {
+  float e[3][NH];
+  const float g = (float)A.gamma;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    // x - (box corner) as a float pair, the corner origin + key B from the layout's pairs
+    const ff lo = ff_add(ff{A.origin_ff[d][0], A.origin_ff[d][1]},
+                         ff_mul_f(ff{A.box_ff[0], A.box_ff[1]}, (float)key[d]));
+    const ff t0 = ff_add(ff{pts[3 * q + d], 0.f}, ff_neg(lo));
+#pragma unroll
+    for (int i = 0; i < NH; ++i) {
+      const float fi = (float)i;
+      const float tt = fmaf(-fi, A.spacing_ff[0], t0.hi) + fmaf(-fi, A.spacing_ff[1], t0.lo);
+      e[d][i] = expf(-g * tt * tt);
+    }
+  }
+  constexpr int m = NH * NH * NH;
+  float s = (float)w[m], c = 0.f;   // bias feature; compensated outer sum
+#pragma unroll
+  for (int i = 0; i < NH; ++i)
+#pragma unroll
+    for (int j = 0; j < NH; ++j) {
+      const float eij = e[0][i] * e[1][j];
+      const double* wr = w + (i * NH + j) * NH;
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < NH; ++k) acc = fmaf((float)wr[k], e[2][k], acc);
+      const ff p = ff_two_sum(s, eij * acc);
+      s = p.hi;
+      c += p.lo;
+    }
+  return s + c;
+}
+
+// Any hinge count (read from the layout; the factor arrays live in private memory).
+__device__ float bhm_logodds32_any(const BhmArgs& A, const float* pts, long q, const long key[3],
+                                   const double* w) {
   const int nh = A.nh;
   float e[3][MAX_HINGES];
   const float g = (float)A.gamma;
   for (int d = 0; d < 3; ++d) {
-    // x - (box corner) as a float pair, the corner origin + key B from the layout's pairs
     const ff lo = ff_add(ff{A.origin_ff[d][0], A.origin_ff[d][1]},
                          ff_mul_f(ff{A.box_ff[0], A.box_ff[1]}, (float)key[d]));
     const ff t0 = ff_add(ff{pts[3 * q + d], 0.f}, ff_neg(lo));
@@ -97,7 +136,7 @@ __device__ float bhm_logodds32(const BhmArgs& A, const float* pts, long q, const
     }
   }
   const int m = nh * nh * nh;
-  float s = (float)w[m], c = 0.f;   // bias feature; compensated outer sum
+  float s = (float)w[m], c = 0.f;
   for (int i = 0; i < nh; ++i)
     for (int j = 0; j < nh; ++j) {
       const float eij = e[0][i] * e[1][j];
@@ -111,19 +150,29 @@ __device__ float bhm_logodds32(const BhmArgs& A, const float* pts, long q, const
   return s + c;
 }
 
+// 7 hinges per axis (the indoor setting) in registers; other counts the general form
+__device__ __forceinline__ float bhm_logodds32(const BhmArgs& A, const float* pts, long q,
+                                               const long key[3], const double* w) {
+  if (A.nh == 7) return bhm_logodds32_t<7>(A, pts, q, key, w);
+  return bhm_logodds32_any(A, pts, q, key, w);
+}
+
 // Points sorted by map box within each block (bitonic sort of (map id, slot) keys in
 // LDS), so that a wave's points mostly share a map: a wave whose points all lie in one
-// map reads its weights through wave-uniform (scalar) loads.  Each point's result goes
-// back to its own index.
+// map reads its weights through wave-uniform (scalar) loads, and one that spans a few
+// maps loads each weight from a few addresses.  The block is large (BS points: four
+// x rows of a 256-wide grid, whose boxes then hold about 16 of its points each) so
+// that a wave meets few maps.  Each point's result goes back to its own index.
+constexpr int BS = 1024;
 template <class T>
 __device__ __forceinline__ void bhm_sorted_slot(const BhmArgs& A, const T* pts, long Q, long* q_out,
                                                 int* id_out) {
-  __shared__ unsigned long long keys[BT];
-  const long q = (long)blockIdx.x * BT + threadIdx.x;
+  __shared__ unsigned long long keys[BS];
+  const long q = (long)blockIdx.x * BS + threadIdx.x;
   long key[3];
   const int id = q < Q ? bhm_box(A, pts, q, key) : INT_MAX - 1;
   keys[threadIdx.x] = ((unsigned long long)(unsigned)(id + 1) << 32) | threadIdx.x;
-  for (int k = 2; k <= BT; k <<= 1)
+  for (int k = 2; k <= BS; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
       __syncthreads();
       const int t = threadIdx.x, o = t ^ j;
@@ -138,12 +187,12 @@ __device__ __forceinline__ void bhm_sorted_slot(const BhmArgs& A, const T* pts, 
     }
   __syncthreads();
   const unsigned long long k = keys[threadIdx.x];
-  *q_out = (long)blockIdx.x * BT + (long)(k & 0xffffffffu);
+  *q_out = (long)blockIdx.x * BS + (long)(k & 0xffffffffu);
   *id_out = (int)(k >> 32) - 1;
 }
 
 template <class T>
-__global__ void __launch_bounds__(BT) bhm_sign_kernel(BhmArgs A, const T* pts, long Q, double tau,
+__global__ void __launch_bounds__(BS) bhm_sign_kernel(BhmArgs A, const T* pts, long Q, double tau,
                                                       int8_t* sign, double* logodds) {
   long q;
   int id;
@@ -294,12 +343,12 @@ int launch_bhm_sign(const ksdf_bhm_layout* L, const int* box_bhm, const double* 
     return KSDF_ERR_INVALID_ARGUMENT;
   }
   if (Q == 0) return KSDF_OK;
-  const unsigned g = (unsigned)((Q + BT - 1) / BT);
+  const unsigned g = (unsigned)((Q + BS - 1) / BS);
   if (dtype == KSDF_DTYPE_F64)
-    hipLaunchKernelGGL(bhm_sign_kernel<double>, dim3(g), dim3(BT), 0, s, A,
+    hipLaunchKernelGGL(bhm_sign_kernel<double>, dim3(g), dim3(BS), 0, s, A,
                        static_cast<const double*>(points), Q, tau, sign, logodds);
   else
-    hipLaunchKernelGGL(bhm_sign_kernel<float>, dim3(g), dim3(BT), 0, s, A,
+    hipLaunchKernelGGL(bhm_sign_kernel<float>, dim3(g), dim3(BS), 0, s, A,
                        static_cast<const float*>(points), Q, tau, sign, logodds);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;

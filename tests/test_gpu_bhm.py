@@ -20,9 +20,9 @@ def _say(msg):
     print(f"[gpu-case] {msg}", flush=True)
 
 
-def _setup():
+def _setup(hinges=7):
     wl = scenes.small_room_workload(n_queries=20000)
-    b = scenes.bhm_weights(wl)
+    b = scenes.bhm_weights(wl, hinges=hinges)
     rng = np.random.default_rng(3)
     near = wl.points[rng.choice(len(wl.points), 20000)] + rng.normal(0, 0.02, (20000, 3))
     q = np.concatenate([near, wl.queries.astype(np.float64)])
@@ -34,10 +34,11 @@ def _args(b):
             torch.from_numpy(b["box_bhm"]).cuda(), torch.from_numpy(b["weights"]).cuda())
 
 
-@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_bhm_sign_matches_oracle(dtype):
-    _say(f"bhm sign {dtype}")
-    wl, b, q = _setup()
+@pytest.mark.parametrize("dtype,hinges", [(torch.float64, 7), (torch.float32, 7), (torch.float32, 5)])
+def test_bhm_sign_matches_oracle(dtype, hinges):
+    """7 hinges per axis runs the FP32 form unrolled for that count; 5 the general one."""
+    _say(f"bhm sign {dtype}, {hinges} hinges per axis")
+    wl, b, q = _setup(hinges)
     qt = torch.from_numpy(q).to("cuda", dtype)
     qd = qt.double().cpu().numpy()
     for tau in (0.0, 0.3):
