@@ -164,11 +164,21 @@ __device__ __forceinline__ float bhm_logodds32(const BhmArgs& A, const float* pt
 // x rows of a 256-wide grid, whose boxes then hold about 16 of its points each) so
 // that a wave meets few maps.  Each point's result goes back to its own index.
 constexpr int BS = 1024;
+// Workgroups go to the 8 XCDs (each with its own L2) in turn; neighbouring blocks of
+// points read the same maps, so each XCD takes one contiguous range of the blocks (a
+// bijection of [0, n); the results do not depend on it).
+__device__ __forceinline__ long bhm_block(long n) {
+  constexpr long NX = 8;
+  const long i = blockIdx.x, q = n / NX, r = n % NX;
+  const long x = i % NX, k = i / NX;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
 template <class T>
 __device__ __forceinline__ void bhm_sorted_slot(const BhmArgs& A, const T* pts, long Q, long* q_out,
                                                 int* id_out) {
   __shared__ unsigned long long keys[BS];
-  const long q = (long)blockIdx.x * BS + threadIdx.x;
+  const long blk = bhm_block(gridDim.x);
+  const long q = blk * BS + threadIdx.x;
   long key[3];
   const int id = q < Q ? bhm_box(A, pts, q, key) : INT_MAX - 1;
   keys[threadIdx.x] = ((unsigned long long)(unsigned)(id + 1) << 32) | threadIdx.x;
@@ -187,7 +197,7 @@ __device__ __forceinline__ void bhm_sorted_slot(const BhmArgs& A, const T* pts, 
     }
   __syncthreads();
   const unsigned long long k = keys[threadIdx.x];
-  *q_out = (long)blockIdx.x * BS + (long)(k & 0xffffffffu);
+  *q_out = blk * BS + (long)(k & 0xffffffffu);
   *id_out = (int)(k >> 32) - 1;
 }
 
