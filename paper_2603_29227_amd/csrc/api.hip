@@ -572,11 +572,8 @@ extern "C" int ksdf_fit_query(ksdf_model* m, const void* surface_pts, int dtype,
     if (rb) return rb;
     if (r) return r;
     m->fitted = true;
-    m->prebucketed = true;
-    r = launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
-                     ws_bytes, s);
-    m->prebucketed = false;
-    return r;
+    return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
+                        ws_bytes, s, true);
   }
   r = launch_fit_query_fused(m, surface_pts, dtype, sample_var, cell_status, points, Q, sign,
                              mean, grad, var, var_f, grad_var, argmin, q_status, workspace, ws_bytes, s);
@@ -650,9 +647,11 @@ extern "C" size_t ksdf_query_workspace_bytes(const ksdf_model* m, long Q) {
   return m ? query_workspace_bytes(m, Q) : 0;
 }
 
-extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
-                          void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
-                          uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
+namespace {
+// ksdf_query and ksdf_query_bucketed: argument checks, then the launches
+int query_entry(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
+                void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status,
+                void* workspace, size_t ws_bytes, void* stream, bool prebucketed) {
   if (int r0 = check_query_args(m, points, Q, mean, grad, var)) return r0;
   if (!m->fitted || !m->index_ready) {
     set_error("ksdf_query: the model has not been fitted or its index is not attached");
@@ -666,7 +665,15 @@ extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const
   int r = check_device(m);
   if (r) return r;
   return launch_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
-                      ws_bytes, (hipStream_t)stream);
+                      ws_bytes, (hipStream_t)stream, prebucketed && m->precision == KSDF_FP32);
+}
+}  // namespace
+
+extern "C" int ksdf_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
+                          void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
+                          uint8_t* q_status, void* workspace, size_t ws_bytes, void* stream) {
+  return query_entry(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
+                     ws_bytes, stream, false);
 }
 
 extern "C" int ksdf_query_bucket(const ksdf_model* m, const void* points, long Q, void* workspace,
@@ -697,12 +704,8 @@ extern "C" int ksdf_query_bucketed(const ksdf_model* m, const void* points, long
                                    const int8_t* sign, void* mean, void* grad, void* var,
                                    void* var_f, void* grad_var, int* argmin, uint8_t* q_status,
                                    void* workspace, size_t ws_bytes, void* stream) {
-  if (!m) return KSDF_ERR_INVALID_ARGUMENT;
-  m->prebucketed = m->precision == KSDF_FP32;
-  const int r = ksdf_query(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status,
-                           workspace, ws_bytes, stream);
-  m->prebucketed = false;
-  return r;
+  return query_entry(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, workspace,
+                     ws_bytes, stream, true);
 }
 
 extern "C" size_t ksdf_backward_workspace_bytes(const ksdf_model* m, long Q) {

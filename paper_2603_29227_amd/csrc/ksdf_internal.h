@@ -128,7 +128,6 @@ struct ksdf_model {
   // ksdf_fit_query, with its fork and join events; null when it could not be made
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  mutable bool prebucketed = false;   // the query's bucketing already sits in the workspace
 };
 
 namespace ksdf {
@@ -171,16 +170,19 @@ int launch_refit(ksdf_model* m, const void* pts, int dtype, const void* svar, fl
 size_t count_queries_workspace_bytes(const ksdf_model* m);
 int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* qcount, float cap,
                          void* ws, hipStream_t s);
+// prebucketed: the workspace already holds launch_query_bucketing's sort of these
+// points (FP32 models), so the query starts after it
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
                  void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
-                 size_t ws_bytes, hipStream_t s);
+                 size_t ws_bytes, hipStream_t s, bool prebucketed = false);
 size_t query_workspace_bytes(const ksdf_model* m, long Q);
 // The query's bucketing alone (the first step of launch_query_fast), for running it
-// beside the fit; launch_query_fast then skips it while m->prebucketed is set.
+// beside the fit; launch_query_fast then skips it when called with prebucketed set.
 int launch_query_bucketing(const ksdf_model* m, const void* points, long Q, void* ws, hipStream_t s);
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
-                      uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s);
+                      uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s,
+                      bool prebucketed = false);
 size_t query_fast_workspace_bytes(const ksdf_model* m, long Q);
 // the softplus margin cost whose mean/var cotangents ksdf_cost_backward forms in the
 // backward kernel (device arrays of the model's precision)

@@ -343,7 +343,7 @@ size_t query_workspace_bytes(const ksdf_model* m, long Q) {
 
 int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* sign, void* mean,
                  void* grad, void* var, void* var_f, void* grad_var, int* argmin, uint8_t* q_status, void* ws,
-                 size_t ws_bytes, hipStream_t s) {
+                 size_t ws_bytes, hipStream_t s, bool prebucketed) {
   if (Q == 0) return KSDF_OK;
   const unsigned grid = (unsigned)((Q + QT - 1) / QT);
   if (m->precision == KSDF_FP64) {
@@ -356,7 +356,7 @@ int launch_query(const ksdf_model* m, const void* points, long Q, const int8_t* 
     timer_mark(m, KSDF_TIMER_QUERY, 1, s);
   } else {
     return launch_query_fast(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status, ws,
-                             ws_bytes, s);
+                             ws_bytes, s, prebucketed);
   }
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;

@@ -77,11 +77,11 @@ int launch_query_bucketing(const ksdf_model* m, const void* points, long Q, void
 
 int launch_query_fast(const ksdf_model* m, const void* points, long Q, const int8_t* sign,
                       void* mean, void* grad, void* var, void* var_f, void* grad_var, int* argmin,
-                      uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s) {
+                      uint8_t* q_status, void* ws, size_t ws_bytes, hipStream_t s, bool prebucketed) {
   (void)ws_bytes;   // checked by the caller against query_workspace_bytes
   if (Q == 0) return KSDF_OK;
   FastArgs A = make_fast_args(m, points, Q, sign, mean, grad, var, var_f, grad_var, argmin, q_status);
-  if (m->prebucketed) {
+  if (prebucketed) {
     A.perm = bucketed_perm(ws, Q);
   } else {
     int r = launch_bucketing(m, A, ws, s);

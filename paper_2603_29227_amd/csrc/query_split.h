@@ -57,12 +57,23 @@ template <int MB, int NT, bool LANE, bool MF = false, bool MAT = false>
 __global__ void __launch_bounds__(NT) query_p2_kernel(FastArgs A, const P1Rec* rec2,
                                                       const int* cursor, const int* count,
                                                       int split_bin, int side) {
-  const long sq = xcd_block(gridDim.x) * NT + threadIdx.x;
   long lo = 0, hi = A.Q;
   if (split_bin >= 0) {
     const long S = (long)cursor[split_bin] - count[split_bin];
     if (side == 0) hi = S;
     else lo = S;
+  }
+  // the blocks of this launch's side [lo, hi) are spread over the 8 XCDs, each XCD one
+  // contiguous range of them (as xcd_block does for a whole launch); the launch has a
+  // block for every query, rounded up to a multiple of 8, so the blocks past the
+  // side's count leave at once
+  const long base = lo / NT * NT;
+  const long nb = (hi - base + NT - 1) / NT;
+  const long per = (nb + N_XCD - 1) / N_XCD;
+  const long bx = (long)blockIdx.x % N_XCD, bk = (long)blockIdx.x / N_XCD;
+  if (bk >= per || bx * per + bk >= nb) return;   // uniform over the block
+  const long sq = base + (bx * per + bk) * NT + threadIdx.x;
+  if (split_bin >= 0) {
     const long w0 = sq - (threadIdx.x & 63);
     if (w0 + 64 <= lo || w0 >= hi) return;   // the whole wave is on the other side
   }
@@ -86,6 +97,7 @@ template <int NT, bool LANE>
 void launch_split_nt(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* rec2, int* count,
                      int* cursor, int* tsum, void* pws, hipStream_t s) {
   const unsigned g = (unsigned)((A.Q + NT - 1) / NT);
+  const unsigned g2 = (g + N_XCD - 1) / N_XCD * N_XCD;   // pass 2: whole rounds of the XCDs
   const long nc = (long)m->n_cells + 1;
   const long tiles = (nc + SCAN_TILE - 1) / SCAN_TILE;
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, s, count, nc, 0);
@@ -104,7 +116,7 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* 
   if constexpr (!LANE) {
     if (m->tuning.query_mfma && m->Linv32 && m->max_m <= 64) {
       if (!m->linv_ok) launch_linv(m, s);
-      hipLaunchKernelGGL((query_p2_kernel<64, NT, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, false, true>), dim3(g2), dim3(NT), 0, s, A, rec2,
                          cursor, count, -1, 0);
       return;
     }
@@ -115,23 +127,23 @@ void launch_split_nt(const ksdf_model* m, const FastArgs& A, P1Rec* rec, P1Rec* 
   // sized for 128
   if (m->max_m <= 64) {
     if (A.matern)
-      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g2), dim3(NT), 0, s, A, rec2,
                          cursor, count, -1, 0);
     else
-      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor,
+      hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g2), dim3(NT), 0, s, A, rec2, cursor,
                          count, -1, 0);
     return;
   }
   const int split = m->bucket_start[3];   // ranks of the cells of up to 64 samples
   if (A.matern) {
-    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE, false, true>), dim3(g2), dim3(NT), 0, s, A, rec2,
                        cursor, count, split, 0);
-    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE, false, true>), dim3(g), dim3(NT), 0, s, A, rec2,
+    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE, false, true>), dim3(g2), dim3(NT), 0, s, A, rec2,
                        cursor, count, split, 1);
   } else {
-    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor, count,
+    hipLaunchKernelGGL((query_p2_kernel<64, NT, LANE>), dim3(g2), dim3(NT), 0, s, A, rec2, cursor, count,
                        split, 0);
-    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g), dim3(NT), 0, s, A, rec2, cursor,
+    hipLaunchKernelGGL((query_p2_kernel<128, NT, LANE>), dim3(g2), dim3(NT), 0, s, A, rec2, cursor,
                        count, split, 1);
   }
 }

@@ -11,6 +11,7 @@ import oracle
 from paper_2603_29227_amd import ksdf, scenes
 
 HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "ksdf.h")
+ERR_INVALID_ARGUMENT = -1   # KSDF_ERR_INVALID_ARGUMENT in ksdf.h
 
 
 def declared_functions():
@@ -96,3 +97,16 @@ def test_model_bytes_is_a_host_query_that_grows_with_the_options():
     bad = ksdf.CellSet(c.offsets.copy(), c.samples.copy(), c.keys.copy())
     bad.samples[0] = len(wl.points) + 1
     assert _bytes(bad, wl) == 0
+
+
+def test_query_entry_points_reject_a_null_model_without_a_device():
+    """Argument errors are returned before any device work: a null model gives
+    KSDF_ERR_INVALID_ARGUMENT from the query calls, also on a host with no GPU."""
+    L = ksdf.lib()
+    L.ksdf_query_bucket.restype = ctypes.c_int
+    L.ksdf_query_bucketed.restype = ctypes.c_int
+    assert L.ksdf_query_bucket(None, None, 0, None, 0, None) == ERR_INVALID_ARGUMENT
+    assert L.ksdf_query_bucketed(None, None, 0, None, None, None, None, None, None, None, None,
+                                 None, 0, None) == ERR_INVALID_ARGUMENT
+    assert L.ksdf_query(None, None, 0, None, None, None, None, None, None, None, None, None, 0,
+                        None) == ERR_INVALID_ARGUMENT
