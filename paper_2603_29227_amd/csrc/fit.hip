@@ -216,6 +216,29 @@ __global__ void __launch_bounds__(256) count_queries_kernel(const int* argmin, l
   }
 }
 
+// The same counts through a histogram in LDS when the cells fit there: each block
+// counts one contiguous range of the queries (neighbouring queries mostly share their
+// argmin cell) and adds its non-zero bins to the global histogram, so the global
+// atomics fall from one per run of equal argmins to one per (block, cell).
+constexpr int CQ_T = 1024;
+constexpr int CQ_LDS_CELLS = 16384;
+__global__ void __launch_bounds__(CQ_T) count_queries_lds_kernel(const int* argmin, long Q,
+                                                                int n_cells, unsigned* hist) {
+  __shared__ unsigned h[CQ_LDS_CELLS];
+  for (int c = threadIdx.x; c < n_cells; c += CQ_T) h[c] = 0u;
+  __syncthreads();
+  const long per = (Q + gridDim.x - 1) / gridDim.x;
+  const long q0 = (long)blockIdx.x * per;
+  const long q1 = q0 + per < Q ? q0 + per : Q;
+  for (long q = q0 + threadIdx.x; q < q1; q += CQ_T) {
+    const int c = argmin[q];
+    if (c >= 0 && c < n_cells) atomicAdd(h + c, 1u);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < n_cells; c += CQ_T)
+    if (h[c]) atomicAdd(hist + c, h[c]);
+}
+
 __global__ void __launch_bounds__(256) count_apply_kernel(const unsigned* hist, float* qcount, int n,
                                                           float cap) {
   const int c = blockIdx.x * 256 + threadIdx.x;
@@ -343,9 +366,14 @@ int launch_count_queries(const ksdf_model* m, const int* argmin, long Q, float* 
   unsigned* hist = static_cast<unsigned*>(ws);
   const unsigned gc = (unsigned)((n + 255) / 256);
   hipLaunchKernelGGL(zero_kernel, dim3(gc), dim3(256), 0, s, hist, n);
-  if (Q > 0)
+  if (Q > 0 && n <= CQ_LDS_CELLS) {
+    const long blocks = std::min<long>(1024, (Q + CQ_T - 1) / CQ_T);
+    hipLaunchKernelGGL(count_queries_lds_kernel, dim3((unsigned)blocks), dim3(CQ_T), 0, s, argmin, Q,
+                       n, hist);
+  } else if (Q > 0) {
     hipLaunchKernelGGL(count_queries_kernel, dim3((unsigned)((Q + 255) / 256)), dim3(256), 0, s,
                        argmin, Q, n, hist);
+  }
   hipLaunchKernelGGL(count_apply_kernel, dim3(gc), dim3(256), 0, s, hist, qcount, n, cap);
   KSDF_HIP_TRY(hipGetLastError());
   return KSDF_OK;
