@@ -160,10 +160,11 @@ __device__ __forceinline__ float bhm_logodds32(const BhmArgs& A, const float* pt
 // Points sorted by map box within each block (bitonic sort of (map id, slot) keys in
 // LDS), so that a wave's points mostly share a map: a wave whose points all lie in one
 // map reads its weights through wave-uniform (scalar) loads, and one that spans a few
-// maps loads each weight from a few addresses.  The block is large (BS points: four
-// x rows of a 256-wide grid, whose boxes then hold about 16 of its points each) so
-// that a wave meets few maps.  Each point's result goes back to its own index.
-constexpr int BS = 1024;
+// maps loads each weight from a few addresses.  A larger block lets a wave meet fewer
+// maps but costs occupancy (on the 256^3 room grid, blocks of 128, 256, 512 and 1024
+// points took 0.85, 0.58, 0.63 and 0.92 ms).  Each point's result goes back to its
+// own index.
+constexpr int BS = 256;
 // Workgroups go to the 8 XCDs (each with its own L2) in turn; neighbouring blocks of
 // points read the same maps, so each XCD takes one contiguous range of the blocks (a
 // bijection of [0, n); the results do not depend on it).
